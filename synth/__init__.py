@@ -1,0 +1,18 @@
+"""Seeded synthetic inputs for the polarization / screened-interaction path.
+
+This package builds input arrays only: lattice, k-mesh, plane-wave spheres,
+orthonormal wavefunction coefficients, band energies, frequency grids,
+transition probabilities and Wannier orbitals on the real-space grid.  It
+holds none of the method's arithmetic (no pair densities, no weights, no
+polarization, no dielectric matrix, no projection).  Both the FP64 oracle and
+the device library consume exactly these arrays.
+"""
+
+from .gen import (  # noqa: F401
+    BOHR_ANGSTROM,
+    HARTREE_EV,
+    Problem,
+    make_config,
+    make_problem,
+    mesh_fractions,
+)
