@@ -1,0 +1,204 @@
+/*
+ * rp.h - C ABI of the MI355X polarization / screened-interaction library.
+ *
+ * The library computes, for one q-point, the constrained-RPA chain of the
+ * RESPACK paper (Nakamura et al., section "Response function with random
+ * phase approximation" and section "Direct-Coulomb and exchange integrals"):
+ *
+ *   pair densities  M^G_{ab}(k+q,k) = <psi_{a,k+q}| e^{i(q+G).r} |psi_{b,k}>   Eq. ism
+ *   polarization    chi_GG'(q,w) = (2/Nk) sum_k sum_a sum_b (1 - T T)
+ *                                  M^G M^G'* X_{a k+q, b k}(w)                  Eq. chi
+ *                   with X integrated by the generalized tetrahedron method    Eqs. Xakqbk, tetrahedron, tak
+ *   dielectric      eps_GG' = delta_GG' - (4 pi/Omega) chi_GG'/(|q+G||q+G'|)   Eq. epsGG
+ *   screened        W_GG' = (4 pi/Omega) eps^-1_GG' / (|q+G||q+G'|)             Eq. Wq
+ *   projection      W_ij(q,w) = (4 pi/(Omega Nq)) [ sum_GG' rho_i(G) eps^-1 rho_j(G')*
+ *                                 + sum_{G in tail} rho_i(G) rho_j(G)* ]       Eqs. matrix_U, rhoiqG
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Units: lattice in bohr; energies, frequencies and the broadening in eV;
+ *   chi in hartree^-1 (atomic units); W and W_ij in eV.  1 Ha = 27.211386245988 eV.
+ * - k mesh: Gamma-centred, k = n/K (fractional), mesh index (n1*K2 + n2)*K3 + n3.
+ *   q = iq/K with iq a mesh index; the q grid is the k grid (Eq. W).
+ * - Real-space grid r_j = (j1/N1, j2/N2, j3/N3) fractional, stored [j1][j2][j3].
+ * - Reciprocal vectors G = m1 b1 + m2 b2 + m3 b3 with integer Miller indices.
+ * - Complex arrays ("c128") are interleaved (re, im) doubles, C-contiguous.
+ * - Pair order: p = ((k-k0)*(e1-e0) + (a-e0))*(o1-o0) + (b-o0): occupied
+ *   band b fastest, then empty band a, then k.
+ * - Memory: the caller owns every array it passes.  "dev" pointers are device
+ *   memory on the context's GPU, "host" pointers are ordinary host memory read
+ *   during the call only.  The context owns its device workspace, which grows
+ *   on demand and is released by rp_destroy.
+ * - Execution: device work is enqueued on the context's stream and is
+ *   asynchronous with respect to the host; host arrays may be reused as soon
+ *   as the call returns.
+ * - Errors: arguments are validated before anything is enqueued; a non-OK
+ *   status means nothing was enqueued (or, for RP_E_DEVICE, that a launch
+ *   failed) and the outputs are undefined.  Faults detected inside kernels
+ *   (a zero pivot, a non-finite value) are reported by rp_synchronize.
+ *   rp_last_error gives a message for the most recent failure.
+ * - One context per host thread.
+ */
+#ifndef RP_H
+#define RP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RP_OK = 0,
+    RP_E_NULL = 1,        /* a required pointer is NULL */
+    RP_E_SHAPE = 2,       /* inconsistent sizes, ranges or counts */
+    RP_E_RANGE = 3,       /* a value outside its domain (e.g. |q+G| = 0, delta < 0) */
+    RP_E_ALIAS = 4,       /* FFT grid too small for alias-free pair products */
+    RP_E_NOMEM = 5,       /* device workspace could not be allocated */
+    RP_E_DEVICE = 6,      /* HIP runtime error */
+    RP_E_SINGULAR = 7,    /* the dielectric matrix had a zero pivot */
+    RP_E_UNSUPPORTED = 8  /* e.g. an FFT length with a prime factor above 5 */
+} rp_status;
+
+typedef enum {
+    RP_FP64 = 0,        /* FP64 everywhere (FP64 matrix cores for chi) */
+    RP_SPLIT_BF16 = 1   /* chi contraction with M split into BF16 hi/mid/lo
+                           terms on BF16 matrix cores, FP32 accumulation,
+                           FP64 reduction into chi; all other steps FP64 */
+} rp_precision;
+
+typedef enum {
+    RP_W_TETRA = 0,     /* generalized tetrahedron integration of X (Eq. tetrahedron) */
+    RP_W_SAMPLING = 1   /* X evaluated at the mesh point (Eq. Xakqbk as written) */
+} rp_weight_mode;
+
+typedef struct rp_ctx rp_ctx;
+
+typedef struct {
+    double lat[3][3]; /* rows a1, a2, a3 (bohr) */
+    int fft[3];       /* real-space grid N1, N2, N3 (factors 2,3,5 only, each <= 256) */
+    int kmesh[3];     /* k mesh K1, K2, K3 */
+} rp_cell;
+
+/* Create a context on GPU `device`.  hip_stream is a hipStream_t to enqueue
+ * on, or NULL for a stream the context creates (default priority) and owns. */
+rp_status rp_create(rp_ctx **ctx, int device, void *hip_stream);
+
+/* Release the workspace and the owned stream.  NULL is accepted. */
+rp_status rp_destroy(rp_ctx *ctx);
+
+/* Wait for the context's stream; report device-side faults (RP_E_SINGULAR for
+ * a zero pivot, RP_E_RANGE for a non-finite value) raised since the last call. */
+rp_status rp_synchronize(rp_ctx *ctx);
+
+/* Message of the most recent failure on ctx ("" if none).  Owned by ctx and
+ * valid until the next call on it. */
+const char *rp_last_error(const rp_ctx *ctx);
+
+/*
+ * Steps a2-a4: pair densities (Eq. ism), evaluated by the FFT route:
+ *   u_{nk}(r_j) = sum_{G in S_psi(k)} C_{Gn}(k) e^{iG.r_j}                       (Eq. pak)
+ *   M_p(G) = (1/N_r) sum_j conj(u_{a,k'}(r_j)) u_{b,k}(r_j) e^{i(G+G0).r_j}
+ * where k+q = k' + G0 with k' on the mesh.  This equals the plane-wave
+ * definition exactly when N_a > 2 mmax_a + max|m_a + G0_a| on each axis.
+ *
+ * nband, npw_max     : bands and padded plane-wave count of coef/miller
+ * npw      (host)    : int[Nk] plane waves per k
+ * mmax     (host)    : int[3] bound on |m_a| over all wavefunction Miller
+ *                      indices (used for the aliasing check and to prune the
+ *                      transforms; a wrong bound gives wrong results)
+ * miller   (dev)     : int[Nk][npw_max][3]
+ * coef     (dev)     : c128[Nk][nband][npw_max], sum_G |C_Gn|^2 = 1
+ * o0..o1 / e0..e1    : occupied bands b at k / empty bands a at k+q
+ * k0..k1             : k range of this call
+ * gsph     (host)    : int[ng][3] Miller indices of the polarization sphere
+ * M        (dev)     : c128[k1-k0][e1-e0][o1-o0][ng] output
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_ALIAS, RP_E_UNSUPPORTED, RP_E_NOMEM,
+ * RP_E_DEVICE.
+ */
+rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband,
+                          int npw_max, const int *npw, const int mmax[3], const int *miller,
+                          const double *coef, int o0, int o1, int e0, int e1, int k0, int k1,
+                          int ng, const int *gsph, double *M);
+
+/*
+ * Step a5: weights w_p(omega_f) = (2/Nk)(1 - T_{a,k+q} T_{b,k}) x_p(omega_f)
+ * (Eqs. chi, tak), x from the generalized tetrahedron method on the linear
+ * interpolant of E_a(k+q) - E_b(k) over the 6 tetrahedra per mesh cell that
+ * share the cell's (0,0,0)-(1,1,1) diagonal (Eq. tetrahedron), with
+ * z = w + i delta and z' = -w + i delta (Eq. Xakqbk), or x = X at the mesh
+ * point for RP_W_SAMPLING.
+ *
+ * energy_eV (dev)    : double[Nk][nband]
+ * T         (dev)    : double[Nk][nband] transition probabilities (Eq. tak),
+ *                      or NULL for the usual RPA (T = 0)
+ * freq_eV   (host)   : c128[nfreq] (real w, or i*nu on the imaginary axis)
+ * delta_eV           : broadening >= 0
+ * w         (dev)    : c128[nfreq][npair] output, hartree^-1
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE, RP_E_NOMEM, RP_E_DEVICE.
+ */
+rp_status rp_weights(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband,
+                     const double *energy_eV, const double *T, int o0, int o1, int e0, int e1,
+                     int k0, int k1, int nfreq, const double *freq_eV, double delta_eV,
+                     rp_weight_mode wm, double *w);
+
+/*
+ * Steps a5-a6: chi_GG'(w) (+)= sum_p w_p(w) M_p(G) conj(M_p(G'))   (Eq. chi)
+ * for the pairs of one rp_pair_density call (same ranges, same M layout).
+ * prec selects the contraction: RP_FP64 (FP64 matrix cores) or
+ * RP_SPLIT_BF16 (BF16 hi/mid/lo products with FP32 accumulation, added
+ * into chi in FP64).  Weights are always FP64.
+ *
+ * M          (dev)   : c128[npair][ng] from rp_pair_density
+ * accumulate         : 0 overwrite chi, 1 add into chi
+ * chi        (dev)   : c128[nfreq][ng][ng], hartree^-1
+ * Errors: as rp_weights.
+ */
+rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband,
+                             const double *energy_eV, const double *T, int o0, int o1, int e0,
+                             int e1, int k0, int k1, int ng, const double *M, int nfreq,
+                             const double *freq_eV, double delta_eV, rp_weight_mode wm,
+                             rp_precision prec, int accumulate, double *chi);
+
+/*
+ * Steps a7-a9: eps = I - v^1/2 chi v^1/2 with v^1/2_G = sqrt(4 pi/Omega)/|q+G|
+ * (Eq. epsGG), eps^-1 per frequency by FP64 Gauss-Jordan elimination with
+ * partial pivoting, and W = v^1/2 eps^-1 v^1/2 in eV (Eq. Wq, inside S_eps).
+ *
+ * gsph    (host)  : int[ng][3], |q+G| > 0 for every entry
+ * chi     (dev)   : c128[nfreq][ng][ng]
+ * eps_inv (dev)   : c128[nfreq][ng][ng] output, or NULL
+ * W       (dev)   : c128[nfreq][ng][ng] output in eV, or NULL
+ * A pivot of magnitude below 1e-13 (eps is dimensionless with a unit-scale
+ * diagonal, so this means a condition number beyond ~1e13) is reported by
+ * rp_synchronize as RP_E_SINGULAR; a non-finite value as RP_E_RANGE.
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE, RP_E_NOMEM, RP_E_DEVICE.
+ */
+rp_status rp_screen_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int ng,
+                      const int *gsph, int nfreq, const double *chi, double *eps_inv,
+                      double *W);
+
+/*
+ * Step a10: W_ij(q,w) = HA * (4 pi/(Omega Nq)) [ sum_{G,G' in S_eps}
+ *     rho_i(G) eps^-1_GG'(w) conj(rho_j(G')) + sum_{G in tail} rho_i(G) conj(rho_j(G)) ]
+ * (the q-term of Eq. matrix_U at R = 0), with rho_i(G) = ntilde_i(q+G)/|q+G|,
+ * ntilde_i(Q) = (Omega/N_r) sum_j phi_i(r_j)^2 e^{iQ.rt_ij}, rt_ij the image
+ * of r_j nearest to the orbital centre (Eq. rhoiqG for the density of orbital i).
+ *
+ * phi         (dev)  : double[nwan][N1][N2][N3], (Omega/N_r) sum_j phi^2 = 1
+ * centre_frac (host) : double[nwan][3] orbital centres, fractional
+ * gsph        (host) : int[ng][3], the rows/columns of eps_inv
+ * gtail       (host) : int[ntail][3], vectors of the bare tail (may be 0)
+ * eps_inv     (dev)  : c128[nfreq][ng][ng]
+ * Wij         (dev)  : c128[nfreq][nwan][nwan] output, eV
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE, RP_E_UNSUPPORTED, RP_E_NOMEM,
+ * RP_E_DEVICE.
+ */
+rp_status rp_wannier_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nwan,
+                       const double *phi, const double *centre_frac, int ng, const int *gsph,
+                       int ntail, const int *gtail, int nfreq, const double *eps_inv,
+                       double *Wij);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RP_H */

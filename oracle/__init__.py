@@ -45,6 +45,8 @@ def lib():
         _lib.or_u_separable.argtypes = [P, c.c_int, P, P, P]
         _lib.or_pair_direct.argtypes = [P, P, P, P, c.c_int, P, P]
         _lib.or_pair_separable.argtypes = [P, P, P, P, c.c_int, P, P]
+        _lib.or_u_batch.argtypes = [P, c.c_int, c.c_int, P, P, c.c_long, P]
+        _lib.or_pair_batch.argtypes = [P, c.c_int, P, c.c_int, P, P, c.c_int, P, P]
         _lib.or_pair_conv.argtypes = [c.c_int, P, P, c.c_int, P, P, P, c.c_int, P, P]
         _lib.or_weights.argtypes = [P, P, c.c_int, P, P, c.c_int, c.c_int, c.c_int, c.c_int,
                                     c.c_int, c.c_int, c.c_int, P, c.c_double, c.c_int, P]
@@ -237,22 +239,39 @@ def wannier_W(lat, kmesh, rho_eps, rho_tail, eps_inv):
 
 
 # ----------------------------------------------------------------- the path
-def pair_densities(prob, o0, o1, e0, e1, k0, k1, method: str = "separable"):
+def u_grids(fft, miller, coef_rows):
+    """u-grids of several bands that share one Miller list (rows of coef)."""
+    fft, miller = _i32(fft), _i32(miller)
+    c = _c128(coef_rows)
+    nb, npw = c.shape
+    u = np.empty((nb,) + tuple(int(x) for x in fft), np.complex128)
+    lib().or_u_batch(_p(fft), int(nb), int(npw), _p(miller), _p(c), int(npw), _p(u))
+    return u
+
+
+def pair_batch(fft, ua, ub, g0, gsph):
+    """M[a][b][G] for all grids ua (empty, at k+q) and ub (occupied, at k)."""
+    fft, g0, gsph = _i32(fft), _i32(g0), _i32(gsph)
+    ua, ub = _c128(ua), _c128(ub)
+    M = np.empty((ua.shape[0], ub.shape[0], gsph.shape[0]), np.complex128)
+    lib().or_pair_batch(_p(fft), int(ua.shape[0]), _p(ua), int(ub.shape[0]), _p(ub), _p(g0),
+                        int(gsph.shape[0]), _p(gsph), _p(M))
+    return M
+
+
+def pair_densities(prob, o0, o1, e0, e1, k0, k1):
     """M[(k,a,b)][G] for occupied b in [o0,o1) at k, empty a in [e0,e1) at
     k+q, k in [k0,k1); the layout of the device library's output."""
     kp, g0 = kq(prob.kmesh, prob.iq)
-    out = np.empty(((k1 - k0) * (e1 - e0) * (o1 - o0), prob.ng), np.complex128)
-    p = 0
+    out = np.empty(((k1 - k0), (e1 - e0), (o1 - o0), prob.ng), np.complex128)
     for k in range(k0, k1):
-        ub = [u_grid(prob.fft, prob.miller[k, :prob.npw[k]], prob.coef[k, b, :prob.npw[k]])
-              for b in range(o0, o1)]
+        n = prob.npw[k]
+        ub = u_grids(prob.fft, prob.miller[k, :n], prob.coef[k, o0:o1, :n])
         kk = int(kp[k])
-        for a in range(e0, e1):
-            ua = u_grid(prob.fft, prob.miller[kk, :prob.npw[kk]], prob.coef[kk, a, :prob.npw[kk]])
-            for b in range(o1 - o0):
-                out[p] = pair_density(prob.fft, ua, ub[b], g0[k], prob.gsph, method)
-                p += 1
-    return out
+        na = prob.npw[kk]
+        ua = u_grids(prob.fft, prob.miller[kk, :na], prob.coef[kk, e0:e1, :na])
+        out[k - k0] = pair_batch(prob.fft, ua, ub, g0[k], prob.gsph)
+    return out.reshape(-1, prob.ng)
 
 
 def prob_weights(prob, o0, o1, e0, e1, k0, k1, mode: Optional[int] = None):

@@ -93,6 +93,20 @@ static cplx unit_root(long n, int N)
     return cos(t) + I * sin(t);
 }
 
+/* table t[n] = e^{2 pi i n / N}, n < N (caller frees) */
+static cplx *root_table(int N)
+{
+    cplx *t = malloc(sizeof(cplx) * N);
+    for (int n = 0; n < N; n++) t[n] = unit_root(n, N);
+    return t;
+}
+
+static cplx root_at(const cplx *t, long n, int N)
+{
+    long r = n % N;
+    return t[r < 0 ? r + N : r];
+}
+
 /* ------------------------------------------------------------------ */
 /* step a1: k+q on the mesh with its umklapp vector                    */
 /* ------------------------------------------------------------------ */
@@ -148,6 +162,8 @@ void or_u_separable(const int *fft, int npw, const int *miller, const cplx *c, c
         }
     if (npw == 0) { memset(u, 0, sizeof(cplx) * (size_t)N[0] * N[1] * N[2]); return; }
     for (int a = 0; a < 3; a++) L[a] = hi[a] - lo[a] + 1;
+    cplx *tw[3];
+    for (int a = 0; a < 3; a++) tw[a] = root_table(N[a]);
     cplx *box = calloc((size_t)L[0] * L[1] * L[2], sizeof(cplx));
     for (int g = 0; g < npw; g++) {
         const int *m = miller + 3 * g;
@@ -155,40 +171,43 @@ void or_u_separable(const int *fft, int npw, const int *miller, const cplx *c, c
     }
     /* over m3: t1[m1][m2][j3] */
     cplx *t1 = calloc((size_t)L[0] * L[1] * N[2], sizeof(cplx));
-#pragma omp parallel for collapse(2) schedule(static)
     for (int a1 = 0; a1 < L[0]; a1++)
         for (int a2 = 0; a2 < L[1]; a2++)
             for (int j3 = 0; j3 < N[2]; j3++) {
                 cplx s = 0;
                 for (int a3 = 0; a3 < L[2]; a3++)
-                    s += box[((size_t)a1 * L[1] + a2) * L[2] + a3] *
-                         unit_root((long)(a3 + lo[2]) * j3, N[2]);
+                    s += box[((size_t)a1 * L[1] + a2) * L[2] + a3] * root_at(tw[2], (long)(a3 + lo[2]) * j3, N[2]);
                 t1[((size_t)a1 * L[1] + a2) * N[2] + j3] = s;
             }
     /* over m2: t2[m1][j2][j3] */
     cplx *t2 = calloc((size_t)L[0] * N[1] * N[2], sizeof(cplx));
-#pragma omp parallel for collapse(2) schedule(static)
     for (int a1 = 0; a1 < L[0]; a1++)
         for (int j2 = 0; j2 < N[1]; j2++)
             for (int j3 = 0; j3 < N[2]; j3++) {
                 cplx s = 0;
                 for (int a2 = 0; a2 < L[1]; a2++)
-                    s += t1[((size_t)a1 * L[1] + a2) * N[2] + j3] *
-                         unit_root((long)(a2 + lo[1]) * j2, N[1]);
+                    s += t1[((size_t)a1 * L[1] + a2) * N[2] + j3] * root_at(tw[1], (long)(a2 + lo[1]) * j2, N[1]);
                 t2[((size_t)a1 * N[1] + j2) * N[2] + j3] = s;
             }
     /* over m1 */
-#pragma omp parallel for collapse(2) schedule(static)
     for (int j1 = 0; j1 < N[0]; j1++)
         for (int j2 = 0; j2 < N[1]; j2++)
             for (int j3 = 0; j3 < N[2]; j3++) {
                 cplx s = 0;
                 for (int a1 = 0; a1 < L[0]; a1++)
-                    s += t2[((size_t)a1 * N[1] + j2) * N[2] + j3] *
-                         unit_root((long)(a1 + lo[0]) * j1, N[0]);
+                    s += t2[((size_t)a1 * N[1] + j2) * N[2] + j3] * root_at(tw[0], (long)(a1 + lo[0]) * j1, N[0]);
                 u[((size_t)j1 * N[1] + j2) * N[2] + j3] = s;
             }
     free(box); free(t1); free(t2);
+    for (int a = 0; a < 3; a++) free(tw[a]);
+}
+
+/* u-grids of nb bands sharing one Miller list (bands in parallel) */
+void or_u_batch(const int *fft, int nb, int npw, const int *miller, const cplx *c, long cstride, cplx *u)
+{
+    long nr = (long)fft[0] * fft[1] * fft[2];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int b = 0; b < nb; b++) or_u_separable(fft, npw, miller, c + (long)b * cstride, u + (long)b * nr);
 }
 
 /* ------------------------------------------------------------------ */
@@ -230,45 +249,55 @@ void or_pair_separable(const int *fft, const cplx *ua, const cplx *ub, const int
         }
     if (ng == 0) return;
     for (int a = 0; a < 3; a++) L[a] = hi[a] - lo[a] + 1;
+    cplx *tw[3];
+    for (int a = 0; a < 3; a++) tw[a] = root_table(N[a]);
     cplx *rho = malloc(sizeof(cplx) * nr);
     for (long j = 0; j < nr; j++) rho[j] = conj(ua[j]) * ub[j];
     /* over j3: t1[j1][j2][m3] */
     cplx *t1 = malloc(sizeof(cplx) * (size_t)N[0] * N[1] * L[2]);
-#pragma omp parallel for collapse(2) schedule(static)
     for (int j1 = 0; j1 < N[0]; j1++)
         for (int j2 = 0; j2 < N[1]; j2++)
             for (int a3 = 0; a3 < L[2]; a3++) {
                 cplx s = 0;
                 for (int j3 = 0; j3 < N[2]; j3++)
-                    s += rho[((size_t)j1 * N[1] + j2) * N[2] + j3] *
-                         unit_root((long)(a3 + lo[2]) * j3, N[2]);
+                    s += rho[((size_t)j1 * N[1] + j2) * N[2] + j3] * root_at(tw[2], (long)(a3 + lo[2]) * j3, N[2]);
                 t1[((size_t)j1 * N[1] + j2) * L[2] + a3] = s;
             }
     /* over j2: t2[j1][m2][m3] */
     cplx *t2 = malloc(sizeof(cplx) * (size_t)N[0] * L[1] * L[2]);
-#pragma omp parallel for collapse(2) schedule(static)
     for (int j1 = 0; j1 < N[0]; j1++)
         for (int a2 = 0; a2 < L[1]; a2++)
             for (int a3 = 0; a3 < L[2]; a3++) {
                 cplx s = 0;
                 for (int j2 = 0; j2 < N[1]; j2++)
-                    s += t1[((size_t)j1 * N[1] + j2) * L[2] + a3] *
-                         unit_root((long)(a2 + lo[1]) * j2, N[1]);
+                    s += t1[((size_t)j1 * N[1] + j2) * L[2] + a3] * root_at(tw[1], (long)(a2 + lo[1]) * j2, N[1]);
                 t2[((size_t)j1 * L[1] + a2) * L[2] + a3] = s;
             }
     /* over j1, only at the requested vectors */
-#pragma omp parallel for schedule(static)
     for (int g = 0; g < ng; g++) {
         int a1 = gsph[3 * g] + g0[0] - lo[0];
         int a2 = gsph[3 * g + 1] + g0[1] - lo[1];
         int a3 = gsph[3 * g + 2] + g0[2] - lo[2];
         cplx s = 0;
         for (int j1 = 0; j1 < N[0]; j1++)
-            s += t2[((size_t)j1 * L[1] + a2) * L[2] + a3] *
-                 unit_root((long)(a1 + lo[0]) * j1, N[0]);
+            s += t2[((size_t)j1 * L[1] + a2) * L[2] + a3] * root_at(tw[0], (long)(a1 + lo[0]) * j1, N[0]);
         M[g] = s / (double)nr;
     }
     free(rho); free(t1); free(t2);
+    for (int a = 0; a < 3; a++) free(tw[a]);
+}
+
+/* all pairs (a, b) of nA grids ua (at k') and nB grids ub (at k):
+ * M[a][b][g], pairs in parallel */
+void or_pair_batch(const int *fft, int nA, const cplx *ua, int nB, const cplx *ub, const int *g0,
+                   int ng, const int *gsph, cplx *M)
+{
+    long nr = (long)fft[0] * fft[1] * fft[2];
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
+    for (int a = 0; a < nA; a++)
+        for (int b = 0; b < nB; b++)
+            or_pair_separable(fft, ua + (long)a * nr, ub + (long)b * nr, g0, ng, gsph,
+                              M + ((long)a * nB + b) * ng);
 }
 
 /* exact plane-wave form: M(G) = sum_{G2 in S_b} conj(C_a[G2+G+G0]) C_b[G2] */
@@ -536,7 +565,7 @@ int or_invert(int n, const cplx *A, cplx *Ainv)
             }
         cplx d = 1.0 / a[(long)c * n + c];
         for (int j = 0; j < n; j++) { a[(long)c * n + j] *= d; Ainv[(long)c * n + j] *= d; }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= 384)
         for (int r = 0; r < n; r++) {
             if (r == c) continue;
             cplx f = a[(long)r * n + c];

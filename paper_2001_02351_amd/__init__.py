@@ -1,0 +1,26 @@
+"""MI355X-native constrained-RPA polarization / screened-interaction library.
+
+The computation lives in librp.so (hand-written HIP for gfx950) behind the C
+ABI declared in include/rp.h; this package is its ctypes binding plus the
+per-q orchestration in `path`.  Importing it does not touch the GPU.
+"""
+
+from ._rp import (  # noqa: F401
+    EXPORTED,
+    RP_FP64,
+    RP_SPLIT_BF16,
+    RP_W_SAMPLING,
+    RP_W_TETRA,
+    Context,
+    RpError,
+    load,
+    make_cell,
+    rp_chi0_accumulate,
+    rp_last_error,
+    rp_pair_density,
+    rp_screen_W,
+    rp_synchronize,
+    rp_wannier_W,
+    rp_weights,
+)
+from .build import build, library_path  # noqa: F401

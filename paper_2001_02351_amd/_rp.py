@@ -1,0 +1,207 @@
+"""ctypes binding of librp.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls and forwards
+its arguments: torch tensors become device pointers, numpy arrays become
+host pointers.  All arithmetic runs in the library's HIP kernels; there is no
+CPU fallback, and a missing library raises on import.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from .build import library_path
+
+RP_OK = 0
+RP_FP64 = 0
+RP_SPLIT_BF16 = 1
+RP_W_TETRA = 0
+RP_W_SAMPLING = 1
+
+STATUS_NAMES = {0: "RP_OK", 1: "RP_E_NULL", 2: "RP_E_SHAPE", 3: "RP_E_RANGE", 4: "RP_E_ALIAS",
+                5: "RP_E_NOMEM", 6: "RP_E_DEVICE", 7: "RP_E_SINGULAR", 8: "RP_E_UNSUPPORTED"}
+
+EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pair_density",
+            "rp_weights", "rp_chi0_accumulate", "rp_screen_W", "rp_wannier_W"]
+
+
+class RpError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class rp_cell(ctypes.Structure):
+    _fields_ = [("lat", (ctypes.c_double * 3) * 3), ("fft", ctypes.c_int * 3),
+                ("kmesh", ctypes.c_int * 3)]
+
+
+def make_cell(lat, fft, kmesh) -> rp_cell:
+    c = rp_cell()
+    lat = np.asarray(lat, dtype=np.float64)
+    for i in range(3):
+        for j in range(3):
+            c.lat[i][j] = float(lat[i, j])
+        c.fft[i] = int(fft[i])
+        c.kmesh[i] = int(kmesh[i])
+    return c
+
+
+_LIB = None
+
+
+def load(path: Optional[str] = None):
+    """Load librp.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = path or library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2001_02351_amd/build.py "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    cellp = ctypes.POINTER(rp_cell)
+    sig = {
+        "rp_create": [ctypes.POINTER(P), I, P],
+        "rp_destroy": [P],
+        "rp_synchronize": [P],
+        "rp_pair_density": [P, cellp, P, I, I, P, P, P, P, I, I, I, I, I, I, I, P, P],
+        "rp_weights": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, D, I, P],
+        "rp_chi0_accumulate": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, I, P, D, I, I, I, P],
+        "rp_screen_W": [P, cellp, P, I, P, I, P, P, P],
+        "rp_wannier_W": [P, cellp, P, I, P, P, I, P, I, P, I, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.rp_last_error.argtypes = [P]
+    lib.rp_last_error.restype = ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _host(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _hp(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dp(t) -> Optional[int]:
+    """Device pointer of a contiguous torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+class Context:
+    """An rp_ctx bound to a dedicated default-priority torch stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.lib = load()
+        self.device = device
+        self.stream = torch.cuda.Stream(device=device)
+        h = ctypes.c_void_p()
+        st = self.lib.rp_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream))
+        if st != RP_OK:
+            raise RpError(st, "rp_create", "context creation failed")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.rp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, where: str):
+        if st != RP_OK:
+            raise RpError(st, where, self.lib.rp_last_error(self.handle).decode())
+
+    def _enter(self):
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        import torch
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+
+def rp_synchronize(ctx: Context):
+    ctx._check(ctx.lib.rp_synchronize(ctx.handle), "rp_synchronize")
+
+
+def rp_last_error(ctx: Context) -> str:
+    return ctx.lib.rp_last_error(ctx.handle).decode()
+
+
+def rp_pair_density(ctx: Context, cell: rp_cell, iq, nband, npw_max, npw, mmax, miller, coef,
+                    o0, o1, e0, e1, k0, k1, ng, gsph, M):
+    iq_h, npw_h, mm_h = _host(iq, np.int32), _host(npw, np.int32), _host(mmax, np.int32)
+    g_h = _host(gsph, np.int32)
+    ctx._enter()
+    st = ctx.lib.rp_pair_density(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(nband), int(npw_max),
+                                 _hp(npw_h), _hp(mm_h), _dp(miller), _dp(coef), o0, o1, e0, e1, k0, k1,
+                                 int(ng), _hp(g_h), _dp(M))
+    ctx._leave()
+    ctx._check(st, "rp_pair_density")
+
+
+def rp_weights(ctx: Context, cell: rp_cell, iq, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, nfreq,
+               freq_eV, delta_eV, wm, w):
+    iq_h, f_h = _host(iq, np.int32), _host(freq_eV, np.complex128)
+    ctx._enter()
+    st = ctx.lib.rp_weights(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(nband), _dp(energy_eV),
+                            _dp(T), o0, o1, e0, e1, k0, k1, int(nfreq), _hp(f_h), float(delta_eV),
+                            int(wm), _dp(w))
+    ctx._leave()
+    ctx._check(st, "rp_weights")
+
+
+def rp_chi0_accumulate(ctx: Context, cell: rp_cell, iq, nband, energy_eV, T, o0, o1, e0, e1, k0, k1,
+                       ng, M, nfreq, freq_eV, delta_eV, wm, prec, accumulate, chi):
+    iq_h, f_h = _host(iq, np.int32), _host(freq_eV, np.complex128)
+    ctx._enter()
+    st = ctx.lib.rp_chi0_accumulate(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(nband),
+                                    _dp(energy_eV), _dp(T), o0, o1, e0, e1, k0, k1, int(ng), _dp(M),
+                                    int(nfreq), _hp(f_h), float(delta_eV), int(wm), int(prec),
+                                    int(accumulate), _dp(chi))
+    ctx._leave()
+    ctx._check(st, "rp_chi0_accumulate")
+
+
+def rp_screen_W(ctx: Context, cell: rp_cell, iq, ng, gsph, nfreq, chi, eps_inv, W):
+    iq_h, g_h = _host(iq, np.int32), _host(gsph, np.int32)
+    ctx._enter()
+    st = ctx.lib.rp_screen_W(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(ng), _hp(g_h), int(nfreq),
+                             _dp(chi), _dp(eps_inv), _dp(W))
+    ctx._leave()
+    ctx._check(st, "rp_screen_W")
+
+
+def rp_wannier_W(ctx: Context, cell: rp_cell, iq, nwan, phi, centre_frac, ng, gsph, ntail, gtail,
+                 nfreq, eps_inv, Wij):
+    iq_h, c_h = _host(iq, np.int32), _host(centre_frac, np.float64)
+    g_h = _host(gsph, np.int32)
+    t_h = _host(gtail, np.int32) if ntail > 0 else None
+    ctx._enter()
+    st = ctx.lib.rp_wannier_W(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(nwan), _dp(phi), _hp(c_h),
+                              int(ng), _hp(g_h), int(ntail), _hp(t_h), int(nfreq), _dp(eps_inv), _dp(Wij))
+    ctx._leave()
+    ctx._check(st, "rp_wannier_W")

@@ -1,0 +1,151 @@
+// Periodic parts of Bloch functions on the real-space grid (step a2, Eq. pak):
+//     u_{nk}(r_j) = sum_{G in S_psi(k)} C_{Gn}(k) e^{iG.r_j}
+// by scattering the sphere coefficients into the N1 x N2 x N3 box and applying
+// three batched 1-D transforms, one axis at a time.  The first two passes are
+// pruned to the lines that can hold a non-zero coefficient (|m_a| <= mmax_a).
+#include <algorithm>
+
+#include "fft_lds.h"
+
+namespace rp {
+
+namespace {
+
+// Lines of one pass.  Flat line index L = o*C + c; the line's first element
+// is at  band*bstride + j1*s1 + j2*s2 + c*cs,  element i at  + i*is,
+// with o = (band*B1 + b1)*B2 + b2 and j_a = (b_a - mm_a) mod N_a.
+struct LineSet {
+    int n;        // transform length
+    int is;       // element stride
+    long nlines;  // O*C
+    int C, cs;
+    int B1, mm1, N1, s1;
+    int B2, mm2, N2, s2;
+    long bstride;
+};
+
+__device__ __forceinline__ long line_base(const LineSet &ls, long L)
+{
+    long o = L / ls.C;
+    int c = (int)(L - o * ls.C);
+    int b2 = (int)(o % ls.B2);
+    long o1 = o / ls.B2;
+    int b1 = (int)(o1 % ls.B1);
+    long band = o1 / ls.B1;
+    int j1 = pmod(b1 - ls.mm1, ls.N1);
+    int j2 = pmod(b2 - ls.mm2, ls.N2);
+    return band * ls.bstride + (long)j1 * ls.s1 + (long)j2 * ls.s2 + (long)c * ls.cs;
+}
+
+// One block transforms `lpb` consecutive lines of the set in LDS.
+__global__ void __launch_bounds__(256) k_fft_lines(double2 *data, LineSet ls, FftPlan plan, int lpb)
+{
+    extern __shared__ double2 smem[];
+    const int n = ls.n;
+    const int ld = n + 1;  // padded line stride against LDS bank conflicts
+    double2 *tw = smem;
+    double2 *a = smem + n;
+    double2 *b = a + (size_t)lpb * ld;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const long L0 = (long)blockIdx.x * lpb;
+    const int nl = (int)min((long)lpb, ls.nlines - L0);
+    fill_twiddles(tw, n, tid, nth);
+    // strided lines are adjacent in memory along c: let consecutive threads
+    // take consecutive lines so the loads coalesce; contiguous lines let
+    // consecutive threads take consecutive elements
+    const bool contiguous = (ls.is == 1);
+    for (int e = tid; e < nl * n; e += nth) {
+        int l, i;
+        if (contiguous) { l = e / n; i = e - l * n; }
+        else { i = e / nl; l = e - i * nl; }
+        a[l * ld + i] = data[line_base(ls, L0 + l) + (long)i * ls.is];
+    }
+    __syncthreads();
+    double2 *r = fft_lines(a, b, plan, nl, ld, 1, tw, tid, nth);
+    for (int e = tid; e < nl * n; e += nth) {
+        int l, i;
+        if (contiguous) { l = e / n; i = e - l * n; }
+        else { i = e / nl; l = e - i * nl; }
+        data[line_base(ls, L0 + l) + (long)i * ls.is] = r[l * ld + i];
+    }
+}
+
+__global__ void k_zero(double2 *p, long n)
+{
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long stride = (long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = make_double2(0.0, 0.0);
+}
+
+// u[band][m mod N] = C[band][g] for g < npw (each Miller index appears once)
+__global__ void k_scatter(const int *miller, const double2 *coef, int npw, int band_stride,
+                          int nbands, int N1, int N2, int N3, double2 *u)
+{
+    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)npw * nbands) return;
+    int band = (int)(t / npw), g = (int)(t - (long)band * npw);
+    int m1 = pmod(miller[3 * g], N1), m2 = pmod(miller[3 * g + 1], N2), m3 = pmod(miller[3 * g + 2], N3);
+    u[(long)band * N1 * N2 * N3 + ((long)m1 * N2 + m2) * N3 + m3] = coef[(long)band * band_stride + g];
+}
+
+int lines_per_block(int n) { return n <= 64 ? 32 : (n <= 128 ? 16 : 8); }
+
+void run_pass(hipStream_t s, double2 *data, const LineSet &ls, const FftPlan &plan)
+{
+    int lpb = lines_per_block(ls.n);
+    long nblk = (ls.nlines + lpb - 1) / lpb;
+    size_t shm = sizeof(double2) * ((size_t)ls.n + 2 * (size_t)lpb * (ls.n + 1));
+    hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)nblk), dim3(256), shm, s, data, ls, plan, lpb);
+}
+
+// box extents along an axis: B lines starting at -mm (mod N); full axis if the
+// pruned range would cover it
+void axis_box(int mmax, int N, int *B, int *mm)
+{
+    if (mmax < 0 || 2 * mmax + 1 >= N) { *B = N; *mm = 0; }
+    else { *B = 2 * mmax + 1; *mm = mmax; }
+}
+
+void fft3d_passes(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,
+                  const int mmax[3], double2 *data)
+{
+    const int N1 = fft[0], N2 = fft[1], N3 = fft[2];
+    const long nr = (long)N1 * N2 * N3;
+    int B1, mm1, B2, mm2;
+    axis_box(mmax[0], N1, &B1, &mm1);
+    axis_box(mmax[1], N2, &B2, &mm2);
+    // axis 3: lines (band, j1 in box, j2 in box), contiguous
+    LineSet l3{N3, 1, (long)ngrids * B1 * B2, 1, 0, B1, mm1, N1, N2 * N3, B2, mm2, N2, N3, nr};
+    run_pass(s, data, l3, plans[2]);
+    // axis 2: lines (band, j1 in box, j3), stride N3
+    LineSet l2{N2, N3, (long)ngrids * B1 * N3, N3, 1, B1, mm1, N1, N2 * N3, 1, 0, 1, 0, nr};
+    run_pass(s, data, l2, plans[1]);
+    // axis 1: lines (band, j2, j3), stride N2*N3
+    LineSet l1{N1, N2 * N3, (long)ngrids * N2 * N3, N2 * N3, 1, 1, 0, 1, 0, 1, 0, 1, 0, nr};
+    run_pass(s, data, l1, plans[0]);
+}
+
+}  // namespace
+
+void launch_ugrid(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
+                  int nbands, int npw, const int *miller_k, const double2 *coef_k,
+                  int band_stride, double2 *u)
+{
+    const long nr = (long)fft[0] * fft[1] * fft[2];
+    const long tot = nr * nbands;
+    unsigned zb = (unsigned)std::min<long>((tot + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_zero, dim3(zb), dim3(256), 0, s, u, tot);
+    long ns = (long)npw * nbands;
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, miller_k,
+                       coef_k, npw, band_stride, nbands, fft[0], fft[1], fft[2], u);
+    fft3d_passes(s, plans, fft, nbands, mmax, u);
+}
+
+void launch_fft3d(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,
+                  double2 *data)
+{
+    const int full[3] = {-1, -1, -1};
+    fft3d_passes(s, plans, fft, ngrids, full, data);
+}
+
+}  // namespace rp

@@ -1,0 +1,440 @@
+// Host side of the C ABI: argument validation, workspace management and the
+// order of launches for each entry point.  All device work goes to the
+// context's stream; nothing here synchronizes except rp_synchronize.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "rp_internal.h"
+
+namespace rp {
+
+rp_status fail(rp_ctx *ctx, rp_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+rp_status ensure(rp_ctx *ctx, DevBuf &b, size_t bytes)
+{
+    if (bytes <= b.bytes) return RP_OK;
+    if (b.p) {
+        // the stream may still be using the old buffer
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+            return fail(ctx, RP_E_DEVICE, "stream synchronize failed before workspace growth");
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = std::max(bytes, (size_t)256);
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(ctx, RP_E_NOMEM, "device workspace allocation of %zu bytes failed", want);
+    }
+    b.bytes = want;
+    return RP_OK;
+}
+
+rp_status check_launch(rp_ctx *ctx, const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, RP_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return RP_OK;
+}
+
+bool make_plan(int n, FftPlan *plan)
+{
+    if (n < 1 || n > 256) return false;
+    plan->n = n;
+    plan->nrad = 0;
+    int m = n;
+    const int order[4] = {4, 2, 3, 5};
+    for (int r : order)
+        while (m % r == 0) {
+            if (plan->nrad >= 12) return false;
+            plan->rad[plan->nrad++] = r;
+            m /= r;
+        }
+    return m == 1;
+}
+
+rp_status geometry(rp_ctx *ctx, const rp_cell *cell, const int iq[3], Geometry *g)
+{
+    if (!cell) return fail(ctx, RP_E_NULL, "cell is NULL");
+    if (!iq) return fail(ctx, RP_E_NULL, "iq is NULL");
+    for (int a = 0; a < 3; a++) {
+        for (int b = 0; b < 3; b++) g->lat[3 * a + b] = cell->lat[a][b];
+        g->fft[a] = cell->fft[a];
+        g->kmesh[a] = cell->kmesh[a];
+        g->iq[a] = iq[a];
+        if (cell->fft[a] < 1 || cell->kmesh[a] < 1)
+            return fail(ctx, RP_E_SHAPE, "fft and kmesh entries must be >= 1");
+        if (iq[a] < 0 || iq[a] >= cell->kmesh[a])
+            return fail(ctx, RP_E_RANGE, "iq[%d] = %d outside the mesh", a, iq[a]);
+    }
+    const double *A = g->lat;
+    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                       A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(std::fabs(det) > 0.0) || !std::isfinite(det))
+        return fail(ctx, RP_E_RANGE, "lattice vectors are degenerate");
+    double inv[9];
+    inv[0] = (A[4] * A[8] - A[5] * A[7]) / det;
+    inv[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+    inv[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+    inv[3] = (A[5] * A[6] - A[3] * A[8]) / det;
+    inv[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+    inv[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+    inv[6] = (A[3] * A[7] - A[4] * A[6]) / det;
+    inv[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+    inv[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) g->rec[3 * i + j] = 2.0 * kPi * inv[3 * j + i];
+    g->volume = std::fabs(det);
+    g->nk = cell->kmesh[0] * cell->kmesh[1] * cell->kmesh[2];
+    return RP_OK;
+}
+
+static double qg_norm(const Geometry &g, const int *m)
+{
+    double f[3], v[3] = {0, 0, 0};
+    for (int a = 0; a < 3; a++) f[a] = (double)g.iq[a] / g.kmesh[a] + m[a];
+    for (int a = 0; a < 3; a++)
+        for (int c = 0; c < 3; c++) v[c] += f[a] * g.rec[3 * a + c];
+    return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+}
+
+static rp_status plans3(rp_ctx *ctx, const Geometry &g, FftPlan plans[3])
+{
+    for (int a = 0; a < 3; a++)
+        if (!make_plan(g.fft[a], &plans[a]))
+            return fail(ctx, RP_E_UNSUPPORTED, "FFT length %d is not 2^a 3^b 5^c <= 256", g.fft[a]);
+    return RP_OK;
+}
+
+static rp_status upload(rp_ctx *ctx, DevBuf &b, const void *host, size_t bytes)
+{
+    rp_status st = ensure(ctx, b, bytes);
+    if (st != RP_OK) return st;
+    if (bytes && hipMemcpyAsync(b.p, host, bytes, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+        return fail(ctx, RP_E_DEVICE, "host-to-device copy failed");
+    return RP_OK;
+}
+
+static rp_status check_ranges(rp_ctx *ctx, const Geometry &g, int nband, int o0, int o1, int e0, int e1,
+                              int k0, int k1)
+{
+    if (nband < 1) return fail(ctx, RP_E_SHAPE, "nband must be >= 1");
+    if (o0 < 0 || o1 < o0 || o1 > nband) return fail(ctx, RP_E_SHAPE, "bad occupied range [%d,%d)", o0, o1);
+    if (e0 < 0 || e1 < e0 || e1 > nband) return fail(ctx, RP_E_SHAPE, "bad empty range [%d,%d)", e0, e1);
+    if (k0 < 0 || k1 < k0 || k1 > g.nk) return fail(ctx, RP_E_SHAPE, "bad k range [%d,%d)", k0, k1);
+    return RP_OK;
+}
+
+static rp_status check_gsph(rp_ctx *ctx, const Geometry &g, int ng, const int *gsph, const char *name)
+{
+    if (ng < 0) return fail(ctx, RP_E_SHAPE, "%s count < 0", name);
+    if (ng > 0 && !gsph) return fail(ctx, RP_E_NULL, "%s is NULL", name);
+    for (int i = 0; i < ng; i++)
+        if (!(qg_norm(g, gsph + 3 * i) > 0.0))
+            return fail(ctx, RP_E_RANGE, "%s[%d]: |q+G| = 0 (drop G = 0 at q = 0)", name, i);
+    return RP_OK;
+}
+
+}  // namespace rp
+
+using namespace rp;
+
+extern "C" {
+
+rp_status rp_create(rp_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return RP_E_NULL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return RP_E_DEVICE;
+    }
+    if (device < 0 || device >= ndev) return RP_E_RANGE;
+    if (hipSetDevice(device) != hipSuccess) return RP_E_DEVICE;
+    rp_ctx *ctx = new rp_ctx();
+    ctx->device = device;
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return RP_E_DEVICE;
+        }
+        ctx->own_stream = true;
+    }
+    if (hipMalloc((void **)&ctx->flag, 4 * sizeof(int)) != hipSuccess ||
+        hipMemsetAsync(ctx->flag, 0, 4 * sizeof(int), ctx->stream) != hipSuccess) {
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+        return RP_E_DEVICE;
+    }
+    *out = ctx;
+    return RP_OK;
+}
+
+rp_status rp_destroy(rp_ctx *ctx)
+{
+    if (!ctx) return RP_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    DevBuf *bufs[] = {&ctx->ugrid, &ctx->weights, &ctx->glist, &ctx->freq,  &ctx->kinfo, &ctx->vsqrt,
+                      &ctx->work,  &ctx->split_a, &ctx->split_b, &ctx->rho, &ctx->piv};
+    for (DevBuf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (ctx->flag) (void)hipFree(ctx->flag);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return RP_OK;
+}
+
+const char *rp_last_error(const rp_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+rp_status rp_synchronize(rp_ctx *ctx)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return fail(ctx, RP_E_DEVICE, "stream synchronize: %s", hipGetErrorString(hipGetLastError()));
+    int flag[4] = {0, 0, 0, 0};
+    if (hipMemcpy(flag, ctx->flag, sizeof flag, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(ctx, RP_E_DEVICE, "flag read failed");
+    if (flag[0]) {
+        (void)hipMemset(ctx->flag, 0, sizeof flag);
+        if (flag[0] & kFlagZeroPivot) return fail(ctx, RP_E_SINGULAR, "zero pivot in the dielectric matrix");
+        return fail(ctx, RP_E_RANGE, "non-finite value detected on the device");
+    }
+    return RP_OK;
+}
+
+rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband, int npw_max,
+                          const int *npw, const int mmax[3], const int *miller, const double *coef,
+                          int o0, int o1, int e0, int e1, int k0, int k1, int ng, const int *gsph,
+                          double *M)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    Geometry g;
+    rp_status st = geometry(ctx, cell, iq, &g);
+    if (st != RP_OK) return st;
+    if (!npw || !mmax || !miller || !coef || !M) return fail(ctx, RP_E_NULL, "NULL array argument");
+    if ((st = check_ranges(ctx, g, nband, o0, o1, e0, e1, k0, k1)) != RP_OK) return st;
+    if (ng < 1 || ng > 6144) return fail(ctx, RP_E_UNSUPPORTED, "ng = %d outside [1, 6144]", ng);
+    if ((st = check_gsph(ctx, g, ng, gsph, "gsph")) != RP_OK) return st;
+    if (npw_max < 1) return fail(ctx, RP_E_SHAPE, "npw_max must be >= 1");
+    FftPlan plans[3];
+    if ((st = plans3(ctx, g, plans)) != RP_OK) return st;
+    for (int k = 0; k < g.nk; k++)
+        if (npw[k] < 0 || npw[k] > npw_max) return fail(ctx, RP_E_SHAPE, "npw[%d] outside [0, npw_max]", k);
+    // alias-free condition per axis: N > 2 mmax + max |m + G0|, G0 in {0, 1} when iq > 0
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = 1 << 30;
+        hi[a] = -(1 << 30);
+        for (int i = 0; i < ng; i++) {
+            lo[a] = std::min(lo[a], gsph[3 * i + a]);
+            hi[a] = std::max(hi[a], gsph[3 * i + a]);
+        }
+        const int up = hi[a] + (iq[a] > 0 ? 1 : 0);
+        const int gmax = std::max(std::abs(lo[a]), std::abs(up));
+        if (mmax[a] < 0) return fail(ctx, RP_E_SHAPE, "mmax[%d] < 0", a);
+        if (g.fft[a] <= 2 * mmax[a] + gmax)
+            return fail(ctx, RP_E_ALIAS, "axis %d: N=%d <= 2*mmax+|G|max = %d (pair products alias)", a,
+                        g.fft[a], 2 * mmax[a] + gmax);
+    }
+    const int nO = o1 - o0, nE = e1 - e0, nK = k1 - k0;
+    if ((long)nO * nE * nK == 0) return RP_OK;
+    const long nr = (long)g.fft[0] * g.fft[1] * g.fft[2];
+    // LDS budget of the pair kernel (window along m3 is at most hi-lo+2)
+    const int L3max = hi[2] - lo[2] + 2;
+    if (pair_lds_bytes(g.fft, L3max, pair_rows(g.fft)) > 160 * 1024)
+        return fail(ctx, RP_E_UNSUPPORTED, "grid %dx%dx%d too large for the pair kernel's LDS plan",
+                    g.fft[0], g.fft[1], g.fft[2]);
+    if ((st = ensure(ctx, ctx->ugrid, sizeof(double2) * nr * (nO + nE))) != RP_OK) return st;
+    if ((st = upload(ctx, ctx->glist, gsph, sizeof(int) * 3 * ng)) != RP_OK) return st;
+    double2 *u_occ = (double2 *)ctx->ugrid.p;
+    double2 *u_emp = u_occ + nr * nO;
+    const int *dg = (const int *)ctx->glist.p;
+    for (int k = k0; k < k1; k++) {
+        const int n1 = k / (g.kmesh[1] * g.kmesh[2]), n2 = (k / g.kmesh[2]) % g.kmesh[1], n3 = k % g.kmesh[2];
+        const int s[3] = {n1 + iq[0], n2 + iq[1], n3 + iq[2]};
+        int r[3], g0[3];
+        for (int a = 0; a < 3; a++) {
+            r[a] = s[a] % g.kmesh[a];
+            g0[a] = s[a] / g.kmesh[a];
+        }
+        const int kp = (r[0] * g.kmesh[1] + r[1]) * g.kmesh[2] + r[2];
+        const double2 *cf = (const double2 *)coef;
+        launch_ugrid(ctx->stream, plans, g.fft, mmax, nO, npw[k], miller + (long)k * npw_max * 3,
+                     cf + ((long)k * nband + o0) * npw_max, npw_max, u_occ);
+        launch_ugrid(ctx->stream, plans, g.fft, mmax, nE, npw[kp], miller + (long)kp * npw_max * 3,
+                     cf + ((long)kp * nband + e0) * npw_max, npw_max, u_emp);
+        const int lo3 = lo[2] + g0[2], L3 = hi[2] - lo[2] + 1;
+        double2 *Mk = (double2 *)M + (long)(k - k0) * nE * nO * ng;
+        launch_pair_k(ctx->stream, plans, g.fft, u_occ, u_emp, nO, nE, ng, dg, g0, lo3, L3, Mk);
+        if ((st = check_launch(ctx, "pair density")) != RP_OK) return st;
+    }
+    return RP_OK;
+}
+
+static rp_status weights_common(rp_ctx *ctx, const Geometry &g, int nband, const double *E,
+                                const double *T, int o0, int o1, int e0, int e1, int k0, int k1,
+                                int nfreq, const double *freq_eV, double delta_eV, rp_weight_mode wm,
+                                double2 *w)
+{
+    rp_status st;
+    if (!E || !freq_eV) return fail(ctx, RP_E_NULL, "NULL energy or frequency array");
+    if (nfreq < 1) return fail(ctx, RP_E_SHAPE, "nfreq must be >= 1");
+    if (!(delta_eV >= 0.0) || !std::isfinite(delta_eV)) return fail(ctx, RP_E_RANGE, "delta must be >= 0");
+    if (wm != RP_W_TETRA && wm != RP_W_SAMPLING) return fail(ctx, RP_E_RANGE, "unknown weight mode");
+    for (int f = 0; f < 2 * nfreq; f++)
+        if (!std::isfinite(freq_eV[f])) return fail(ctx, RP_E_RANGE, "non-finite frequency");
+    if ((st = upload(ctx, ctx->freq, freq_eV, sizeof(double2) * nfreq)) != RP_OK) return st;
+    launch_weights(ctx->stream, g.kmesh, g.iq, nband, E, T, o0, o1, e0, e1, k0, k1, nfreq,
+                   (const double2 *)ctx->freq.p, delta_eV, (int)wm, w);
+    return check_launch(ctx, "weights");
+}
+
+rp_status rp_weights(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband,
+                     const double *energy_eV, const double *T, int o0, int o1, int e0, int e1, int k0,
+                     int k1, int nfreq, const double *freq_eV, double delta_eV, rp_weight_mode wm,
+                     double *w)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    Geometry g;
+    rp_status st = geometry(ctx, cell, iq, &g);
+    if (st != RP_OK) return st;
+    if ((st = check_ranges(ctx, g, nband, o0, o1, e0, e1, k0, k1)) != RP_OK) return st;
+    if (!w) return fail(ctx, RP_E_NULL, "w is NULL");
+    return weights_common(ctx, g, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, nfreq, freq_eV, delta_eV,
+                          wm, (double2 *)w);
+}
+
+rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband,
+                             const double *energy_eV, const double *T, int o0, int o1, int e0, int e1,
+                             int k0, int k1, int ng, const double *M, int nfreq, const double *freq_eV,
+                             double delta_eV, rp_weight_mode wm, rp_precision prec, int accumulate,
+                             double *chi)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    Geometry g;
+    rp_status st = geometry(ctx, cell, iq, &g);
+    if (st != RP_OK) return st;
+    if ((st = check_ranges(ctx, g, nband, o0, o1, e0, e1, k0, k1)) != RP_OK) return st;
+    if (!M || !chi) return fail(ctx, RP_E_NULL, "NULL M or chi");
+    if (ng < 1) return fail(ctx, RP_E_SHAPE, "ng must be >= 1");
+    if (prec != RP_FP64 && prec != RP_SPLIT_BF16) return fail(ctx, RP_E_RANGE, "unknown precision");
+    if (accumulate != 0 && accumulate != 1) return fail(ctx, RP_E_RANGE, "accumulate must be 0 or 1");
+    const long npair = (long)(k1 - k0) * (e1 - e0) * (o1 - o0);
+    if ((st = ensure(ctx, ctx->weights, sizeof(double2) * std::max(1L, npair) * nfreq)) != RP_OK) return st;
+    double2 *w = (double2 *)ctx->weights.p;
+    if (npair > 0) {
+        st = weights_common(ctx, g, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, nfreq, freq_eV, delta_eV,
+                            wm, w);
+        if (st != RP_OK) return st;
+    } else if (!energy_eV || !freq_eV) {
+        return fail(ctx, RP_E_NULL, "NULL energy or frequency array");
+    }
+    if (prec == RP_FP64) {
+        launch_chi_f64(ctx->stream, npair, ng, (const double2 *)M, nfreq, w, accumulate, (double2 *)chi);
+    } else {
+        if ((st = ensure(ctx, ctx->split_a, split_a_bytes(npair, ng))) != RP_OK) return st;
+        if ((st = ensure(ctx, ctx->split_b, split_b_bytes(npair, ng))) != RP_OK) return st;
+        launch_chi_bf16(ctx->stream, npair, ng, (const double2 *)M, nfreq, w, accumulate, (double2 *)chi,
+                        ctx->split_a.p, ctx->split_b.p);
+    }
+    return check_launch(ctx, "chi0 contraction");
+}
+
+rp_status rp_screen_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int ng, const int *gsph,
+                      int nfreq, const double *chi, double *eps_inv, double *W)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    Geometry g;
+    rp_status st = geometry(ctx, cell, iq, &g);
+    if (st != RP_OK) return st;
+    if (!chi) return fail(ctx, RP_E_NULL, "chi is NULL");
+    if (ng < 1 || nfreq < 1) return fail(ctx, RP_E_SHAPE, "ng and nfreq must be >= 1");
+    if ((st = check_gsph(ctx, g, ng, gsph, "gsph")) != RP_OK) return st;
+    const size_t mat = sizeof(double2) * (size_t)ng * ng * nfreq;
+    double2 *a = (double2 *)eps_inv;
+    if (!a) {
+        if ((st = ensure(ctx, ctx->work, mat)) != RP_OK) return st;
+        a = (double2 *)ctx->work.p;
+    }
+    if ((st = upload(ctx, ctx->glist, gsph, sizeof(int) * 3 * ng)) != RP_OK) return st;
+    if ((st = ensure(ctx, ctx->vsqrt, sizeof(double) * ng)) != RP_OK) return st;
+    if ((st = ensure(ctx, ctx->piv, sizeof(int) * (size_t)ng * nfreq)) != RP_OK) return st;
+    if ((st = ensure(ctx, ctx->rho, sizeof(double2) * (size_t)ng * nfreq)) != RP_OK) return st;
+    double *vs = (double *)ctx->vsqrt.p;
+    launch_vsqrt(ctx->stream, g, ng, (const int *)ctx->glist.p, vs, ctx->flag);
+    launch_eps(ctx->stream, nfreq, ng, vs, (const double2 *)chi, a);
+    launch_invert(ctx->stream, nfreq, ng, a, (double2 *)ctx->rho.p, (int *)ctx->piv.p, ctx->flag);
+    if (W) launch_W(ctx->stream, nfreq, ng, vs, a, (double2 *)W);
+    return check_launch(ctx, "screen");
+}
+
+rp_status rp_wannier_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nwan, const double *phi,
+                       const double *centre_frac, int ng, const int *gsph, int ntail, const int *gtail,
+                       int nfreq, const double *eps_inv, double *Wij)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    Geometry g;
+    rp_status st = geometry(ctx, cell, iq, &g);
+    if (st != RP_OK) return st;
+    if (!phi || !centre_frac || !eps_inv || !Wij) return fail(ctx, RP_E_NULL, "NULL array argument");
+    if (nwan < 1 || nwan > 32) return fail(ctx, RP_E_UNSUPPORTED, "nwan = %d outside [1, 32]", nwan);
+    if (ng < 1 || nfreq < 1 || ntail < 0) return fail(ctx, RP_E_SHAPE, "bad ng, ntail or nfreq");
+    if ((st = check_gsph(ctx, g, ng, gsph, "gsph")) != RP_OK) return st;
+    if ((st = check_gsph(ctx, g, ntail, gtail, "gtail")) != RP_OK) return st;
+    for (int i = 0; i < 3 * nwan; i++)
+        if (!std::isfinite(centre_frac[i])) return fail(ctx, RP_E_RANGE, "non-finite centre");
+    FftPlan plans[3];
+    if ((st = plans3(ctx, g, plans)) != RP_OK) return st;
+    const long nr = (long)g.fft[0] * g.fft[1] * g.fft[2];
+    // layout of the Wannier workspace (double2 units):
+    //   grids [nwan][nr] | rho_eps [nwan][ng] | rho_tail [nwan][ntail] | T [nfreq][ng][nwan]
+    const size_t n_grid = (size_t)nwan * nr, n_re = (size_t)nwan * ng, n_rt = (size_t)nwan * ntail;
+    const size_t n_T = (size_t)nfreq * ng * nwan;
+    if ((st = ensure(ctx, ctx->work, sizeof(double2) * (n_grid + n_re + n_rt + n_T))) != RP_OK) return st;
+    // host lists: centres, gsph, gtail packed into one upload
+    std::vector<char> host(sizeof(double) * 3 * nwan + sizeof(int) * 3 * (ng + ntail));
+    std::memcpy(host.data(), centre_frac, sizeof(double) * 3 * nwan);
+    std::memcpy(host.data() + sizeof(double) * 3 * nwan, gsph, sizeof(int) * 3 * ng);
+    if (ntail) std::memcpy(host.data() + sizeof(double) * 3 * nwan + sizeof(int) * 3 * ng, gtail, sizeof(int) * 3 * ntail);
+    if ((st = upload(ctx, ctx->kinfo, host.data(), host.size())) != RP_OK) return st;
+    const double *dcen = (const double *)ctx->kinfo.p;
+    const int *dgs = (const int *)((const char *)ctx->kinfo.p + sizeof(double) * 3 * nwan);
+    const int *dgt = dgs + 3 * ng;
+    double2 *grids = (double2 *)ctx->work.p;
+    double2 *rho_e = grids + n_grid;
+    double2 *rho_t = rho_e + n_re;
+    double2 *T = rho_t + n_rt;
+    launch_wannier_density(ctx->stream, g, plans, nwan, phi, dcen, grids);
+    launch_wannier_gather(ctx->stream, g, nwan, ng, dgs, grids, rho_e, ctx->flag);
+    launch_wannier_gather(ctx->stream, g, nwan, ntail, dgt, grids, rho_t, ctx->flag);
+    const double pre = kHartreeEv * 4.0 * kPi / (g.volume * g.nk);
+    launch_wannier_W(ctx->stream, nfreq, nwan, ng, rho_e, ntail, rho_t, (const double2 *)eps_inv, pre, T,
+                     (double2 *)Wij);
+    return check_launch(ctx, "wannier projection");
+}
+
+}  // extern "C"

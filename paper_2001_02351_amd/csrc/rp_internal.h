@@ -1,0 +1,128 @@
+// Internal declarations shared by the host side of the library and the
+// kernel translation units.  Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "rp.h"
+
+namespace rp {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kHartreeEv = 27.211386245988;  // CODATA 2018
+
+// A device buffer that grows on demand and is freed with the context.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// Bits of the device-side fault flag.
+enum : int { kFlagZeroPivot = 1, kFlagNonFinite = 2 };
+
+// Radix plan of one FFT length: n = prod(rad[0..nrad-1]), radices in {2,3,4,5}.
+struct FftPlan {
+    int n;
+    int nrad;
+    int rad[12];
+};
+
+bool make_plan(int n, FftPlan *plan);
+
+// Geometry of one call, computed on the host.
+struct Geometry {
+    double lat[9];
+    double rec[9];     // rows b_i, a_i.b_j = 2 pi delta_ij
+    double volume;
+    int fft[3];
+    int kmesh[3];
+    int iq[3];
+    int nk;
+};
+
+}  // namespace rp
+
+struct rp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    int *flag = nullptr;            // device int[4] fault flags
+    rp::DevBuf ugrid;               // u-grids of one k: [nO + nE][N1][N2][N3] c128
+    rp::DevBuf weights;             // w[nfreq][npair] c128
+    rp::DevBuf glist;               // int[...] copies of host G lists
+    rp::DevBuf freq;                // c128[nfreq]
+    rp::DevBuf kinfo;               // per-k tables
+    rp::DevBuf vsqrt;               // double[ng]
+    rp::DevBuf work;                // eps / inversion workspace
+    rp::DevBuf split_a;             // split-BF16 row operand (FP32 complex)
+    rp::DevBuf split_b;             // split-BF16 column operand (BF16 planes)
+    rp::DevBuf rho;                 // Wannier densities
+    rp::DevBuf piv;                 // pivots
+};
+
+namespace rp {
+
+rp_status fail(rp_ctx *ctx, rp_status st, const char *fmt, ...);
+rp_status ensure(rp_ctx *ctx, DevBuf &b, size_t bytes);
+rp_status check_launch(rp_ctx *ctx, const char *what);
+rp_status geometry(rp_ctx *ctx, const rp_cell *cell, const int iq[3], Geometry *g);
+
+// ---- kernel launchers (one translation unit each) --------------------------
+
+// fft.hip: u-grids of several bands of one k: scatter + 3-D transform.
+void launch_ugrid(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
+                  int nbands, int npw, const int *miller_k, const double2 *coef_k,
+                  int band_stride, double2 *u);
+
+// fft.hip: in-place batched positive-exponent transform of whole grids.
+void launch_fft3d(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,
+                  double2 *data);
+
+// pair.hip: pair densities of one k.
+size_t pair_lds_bytes(const int fft[3], int L3, int rows);
+int pair_rows(const int fft[3]);
+void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], const double2 *u_occ,
+                   const double2 *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3],
+                   int lo3, int L3, double2 *M);
+
+// tetra.hip: weights of a pair range.
+void launch_weights(hipStream_t s, const int kmesh[3], const int iq[3], int nband,
+                    const double *E_eV, const double *T, int o0, int o1, int e0, int e1,
+                    int k0, int k1, int nfreq, const double2 *freq_eV, double delta_eV,
+                    int mode, double2 *w);
+
+// chi_f64.hip: chi += sum_p w_p M_p M_p^H on FP64 matrix cores.
+void launch_chi_f64(hipStream_t s, long npair, int ng, const double2 *M, int nfreq,
+                    const double2 *w, int accumulate, double2 *chi);
+
+// chi_bf16.hip: split-BF16 contraction.
+size_t split_a_bytes(long npair, int ng);
+size_t split_b_bytes(long npair, int ng);
+void launch_chi_bf16(hipStream_t s, long npair, int ng, const double2 *M, int nfreq,
+                     const double2 *w, int accumulate, double2 *chi, void *split_a,
+                     void *split_b);
+
+// screen.hip
+void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, double *vs, int *flag);
+void launch_eps(hipStream_t s, int nfreq, int ng, const double *vs, const double2 *chi,
+                double2 *eps);
+void launch_invert(hipStream_t s, int nfreq, int ng, double2 *a, double2 *col, int *piv,
+                   int *flag);
+void launch_W(hipStream_t s, int nfreq, int ng, const double *vs, const double2 *einv,
+              double2 *W);
+
+// wannier.hip
+void launch_wannier_density(hipStream_t s, const Geometry &g, const FftPlan plans[3], int nwan,
+                            const double *phi, const double *centre_frac_dev, double2 *f);
+void launch_wannier_gather(hipStream_t s, const Geometry &g, int nwan, int nlist,
+                           const int *glist, const double2 *fgrid, double2 *rho, int *flag);
+void launch_wannier_W(hipStream_t s, int nfreq, int nwan, int ng, const double2 *rho_eps,
+                      int ntail, const double2 *rho_tail, const double2 *einv, double pre,
+                      double2 *T, double2 *Wij);
+
+}  // namespace rp

@@ -1,0 +1,130 @@
+"""One q-point through the library: pair densities and chi0 per k batch, then
+eps^-1 / W, then W_ij.  Orchestration and device-memory plumbing only; every
+step runs in librp.so.
+
+`prob` is any object with the attributes of a plane-wave problem: lat, fft,
+kmesh, iq, nocc, nemp, npw, miller, coef, energy_eV, T, gsph, gtail,
+freq_eV, delta_eV and optionally phi, centre_frac.
+"""
+
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+from . import _rp
+
+
+class DeviceInputs:
+    """Device copies of a problem's large arrays (torch tensors)."""
+
+    def __init__(self, prob, device: int = 0):
+        import torch
+        dev = torch.device("cuda", device)
+        self.prob = prob
+        self.cell = _rp.make_cell(prob.lat, prob.fft, prob.kmesh)
+        self.miller = torch.from_numpy(np.ascontiguousarray(prob.miller, dtype=np.int32)).to(dev)
+        coef = np.ascontiguousarray(prob.coef, dtype=np.complex128)
+        self.coef = torch.from_numpy(coef.view(np.float64)).to(dev)
+        self.energy = torch.from_numpy(np.ascontiguousarray(prob.energy_eV, dtype=np.float64)).to(dev)
+        self.T = None if prob.T is None else torch.from_numpy(np.ascontiguousarray(prob.T, np.float64)).to(dev)
+        self.phi = None
+        if getattr(prob, "phi", None) is not None:
+            self.phi = torch.from_numpy(np.ascontiguousarray(prob.phi, dtype=np.float64)).to(dev)
+        self.mmax = np.abs(np.asarray(prob.miller)).max(axis=(0, 1)).astype(np.int32)
+        self.nk = int(np.prod(prob.kmesh))
+        self.nband = prob.nocc + prob.nemp
+        self.ng = int(prob.gsph.shape[0])
+        self.nfreq = int(len(prob.freq_eV))
+        self.device = dev
+
+
+def weight_mode(prob) -> int:
+    return _rp.RP_W_SAMPLING if int(np.prod(prob.kmesh)) == 1 else _rp.RP_W_TETRA
+
+
+def pair_density(ctx, d: DeviceInputs, k0: int, k1: int, o=None, e=None, out=None):
+    import torch
+    p = d.prob
+    o0, o1 = o if o else (0, p.nocc)
+    e0, e1 = e if e else (p.nocc, p.nocc + p.nemp)
+    npair = (k1 - k0) * (e1 - e0) * (o1 - o0)
+    if out is None:
+        out = torch.empty((npair, d.ng, 2), dtype=torch.float64, device=d.device)
+    _rp.rp_pair_density(ctx, d.cell, p.iq, d.nband, p.miller.shape[1], p.npw, d.mmax, d.miller, d.coef,
+                        o0, o1, e0, e1, k0, k1, d.ng, p.gsph, out)
+    return out
+
+
+def weights(ctx, d: DeviceInputs, k0, k1, o=None, e=None, mode: Optional[int] = None):
+    import torch
+    p = d.prob
+    o0, o1 = o if o else (0, p.nocc)
+    e0, e1 = e if e else (p.nocc, p.nocc + p.nemp)
+    npair = (k1 - k0) * (e1 - e0) * (o1 - o0)
+    w = torch.empty((d.nfreq, npair, 2), dtype=torch.float64, device=d.device)
+    _rp.rp_weights(ctx, d.cell, p.iq, d.nband, d.energy, d.T, o0, o1, e0, e1, k0, k1, d.nfreq,
+                   p.freq_eV, p.delta_eV, weight_mode(p) if mode is None else mode, w)
+    return w
+
+
+def chi0(ctx, d: DeviceInputs, prec: int = _rp.RP_FP64, kbatch: int = 1, k0: int = 0,
+         k1: Optional[int] = None, chi=None, Mbuf=None):
+    """chi0 over k in [k0, k1) (all bands), pair densities streamed per k batch."""
+    import torch
+    p = d.prob
+    k1 = d.nk if k1 is None else k1
+    if chi is None:
+        chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device=d.device)
+    npk = p.nocc * p.nemp
+    if Mbuf is None:
+        Mbuf = torch.empty((kbatch * npk, d.ng, 2), dtype=torch.float64, device=d.device)
+    first = True
+    for ka in range(k0, k1, kbatch):
+        kb = min(k1, ka + kbatch)
+        M = Mbuf[: (kb - ka) * npk]
+        pair_density(ctx, d, ka, kb, out=M)
+        _rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, d.T, 0, p.nocc, p.nocc,
+                               p.nocc + p.nemp, ka, kb, d.ng, M, d.nfreq, p.freq_eV, p.delta_eV,
+                               weight_mode(p), prec, 0 if first else 1, chi)
+        first = False
+    if first:
+        chi.zero_()
+    return chi
+
+
+def screen(ctx, d: DeviceInputs, chi, want_eps_inv: bool = True, want_W: bool = True):
+    import torch
+    p = d.prob
+    einv = torch.empty_like(chi) if want_eps_inv else None
+    W = torch.empty_like(chi) if want_W else None
+    _rp.rp_screen_W(ctx, d.cell, p.iq, d.ng, p.gsph, d.nfreq, chi, einv, W)
+    return einv, W
+
+
+def wannier(ctx, d: DeviceInputs, eps_inv):
+    import torch
+    p = d.prob
+    nwan = int(p.phi.shape[0])
+    Wij = torch.empty((d.nfreq, nwan, nwan, 2), dtype=torch.float64, device=d.device)
+    gt = p.gtail if p.gtail is not None else np.zeros((0, 3), np.int32)
+    _rp.rp_wannier_W(ctx, d.cell, p.iq, nwan, d.phi, p.centre_frac, d.ng, p.gsph, int(gt.shape[0]), gt,
+                     d.nfreq, eps_inv, Wij)
+    return Wij
+
+
+def run_q(ctx, d: DeviceInputs, prec: int = _rp.RP_FP64, kbatch: int = 1):
+    """a1..a10 for one q-point; returns device tensors (complex as [..., 2])."""
+    chi = chi0(ctx, d, prec=prec, kbatch=kbatch)
+    einv, W = screen(ctx, d, chi)
+    out = dict(chi=chi, eps_inv=einv, W=W)
+    if d.phi is not None:
+        out["Wij"] = wannier(ctx, d, einv)
+    return out
+
+
+def to_complex(t) -> np.ndarray:
+    """Device [..., 2] float64 tensor -> host complex128 array."""
+    a = t.detach().cpu().numpy()
+    return np.ascontiguousarray(a).view(np.complex128)[..., 0]
