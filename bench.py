@@ -1,0 +1,240 @@
+#!/usr/bin/env python
+"""chi0 build TFLOP/s and seconds per q-point on one MI355X, split-BF16 and
+FP64 side by side, on the SrVO3-shaped workload (48^3 grid, 8^3 k mesh,
+40 + 200 bands, N_G = 1500, 20 real frequencies, one q-point).
+
+A step is one q-point through the whole path: pair densities and chi0 for all
+512 k (streamed in k batches), eps^-1 and W, and the Wannier projection W_ij.
+Inputs are resident in HBM before the timed region.
+
+  value         split-BF16 chi0 build rate F_chi / t_chi0 (TFLOP/s), with
+                F_chi = 8 N_G^2 P N_w the algorithmic flops of Eq. chi
+                (P = 4 096 000 pairs) and t_chi0 the wall time of the pair
+                densities + weights + contraction of one q-point
+  fp64          the same for the FP64 path
+  roofline      the chi contraction kernel of the split path: algorithmic
+                flops per launch / its mean launch time (HIP events on the
+                library's stream) against the BF16 dense peak
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "χ0 build TFLOP/s + s/q-point, split-BF16 vs FP64, at rel err ≤1e-5 vs oracle"
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP64_TFLOPS = 78.6
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prob, nemp_sample: int = 25, nfreq_sample: int = 2):
+    """Time the FP64 oracle on a bounded sample: k = 0, all occupied bands x
+    the first `nemp_sample` empty bands, the first `nfreq_sample` frequencies
+    (pair densities, tetrahedron weights over the full mesh, chi0)."""
+    import copy
+
+    import numpy as np
+
+    import oracle
+    p = copy.copy(prob)
+    p.freq_eV = np.ascontiguousarray(prob.freq_eV[:nfreq_sample])
+    o0, o1, e0, e1 = 0, p.nocc, p.nocc, p.nocc + nemp_sample
+    t0 = time.perf_counter()
+    M = oracle.pair_densities(p, o0, o1, e0, e1, 0, 1)
+    t1 = time.perf_counter()
+    w = oracle.prob_weights(p, o0, o1, e0, e1, 0, 1)
+    t2 = time.perf_counter()
+    oracle.chi0(M, w)
+    t3 = time.perf_counter()
+    npair = M.shape[0]
+    flops = 8.0 * p.ng ** 2 * npair * nfreq_sample
+    return {
+        "value": flops / (t3 - t0) / 1e12,
+        "unit": "TFLOP/s",
+        "cores": oracle.threads_used(),
+        "kind": "oracle",
+        "sample": (f"k=0 only, {p.nocc} occupied x {nemp_sample} empty bands ({npair} pairs), "
+                   f"{nfreq_sample} of {prob.nfreq} frequencies, N_G={p.ng}: pair densities "
+                   f"{t1 - t0:.1f} s, weights {t2 - t1:.1f} s, chi0 {t3 - t2:.1f} s"),
+        "seconds": t3 - t0,
+    }
+
+
+def run_leg(rp, path, ctx, d, prec, steps, warmup, kbatch):
+    import torch
+    npair_total = d.nk * d.prob.nocc * d.prob.nemp
+    flops = 8.0 * d.ng ** 2 * npair_total * d.nfreq
+    Mbuf = torch.empty((kbatch * d.prob.nocc * d.prob.nemp, d.ng, 2), dtype=torch.float64, device=d.device)
+    chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device=d.device)
+    for i in range(warmup):
+        log(f"prec={prec} warmup step {i}")
+        c = path.chi0(ctx, d, prec=prec, kbatch=kbatch, chi=chi, Mbuf=Mbuf)
+        einv, W = path.screen(ctx, d, c)
+        path.wannier(ctx, d, einv)
+        rp.rp_synchronize(ctx)
+    rp.rp_profile(ctx, True)
+    t_chi, t_step = [], []
+    for i in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = path.chi0(ctx, d, prec=prec, kbatch=kbatch, chi=chi, Mbuf=Mbuf)
+        rp.rp_synchronize(ctx)
+        t1 = time.perf_counter()
+        einv, W = path.screen(ctx, d, c)
+        Wij = path.wannier(ctx, d, einv)
+        rp.rp_synchronize(ctx)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_chi.append(t1 - t0)
+        t_step.append(t2 - t0)
+        log(f"prec={prec} step {i}: chi0 {t1 - t0:.3f} s, step {t2 - t0:.3f} s")
+    stages = rp.rp_profile_read(ctx)
+    rp.rp_profile(ctx, False)
+    tc = sorted(t_chi)[len(t_chi) // 2]
+    ts = sorted(t_step)[len(t_step) // 2]
+    ms_chi, n_chi = stages["chi"]
+    per_launch_pairs = kbatch * d.prob.nocc * d.prob.nemp
+    chi_launch_ms = ms_chi / max(1, n_chi)
+    res = {
+        "chi0_tflops": flops / tc / 1e12,
+        "s_per_qpoint": ts,
+        "t_chi0_s": tc,
+        "gemm_tflops": flops / (ms_chi / steps / 1e3) / 1e12 if ms_chi > 0 else None,
+        "chi_kernel_ms_per_launch": chi_launch_ms,
+        "chi_kernel_launches_per_step": n_chi // steps,
+        "chi_kernel_flops_per_launch": 8.0 * d.ng ** 2 * per_launch_pairs * d.nfreq,
+        "stage_ms_per_step": {k: v[0] / steps for k, v in stages.items()},
+    }
+    return res, chi, einv, Wij
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--fp64-warmup", type=int, default=0)
+    ap.add_argument("--kbatch", type=int, default=2)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    from synth import make_config
+    log("generating the SrVO3-shaped workload (48^3, 8^3 k, 40+200 bands, N_G=1500, 20 w)")
+    t0 = time.perf_counter()
+    prob = make_config(2)
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+
+    baseline = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample (host cores)")
+        baseline = cpu_baseline(prob)
+        log(f"oracle sample: {baseline['sample']}")
+
+    import torch
+
+    import paper_2001_02351_amd as rp
+    from paper_2001_02351_amd import path
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    rp.load()
+    ctx = rp.Context(0)
+    d = path.DeviceInputs(prob)
+    torch.cuda.synchronize()
+    log("inputs resident on the device")
+
+    split, chi_s, einv_s, wij_s = run_leg(rp, path, ctx, d, rp.RP_SPLIT_BF16, args.steps, args.warmup,
+                                          args.kbatch)
+    chi_s = chi_s.clone()
+    einv_s = einv_s.clone()
+    wij_s = wij_s.clone()
+    fp64 = None
+    agree = None
+    if not args.no_fp64:
+        fp64, chi_d, einv_d, wij_d = run_leg(rp, path, ctx, d, rp.RP_FP64, args.fp64_steps, args.fp64_warmup,
+                                             args.kbatch)
+
+        def rel(a, b):
+            a = torch.view_as_complex(a)
+            b = torch.view_as_complex(b)
+            return max(float(torch.linalg.norm(a[f] - b[f]) / torch.linalg.norm(b[f])) for f in range(b.shape[0]))
+
+        wd = torch.view_as_complex(wij_d)
+        agree = {
+            "chi": rel(chi_s, chi_d),
+            "eps_inv": rel(einv_s, einv_d),
+            "W_ij_max_elementwise": float((torch.abs(torch.view_as_complex(wij_s) - wd) / torch.abs(wd)).max()),
+        }
+    ctx.close()
+
+    npair_total = d.nk * prob.nocc * prob.nemp
+    achieved = split["chi_kernel_flops_per_launch"] / (split["chi_kernel_ms_per_launch"] / 1e3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": split["chi0_tflops"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": split["s_per_qpoint"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": "SrVO3-shaped q-point: 48^3 grid, 8^3 k mesh, 40+200 bands, N_G=1500, "
+                        "20 real frequencies, delta=0.1 eV, generalized tetrahedron, 10 Wannier orbitals",
+            "pairs": npair_total,
+            "ng": d.ng,
+            "nfreq": d.nfreq,
+            "kbatch": args.kbatch,
+            "precision": "split-BF16 chi0 (3 BF16 terms, 6 products, FP32 accumulation, FP64 sum), "
+                         "FP64 weights, eps^-1 and W_ij",
+        },
+        "s_per_qpoint": split["s_per_qpoint"],
+        "split_bf16": split,
+        "fp64": fp64,
+        "split_vs_fp64_rel": agree,
+        "roofline": {
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": PEAK_BF16_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_BF16_TFLOPS,
+            "traffic": None,
+            "kernel": "k_chi_bf16 (chi0 contraction, split-BF16)",
+            "mfma_executed_frac": 6.0 * achieved / PEAK_BF16_TFLOPS,
+        },
+        "cpu_baseline": None if baseline is None else {k: baseline[k] for k in
+                                                        ("value", "unit", "cores", "kind", "sample")},
+    }
+    if fp64 is not None:
+        a64 = fp64["chi_kernel_flops_per_launch"] / (fp64["chi_kernel_ms_per_launch"] / 1e3) / 1e12
+        out["fp64"]["roofline"] = {"bound": "mfma", "achieved": a64, "peak": PEAK_FP64_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": a64 / PEAK_FP64_TFLOPS,
+                                   "kernel": "k_chi_f64 (chi0 contraction, FP64)"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

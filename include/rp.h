@@ -197,6 +197,35 @@ rp_status rp_wannier_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nw
                        int ntail, const int *gtail, int nfreq, const double *eps_inv,
                        double *Wij);
 
+/*
+ * Stage timers.  While enabled, the context records a pair of HIP events on
+ * its stream around every kernel launch of a stage and accumulates the
+ * elapsed device time per stage.  Stages:
+ *   RP_STAGE_UGRID    u-grids (coefficient scatter and 3-D transform), a2
+ *   RP_STAGE_PAIR     pair-density kernel, a3-a4
+ *   RP_STAGE_WEIGHTS  tetrahedron weights, a5
+ *   RP_STAGE_PREP     split-BF16 operand preparation, a6
+ *   RP_STAGE_CHI      chi contraction kernel (FP64 or split-BF16), a6
+ *   RP_STAGE_SCREEN   eps, inversion and W, a7-a9
+ *   RP_STAGE_WANNIER  Wannier densities and projection, a10
+ * rp_profile(ctx, 1) enables and resets; rp_profile(ctx, 0) disables.
+ * rp_profile_read synchronizes the stream and returns, per stage, the summed
+ * milliseconds and the number of timed launches (arrays of RP_NSTAGE).
+ */
+enum {
+    RP_STAGE_UGRID = 0,
+    RP_STAGE_PAIR = 1,
+    RP_STAGE_WEIGHTS = 2,
+    RP_STAGE_PREP = 3,
+    RP_STAGE_CHI = 4,
+    RP_STAGE_SCREEN = 5,
+    RP_STAGE_WANNIER = 6,
+    RP_NSTAGE = 7
+};
+
+rp_status rp_profile(rp_ctx *ctx, int enable);
+rp_status rp_profile_read(rp_ctx *ctx, double *ms, long *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,6 +7,7 @@ per-q orchestration in `path`.  Importing it does not touch the GPU.
 
 from ._rp import (  # noqa: F401
     EXPORTED,
+    STAGES,
     RP_FP64,
     RP_SPLIT_BF16,
     RP_W_SAMPLING,
@@ -18,6 +19,8 @@ from ._rp import (  # noqa: F401
     rp_chi0_accumulate,
     rp_last_error,
     rp_pair_density,
+    rp_profile,
+    rp_profile_read,
     rp_screen_W,
     rp_synchronize,
     rp_wannier_W,

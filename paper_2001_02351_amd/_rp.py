@@ -26,7 +26,10 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_E_NULL", 2: "RP_E_SHAPE", 3: "RP_E_RANGE", 4:
                 5: "RP_E_NOMEM", 6: "RP_E_DEVICE", 7: "RP_E_SINGULAR", 8: "RP_E_UNSUPPORTED"}
 
 EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pair_density",
-            "rp_weights", "rp_chi0_accumulate", "rp_screen_W", "rp_wannier_W"]
+            "rp_weights", "rp_chi0_accumulate", "rp_screen_W", "rp_wannier_W", "rp_profile",
+            "rp_profile_read"]
+
+STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier"]
 
 
 class RpError(RuntimeError):
@@ -75,6 +78,8 @@ def load(path: Optional[str] = None):
         "rp_chi0_accumulate": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, I, P, D, I, I, I, P],
         "rp_screen_W": [P, cellp, P, I, P, I, P, P, P],
         "rp_wannier_W": [P, cellp, P, I, P, P, I, P, I, P, I, P, P],
+        "rp_profile": [P, I],
+        "rp_profile_read": [P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -205,3 +210,15 @@ def rp_wannier_W(ctx: Context, cell: rp_cell, iq, nwan, phi, centre_frac, ng, gs
                               int(ng), _hp(g_h), int(ntail), _hp(t_h), int(nfreq), _dp(eps_inv), _dp(Wij))
     ctx._leave()
     ctx._check(st, "rp_wannier_W")
+
+
+def rp_profile(ctx: Context, enable: bool):
+    ctx._check(ctx.lib.rp_profile(ctx.handle, int(bool(enable))), "rp_profile")
+
+
+def rp_profile_read(ctx: Context) -> dict:
+    """{stage: (milliseconds, launches)} accumulated since rp_profile(ctx, True)."""
+    ms = (ctypes.c_double * len(STAGES))()
+    cnt = (ctypes.c_long * len(STAGES))()
+    ctx._check(ctx.lib.rp_profile_read(ctx.handle, ms, cnt), "rp_profile_read")
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}

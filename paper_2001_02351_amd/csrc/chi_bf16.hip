@@ -225,18 +225,25 @@ int pad_ng(int ng) { return (ng + kTile - 1) / kTile * kTile; }
 size_t split_a_bytes(long npair, int ng) { return (size_t)pad_pairs(npair) * pad_ng(ng) * sizeof(float2); }
 size_t split_b_bytes(long npair, int ng) { return (size_t)6 * pad_pairs(npair) * pad_ng(ng) * 2; }
 
-void launch_chi_bf16(hipStream_t s, long npair, int ng, const double2 *M, int nfreq, const double2 *w,
-                     int accumulate, double2 *chi, void *split_a, void *split_b)
+void launch_split_prep(hipStream_t s, long npair, int ng, const double2 *M, void *split_a, void *split_b)
 {
     const long KP = pad_pairs(npair);
     const int NGP = pad_ng(ng);
     const int npg = (int)(KP / 8);
-    float2 *Ap = (float2 *)split_a;
-    bf8 *Bp = (bf8 *)split_b;
     const long nt = (long)npg * NGP;
     if (nt > 0)
         hipLaunchKernelGGL(k_split_prep, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, npair, ng, npg,
-                           NGP, M, Ap, Bp);
+                           NGP, M, (float2 *)split_a, (bf8 *)split_b);
+}
+
+void launch_chi_bf16(hipStream_t s, long npair, int ng, int nfreq, const double2 *w, int accumulate,
+                     double2 *chi, const void *split_a, const void *split_b)
+{
+    const long KP = pad_pairs(npair);
+    const int NGP = pad_ng(ng);
+    const int npg = (int)(KP / 8);
+    const float2 *Ap = (const float2 *)split_a;
+    const bf8 *Bp = (const bf8 *)split_b;
     const unsigned t = (unsigned)(NGP / kTile);
     if (nfreq >= 2)
         hipLaunchKernelGGL(k_chi_bf16<2>, dim3(t, t, (nfreq + 1) / 2), dim3(256), 0, s, npg, NGP, npair, ng,

@@ -103,6 +103,37 @@ rp_status geometry(rp_ctx *ctx, const rp_cell *cell, const int iq[3], Geometry *
     return RP_OK;
 }
 
+static hipEvent_t take_event(rp_ctx *ctx)
+{
+    if (!ctx->spare.empty()) {
+        hipEvent_t e = ctx->spare.back();
+        ctx->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+StageTimer::StageTimer(rp_ctx *ctx, int stage) : ctx_(ctx), stage_(stage)
+{
+    if (!ctx_->profiling) return;
+    a_ = take_event(ctx_);
+    if (a_) (void)hipEventRecord(a_, ctx_->stream);
+}
+
+StageTimer::~StageTimer()
+{
+    if (!a_) return;
+    hipEvent_t b = take_event(ctx_);
+    if (!b) {
+        ctx_->spare.push_back(a_);
+        return;
+    }
+    (void)hipEventRecord(b, ctx_->stream);
+    ctx_->marks.push_back({stage_, a_, b});
+}
+
 static double qg_norm(const Geometry &g, const int *m)
 {
     double f[3], v[3] = {0, 0, 0};
@@ -187,11 +218,52 @@ rp_status rp_create(rp_ctx **out, int device, void *hip_stream)
     return RP_OK;
 }
 
+static void release_marks(rp_ctx *ctx)
+{
+    for (auto &m : ctx->marks) {
+        ctx->spare.push_back(m.a);
+        ctx->spare.push_back(m.b);
+    }
+    ctx->marks.clear();
+}
+
+rp_status rp_profile(rp_ctx *ctx, int enable)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, RP_E_DEVICE, "stream synchronize failed");
+    release_marks(ctx);
+    ctx->profiling = enable != 0;
+    return RP_OK;
+}
+
+rp_status rp_profile_read(rp_ctx *ctx, double *ms, long *count)
+{
+    if (!ctx) return RP_E_NULL;
+    if (!ms || !count) return fail(ctx, RP_E_NULL, "NULL output array");
+    (void)hipSetDevice(ctx->device);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, RP_E_DEVICE, "stream synchronize failed");
+    for (int i = 0; i < RP_NSTAGE; i++) {
+        ms[i] = 0.0;
+        count[i] = 0;
+    }
+    for (auto &m : ctx->marks) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, m.a, m.b) != hipSuccess) return fail(ctx, RP_E_DEVICE, "event timing failed");
+        ms[m.stage] += t;
+        count[m.stage] += 1;
+    }
+    return RP_OK;
+}
+
 rp_status rp_destroy(rp_ctx *ctx)
 {
     if (!ctx) return RP_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    release_marks(ctx);
+    for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
+    ctx->spare.clear();
     DevBuf *bufs[] = {&ctx->ugrid, &ctx->weights, &ctx->glist, &ctx->freq,  &ctx->kinfo, &ctx->vsqrt,
                       &ctx->work,  &ctx->split_a, &ctx->split_b, &ctx->rho, &ctx->piv};
     for (DevBuf *b : bufs)
@@ -279,13 +351,19 @@ rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int
         }
         const int kp = (r[0] * g.kmesh[1] + r[1]) * g.kmesh[2] + r[2];
         const double2 *cf = (const double2 *)coef;
-        launch_ugrid(ctx->stream, plans, g.fft, mmax, nO, npw[k], miller + (long)k * npw_max * 3,
-                     cf + ((long)k * nband + o0) * npw_max, npw_max, u_occ);
-        launch_ugrid(ctx->stream, plans, g.fft, mmax, nE, npw[kp], miller + (long)kp * npw_max * 3,
-                     cf + ((long)kp * nband + e0) * npw_max, npw_max, u_emp);
+        {
+            StageTimer t(ctx, RP_STAGE_UGRID);
+            launch_ugrid(ctx->stream, plans, g.fft, mmax, nO, npw[k], miller + (long)k * npw_max * 3,
+                         cf + ((long)k * nband + o0) * npw_max, npw_max, u_occ);
+            launch_ugrid(ctx->stream, plans, g.fft, mmax, nE, npw[kp], miller + (long)kp * npw_max * 3,
+                         cf + ((long)kp * nband + e0) * npw_max, npw_max, u_emp);
+        }
         const int lo3 = lo[2] + g0[2], L3 = hi[2] - lo[2] + 1;
         double2 *Mk = (double2 *)M + (long)(k - k0) * nE * nO * ng;
-        launch_pair_k(ctx->stream, plans, g.fft, u_occ, u_emp, nO, nE, ng, dg, g0, lo3, L3, Mk);
+        {
+            StageTimer t(ctx, RP_STAGE_PAIR);
+            launch_pair_k(ctx->stream, plans, g.fft, u_occ, u_emp, nO, nE, ng, dg, g0, lo3, L3, Mk);
+        }
         if ((st = check_launch(ctx, "pair density")) != RP_OK) return st;
     }
     return RP_OK;
@@ -304,8 +382,11 @@ static rp_status weights_common(rp_ctx *ctx, const Geometry &g, int nband, const
     for (int f = 0; f < 2 * nfreq; f++)
         if (!std::isfinite(freq_eV[f])) return fail(ctx, RP_E_RANGE, "non-finite frequency");
     if ((st = upload(ctx, ctx->freq, freq_eV, sizeof(double2) * nfreq)) != RP_OK) return st;
-    launch_weights(ctx->stream, g.kmesh, g.iq, nband, E, T, o0, o1, e0, e1, k0, k1, nfreq,
-                   (const double2 *)ctx->freq.p, delta_eV, (int)wm, w);
+    {
+        StageTimer t(ctx, RP_STAGE_WEIGHTS);
+        launch_weights(ctx->stream, g.kmesh, g.iq, nband, E, T, o0, o1, e0, e1, k0, k1, nfreq,
+                       (const double2 *)ctx->freq.p, delta_eV, (int)wm, w);
+    }
     return check_launch(ctx, "weights");
 }
 
@@ -352,12 +433,18 @@ rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], 
         return fail(ctx, RP_E_NULL, "NULL energy or frequency array");
     }
     if (prec == RP_FP64) {
+        StageTimer t(ctx, RP_STAGE_CHI);
         launch_chi_f64(ctx->stream, npair, ng, (const double2 *)M, nfreq, w, accumulate, (double2 *)chi);
     } else {
         if ((st = ensure(ctx, ctx->split_a, split_a_bytes(npair, ng))) != RP_OK) return st;
         if ((st = ensure(ctx, ctx->split_b, split_b_bytes(npair, ng))) != RP_OK) return st;
-        launch_chi_bf16(ctx->stream, npair, ng, (const double2 *)M, nfreq, w, accumulate, (double2 *)chi,
-                        ctx->split_a.p, ctx->split_b.p);
+        {
+            StageTimer t(ctx, RP_STAGE_PREP);
+            launch_split_prep(ctx->stream, npair, ng, (const double2 *)M, ctx->split_a.p, ctx->split_b.p);
+        }
+        StageTimer t(ctx, RP_STAGE_CHI);
+        launch_chi_bf16(ctx->stream, npair, ng, nfreq, w, accumulate, (double2 *)chi, ctx->split_a.p,
+                        ctx->split_b.p);
     }
     return check_launch(ctx, "chi0 contraction");
 }
@@ -384,6 +471,7 @@ rp_status rp_screen_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int ng,
     if ((st = ensure(ctx, ctx->piv, sizeof(int) * (size_t)ng * nfreq)) != RP_OK) return st;
     if ((st = ensure(ctx, ctx->rho, sizeof(double2) * (size_t)ng * nfreq)) != RP_OK) return st;
     double *vs = (double *)ctx->vsqrt.p;
+    StageTimer t(ctx, RP_STAGE_SCREEN);
     launch_vsqrt(ctx->stream, g, ng, (const int *)ctx->glist.p, vs, ctx->flag);
     launch_eps(ctx->stream, nfreq, ng, vs, (const double2 *)chi, a);
     launch_invert(ctx->stream, nfreq, ng, a, (double2 *)ctx->rho.p, (int *)ctx->piv.p, ctx->flag);
@@ -428,6 +516,7 @@ rp_status rp_wannier_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nw
     double2 *rho_e = grids + n_grid;
     double2 *rho_t = rho_e + n_re;
     double2 *T = rho_t + n_rt;
+    StageTimer t(ctx, RP_STAGE_WANNIER);
     launch_wannier_density(ctx->stream, g, plans, nwan, phi, dcen, grids);
     launch_wannier_gather(ctx->stream, g, nwan, ng, dgs, grids, rho_e, ctx->flag);
     launch_wannier_gather(ctx->stream, g, nwan, ntail, dgt, grids, rho_t, ctx->flag);

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "rp.h"
 
@@ -63,6 +64,14 @@ struct rp_ctx {
     rp::DevBuf split_b;             // split-BF16 column operand (BF16 planes)
     rp::DevBuf rho;                 // Wannier densities
     rp::DevBuf piv;                 // pivots
+    // stage timers
+    bool profiling = false;
+    struct Mark {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> spare;
 };
 
 namespace rp {
@@ -71,6 +80,18 @@ rp_status fail(rp_ctx *ctx, rp_status st, const char *fmt, ...);
 rp_status ensure(rp_ctx *ctx, DevBuf &b, size_t bytes);
 rp_status check_launch(rp_ctx *ctx, const char *what);
 rp_status geometry(rp_ctx *ctx, const rp_cell *cell, const int iq[3], Geometry *g);
+
+// Brackets the launches of one stage with events when profiling is on.
+class StageTimer {
+  public:
+    StageTimer(rp_ctx *ctx, int stage);
+    ~StageTimer();
+
+  private:
+    rp_ctx *ctx_;
+    int stage_;
+    hipEvent_t a_ = nullptr;
+};
 
 // ---- kernel launchers (one translation unit each) --------------------------
 
@@ -103,9 +124,10 @@ void launch_chi_f64(hipStream_t s, long npair, int ng, const double2 *M, int nfr
 // chi_bf16.hip: split-BF16 contraction.
 size_t split_a_bytes(long npair, int ng);
 size_t split_b_bytes(long npair, int ng);
-void launch_chi_bf16(hipStream_t s, long npair, int ng, const double2 *M, int nfreq,
-                     const double2 *w, int accumulate, double2 *chi, void *split_a,
-                     void *split_b);
+void launch_split_prep(hipStream_t s, long npair, int ng, const double2 *M, void *split_a,
+                       void *split_b);
+void launch_chi_bf16(hipStream_t s, long npair, int ng, int nfreq, const double2 *w,
+                     int accumulate, double2 *chi, const void *split_a, const void *split_b);
 
 // screen.hip
 void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, double *vs, int *flag);
