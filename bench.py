@@ -39,7 +39,7 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, nemp_sample: int = 25, nfreq_sample: int = 2):
+def cpu_baseline(prob, nemp_sample: int = 100, nfreq_sample: int = 4):
     """Time the FP64 oracle on a bounded sample: k = 0, all occupied bands x
     the first `nemp_sample` empty bands, the first `nfreq_sample` frequencies
     (pair densities, tetrahedron weights over the full mesh, chi0)."""
