@@ -59,10 +59,17 @@ typedef enum {
 } rp_status;
 
 typedef enum {
-    RP_FP64 = 0,        /* FP64 everywhere (FP64 matrix cores for chi) */
-    RP_SPLIT_BF16 = 1   /* chi contraction with M split into BF16 hi/mid/lo
-                           terms on BF16 matrix cores, FP32 accumulation,
-                           FP64 reduction into chi; all other steps FP64 */
+    RP_FP64 = 0,          /* FP64 everywhere (FP64 matrix cores for chi) */
+    RP_SPLIT_BF16 = 1,    /* chi contraction on BF16 matrix cores: each operand
+                             x = x_hi + x_mid (BF16 terms of its FP32 value),
+                             products by the three-term compensated form
+                             x_hi y_hi + x_hi y_mid + x_mid y_hi, FP32
+                             accumulation, FP64 reduction into chi; pair
+                             densities computed on FP32 grids; weights,
+                             eps^-1 and W_ij in FP64 */
+    RP_SPLIT_BF16_X6 = 2  /* as RP_SPLIT_BF16 with x = x_hi + x_mid + x_lo and
+                             the six products of order <= 2 (about FP32
+                             accuracy, twice the matrix-core work) */
 } rp_precision;
 
 typedef enum {
@@ -110,14 +117,17 @@ const char *rp_last_error(const rp_ctx *ctx);
  * o0..o1 / e0..e1    : occupied bands b at k / empty bands a at k+q
  * k0..k1             : k range of this call
  * gsph     (host)    : int[ng][3] Miller indices of the polarization sphere
+ * prec               : RP_FP64 computes the grids and transforms in FP64; the
+ *                      split modes in FP32 (M then carries ~1e-7 relative
+ *                      error, far below what the split contraction keeps)
  * M        (dev)     : c128[k1-k0][e1-e0][o1-o0][ng] output
- * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_ALIAS, RP_E_UNSUPPORTED, RP_E_NOMEM,
- * RP_E_DEVICE.
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE, RP_E_ALIAS, RP_E_UNSUPPORTED,
+ * RP_E_NOMEM, RP_E_DEVICE.
  */
 rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband,
                           int npw_max, const int *npw, const int mmax[3], const int *miller,
                           const double *coef, int o0, int o1, int e0, int e1, int k0, int k1,
-                          int ng, const int *gsph, double *M);
+                          int ng, const int *gsph, rp_precision prec, double *M);
 
 /*
  * Step a5: weights w_p(omega_f) = (2/Nk)(1 - T_{a,k+q} T_{b,k}) x_p(omega_f)
@@ -143,9 +153,9 @@ rp_status rp_weights(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nban
 /*
  * Steps a5-a6: chi_GG'(w) (+)= sum_p w_p(w) M_p(G) conj(M_p(G'))   (Eq. chi)
  * for the pairs of one rp_pair_density call (same ranges, same M layout).
- * prec selects the contraction: RP_FP64 (FP64 matrix cores) or
- * RP_SPLIT_BF16 (BF16 hi/mid/lo products with FP32 accumulation, added
- * into chi in FP64).  Weights are always FP64.
+ * prec selects the contraction: RP_FP64 (FP64 matrix cores), RP_SPLIT_BF16
+ * or RP_SPLIT_BF16_X6 (BF16 split products with FP32 accumulation, added into
+ * chi in FP64).  Weights are always FP64.
  *
  * M          (dev)   : c128[npair][ng] from rp_pair_density
  * accumulate         : 0 overwrite chi, 1 add into chi

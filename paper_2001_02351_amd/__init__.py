@@ -10,6 +10,7 @@ from ._rp import (  # noqa: F401
     STAGES,
     RP_FP64,
     RP_SPLIT_BF16,
+    RP_SPLIT_BF16_X6,
     RP_W_SAMPLING,
     RP_W_TETRA,
     Context,

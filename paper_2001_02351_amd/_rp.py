@@ -19,6 +19,7 @@ from .build import library_path
 RP_OK = 0
 RP_FP64 = 0
 RP_SPLIT_BF16 = 1
+RP_SPLIT_BF16_X6 = 2
 RP_W_TETRA = 0
 RP_W_SAMPLING = 1
 
@@ -73,7 +74,7 @@ def load(path: Optional[str] = None):
         "rp_create": [ctypes.POINTER(P), I, P],
         "rp_destroy": [P],
         "rp_synchronize": [P],
-        "rp_pair_density": [P, cellp, P, I, I, P, P, P, P, I, I, I, I, I, I, I, P, P],
+        "rp_pair_density": [P, cellp, P, I, I, P, P, P, P, I, I, I, I, I, I, I, P, I, P],
         "rp_weights": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, D, I, P],
         "rp_chi0_accumulate": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, I, P, D, I, I, I, P],
         "rp_screen_W": [P, cellp, P, I, P, I, P, P, P],
@@ -157,13 +158,13 @@ def rp_last_error(ctx: Context) -> str:
 
 
 def rp_pair_density(ctx: Context, cell: rp_cell, iq, nband, npw_max, npw, mmax, miller, coef,
-                    o0, o1, e0, e1, k0, k1, ng, gsph, M):
+                    o0, o1, e0, e1, k0, k1, ng, gsph, prec, M):
     iq_h, npw_h, mm_h = _host(iq, np.int32), _host(npw, np.int32), _host(mmax, np.int32)
     g_h = _host(gsph, np.int32)
     ctx._enter()
     st = ctx.lib.rp_pair_density(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(nband), int(npw_max),
                                  _hp(npw_h), _hp(mm_h), _dp(miller), _dp(coef), o0, o1, e0, e1, k0, k1,
-                                 int(ng), _hp(g_h), _dp(M))
+                                 int(ng), _hp(g_h), int(prec), _dp(M))
     ctx._leave()
     ctx._check(st, "rp_pair_density")
 

@@ -2,21 +2,29 @@
 //
 //   chi_GG'(w) (+)= sum_p a_p(G) conj(b_p(G')),  a = w(w) M (row side), b = M (column side)
 //
-// Each FP32 value x is written as x ~ x_h + x_m + x_l with three BF16 terms
-// (x_h = bf16(x), x_m = bf16(x - x_h), x_l = bf16(x - x_h - x_m); each
-// remainder is exact in FP32), and a product x y is formed from the six
-// partial products with s + t <= 2 (h=0, m=1, l=2), which keeps it to about
-// 2^-24 relative.  The products run on v_mfma_f32_16x16x32_bf16 with FP32
-// accumulators; each call's partial sums are added into chi in FP64.
+// Each FP32 value x is written as a sum of NT BF16 terms x_0 + x_1 (+ x_2),
+// x_0 = bf16(x), x_1 = bf16(x - x_0), x_2 = bf16(x - x_0 - x_1) (each
+// remainder is exact in FP32), and a product x y is formed from the partial
+// products x_s y_t with s + t < NT:
+//   NT = 2: x_0 y_0 + x_0 y_1 + x_1 y_0   (three-term compensated product,
+//           relative error about 3 2^-16 per product)
+//   NT = 3: the six terms with s + t <= 2  (about 2^-24, i.e. FP32)
+// The products run on v_mfma_f32_16x16x32_bf16 with FP32 accumulators; each
+// call's partial sums are added into chi in FP64.
 //
 // A prep pass converts the FP64 pair densities once per call into
-//   Ap: FP32 complex, [KP/8][NGP][8]      (row side, scaled by w in registers)
-//   Bp: 6 BF16 planes [6][KP/8][NGP][8]   (column side; re h,m,l then im h,m,l)
-// with KP = pairs padded to 32 and NGP = ng padded to 128 (zeros), so that a
-// lane's 8 consecutive pairs are one contiguous 64-byte / 16-byte load.
+//   Ap: FP32 complex, 1 KB blocks [KP/8][NGP/16][4][16][2]: for a group of 8
+//       pairs and 16 rows, pair quarter q holds rows 0..15 x pairs 2q, 2q+1
+//       (row side, scaled by w and split in registers)
+//   Bp: 2 NT BF16 planes [2 NT][KP/8][NGP][8] (column side; re terms, im terms)
+//   Wq: FP32 weights [nfreq][KP]
+// with KP = pairs padded to 32 and NGP = ng padded to 128 (zeros).
 //
-// Tiling: a 256-thread block owns a 128x128 tile of (G, G') for NW
-// frequencies; each wave a 64x64 sub-tile (4x4 blocks of 16x16).
+// Tiling: a 256-thread block owns a 128x128 tile of (G, G') for NW = 2
+// frequencies; each wave a 64x64 sub-tile (4x4 blocks of 16x16).  Steps of 32
+// pairs stream through two LDS buffers (32 KB of A and 16 NT KB of B each)
+// by global_load_lds DMA, so the next step's operands arrive while the matrix
+// cores work on the current one.
 #include "fft_lds.h"
 
 namespace rp {
@@ -29,19 +37,21 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 128;
 constexpr int kStep = 32;  // pairs per matrix-core step
+constexpr int kNW = 2;     // frequencies per block
 
 __device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l)
+template <int NT> __device__ __forceinline__ void split(float x, __bf16 (&t)[NT])
 {
-    h = (__bf16)x;
-    const float r1 = x - (float)h;
-    m = (__bf16)r1;
-    const float r2 = r1 - (float)m;
-    l = (__bf16)r2;
+    float r = x;
+#pragma unroll
+    for (int s = 0; s < NT; s++) {
+        t[s] = (__bf16)r;
+        if (s + 1 < NT) r = r - (float)t[s];
+    }
 }
 
 __device__ __forceinline__ bf8 negate(bf8 v)
@@ -51,7 +61,13 @@ __device__ __forceinline__ bf8 negate(bf8 v)
     return __builtin_bit_cast(bf8, u);
 }
 
+__device__ __forceinline__ void dma16(const void *src, void *lds)
+{
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
+
 // one thread per (pair group of 8, G)
+template <int NT>
 __global__ void k_split_prep(long npair, int ng, int npg, int NGP, const double2 *__restrict__ M,
                              float2 *__restrict__ Ap, bf8 *__restrict__ Bp)
 {
@@ -59,7 +75,7 @@ __global__ void k_split_prep(long npair, int ng, int npg, int NGP, const double2
     if (t >= (long)npg * NGP) return;
     const int pg = (int)(t / NGP), G = (int)(t - (long)pg * NGP);
     float2 a[8];
-    bf8 pl[6];
+    bf8 pl[2 * NT];
 #pragma unroll
     for (int j = 0; j < 8; j++) {
         const long p = (long)pg * 8 + j;
@@ -67,36 +83,87 @@ __global__ void k_split_prep(long npair, int ng, int npg, int NGP, const double2
         if (p < npair && G < ng) v = M[p * ng + G];
         const float re = (float)v.x, im = (float)v.y;
         a[j] = make_float2(re, im);
-        __bf16 h, m, l;
-        split3(re, h, m, l);
-        pl[0][j] = h;
-        pl[1][j] = m;
-        pl[2][j] = l;
-        split3(im, h, m, l);
-        pl[3][j] = h;
-        pl[4][j] = m;
-        pl[5][j] = l;
-    }
-    float2 *ao = Ap + t * 8;
+        __bf16 tr[NT], ti[NT];
+        split<NT>(re, tr);
+        split<NT>(im, ti);
 #pragma unroll
-    for (int j = 0; j < 8; j++) ao[j] = a[j];
+        for (int s = 0; s < NT; s++) {
+            pl[s][j] = tr[s];
+            pl[NT + s][j] = ti[s];
+        }
+    }
+    float2 *blk = Ap + ((long)pg * (NGP / 16) + G / 16) * 128 + (G % 16) * 2;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        blk[q * 32] = a[2 * q];
+        blk[q * 32 + 1] = a[2 * q + 1];
+    }
     const long plane = (long)npg * NGP;
 #pragma unroll
-    for (int s = 0; s < 6; s++) Bp[s * plane + t] = pl[s];
+    for (int s = 0; s < 2 * NT; s++) Bp[s * plane + t] = pl[s];
 }
 
-template <int NW>
-__global__ void __launch_bounds__(256)
-k_chi_bf16(int npg, int NGP, long npair, int ng, const float2 *__restrict__ Ap, const bf8 *__restrict__ Bp,
-           int nfreq, const double2 *__restrict__ w, int accumulate, double2 *__restrict__ chi)
+__global__ void k_weight_prep(long npair, long KP, int nfreq, const double2 *__restrict__ w,
+                              float2 *__restrict__ wq)
 {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= KP * nfreq) return;
+    const int f = (int)(t / KP);
+    const long p = t - (long)f * KP;
+    double2 v = make_double2(0.0, 0.0);
+    if (p < npair) v = w[(long)f * npair + p];
+    wq[t] = make_float2((float)v.x, (float)v.y);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256)
+k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, const bf8 *__restrict__ Bp,
+           int nfreq, const float2 *__restrict__ wq, int accumulate, double2 *__restrict__ chi)
+{
+    constexpr int NW = kNW;
+    constexpr int NPL = 2 * NT;  // B planes
+    // per stage: A [4 kg][8 row blocks][4 q][16][2] float2 (32 KB) and
+    //            B [NPL planes][4 kg][128 cols] bf8 (8 NPL KB)
+    __shared__ float2 sA[2][4 * 8 * 128];
+    __shared__ bf8 sB[2][NPL * 4 * 128];
+
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
-    const int row0 = blockIdx.y * kTile + (wave >> 1) * 64;
-    const int col0 = blockIdx.x * kTile + (wave & 1) * 64;
+    const int rt0 = blockIdx.y * kTile, ct0 = blockIdx.x * kTile;
+    const int wr = wave >> 1, wc = wave & 1;
     const int f0 = blockIdx.z * NW;
     const long plane = (long)npg * NGP;
+    const int nstep = npg / 4;
+
+    // DMA segments of 1 KB; wave w moves pair group kg = w: its 8 A row
+    // blocks and its NPL x 2 B half-rows
+    const float2 *srcA = Ap + ((long)wave * (NGP / 16) + rt0 / 16) * 128 + lane * 2;
+    const bf8 *srcB = Bp + (long)wave * NGP + ct0 + lane;
+    auto issue = [&](int stg, int kg0) {
+        const float2 *a = srcA + (long)kg0 * (NGP / 16) * 128;
+        float2 *da = sA[stg] + wave * 8 * 128;
+#pragma unroll
+        for (int rb = 0; rb < 8; rb++) dma16(a + rb * 128, da + rb * 128);
+        const bf8 *b = srcB + (long)kg0 * NGP;
+#pragma unroll
+        for (int sp = 0; sp < NPL; sp++)
+#pragma unroll
+            for (int h = 0; h < 2; h++) dma16(b + sp * plane + 64 * h, sB[stg] + (sp * 4 + wave) * 128 + 64 * h);
+    };
+    auto wload = [&](int step, float2 (&dst)[NW][8]) {
+#pragma unroll
+        for (int iw = 0; iw < NW; iw++) {
+            const int f = min(f0 + iw, nfreq - 1);
+            const float4 *src = (const float4 *)(wq + (long)f * KP + (long)(step * 4 + lk) * 8);
+#pragma unroll
+            for (int h = 0; h < 4; h++) {
+                const float4 v = src[h];
+                dst[iw][2 * h] = make_float2(v.x, v.y);
+                dst[iw][2 * h + 1] = make_float2(v.z, v.w);
+            }
+        }
+    };
 
     f4 accR[NW][4][4], accI[NW][4][4];
 #pragma unroll
@@ -109,86 +176,82 @@ k_chi_bf16(int npg, int NGP, long npair, int ng, const float2 *__restrict__ Ap, 
                 accI[iw][rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
             }
 
-    for (int kg0 = 0; kg0 < npg; kg0 += kStep / 8) {
-        const int kg = kg0 + lk;
-        // column operand: 4 blocks x 6 planes
-        bf8 B[4][6];
+    float2 wcur[NW][8];
+    if (nstep > 0) issue(0, 0);
+    for (int t = 0; t < nstep; t++) {
+        const int stg = t & 1;
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (t + 1 < nstep) issue(stg ^ 1, 4 * (t + 1));
+        wload(t, wcur);
+        // column operand: 4 blocks x NPL planes
+        bf8 B[4][NPL];
 #pragma unroll
         for (int cb = 0; cb < 4; cb++)
 #pragma unroll
-            for (int s = 0; s < 6; s++) B[cb][s] = Bp[s * plane + (long)kg * NGP + col0 + cb * 16 + li];
-        // weights of this lane's 8 pairs
-        float2 wf[NW][8];
-#pragma unroll
-        for (int iw = 0; iw < NW; iw++)
-#pragma unroll
-            for (int j = 0; j < 8; j++) {
-                const long p = (long)kg * 8 + j;
-                double2 v = make_double2(0.0, 0.0);
-                if (p < npair && f0 + iw < nfreq) v = w[(long)(f0 + iw) * npair + p];
-                wf[iw][j] = make_float2((float)v.x, (float)v.y);
-            }
+            for (int sp = 0; sp < NPL; sp++) B[cb][sp] = sB[stg][(sp * 4 + lk) * 128 + wc * 64 + cb * 16 + li];
 #pragma unroll
         for (int rb = 0; rb < 4; rb++) {
-            const float2 *src = Ap + ((long)kg * NGP + row0 + rb * 16 + li) * 8;
+            const float2 *blk = sA[stg] + (lk * 8 + wr * 4 + rb) * 128 + li * 2;
             float2 araw[8];
 #pragma unroll
-            for (int j = 0; j < 8; j++) araw[j] = src[j];
+            for (int q = 0; q < 4; q++) {
+                const float4 v = *(const float4 *)(blk + q * 32);
+                araw[2 * q] = make_float2(v.x, v.y);
+                araw[2 * q + 1] = make_float2(v.z, v.w);
+            }
 #pragma unroll
             for (int iw = 0; iw < NW; iw++) {
-                bf8 rh, rm, rl, ih, im, il;
+                bf8 ar[NT], ai[NT], an[NT];
 #pragma unroll
                 for (int j = 0; j < 8; j++) {
-                    const float2 x = araw[j], y = wf[iw][j];
-                    const float re = x.x * y.x - x.y * y.y;
-                    const float imv = x.x * y.y + x.y * y.x;
-                    __bf16 h, m, l;
-                    split3(re, h, m, l);
-                    rh[j] = h;
-                    rm[j] = m;
-                    rl[j] = l;
-                    split3(imv, h, m, l);
-                    ih[j] = h;
-                    im[j] = m;
-                    il[j] = l;
+                    const float2 x = araw[j], y = wcur[iw][j];
+                    __bf16 tr[NT], ti[NT];
+                    split<NT>(x.x * y.x - x.y * y.y, tr);
+                    split<NT>(x.x * y.y + x.y * y.x, ti);
+#pragma unroll
+                    for (int s = 0; s < NT; s++) {
+                        ar[s][j] = tr[s];
+                        ai[s][j] = ti[s];
+                    }
                 }
 #pragma unroll
-                for (int cb = 0; cb < 4; cb++) {
-                    f4 cr = accR[iw][rb][cb], ci = accI[iw][rb][cb];
-                    // Re += Re a Re b + Im a Im b   (terms with s + t <= 2)
-                    cr = mfma_bf16(rh, B[cb][0], cr);
-                    cr = mfma_bf16(rh, B[cb][1], cr);
-                    cr = mfma_bf16(rm, B[cb][0], cr);
-                    cr = mfma_bf16(rh, B[cb][2], cr);
-                    cr = mfma_bf16(rm, B[cb][1], cr);
-                    cr = mfma_bf16(rl, B[cb][0], cr);
-                    cr = mfma_bf16(ih, B[cb][3], cr);
-                    cr = mfma_bf16(ih, B[cb][4], cr);
-                    cr = mfma_bf16(im, B[cb][3], cr);
-                    cr = mfma_bf16(ih, B[cb][5], cr);
-                    cr = mfma_bf16(im, B[cb][4], cr);
-                    cr = mfma_bf16(il, B[cb][3], cr);
-                    // Im += Im a Re b - Re a Im b
-                    ci = mfma_bf16(ih, B[cb][0], ci);
-                    ci = mfma_bf16(ih, B[cb][1], ci);
-                    ci = mfma_bf16(im, B[cb][0], ci);
-                    ci = mfma_bf16(ih, B[cb][2], ci);
-                    ci = mfma_bf16(im, B[cb][1], ci);
-                    ci = mfma_bf16(il, B[cb][0], ci);
-                    accR[iw][rb][cb] = cr;
-                    accI[iw][rb][cb] = ci;
-                }
-                const bf8 nh = negate(rh), nm = negate(rm), nl = negate(rl);
+                for (int s = 0; s < NT; s++) an[s] = negate(ar[s]);
+                // Re += Re a Re b + Im a Im b;  Im += Im a Re b - Re a Im b, over
+                // the products s + t < NT; the column block is the innermost index
+                // so consecutive matrix-core ops update 8 independent accumulators
+                f4 cr[4], ci[4];
 #pragma unroll
                 for (int cb = 0; cb < 4; cb++) {
-                    f4 ci = accI[iw][rb][cb];
-                    ci = mfma_bf16(nh, B[cb][3], ci);
-                    ci = mfma_bf16(nh, B[cb][4], ci);
-                    ci = mfma_bf16(nm, B[cb][3], ci);
-                    ci = mfma_bf16(nh, B[cb][5], ci);
-                    ci = mfma_bf16(nm, B[cb][4], ci);
-                    ci = mfma_bf16(nl, B[cb][3], ci);
-                    accI[iw][rb][cb] = ci;
+                    cr[cb] = accR[iw][rb][cb];
+                    ci[cb] = accI[iw][rb][cb];
+                }
+#pragma unroll
+                for (int s = 0; s < NT; s++)
+#pragma unroll
+                    for (int u = 0; u < NT; u++) {
+                        if (s + u >= NT) continue;
+#pragma unroll
+                        for (int cb = 0; cb < 4; cb++) {
+                            cr[cb] = mfma_bf16(ar[s], B[cb][u], cr[cb]);
+                            ci[cb] = mfma_bf16(ai[s], B[cb][u], ci[cb]);
+                        }
+                    }
+#pragma unroll
+                for (int s = 0; s < NT; s++)
+#pragma unroll
+                    for (int u = 0; u < NT; u++) {
+                        if (s + u >= NT) continue;
+#pragma unroll
+                        for (int cb = 0; cb < 4; cb++) {
+                            cr[cb] = mfma_bf16(ai[s], B[cb][NT + u], cr[cb]);
+                            ci[cb] = mfma_bf16(an[s], B[cb][NT + u], ci[cb]);
+                        }
+                    }
+#pragma unroll
+                for (int cb = 0; cb < 4; cb++) {
+                    accR[iw][rb][cb] = cr[cb];
+                    accI[iw][rb][cb] = ci[cb];
                 }
             }
         }
@@ -205,8 +268,8 @@ k_chi_bf16(int npg, int NGP, long npair, int ng, const float2 *__restrict__ Ap, 
             for (int cb = 0; cb < 4; cb++)
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const int i = row0 + rb * 16 + 4 * lk + r;
-                    const int j = col0 + cb * 16 + li;
+                    const int i = rt0 + wr * 64 + rb * 16 + 4 * lk + r;
+                    const int j = ct0 + wc * 64 + cb * 16 + li;
                     if (i < ng && j < ng) {
                         double2 v = make_double2((double)accR[iw][rb][cb][r], (double)accI[iw][rb][cb][r]);
                         const long idx = (long)i * ng + j;
@@ -224,33 +287,42 @@ int pad_ng(int ng) { return (ng + kTile - 1) / kTile * kTile; }
 
 size_t split_a_bytes(long npair, int ng) { return (size_t)pad_pairs(npair) * pad_ng(ng) * sizeof(float2); }
 size_t split_b_bytes(long npair, int ng) { return (size_t)6 * pad_pairs(npair) * pad_ng(ng) * 2; }
+size_t split_w_bytes(long npair, int nfreq) { return (size_t)pad_pairs(npair) * nfreq * sizeof(float2); }
 
-void launch_split_prep(hipStream_t s, long npair, int ng, const double2 *M, void *split_a, void *split_b)
+void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, const double2 *M,
+                       const double2 *w, void *split_a, void *split_b, void *split_w)
 {
     const long KP = pad_pairs(npair);
     const int NGP = pad_ng(ng);
     const int npg = (int)(KP / 8);
     const long nt = (long)npg * NGP;
-    if (nt > 0)
-        hipLaunchKernelGGL(k_split_prep, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, npair, ng, npg,
-                           NGP, M, (float2 *)split_a, (bf8 *)split_b);
+    if (nt == 0) return;
+    const dim3 grid((unsigned)((nt + 255) / 256));
+    if (nterm == 2)
+        hipLaunchKernelGGL(k_split_prep<2>, grid, dim3(256), 0, s, npair, ng, npg, NGP, M, (float2 *)split_a,
+                           (bf8 *)split_b);
+    else
+        hipLaunchKernelGGL(k_split_prep<3>, grid, dim3(256), 0, s, npair, ng, npg, NGP, M, (float2 *)split_a,
+                           (bf8 *)split_b);
+    const long nw = KP * nfreq;
+    hipLaunchKernelGGL(k_weight_prep, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, npair, KP, nfreq, w,
+                       (float2 *)split_w);
 }
 
-void launch_chi_bf16(hipStream_t s, long npair, int ng, int nfreq, const double2 *w, int accumulate,
-                     double2 *chi, const void *split_a, const void *split_b)
+void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, int accumulate, double2 *chi,
+                     const void *split_a, const void *split_b, const void *split_w)
 {
     const long KP = pad_pairs(npair);
     const int NGP = pad_ng(ng);
     const int npg = (int)(KP / 8);
-    const float2 *Ap = (const float2 *)split_a;
-    const bf8 *Bp = (const bf8 *)split_b;
     const unsigned t = (unsigned)(NGP / kTile);
-    if (nfreq >= 2)
-        hipLaunchKernelGGL(k_chi_bf16<2>, dim3(t, t, (nfreq + 1) / 2), dim3(256), 0, s, npg, NGP, npair, ng,
-                           Ap, Bp, nfreq, w, accumulate, chi);
+    const dim3 grid(t, t, (nfreq + kNW - 1) / kNW);
+    if (nterm == 2)
+        hipLaunchKernelGGL(k_chi_bf16<2>, grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a,
+                           (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi);
     else
-        hipLaunchKernelGGL(k_chi_bf16<1>, dim3(t, t, nfreq), dim3(256), 0, s, npg, NGP, npair, ng, Ap, Bp,
-                           nfreq, w, accumulate, chi);
+        hipLaunchKernelGGL(k_chi_bf16<3>, grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a,
+                           (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi);
 }
 
 }  // namespace rp

@@ -1,4 +1,5 @@
-// Batched 1-D FFTs staged in LDS (device code shared by the grid kernels).
+// Batched 1-D FFTs staged in LDS (device code shared by the grid kernels),
+// for complex FP64 (double2) and FP32 (float2) data.
 //
 // Transform convention used throughout the library:
 //     y[k] = sum_j x[j] e^{+2 pi i j k / n}      (no scaling)
@@ -18,58 +19,74 @@
 
 namespace rp {
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b)
-{
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cmulc(double2 a, double2 b)  // conj(a) * b
-{
-    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
-__device__ __forceinline__ double2 mul_i(double2 a) { return make_double2(-a.y, a.x); }
+template <typename C> struct CxT;
+template <> struct CxT<double2> { typedef double T; };
+template <> struct CxT<float2> { typedef float T; };
 
-// tw[t] = e^{+2 pi i t/n}, t < n
-__device__ __forceinline__ void fill_twiddles(double2 *tw, int n, int tid, int nth)
+template <typename C> __device__ __forceinline__ C mkc(typename CxT<C>::T x, typename CxT<C>::T y)
+{
+    C c;
+    c.x = x;
+    c.y = y;
+    return c;
+}
+
+template <typename C> __device__ __forceinline__ C cmul(C a, C b)
+{
+    return mkc<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b)  // conj(a) * b
+{
+    return mkc<C>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mkc<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mkc<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cscale(C a, typename CxT<C>::T s)
+{
+    return mkc<C>(a.x * s, a.y * s);
+}
+template <typename C> __device__ __forceinline__ C mul_i(C a) { return mkc<C>(-a.y, a.x); }
+
+// tw[t] = e^{+2 pi i t/n}, t < n (evaluated in FP64)
+template <typename C> __device__ __forceinline__ void fill_twiddles(C *tw, int n, int tid, int nth)
 {
     for (int t = tid; t < n; t += nth) {
         double s, c;
         sincospi(2.0 * (double)t / (double)n, &s, &c);
-        tw[t] = make_double2(c, s);
+        tw[t] = mkc<C>((typename CxT<C>::T)c, (typename CxT<C>::T)s);
     }
 }
 
-template <int R> struct Dft;
+template <int R, typename C> struct Dft;
 
-template <> struct Dft<2> {
-    __device__ static __forceinline__ void run(double2 *v)
+template <typename C> struct Dft<2, C> {
+    __device__ static __forceinline__ void run(C *v)
     {
-        double2 a = v[0];
+        C a = v[0];
         v[0] = cadd(a, v[1]);
         v[1] = csub(a, v[1]);
     }
 };
 
-template <> struct Dft<3> {
-    __device__ static __forceinline__ void run(double2 *v)
+template <typename C> struct Dft<3, C> {
+    __device__ static __forceinline__ void run(C *v)
     {
-        const double h = 0.86602540378443864676;  // sqrt(3)/2
-        double2 s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
-        double2 t = make_double2(v[0].x - 0.5 * s.x, v[0].y - 0.5 * s.y);
+        typedef typename CxT<C>::T T;
+        const T h = (T)0.86602540378443864676;  // sqrt(3)/2
+        C s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+        C t = mkc<C>(v[0].x - (T)0.5 * s.x, v[0].y - (T)0.5 * s.y);
         v[0] = cadd(v[0], s);
-        double2 id = mul_i(d);
-        v[1] = make_double2(t.x + h * id.x, t.y + h * id.y);
-        v[2] = make_double2(t.x - h * id.x, t.y - h * id.y);
+        C id = mul_i(d);
+        v[1] = mkc<C>(t.x + h * id.x, t.y + h * id.y);
+        v[2] = mkc<C>(t.x - h * id.x, t.y - h * id.y);
     }
 };
 
-template <> struct Dft<4> {
-    __device__ static __forceinline__ void run(double2 *v)
+template <typename C> struct Dft<4, C> {
+    __device__ static __forceinline__ void run(C *v)
     {
-        double2 s0 = cadd(v[0], v[2]), s1 = csub(v[0], v[2]);
-        double2 s2 = cadd(v[1], v[3]), s3 = mul_i(csub(v[1], v[3]));
+        C s0 = cadd(v[0], v[2]), s1 = csub(v[0], v[2]);
+        C s2 = cadd(v[1], v[3]), s3 = mul_i(csub(v[1], v[3]));
         v[0] = cadd(s0, s2);
         v[2] = csub(s0, s2);
         v[1] = cadd(s1, s3);
@@ -77,18 +94,19 @@ template <> struct Dft<4> {
     }
 };
 
-template <> struct Dft<5> {
-    __device__ static __forceinline__ void run(double2 *v)
+template <typename C> struct Dft<5, C> {
+    __device__ static __forceinline__ void run(C *v)
     {
-        const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;  // cos 2pi/5, cos 4pi/5
-        const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;   // sin 2pi/5, sin 4pi/5
-        double2 a = v[0];
-        double2 be = cadd(v[1], v[4]), bme = csub(v[1], v[4]);
-        double2 cd = cadd(v[2], v[3]), cmd = csub(v[2], v[3]);
-        double2 r1 = make_double2(a.x + c1 * be.x + c2 * cd.x, a.y + c1 * be.y + c2 * cd.y);
-        double2 r2 = make_double2(a.x + c2 * be.x + c1 * cd.x, a.y + c2 * be.y + c1 * cd.y);
-        double2 i1 = mul_i(make_double2(s1 * bme.x + s2 * cmd.x, s1 * bme.y + s2 * cmd.y));
-        double2 i2 = mul_i(make_double2(s2 * bme.x - s1 * cmd.x, s2 * bme.y - s1 * cmd.y));
+        typedef typename CxT<C>::T T;
+        const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;  // cos 2pi/5, cos 4pi/5
+        const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;   // sin 2pi/5, sin 4pi/5
+        C a = v[0];
+        C be = cadd(v[1], v[4]), bme = csub(v[1], v[4]);
+        C cd = cadd(v[2], v[3]), cmd = csub(v[2], v[3]);
+        C r1 = mkc<C>(a.x + c1 * be.x + c2 * cd.x, a.y + c1 * be.y + c2 * cd.y);
+        C r2 = mkc<C>(a.x + c2 * be.x + c1 * cd.x, a.y + c2 * be.y + c1 * cd.y);
+        C i1 = mul_i(mkc<C>(s1 * bme.x + s2 * cmd.x, s1 * bme.y + s2 * cmd.y));
+        C i2 = mul_i(mkc<C>(s2 * bme.x - s1 * cmd.x, s2 * bme.y - s1 * cmd.y));
         v[0] = cadd(a, cadd(be, cd));
         v[1] = cadd(r1, i1);
         v[4] = csub(r1, i1);
@@ -99,9 +117,9 @@ template <> struct Dft<5> {
 
 // One Stockham stage over `nlines` lines; element i of line l sits at
 // buf[l*ls + i*es] in both the input and the output buffer.
-template <int R>
-__device__ __forceinline__ void fft_stage(const double2 *in, double2 *out, int n, int ns, int nlines,
-                                          int ls, int es, const double2 *tw, int tid, int nth)
+template <int R, typename C>
+__device__ __forceinline__ void fft_stage(const C *in, C *out, int n, int ns, int nlines, int ls, int es,
+                                          const C *tw, int tid, int nth)
 {
     const int nb = n / R;
     const int total = nlines * nb;
@@ -109,17 +127,17 @@ __device__ __forceinline__ void fft_stage(const double2 *in, double2 *out, int n
     for (int idx = tid; idx < total; idx += nth) {
         int l = idx / nb;
         int j = idx - l * nb;
-        const double2 *src = in + l * ls;
-        double2 v[R];
+        const C *src = in + l * ls;
+        C v[R];
 #pragma unroll
         for (int r = 0; r < R; r++) v[r] = src[(j + r * nb) * es];
         int jm = j % ns;
         int t = jm * tstep;
 #pragma unroll
         for (int r = 1; r < R; r++) v[r] = cmul(v[r], tw[t * r]);
-        Dft<R>::run(v);
+        Dft<R, C>::run(v);
         int od = (j / ns) * ns * R + jm;
-        double2 *dst = out + l * ls;
+        C *dst = out + l * ls;
 #pragma unroll
         for (int r = 0; r < R; r++) dst[(od + r * ns) * es] = v[r];
     }
@@ -127,8 +145,9 @@ __device__ __forceinline__ void fft_stage(const double2 *in, double2 *out, int n
 
 // Full transform of `nlines` lines held in a (ping-pong partner b).  Every
 // thread of the block must call it.  Returns the buffer holding the result.
-__device__ __forceinline__ double2 *fft_lines(double2 *a, double2 *b, const FftPlan &p, int nlines,
-                                              int ls, int es, const double2 *tw, int tid, int nth)
+template <typename C>
+__device__ __forceinline__ C *fft_lines(C *a, C *b, const FftPlan &p, int nlines, int ls, int es, const C *tw,
+                                        int tid, int nth)
 {
     int ns = 1;
     for (int s = 0; s < p.nrad; s++) {
@@ -138,7 +157,7 @@ __device__ __forceinline__ double2 *fft_lines(double2 *a, double2 *b, const FftP
         else if (R == 3) fft_stage<3>(a, b, p.n, ns, nlines, ls, es, tw, tid, nth);
         else fft_stage<5>(a, b, p.n, ns, nlines, ls, es, tw, tid, nth);
         __syncthreads();
-        double2 *t = a;
+        C *t = a;
         a = b;
         b = t;
         ns *= R;
@@ -150,6 +169,88 @@ __device__ __forceinline__ int pmod(int a, int n)
 {
     int r = a % n;
     return r < 0 ? r + n : r;
+}
+
+}  // namespace rp
+
+namespace rp {
+
+// ---------------------------------------------------------------------------
+// Register FFT: one thread transforms a whole line of compile-time length N
+// held in registers (same Stockham stages as above, fully unrolled, no
+// synchronization).  tw is a table e^{+2 pi i t/N}, t < N, whose reads are
+// uniform across the wave.
+
+constexpr int fft_nstages(int n)
+{
+    int c = 0;
+    for (int r = 4; r >= 2; r -= 2)
+        while (n % r == 0) { n /= r; c++; }
+    while (n % 3 == 0) { n /= 3; c++; }
+    while (n % 5 == 0) { n /= 5; c++; }
+    return n == 1 ? c : -1;
+}
+
+constexpr int fft_radix(int n, int s)
+{
+    int c = 0;
+    for (int r = 4; r >= 2; r -= 2)
+        while (n % r == 0) { if (c == s) return r; n /= r; c++; }
+    while (n % 3 == 0) { if (c == s) return 3; n /= 3; c++; }
+    while (n % 5 == 0) { if (c == s) return 5; n /= 5; c++; }
+    return 1;
+}
+
+constexpr int fft_span(int n, int s)
+{
+    int p = 1;
+    for (int i = 0; i < s; i++) p *= fft_radix(n, i);
+    return p;
+}
+
+template <int N, int S, typename C>
+__device__ __forceinline__ void reg_fft_stage(const C (&in)[N], C (&out)[N], const C *tw)
+{
+    constexpr int R = fft_radix(N, S), NS = fft_span(N, S), NB = N / R, TSTEP = N / (NS * R);
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        C v[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) v[r] = in[j + r * NB];
+        const int jm = j % NS;
+        const int t = jm * TSTEP;
+        if (t != 0) {
+#pragma unroll
+            for (int r = 1; r < R; r++) v[r] = cmul(v[r], tw[t * r]);
+        }
+        Dft<R, C>::run(v);
+        const int od = (j / NS) * NS * R + jm;
+#pragma unroll
+        for (int r = 0; r < R; r++) out[od + r * NS] = v[r];
+    }
+}
+
+template <int N, int S, typename C> struct RegFft {
+    // transforms a (scratch b); the result ends in a
+    __device__ static __forceinline__ void run(C (&a)[N], C (&b)[N], const C *tw)
+    {
+        reg_fft_stage<N, S>(a, b, tw);
+        if constexpr (S + 1 < fft_nstages(N)) {
+            RegFft<N, S + 1, C>::run(b, a, tw);
+#pragma unroll
+            for (int i = 0; i < N; i++) a[i] = b[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; i++) a[i] = b[i];
+        }
+    }
+};
+
+template <int N, typename C> __device__ __forceinline__ void reg_fft(C (&a)[N], const C *tw)
+{
+    static_assert(fft_nstages(N) > 0, "FFT length must factor into 2, 3, 5");
+    C b[N];
+    RegFft<N, 0, C>::run(a, b, tw);
 }
 
 }  // namespace rp

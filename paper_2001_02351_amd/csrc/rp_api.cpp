@@ -264,8 +264,8 @@ rp_status rp_destroy(rp_ctx *ctx)
     release_marks(ctx);
     for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
     ctx->spare.clear();
-    DevBuf *bufs[] = {&ctx->ugrid, &ctx->weights, &ctx->glist, &ctx->freq,  &ctx->kinfo, &ctx->vsqrt,
-                      &ctx->work,  &ctx->split_a, &ctx->split_b, &ctx->rho, &ctx->piv};
+    DevBuf *bufs[] = {&ctx->ugrid, &ctx->ugrid32, &ctx->weights, &ctx->glist, &ctx->freq,  &ctx->kinfo, &ctx->vsqrt,
+                      &ctx->work,  &ctx->split_a, &ctx->split_b, &ctx->split_w, &ctx->rho, &ctx->piv};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->flag) (void)hipFree(ctx->flag);
@@ -296,7 +296,7 @@ rp_status rp_synchronize(rp_ctx *ctx)
 rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband, int npw_max,
                           const int *npw, const int mmax[3], const int *miller, const double *coef,
                           int o0, int o1, int e0, int e1, int k0, int k1, int ng, const int *gsph,
-                          double *M)
+                          rp_precision prec, double *M)
 {
     if (!ctx) return RP_E_NULL;
     (void)hipSetDevice(ctx->device);
@@ -308,6 +308,9 @@ rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int
     if (ng < 1 || ng > 6144) return fail(ctx, RP_E_UNSUPPORTED, "ng = %d outside [1, 6144]", ng);
     if ((st = check_gsph(ctx, g, ng, gsph, "gsph")) != RP_OK) return st;
     if (npw_max < 1) return fail(ctx, RP_E_SHAPE, "npw_max must be >= 1");
+    if (prec != RP_FP64 && prec != RP_SPLIT_BF16 && prec != RP_SPLIT_BF16_X6)
+        return fail(ctx, RP_E_RANGE, "unknown precision");
+    const bool fp32 = prec != RP_FP64;
     FftPlan plans[3];
     if ((st = plans3(ctx, g, plans)) != RP_OK) return st;
     for (int k = 0; k < g.nk; k++)
@@ -333,10 +336,11 @@ rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int
     const long nr = (long)g.fft[0] * g.fft[1] * g.fft[2];
     // LDS budget of the pair kernel (window along m3 is at most hi-lo+2)
     const int L3max = hi[2] - lo[2] + 2;
-    if (pair_lds_bytes(g.fft, L3max, pair_rows(g.fft)) > 160 * 1024)
+    if (pair_lds_bytes(g.fft, L3max, pair_rows(g.fft), fp32 ? 8 : 16, 4) > 160 * 1024)
         return fail(ctx, RP_E_UNSUPPORTED, "grid %dx%dx%d too large for the pair kernel's LDS plan",
                     g.fft[0], g.fft[1], g.fft[2]);
     if ((st = ensure(ctx, ctx->ugrid, sizeof(double2) * nr * (nO + nE))) != RP_OK) return st;
+    if (fp32 && (st = ensure(ctx, ctx->ugrid32, sizeof(float2) * nr * (nO + nE))) != RP_OK) return st;
     if ((st = upload(ctx, ctx->glist, gsph, sizeof(int) * 3 * ng)) != RP_OK) return st;
     double2 *u_occ = (double2 *)ctx->ugrid.p;
     double2 *u_emp = u_occ + nr * nO;
@@ -357,12 +361,18 @@ rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int
                          cf + ((long)k * nband + o0) * npw_max, npw_max, u_occ);
             launch_ugrid(ctx->stream, plans, g.fft, mmax, nE, npw[kp], miller + (long)kp * npw_max * 3,
                          cf + ((long)kp * nband + e0) * npw_max, npw_max, u_emp);
+            if (fp32) launch_to_f32(ctx->stream, u_occ, ctx->ugrid32.p, nr * (nO + nE));
         }
         const int lo3 = lo[2] + g0[2], L3 = hi[2] - lo[2] + 1;
         double2 *Mk = (double2 *)M + (long)(k - k0) * nE * nO * ng;
         {
             StageTimer t(ctx, RP_STAGE_PAIR);
-            launch_pair_k(ctx->stream, plans, g.fft, u_occ, u_emp, nO, nE, ng, dg, g0, lo3, L3, Mk);
+            if (fp32) {
+                const float2 *v = (const float2 *)ctx->ugrid32.p;
+                launch_pair_k(ctx->stream, plans, g.fft, v, v + nr * nO, nO, nE, ng, dg, g0, lo3, L3, true, Mk);
+            } else {
+                launch_pair_k(ctx->stream, plans, g.fft, u_occ, u_emp, nO, nE, ng, dg, g0, lo3, L3, false, Mk);
+            }
         }
         if ((st = check_launch(ctx, "pair density")) != RP_OK) return st;
     }
@@ -420,7 +430,8 @@ rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], 
     if ((st = check_ranges(ctx, g, nband, o0, o1, e0, e1, k0, k1)) != RP_OK) return st;
     if (!M || !chi) return fail(ctx, RP_E_NULL, "NULL M or chi");
     if (ng < 1) return fail(ctx, RP_E_SHAPE, "ng must be >= 1");
-    if (prec != RP_FP64 && prec != RP_SPLIT_BF16) return fail(ctx, RP_E_RANGE, "unknown precision");
+    if (prec != RP_FP64 && prec != RP_SPLIT_BF16 && prec != RP_SPLIT_BF16_X6)
+        return fail(ctx, RP_E_RANGE, "unknown precision");
     if (accumulate != 0 && accumulate != 1) return fail(ctx, RP_E_RANGE, "accumulate must be 0 or 1");
     const long npair = (long)(k1 - k0) * (e1 - e0) * (o1 - o0);
     if ((st = ensure(ctx, ctx->weights, sizeof(double2) * std::max(1L, npair) * nfreq)) != RP_OK) return st;
@@ -436,15 +447,18 @@ rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], 
         StageTimer t(ctx, RP_STAGE_CHI);
         launch_chi_f64(ctx->stream, npair, ng, (const double2 *)M, nfreq, w, accumulate, (double2 *)chi);
     } else {
+        const int nterm = prec == RP_SPLIT_BF16 ? 2 : 3;
         if ((st = ensure(ctx, ctx->split_a, split_a_bytes(npair, ng))) != RP_OK) return st;
         if ((st = ensure(ctx, ctx->split_b, split_b_bytes(npair, ng))) != RP_OK) return st;
+        if ((st = ensure(ctx, ctx->split_w, split_w_bytes(npair, nfreq))) != RP_OK) return st;
         {
             StageTimer t(ctx, RP_STAGE_PREP);
-            launch_split_prep(ctx->stream, npair, ng, (const double2 *)M, ctx->split_a.p, ctx->split_b.p);
+            launch_split_prep(ctx->stream, nterm, npair, ng, nfreq, (const double2 *)M, w, ctx->split_a.p,
+                              ctx->split_b.p, ctx->split_w.p);
         }
         StageTimer t(ctx, RP_STAGE_CHI);
-        launch_chi_bf16(ctx->stream, npair, ng, nfreq, w, accumulate, (double2 *)chi, ctx->split_a.p,
-                        ctx->split_b.p);
+        launch_chi_bf16(ctx->stream, nterm, npair, ng, nfreq, accumulate, (double2 *)chi, ctx->split_a.p,
+                        ctx->split_b.p, ctx->split_w.p);
     }
     return check_launch(ctx, "chi0 contraction");
 }
@@ -473,7 +487,7 @@ rp_status rp_screen_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int ng,
     double *vs = (double *)ctx->vsqrt.p;
     StageTimer t(ctx, RP_STAGE_SCREEN);
     launch_vsqrt(ctx->stream, g, ng, (const int *)ctx->glist.p, vs, ctx->flag);
-    launch_eps(ctx->stream, nfreq, ng, vs, (const double2 *)chi, a);
+    launch_eps(ctx->stream, nfreq, ng, vs, (const double2 *)chi, a, ctx->flag);
     launch_invert(ctx->stream, nfreq, ng, a, (double2 *)ctx->rho.p, (int *)ctx->piv.p, ctx->flag);
     if (W) launch_W(ctx->stream, nfreq, ng, vs, a, (double2 *)W);
     return check_launch(ctx, "screen");

@@ -54,6 +54,7 @@ struct rp_ctx {
     std::string err;
     int *flag = nullptr;            // device int[4] fault flags
     rp::DevBuf ugrid;               // u-grids of one k: [nO + nE][N1][N2][N3] c128
+    rp::DevBuf ugrid32;             // the same grids in FP32 (split-precision path)
     rp::DevBuf weights;             // w[nfreq][npair] c128
     rp::DevBuf glist;               // int[...] copies of host G lists
     rp::DevBuf freq;                // c128[nfreq]
@@ -62,6 +63,7 @@ struct rp_ctx {
     rp::DevBuf work;                // eps / inversion workspace
     rp::DevBuf split_a;             // split-BF16 row operand (FP32 complex)
     rp::DevBuf split_b;             // split-BF16 column operand (BF16 planes)
+    rp::DevBuf split_w;             // split-BF16 weights (FP32)
     rp::DevBuf rho;                 // Wannier densities
     rp::DevBuf piv;                 // pivots
     // stage timers
@@ -104,12 +106,13 @@ void launch_ugrid(hipStream_t s, const FftPlan plans[3], const int fft[3], const
 void launch_fft3d(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,
                   double2 *data);
 
-// pair.hip: pair densities of one k.
-size_t pair_lds_bytes(const int fft[3], int L3, int rows);
+// pair.hip: pair densities of one k (grids in FP64, or FP32 when fp32).
+size_t pair_lds_bytes(const int fft[3], int L3, int rows, size_t csize, int npairs);
 int pair_rows(const int fft[3]);
-void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], const double2 *u_occ,
-                   const double2 *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3],
-                   int lo3, int L3, double2 *M);
+void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], const void *u_occ,
+                   const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3],
+                   int lo3, int L3, bool fp32, double2 *M);
+void launch_to_f32(hipStream_t s, const double2 *in, void *out, long n);
 
 // tetra.hip: weights of a pair range.
 void launch_weights(hipStream_t s, const int kmesh[3], const int iq[3], int nband,
@@ -124,15 +127,16 @@ void launch_chi_f64(hipStream_t s, long npair, int ng, const double2 *M, int nfr
 // chi_bf16.hip: split-BF16 contraction.
 size_t split_a_bytes(long npair, int ng);
 size_t split_b_bytes(long npair, int ng);
-void launch_split_prep(hipStream_t s, long npair, int ng, const double2 *M, void *split_a,
-                       void *split_b);
-void launch_chi_bf16(hipStream_t s, long npair, int ng, int nfreq, const double2 *w,
-                     int accumulate, double2 *chi, const void *split_a, const void *split_b);
+size_t split_w_bytes(long npair, int nfreq);
+void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, const double2 *M,
+                       const double2 *w, void *split_a, void *split_b, void *split_w);
+void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, int accumulate,
+                     double2 *chi, const void *split_a, const void *split_b, const void *split_w);
 
 // screen.hip
 void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, double *vs, int *flag);
 void launch_eps(hipStream_t s, int nfreq, int ng, const double *vs, const double2 *chi,
-                double2 *eps);
+                double2 *eps, int *flag);
 void launch_invert(hipStream_t s, int nfreq, int ng, double2 *a, double2 *col, int *piv,
                    int *flag);
 void launch_W(hipStream_t s, int nfreq, int ng, const double *vs, const double2 *einv,

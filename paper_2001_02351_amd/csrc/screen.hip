@@ -38,7 +38,7 @@ __global__ void k_vsqrt(int ng, const int *g, double r0, double r1, double r2, d
     if (!(qg > 0.0)) atomicOr(flag, kFlagNonFinite);
 }
 
-__global__ void k_eps(int nfreq, int ng, const double *vs, const double2 *chi, double2 *eps)
+__global__ void k_eps(int nfreq, int ng, const double *vs, const double2 *chi, double2 *eps, int *flag)
 {
     const long n2 = (long)ng * ng;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -47,6 +47,7 @@ __global__ void k_eps(int nfreq, int ng, const double *vs, const double2 *chi, d
     const int g = (int)(e / ng), h = (int)(e - (long)g * ng);
     const double s = vs[g] * vs[h];
     const double2 c = chi[t];
+    if (!isfinite(c.x) || !isfinite(c.y)) atomicOr(flag, kFlagNonFinite);
     eps[t] = make_double2((g == h ? 1.0 : 0.0) - s * c.x, -s * c.y);
 }
 
@@ -159,11 +160,12 @@ void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, dou
                        (double)g.iq[2] / g.kmesh[2], pref, vs, flag);
 }
 
-void launch_eps(hipStream_t s, int nfreq, int ng, const double *vs, const double2 *chi, double2 *eps)
+void launch_eps(hipStream_t s, int nfreq, int ng, const double *vs, const double2 *chi, double2 *eps,
+                int *flag)
 {
     const long tot = (long)nfreq * ng * ng;
     hipLaunchKernelGGL(k_eps, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nfreq, ng, vs, chi,
-                       eps);
+                       eps, flag);
 }
 
 void launch_invert(hipStream_t s, int nfreq, int ng, double2 *a, double2 *col, int *piv, int *flag)

@@ -44,7 +44,8 @@ def weight_mode(prob) -> int:
     return _rp.RP_W_SAMPLING if int(np.prod(prob.kmesh)) == 1 else _rp.RP_W_TETRA
 
 
-def pair_density(ctx, d: DeviceInputs, k0: int, k1: int, o=None, e=None, out=None):
+def pair_density(ctx, d: DeviceInputs, k0: int, k1: int, o=None, e=None, out=None,
+                 prec: int = _rp.RP_FP64):
     import torch
     p = d.prob
     o0, o1 = o if o else (0, p.nocc)
@@ -53,7 +54,7 @@ def pair_density(ctx, d: DeviceInputs, k0: int, k1: int, o=None, e=None, out=Non
     if out is None:
         out = torch.empty((npair, d.ng, 2), dtype=torch.float64, device=d.device)
     _rp.rp_pair_density(ctx, d.cell, p.iq, d.nband, p.miller.shape[1], p.npw, d.mmax, d.miller, d.coef,
-                        o0, o1, e0, e1, k0, k1, d.ng, p.gsph, out)
+                        o0, o1, e0, e1, k0, k1, d.ng, p.gsph, prec, out)
     return out
 
 
@@ -84,7 +85,7 @@ def chi0(ctx, d: DeviceInputs, prec: int = _rp.RP_FP64, kbatch: int = 1, k0: int
     for ka in range(k0, k1, kbatch):
         kb = min(k1, ka + kbatch)
         M = Mbuf[: (kb - ka) * npk]
-        pair_density(ctx, d, ka, kb, out=M)
+        pair_density(ctx, d, ka, kb, out=M, prec=prec)
         _rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, d.T, 0, p.nocc, p.nocc,
                                p.nocc + p.nemp, ka, kb, d.ng, M, d.nfreq, p.freq_eV, p.delta_eV,
                                weight_mode(p), prec, 0 if first else 1, chi)

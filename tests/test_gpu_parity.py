@@ -69,6 +69,9 @@ def test_pair_density_matches_oracle(ctx, c1, d1):
     want = oracle.pair_densities(p, *o, *e, *k)
     assert M2.shape == want.shape
     assert _rel(M2, want) < 1e-12
+    # FP32 grids (split-precision path)
+    M3 = path.to_complex(path.pair_density(ctx, d1, *k, o=o, e=e, prec=1))
+    assert _rel(M3, want) < 2e-6
 
 
 def test_weights_match_oracle(ctx, rp, c1, d1):
@@ -162,16 +165,16 @@ def test_abi_errors(ctx, rp, c1, d1):
     small = rp.make_cell(p.lat, (10, 10, 10), p.kmesh)
     with pytest.raises(rp.RpError) as e:
         rp.rp_pair_density(ctx, small, p.iq, d.nband, p.miller.shape[1], p.npw, d.mmax, d.miller,
-                           d.coef, 0, p.nocc, p.nocc, p.nband, 0, 1, p.ng, p.gsph, M)
+                           d.coef, 0, p.nocc, p.nocc, p.nband, 0, 1, p.ng, p.gsph, 0, M)
     assert e.value.status == 4            # RP_E_ALIAS
     odd = rp.make_cell(p.lat, (16, 16, 14), p.kmesh)
     with pytest.raises(rp.RpError) as e:
         rp.rp_pair_density(ctx, odd, p.iq, d.nband, p.miller.shape[1], p.npw, d.mmax, d.miller,
-                           d.coef, 0, p.nocc, p.nocc, p.nband, 0, 1, p.ng, p.gsph, M)
+                           d.coef, 0, p.nocc, p.nocc, p.nband, 0, 1, p.ng, p.gsph, 0, M)
     assert e.value.status == 8            # RP_E_UNSUPPORTED (factor 7)
     with pytest.raises(rp.RpError) as e:
         rp.rp_pair_density(ctx, d.cell, p.iq, d.nband, p.miller.shape[1], p.npw, d.mmax, d.miller,
-                           d.coef, 0, p.nocc + 1, p.nocc, p.nband + 2, 0, 1, p.ng, p.gsph, M)
+                           d.coef, 0, p.nocc + 1, p.nocc, p.nband + 2, 0, 1, p.ng, p.gsph, 0, M)
     assert e.value.status == 2            # RP_E_SHAPE
     chi = torch.zeros((1, 4, 4, 2), dtype=torch.float64, device="cuda")
     g_with_zero = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], np.int32)
