@@ -12,6 +12,7 @@ Inputs are resident in HBM before the timed region.
                 (P = 4 096 000 pairs) and t_chi0 the wall time of the pair
                 densities + weights + contraction of one q-point
   fp64          the same for the FP64 path
+  split_bf16_x6 the six-product (hi/mid/lo) split form
   roofline      the chi contraction kernel of the split path: algorithmic
                 flops per launch / its mean launch time (HIP events on the
                 library's stream) against the BF16 dense peak
@@ -129,6 +130,7 @@ def main():
     ap.add_argument("--fp64-warmup", type=int, default=0)
     ap.add_argument("--kbatch", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-x6", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -167,6 +169,9 @@ def main():
     chi_s = chi_s.clone()
     einv_s = einv_s.clone()
     wij_s = wij_s.clone()
+    x6 = None
+    if not args.no_x6:
+        x6, _, _, _ = run_leg(rp, path, ctx, d, rp.RP_SPLIT_BF16_X6, 1, 0, args.kbatch)
     fp64 = None
     agree = None
     if not args.no_fp64:
@@ -208,11 +213,12 @@ def main():
             "ng": d.ng,
             "nfreq": d.nfreq,
             "kbatch": args.kbatch,
-            "precision": "split-BF16 chi0 (3 BF16 terms, 6 products, FP32 accumulation, FP64 sum), "
-                         "FP64 weights, eps^-1 and W_ij",
+            "precision": "split-BF16 chi0 (hi/mid BF16 terms, three-term compensated products, FP32 "
+                         "accumulation, FP64 sum; FP32 pair-density grids), FP64 weights, eps^-1 and W_ij",
         },
         "s_per_qpoint": split["s_per_qpoint"],
         "split_bf16": split,
+        "split_bf16_x6": x6,
         "fp64": fp64,
         "split_vs_fp64_rel": agree,
         "roofline": {
@@ -223,7 +229,7 @@ def main():
             "frac": achieved / PEAK_BF16_TFLOPS,
             "traffic": None,
             "kernel": "k_chi_bf16 (chi0 contraction, split-BF16)",
-            "mfma_executed_frac": 6.0 * achieved / PEAK_BF16_TFLOPS,
+            "mfma_executed_frac": 3.0 * achieved / PEAK_BF16_TFLOPS,
         },
         "cpu_baseline": None if baseline is None else {k: baseline[k] for k in
                                                         ("value", "unit", "cores", "kind", "sample")},
