@@ -155,7 +155,7 @@ k_pair_reg(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int
 
     C *tw1 = smem;
     C *twN = tw1 + N1;
-    C *buf[2] = {twN + N, twN + N + (size_t)NP * N * L3};   // [NP][N][L3] each
+    C *buf0 = twN + N;                                       // two [NP][N][L3] windows
     fill_twiddles(tw1, N1, tid, 256);
     fill_twiddles(twN, N, tid, 256);
 
@@ -178,7 +178,7 @@ k_pair_reg(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int
     __syncthreads();
 
     for (int j1 = 0; j1 < N1; j1++) {
-        C *B = buf[j1 & 1];
+        C *B = buf0 + (size_t)(j1 & 1) * NP * N * L3;
         // (A) rows along j3
         for (int L = tid; L < NP * N; L += 256) {
             const int q = L / N, j2 = L - q * N;
@@ -240,6 +240,189 @@ k_pair_reg(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int
             if (g < ng) out[g] = make_double2((double)acc[q][t].x * inv, (double)acc[q][t].y * inv);
         }
     }
+}
+
+// Workgroup barrier over LDS only: waits for this wave's LDS operations, not
+// for global-to-LDS DMAs still in flight (which __syncthreads would drain).
+__device__ __forceinline__ void lds_sync()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// widest m3 window the quad form holds in LDS
+template <int N> constexpr int quad_l3max() { return N >= 48 ? N / 2 : N; }
+
+// Quad-FFT form (FP32), the path for N2 = N3 in {16, 24, 32, 48}.  Per plane
+// j1: (A) each quad of lanes (pair q, row j2) forms the product row and
+// transforms it along j3 (quad_fft: every lane holds a quarter of the line),
+// keeping the m3 window; (B) each quad (q, column t3) transforms along j2 in
+// place; (C) every sphere point accumulates its j1 phase in registers.  All
+// four waves share phases A and B evenly, and a lane holds N/4 points of a
+// line instead of N, which leaves room for the sphere accumulators.
+// The rows of plane j1+1 stream into LDS by global_load_lds (one row per
+// instruction; the row stride N+4 puts the quads of neighbouring rows on
+// different banks) while phases B and C of plane j1 run.  The DMA target and
+// the two m3-window buffers are separate LDS objects (planes are processed in
+// pairs, so each window is fixed at compile time): the compiler can then see
+// that phases B and C never read what the DMA writes, and the barriers inside
+// a plane are LDS-only, so the DMA is waited for once per plane.
+template <int N, int NA, int NB, int MAXG>
+__global__ void __launch_bounds__(256)
+k_pair_quad(const float2 *__restrict__ u_occ, const float2 *__restrict__ u_emp, int nO, int nE, int N1, int ng,
+            const int *__restrict__ gsph, int g01, int g02, int g03, int lo3, int L3, double2 *__restrict__ M)
+{
+    typedef float2 C;
+    constexpr int Q = N / 4, NP = NA * NB, NG = NA + NB;
+    constexpr int LD = N + 4;                 // row stride (complex), a multiple of 16 bytes
+    constexpr int LPR = N / 2;                // DMA lanes per row, 16 bytes each
+    constexpr int L3M = quad_l3max<N>();
+    constexpr int TA = (NP * N + 63) / 64;    // phase-A lines per quad
+    __shared__ __attribute__((aligned(16))) C raw[NG * N * LD];   // [NG][N][LD]
+    __shared__ C win0[NP * N * L3M];                              // [NP][N][L3]
+    __shared__ C win1[NP * N * L3M];
+    __shared__ C tw1[256];
+    __shared__ C twN[N];
+    __shared__ C twQ[Q];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int s = tid & 3, quad = tid >> 2, r = quad_row(s);
+    const int nbB = (nO + NB - 1) / NB;
+    const int a0 = (blockIdx.x / nbB) * NA, b0 = (blockIdx.x % nbB) * NB;
+    const long nr = (long)N1 * N * N;
+    fill_twiddles(tw1, N1, tid, 256);
+    fill_twiddles(twN, N, tid, 256);
+    fill_twiddles(twQ, Q, tid, 256);
+
+    const C *grid[NG];
+#pragma unroll
+    for (int i = 0; i < NA; i++) grid[i] = u_emp + (long)min(a0 + i, nE - 1) * nr;
+#pragma unroll
+    for (int i = 0; i < NB; i++) grid[NA + i] = u_occ + (long)min(b0 + i, nO - 1) * nr;
+    // rows j2 = wave, wave + 4, ... of every grid of one plane (the grid index
+    // is a compile-time constant, so the row addresses stay in registers and
+    // the DMAs are issued back to back)
+    auto issue = [&](int j1) {
+#pragma unroll
+        for (int gi = 0; gi < NG; gi++) {
+            const C *src = grid[gi] + (long)j1 * N * N + lane * 2;
+            C *dst = raw + (size_t)gi * N * LD;
+            for (int j2 = wave; j2 < N; j2 += 4)
+                if (lane < LPR)
+                    __builtin_amdgcn_global_load_lds(src + j2 * N,
+                                                     (__attribute__((address_space(3))) void *)(dst + j2 * LD), 16, 0,
+                                                     0);
+        }
+    };
+
+    C acc[NP][MAXG];
+    int cidx[MAXG], step1[MAXG], ph[MAXG];
+#pragma unroll
+    for (int t = 0; t < MAXG; t++) {
+        const int g = tid + t * 256;
+#pragma unroll
+        for (int q = 0; q < NP; q++) acc[q][t] = mkc<C>(0, 0);
+        cidx[t] = 0;
+        step1[t] = 0;
+        ph[t] = 0;
+        if (g < ng) {
+            const int m1 = gsph[3 * g] + g01, m2 = gsph[3 * g + 1] + g02, m3 = gsph[3 * g + 2] + g03;
+            cidx[t] = pmod(m2, N) * L3 + (m3 - lo3);
+            step1[t] = pmod(m1, N1);
+        }
+    }
+    issue(0);
+
+    auto plane = [&](int j1, C *B) {
+        __builtin_amdgcn_s_waitcnt(0);       // this wave's DMAs of plane j1
+        __syncthreads();                     // ... and everybody else's
+        // (A) product rows along j3
+#pragma unroll
+        for (int it = 0; it < TA; it++) {
+            const int task = quad + 64 * it;
+            if (task < NP * N) {
+                const int q = task / N, j2 = task - q * N;
+                const C *ra = raw + (size_t)((q / NB) * N + j2) * LD + s;
+                const C *rb = raw + (size_t)((NA + q % NB) * N + j2) * LD + s;
+                C x[Q];
+#pragma unroll
+                for (int n = 0; n < Q; n++) x[n] = cmulc(ra[4 * n], rb[4 * n]);
+                quad_fft<Q>(x, twQ, twN, s);
+                C *dst = B + ((size_t)q * N + j2) * L3;
+#pragma unroll
+                for (int k = 0; k < Q; k++) {
+                    int t3 = Q * r + k - lo3;
+                    t3 = t3 < 0 ? t3 + N : (t3 >= N ? t3 - N : t3);
+                    if (t3 < L3) dst[t3] = x[k];
+                }
+            }
+        }
+        lds_sync();
+        // every row of plane j1 has been read: stream in plane j1 + 1
+        if (j1 + 1 < N1) issue(j1 + 1);
+        // (B) columns along j2, in place (a quad reads its whole column
+        // before any of its lanes writes)
+        for (int task = quad; task < NP * L3; task += 64) {
+            const int qq = task / L3, t3 = task - qq * L3;
+            C *col = B + (size_t)qq * N * L3 + t3;
+            C y[Q];
+#pragma unroll
+            for (int n = 0; n < Q; n++) y[n] = col[(4 * n + s) * L3];
+            quad_fft<Q>(y, twQ, twN, s);
+#pragma unroll
+            for (int k = 0; k < Q; k++) col[(Q * r + k) * L3] = y[k];
+        }
+        lds_sync();
+        // (C) sphere points
+#pragma unroll
+        for (int t = 0; t < MAXG; t++) {
+            const int g = tid + t * 256;
+            if (g < ng) {
+                const C e = tw1[ph[t]];
+#pragma unroll
+                for (int qq = 0; qq < NP; qq++) {
+                    const C v = B[(size_t)qq * N * L3 + cidx[t]];
+                    acc[qq][t].x += v.x * e.x - v.y * e.y;
+                    acc[qq][t].y += v.x * e.y + v.y * e.x;
+                }
+                ph[t] += step1[t];
+                if (ph[t] >= N1) ph[t] -= N1;
+            }
+        }
+    };
+    // window j1 & 1 is rewritten by phase A of plane j1 + 2, which every
+    // thread starts only after the barriers of plane j1 + 1
+    for (int j1 = 0; j1 < N1; j1 += 2) {
+        plane(j1, win0);
+        if (j1 + 1 < N1) plane(j1 + 1, win1);
+    }
+    const double inv = 1.0 / (double)nr;
+#pragma unroll
+    for (int qq = 0; qq < NP; qq++) {
+        const int a = a0 + qq / NB, b = b0 + qq % NB;
+        if (a >= nE || b >= nO) continue;
+        double2 *out = M + ((long)a * nO + b) * ng;
+#pragma unroll
+        for (int t = 0; t < MAXG; t++) {
+            const int g = tid + t * 256;
+            if (g < ng) out[g] = make_double2((double)acc[qq][t].x * inv, (double)acc[qq][t].y * inv);
+        }
+    }
+}
+
+template <int N, int NA, int NB>
+void launch_pair_quad(hipStream_t s, int N1, const float2 *u_occ, const float2 *u_emp, int nO, int nE, int ng,
+                      const int *gsph, const int g0[3], int lo3, int L3, double2 *M)
+{
+    const unsigned nblk = (unsigned)(((nE + NA - 1) / NA) * ((nO + NB - 1) / NB));
+#define RP_PAIRQ(G)                                                                                          \
+    hipLaunchKernelGGL((k_pair_quad<N, NA, NB, G>), dim3(nblk), dim3(256), 0, s, u_occ, u_emp, nO, nE, N1,   \
+                       ng, gsph, g0[0], g0[1], g0[2], lo3, L3, M)
+    if (ng <= 512) RP_PAIRQ(2);
+    else if (ng <= 1024) RP_PAIRQ(4);
+    else RP_PAIRQ(8);
+#undef RP_PAIRQ
 }
 
 template <typename C, int N, int NA, int NB>
@@ -304,10 +487,34 @@ bool pair_reg_supported(const int fft[3], int ng, bool fp32)
     }
 }
 
+// the quad form: N2 = N3 in {16, 24, 32, 48}, N1 <= 256, ng <= 2048, and the
+// m3 window within its LDS plan
+static bool pair_quad_supported(const int fft[3], int ng, int L3)
+{
+    if (fft[0] > 256 || fft[1] != fft[2] || ng > 2048) return false;
+    switch (fft[1]) {
+    case 16: return L3 <= quad_l3max<16>();
+    case 24: return L3 <= quad_l3max<24>();
+    case 32: return L3 <= quad_l3max<32>();
+    case 48: return L3 <= quad_l3max<48>();
+    default: return false;
+    }
+}
+
 void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], const void *u_occ,
                    const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3], int lo3,
                    int L3, bool fp32, double2 *M)
 {
+    if (fp32 && pair_quad_supported(fft, ng, L3)) {
+        const float2 *uo = (const float2 *)u_occ, *ue = (const float2 *)u_emp;
+        switch (fft[1]) {
+        case 16: launch_pair_quad<16, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+        case 24: launch_pair_quad<24, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+        case 32: launch_pair_quad<32, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+        case 48: launch_pair_quad<48, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+        default: break;
+        }
+    }
     if (pair_reg_supported(fft, ng, fp32)) {
 #define RP_REG(NN)                                                                                             \
     case NN:                                                                                                 \

@@ -345,6 +345,7 @@ rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int
     double2 *u_occ = (double2 *)ctx->ugrid.p;
     double2 *u_emp = u_occ + nr * nO;
     const int *dg = (const int *)ctx->glist.p;
+    const int L3 = hi[2] - lo[2] + 1;
     for (int k = k0; k < k1; k++) {
         const int n1 = k / (g.kmesh[1] * g.kmesh[2]), n2 = (k / g.kmesh[2]) % g.kmesh[1], n3 = k % g.kmesh[2];
         const int s[3] = {n1 + iq[0], n2 + iq[1], n3 + iq[2]};
@@ -363,7 +364,7 @@ rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int
                          cf + ((long)kp * nband + e0) * npw_max, npw_max, u_emp);
             if (fp32) launch_to_f32(ctx->stream, u_occ, ctx->ugrid32.p, nr * (nO + nE));
         }
-        const int lo3 = lo[2] + g0[2], L3 = hi[2] - lo[2] + 1;
+        const int lo3 = lo[2] + g0[2];
         double2 *Mk = (double2 *)M + (long)(k - k0) * nE * nO * ng;
         {
             StageTimer t(ctx, RP_STAGE_PAIR);
