@@ -255,12 +255,14 @@ template <int N, typename C> __device__ __forceinline__ void reg_fft(C (&a)[N], 
 
 // ---------------------------------------------------------------------------
 // Quad FFT: a line of length N = 4Q spread over the four lanes of a quad
-// (lanes 4i .. 4i+3 of a wave, all active together).  Lane s holds the
-// decimated inputs x[4n + s], n < Q.  With Y_s the length-Q transform of lane
-// s's inputs, the output X[k + Q r] = sum_s i^{r s} e^{2 pi i s k/N} Y_s[k]
-// is a 4-point DFT across the quad for every k, done as two radix-2 steps with
-// DPP quad permutations (lane xor 2, then lane xor 1).  On return lane s
-// holds X[Q qrow(s) + k] in x[k], with qrow(s) = (s >> 1) | ((s & 1) << 1).
+// (lanes 4i .. 4i+3 of a wave, all active together), decimated in frequency.
+// Lane s holds the contiguous inputs x[Q s + n], n < Q.  Writing the output
+// index as 4k + r,
+//     X[4k + r] = sum_n e^{2 pi i k n/Q} e^{2 pi i r n/N} sum_s i^{r s} x[Q s + n],
+// so a 4-point DFT across the quad (two radix-2 steps with DPP quad
+// permutations: lane xor 2, then lane xor 1) comes first, then a twiddle and
+// a length-Q transform inside each lane.  On return lane s holds
+// X[4k + qrow(s)] in x[k], with qrow(s) = (s >> 1) | ((s & 1) << 1).
 
 __device__ __forceinline__ int quad_row(int s) { return (s >> 1) | ((s & 1) << 1); }
 
@@ -269,27 +271,33 @@ template <int CTRL> __device__ __forceinline__ float quad_perm(float v)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// twQ[t] = e^{2 pi i t/Q}, t < Q; twN[t] = e^{2 pi i t/N}, t < N
-template <int Q>
-__device__ __forceinline__ void quad_fft(float2 (&x)[Q], const float2 *twQ, const float2 *twN, int s)
+// y_r = sum_s i^{r s} v_s across the quad; lane s ends with r = qrow(s)
+template <int Q> __device__ __forceinline__ void quad_dft4(float2 (&x)[Q], int s)
 {
-    reg_fft<Q>(x, twQ);
-#pragma unroll
-    for (int k = 1; k < Q; k++) x[k] = cmul(x[k], twN[s * k]);
     // step 1, partner s ^ 2: lanes with bit 1 clear keep own + partner, the
-    // others partner - own
+    // others partner - own; step 2, partner s ^ 1, after lane 3 (odd s, r
+    // bit 0 set) has multiplied its value by i
     const float sg1 = (s & 2) ? -1.f : 1.f, sg0 = (s & 1) ? -1.f : 1.f;
-    const bool rot = s == 3;   // lane holding the odd-s half with r0 = 1: times i
+    const bool rot = s == 3;
 #pragma unroll
     for (int k = 0; k < Q; k++) {
         const float px = quad_perm<0x4E>(x[k].x), py = quad_perm<0x4E>(x[k].y);
-        float vx = px + sg1 * x[k].x, vy = py + sg1 * x[k].y;
+        const float vx = px + sg1 * x[k].x, vy = py + sg1 * x[k].y;
         const float rx = rot ? -vy : vx, ry = rot ? vx : vy;
-        // step 2, partner s ^ 1
         const float qx = quad_perm<0xB1>(rx), qy = quad_perm<0xB1>(ry);
         x[k] = make_float2(qx + sg0 * rx, qy + sg0 * ry);
     }
 }
 
+// twQ[t] = e^{2 pi i t/Q}, t < Q; twN[t] = e^{2 pi i t/N}, t < N
+template <int Q>
+__device__ __forceinline__ void quad_fft(float2 (&x)[Q], const float2 *twQ, const float2 *twN, int s)
+{
+    quad_dft4<Q>(x, s);
+    const int r = quad_row(s);
+#pragma unroll
+    for (int n = 1; n < Q; n++) x[n] = cmul(x[n], twN[r * n]);
+    reg_fft<Q>(x, twQ);
+}
 
 }  // namespace rp

@@ -256,37 +256,32 @@ __device__ __forceinline__ void lds_sync()
 template <int N> constexpr int quad_l3max() { return N >= 48 ? N / 2 : N; }
 
 // Quad-FFT form (FP32), the path for N2 = N3 in {16, 24, 32, 48}.  Per plane
-// j1: (A) each quad of lanes (pair q, row j2) forms the product row and
-// transforms it along j3 (quad_fft: every lane holds a quarter of the line),
-// keeping the m3 window; (B) each quad (q, column t3) transforms along j2 in
-// place; (C) every sphere point accumulates its j1 phase in registers.  All
-// four waves share phases A and B evenly, and a lane holds N/4 points of a
-// line instead of N, which leaves room for the sphere accumulators.
-// The rows of plane j1+1 stream into LDS by global_load_lds (one row per
-// instruction; the row stride N+4 puts the quads of neighbouring rows on
-// different banks) while phases B and C of plane j1 run.  The DMA target and
-// the two m3-window buffers are separate LDS objects (planes are processed in
-// pairs, so each window is fixed at compile time): the compiler can then see
-// that phases B and C never read what the DMA writes, and the barriers inside
-// a plane are LDS-only, so the DMA is waited for once per plane.
+// j1: (A) each quad of lanes (pair q, row j2) loads its two grid rows (each
+// lane a contiguous quarter, in 16-byte loads), forms the product and
+// transforms it along j3 (quad_fft), keeping the m3 window; (B) each quad
+// (q, column t3) transforms along j2 in place; (C) every sphere point
+// accumulates its j1 phase in registers.  All four waves share phases A and B
+// evenly, and a lane holds N/4 points of a line instead of N, which leaves
+// room for the sphere accumulators.  The two m3-window buffers alternate
+// between planes, so phase A of plane j1+1 may start while other waves still
+// read plane j1's window in phase C: two barriers per plane.  LDS stays under
+// half a CU's, so two workgroups share a CU and cover each other's load and
+// barrier waits.
 template <int N, int NA, int NB, int MAXG>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_pair_quad(const float2 *__restrict__ u_occ, const float2 *__restrict__ u_emp, int nO, int nE, int N1, int ng,
             const int *__restrict__ gsph, int g01, int g02, int g03, int lo3, int L3, double2 *__restrict__ M)
 {
     typedef float2 C;
-    constexpr int Q = N / 4, NP = NA * NB, NG = NA + NB;
-    constexpr int LD = N + 4;                 // row stride (complex), a multiple of 16 bytes
-    constexpr int LPR = N / 2;                // DMA lanes per row, 16 bytes each
+    constexpr int Q = N / 4, NP = NA * NB;
     constexpr int L3M = quad_l3max<N>();
     constexpr int TA = (NP * N + 63) / 64;    // phase-A lines per quad
-    __shared__ __attribute__((aligned(16))) C raw[NG * N * LD];   // [NG][N][LD]
-    __shared__ C win0[NP * N * L3M];                              // [NP][N][L3]
+    __shared__ C win0[NP * N * L3M];          // [NP][N][L3]
     __shared__ C win1[NP * N * L3M];
     __shared__ C tw1[256];
     __shared__ C twN[N];
     __shared__ C twQ[Q];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x;
     const int s = tid & 3, quad = tid >> 2, r = quad_row(s);
     const int nbB = (nO + NB - 1) / NB;
     const int a0 = (blockIdx.x / nbB) * NA, b0 = (blockIdx.x % nbB) * NB;
@@ -294,27 +289,6 @@ k_pair_quad(const float2 *__restrict__ u_occ, const float2 *__restrict__ u_emp, 
     fill_twiddles(tw1, N1, tid, 256);
     fill_twiddles(twN, N, tid, 256);
     fill_twiddles(twQ, Q, tid, 256);
-
-    const C *grid[NG];
-#pragma unroll
-    for (int i = 0; i < NA; i++) grid[i] = u_emp + (long)min(a0 + i, nE - 1) * nr;
-#pragma unroll
-    for (int i = 0; i < NB; i++) grid[NA + i] = u_occ + (long)min(b0 + i, nO - 1) * nr;
-    // rows j2 = wave, wave + 4, ... of every grid of one plane (the grid index
-    // is a compile-time constant, so the row addresses stay in registers and
-    // the DMAs are issued back to back)
-    auto issue = [&](int j1) {
-#pragma unroll
-        for (int gi = 0; gi < NG; gi++) {
-            const C *src = grid[gi] + (long)j1 * N * N + lane * 2;
-            C *dst = raw + (size_t)gi * N * LD;
-            for (int j2 = wave; j2 < N; j2 += 4)
-                if (lane < LPR)
-                    __builtin_amdgcn_global_load_lds(src + j2 * N,
-                                                     (__attribute__((address_space(3))) void *)(dst + j2 * LD), 16, 0,
-                                                     0);
-        }
-    };
 
     C acc[NP][MAXG];
     int cidx[MAXG], step1[MAXG], ph[MAXG];
@@ -332,35 +306,36 @@ k_pair_quad(const float2 *__restrict__ u_occ, const float2 *__restrict__ u_emp, 
             step1[t] = pmod(m1, N1);
         }
     }
-    issue(0);
+    __syncthreads();
 
     auto plane = [&](int j1, C *B) {
-        __builtin_amdgcn_s_waitcnt(0);       // this wave's DMAs of plane j1
-        __syncthreads();                     // ... and everybody else's
         // (A) product rows along j3
-#pragma unroll
+#pragma unroll 1
         for (int it = 0; it < TA; it++) {
             const int task = quad + 64 * it;
             if (task < NP * N) {
                 const int q = task / N, j2 = task - q * N;
-                const C *ra = raw + (size_t)((q / NB) * N + j2) * LD + s;
-                const C *rb = raw + (size_t)((NA + q % NB) * N + j2) * LD + s;
+                const long off = ((long)j1 * N + j2) * N + Q * s;
+                const float4 *ra = (const float4 *)(u_emp + (long)min(a0 + q / NB, nE - 1) * nr + off);
+                const float4 *rb = (const float4 *)(u_occ + (long)min(b0 + q % NB, nO - 1) * nr + off);
                 C x[Q];
 #pragma unroll
-                for (int n = 0; n < Q; n++) x[n] = cmulc(ra[4 * n], rb[4 * n]);
+                for (int n = 0; n < Q / 2; n++) {
+                    const float4 va = ra[n], vb = rb[n];
+                    x[2 * n] = cmulc(make_float2(va.x, va.y), make_float2(vb.x, vb.y));
+                    x[2 * n + 1] = cmulc(make_float2(va.z, va.w), make_float2(vb.z, vb.w));
+                }
                 quad_fft<Q>(x, twQ, twN, s);
                 C *dst = B + ((size_t)q * N + j2) * L3;
 #pragma unroll
                 for (int k = 0; k < Q; k++) {
-                    int t3 = Q * r + k - lo3;
+                    int t3 = 4 * k + r - lo3;
                     t3 = t3 < 0 ? t3 + N : (t3 >= N ? t3 - N : t3);
                     if (t3 < L3) dst[t3] = x[k];
                 }
             }
         }
         lds_sync();
-        // every row of plane j1 has been read: stream in plane j1 + 1
-        if (j1 + 1 < N1) issue(j1 + 1);
         // (B) columns along j2, in place (a quad reads its whole column
         // before any of its lanes writes)
         for (int task = quad; task < NP * L3; task += 64) {
@@ -368,10 +343,10 @@ k_pair_quad(const float2 *__restrict__ u_occ, const float2 *__restrict__ u_emp, 
             C *col = B + (size_t)qq * N * L3 + t3;
             C y[Q];
 #pragma unroll
-            for (int n = 0; n < Q; n++) y[n] = col[(4 * n + s) * L3];
+            for (int n = 0; n < Q; n++) y[n] = col[(Q * s + n) * L3];
             quad_fft<Q>(y, twQ, twN, s);
 #pragma unroll
-            for (int k = 0; k < Q; k++) col[(Q * r + k) * L3] = y[k];
+            for (int k = 0; k < Q; k++) col[(4 * k + r) * L3] = y[k];
         }
         lds_sync();
         // (C) sphere points
@@ -421,6 +396,7 @@ void launch_pair_quad(hipStream_t s, int N1, const float2 *u_occ, const float2 *
                        ng, gsph, g0[0], g0[1], g0[2], lo3, L3, M)
     if (ng <= 512) RP_PAIRQ(2);
     else if (ng <= 1024) RP_PAIRQ(4);
+    else if (ng <= 1536) RP_PAIRQ(6);
     else RP_PAIRQ(8);
 #undef RP_PAIRQ
 }
