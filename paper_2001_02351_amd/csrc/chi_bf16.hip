@@ -140,16 +140,16 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     // blocks and its NPL x 2 B half-rows
     const float2 *srcA = Ap + ((long)wave * (NGP / 16) + rt0 / 16) * 128 + lane * 2;
     const bf8 *srcB = Bp + (long)wave * NGP + ct0 + lane;
-    auto issue = [&](int stg, int kg0) {
+    auto issue = [&](float2 *dA, bf8 *dB, int kg0) {
         const float2 *a = srcA + (long)kg0 * (NGP / 16) * 128;
-        float2 *da = sA[stg] + wave * 8 * 128;
+        float2 *da = dA + wave * 8 * 128;
 #pragma unroll
         for (int rb = 0; rb < 8; rb++) dma16(a + rb * 128, da + rb * 128);
         const bf8 *b = srcB + (long)kg0 * NGP;
 #pragma unroll
         for (int sp = 0; sp < NPL; sp++)
 #pragma unroll
-            for (int h = 0; h < 2; h++) dma16(b + sp * plane + 64 * h, sB[stg] + (sp * 4 + wave) * 128 + 64 * h);
+            for (int h = 0; h < 2; h++) dma16(b + sp * plane + 64 * h, dB + (sp * 4 + wave) * 128 + 64 * h);
     };
     auto wload = [&](int step, float2 (&dst)[NW][8]) {
 #pragma unroll
@@ -176,23 +176,24 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
                 accI[iw][rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
             }
 
-    float2 wcur[NW][8];
-    if (nstep > 0) issue(0, 0);
-    for (int t = 0; t < nstep; t++) {
-        const int stg = t & 1;
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (t + 1 < nstep) issue(stg ^ 1, 4 * (t + 1));
-        wload(t, wcur);
+    // One step: issue the DMA of the next step into the other stage and
+    // compute the current one.  The stage pointers are restrict-qualified
+    // parameters, so the compiler knows that the current stage's LDS reads do
+    // not touch what the DMA writes and leaves the DMA in flight during the
+    // matrix-core work (with plain indexing of one array it would wait for
+    // the DMA before the first LDS read).
+    auto step = [&](float2 *__restrict__ nA, bf8 *__restrict__ nB, const float2 *__restrict__ cA,
+                    const bf8 *__restrict__ cB, int kgn, const float2 (&wcur)[NW][8]) {
+        if (kgn >= 0) issue(nA, nB, kgn);
         // column operand: 4 blocks x NPL planes
         bf8 B[4][NPL];
 #pragma unroll
         for (int cb = 0; cb < 4; cb++)
 #pragma unroll
-            for (int sp = 0; sp < NPL; sp++) B[cb][sp] = sB[stg][(sp * 4 + lk) * 128 + wc * 64 + cb * 16 + li];
+            for (int sp = 0; sp < NPL; sp++) B[cb][sp] = cB[(sp * 4 + lk) * 128 + wc * 64 + cb * 16 + li];
 #pragma unroll
         for (int rb = 0; rb < 4; rb++) {
-            const float2 *blk = sA[stg] + (lk * 8 + wr * 4 + rb) * 128 + li * 2;
+            const float2 *blk = cA + (lk * 8 + wr * 4 + rb) * 128 + li * 2;
             float2 araw[8];
 #pragma unroll
             for (int q = 0; q < 4; q++) {
@@ -255,6 +256,27 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
                 }
             }
         }
+    };
+
+    // The weights of step t+1 are loaded into registers before the DMA of
+    // step t+1 is issued: they are waited for at the top of the next step,
+    // together with that DMA, so no wait inside a step covers the DMA.
+    float2 wcur[NW][8], wnext[NW][8];
+    if (nstep > 0) {
+        wload(0, wnext);
+        issue(sA[0], sB[0], 0);
+    }
+    for (int t = 0; t < nstep; t++) {
+        const int stg = t & 1;
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+#pragma unroll
+        for (int iw = 0; iw < NW; iw++)
+#pragma unroll
+            for (int j = 0; j < 8; j++) wcur[iw][j] = wnext[iw][j];
+        const bool more = t + 1 < nstep;
+        if (more) wload(t + 1, wnext);
+        step(sA[stg ^ 1], sB[stg ^ 1], sA[stg], sB[stg], more ? 4 * (t + 1) : -1, wcur);
     }
 
     // result register r of lane (li, lk) holds row 4 lk + r, column li of a 16x16 block
