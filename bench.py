@@ -15,8 +15,16 @@ Inputs are resident in HBM before the timed region.
   split_bf16_x6 the six-product (hi/mid/lo) split form
   roofline      the chi contraction kernel of the split path: algorithmic
                 flops per launch / its mean launch time (HIP events on the
-                library's stream) against the BF16 dense peak
+                library's stream) against the BF16 dense peak; traffic is the
+                HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE
+                counters, scaled by what they read for a plain copy, as
+                recorded in profiles/k_chi_bf16_traffic.md (reported only
+                while the kernel source matches the recorded hash)
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload
+
+Counter runs use two extra modes: --copy-calibration (a plain 1 GiB device
+copy, three times) and --profile-k N (the split chi0 build over the first N
+k-points in the launch configuration of the timed legs).
 """
 
 from __future__ import annotations
@@ -34,6 +42,39 @@ if ROOT not in sys.path:
 METRIC = "χ0 build TFLOP/s + s/q-point, split-BF16 vs FP64, at rel err ≤1e-5 vs oracle"
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_chi_bf16_traffic.md")
+CHI_SOURCE = os.path.join(ROOT, "paper_2001_02351_amd", "csrc", "chi_bf16.hip")
+
+
+def recorded_traffic():
+    """HBM bytes per k_chi_bf16 launch from the committed counter summary, or
+    None when there is none or the kernel source changed since it was taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            line = line.strip().strip("`")
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    with open(CHI_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if vals.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB, three times (counter scale)."""
+    import torch
+    a = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": a.numel() * 4, "repeats": 3}), flush=True)
 
 
 def log(msg: str):
@@ -132,12 +173,17 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-x6", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--profile-k", type=int, default=0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     from synth import make_config
     log("generating the SrVO3-shaped workload (48^3, 8^3 k, 40+200 bands, N_G=1500, 20 w)")
@@ -146,7 +192,7 @@ def main():
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
     baseline = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.profile_k:
         log("timing the FP64 oracle on a bounded sample (host cores)")
         baseline = cpu_baseline(prob)
         log(f"oracle sample: {baseline['sample']}")
@@ -163,6 +209,12 @@ def main():
     d = path.DeviceInputs(prob)
     torch.cuda.synchronize()
     log("inputs resident on the device")
+    if args.profile_k:
+        path.chi0(ctx, d, prec=rp.RP_SPLIT_BF16, kbatch=args.kbatch, k0=0, k1=args.profile_k)
+        rp.rp_synchronize(ctx)
+        log(f"split chi0 over k < {args.profile_k} done")
+        ctx.close()
+        return
 
     split, chi_s, einv_s, wij_s = run_leg(rp, path, ctx, d, rp.RP_SPLIT_BF16, args.steps, args.warmup,
                                           args.kbatch)
@@ -227,7 +279,7 @@ def main():
             "peak": PEAK_BF16_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_BF16_TFLOPS,
-            "traffic": None,
+            "traffic": recorded_traffic(),
             "kernel": "k_chi_bf16 (chi0 contraction, split-BF16)",
             "mfma_executed_frac": 3.0 * achieved / PEAK_BF16_TFLOPS,
         },
