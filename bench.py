@@ -185,10 +185,10 @@ def main():
         copy_calibration()
         return
 
-    from synth import make_config
+    from synth import srvo3_workload
     log("generating the SrVO3-shaped workload (48^3, 8^3 k, 40+200 bands, N_G=1500, 20 w)")
     t0 = time.perf_counter()
-    prob = make_config(2)
+    prob = srvo3_workload()
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
     baseline = None

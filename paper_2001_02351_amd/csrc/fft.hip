@@ -3,6 +3,8 @@
 // by scattering the sphere coefficients into the N1 x N2 x N3 box and applying
 // three batched 1-D transforms, one axis at a time.  The first two passes are
 // pruned to the lines that can hold a non-zero coefficient (|m_a| <= mmax_a).
+// The grids are FP64 (double2) or, for the split-precision path, FP32
+// (float2: coefficients rounded to FP32, transforms in FP32).
 #include <algorithm>
 
 #include "fft_lds.h"
@@ -38,14 +40,16 @@ __device__ __forceinline__ long line_base(const LineSet &ls, long L)
 }
 
 // One block transforms `lpb` consecutive lines of the set in LDS.
-__global__ void __launch_bounds__(256) k_fft_lines(double2 *data, LineSet ls, FftPlan plan, int lpb)
+template <typename C>
+__global__ void __launch_bounds__(256) k_fft_lines(C *data, LineSet ls, FftPlan plan, int lpb)
 {
-    extern __shared__ double2 smem[];
+    extern __shared__ double2 smem_d[];
+    C *smem = (C *)smem_d;
     const int n = ls.n;
     const int ld = n + 1;  // padded line stride against LDS bank conflicts
-    double2 *tw = smem;
-    double2 *a = smem + n;
-    double2 *b = a + (size_t)lpb * ld;
+    C *tw = smem;
+    C *a = smem + n;
+    C *b = a + (size_t)lpb * ld;
     const int tid = threadIdx.x, nth = blockDim.x;
     const long L0 = (long)blockIdx.x * lpb;
     const int nl = (int)min((long)lpb, ls.nlines - L0);
@@ -61,7 +65,7 @@ __global__ void __launch_bounds__(256) k_fft_lines(double2 *data, LineSet ls, Ff
         a[l * ld + i] = data[line_base(ls, L0 + l) + (long)i * ls.is];
     }
     __syncthreads();
-    double2 *r = fft_lines(a, b, plan, nl, ld, 1, tw, tid, nth);
+    C *r = fft_lines(a, b, plan, nl, ld, 1, tw, tid, nth);
     for (int e = tid; e < nl * n; e += nth) {
         int l, i;
         if (contiguous) { l = e / n; i = e - l * n; }
@@ -70,32 +74,36 @@ __global__ void __launch_bounds__(256) k_fft_lines(double2 *data, LineSet ls, Ff
     }
 }
 
-__global__ void k_zero(double2 *p, long n)
+template <typename C> __global__ void k_zero(C *p, long n)
 {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     long stride = (long)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) p[i] = make_double2(0.0, 0.0);
+    for (; i < n; i += stride) p[i] = mkc<C>(0, 0);
 }
 
-// u[band][m mod N] = C[band][g] for g < npw (each Miller index appears once)
+// u[band][m mod N] = C[band][g] for g < npw (each Miller index appears once),
+// rounded to the grid's precision
+template <typename C>
 __global__ void k_scatter(const int *miller, const double2 *coef, int npw, int band_stride,
-                          int nbands, int N1, int N2, int N3, double2 *u)
+                          int nbands, int N1, int N2, int N3, C *u)
 {
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long)npw * nbands) return;
     int band = (int)(t / npw), g = (int)(t - (long)band * npw);
     int m1 = pmod(miller[3 * g], N1), m2 = pmod(miller[3 * g + 1], N2), m3 = pmod(miller[3 * g + 2], N3);
-    u[(long)band * N1 * N2 * N3 + ((long)m1 * N2 + m2) * N3 + m3] = coef[(long)band * band_stride + g];
+    const double2 c = coef[(long)band * band_stride + g];
+    typedef typename CxT<C>::T T;
+    u[(long)band * N1 * N2 * N3 + ((long)m1 * N2 + m2) * N3 + m3] = mkc<C>((T)c.x, (T)c.y);
 }
 
 int lines_per_block(int n) { return n <= 64 ? 32 : (n <= 128 ? 16 : 8); }
 
-void run_pass(hipStream_t s, double2 *data, const LineSet &ls, const FftPlan &plan)
+template <typename C> void run_pass(hipStream_t s, C *data, const LineSet &ls, const FftPlan &plan)
 {
     int lpb = lines_per_block(ls.n);
     long nblk = (ls.nlines + lpb - 1) / lpb;
-    size_t shm = sizeof(double2) * ((size_t)ls.n + 2 * (size_t)lpb * (ls.n + 1));
-    hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)nblk), dim3(256), shm, s, data, ls, plan, lpb);
+    size_t shm = sizeof(C) * ((size_t)ls.n + 2 * (size_t)lpb * (ls.n + 1));
+    hipLaunchKernelGGL(k_fft_lines<C>, dim3((unsigned)nblk), dim3(256), shm, s, data, ls, plan, lpb);
 }
 
 // box extents along an axis: B lines starting at -mm (mod N); full axis if the
@@ -106,8 +114,9 @@ void axis_box(int mmax, int N, int *B, int *mm)
     else { *B = 2 * mmax + 1; *mm = mmax; }
 }
 
+template <typename C>
 void fft3d_passes(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,
-                  const int mmax[3], double2 *data)
+                  const int mmax[3], C *data)
 {
     const int N1 = fft[0], N2 = fft[1], N3 = fft[2];
     const long nr = (long)N1 * N2 * N3;
@@ -125,20 +134,34 @@ void fft3d_passes(hipStream_t s, const FftPlan plans[3], const int fft[3], int n
     run_pass(s, data, l1, plans[0]);
 }
 
+template <typename C>
+void ugrid_t(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3], int nbands, int npw,
+             const int *miller_k, const double2 *coef_k, int band_stride, C *u)
+{
+    const long nr = (long)fft[0] * fft[1] * fft[2];
+    const long tot = nr * nbands;
+    unsigned zb = (unsigned)std::min<long>((tot + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_zero<C>, dim3(zb), dim3(256), 0, s, u, tot);
+    long ns = (long)npw * nbands;
+    hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, miller_k,
+                       coef_k, npw, band_stride, nbands, fft[0], fft[1], fft[2], u);
+    fft3d_passes(s, plans, fft, nbands, mmax, u);
+}
+
 }  // namespace
 
 void launch_ugrid(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
                   int nbands, int npw, const int *miller_k, const double2 *coef_k,
                   int band_stride, double2 *u)
 {
-    const long nr = (long)fft[0] * fft[1] * fft[2];
-    const long tot = nr * nbands;
-    unsigned zb = (unsigned)std::min<long>((tot + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_zero, dim3(zb), dim3(256), 0, s, u, tot);
-    long ns = (long)npw * nbands;
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, miller_k,
-                       coef_k, npw, band_stride, nbands, fft[0], fft[1], fft[2], u);
-    fft3d_passes(s, plans, fft, nbands, mmax, u);
+    ugrid_t(s, plans, fft, mmax, nbands, npw, miller_k, coef_k, band_stride, u);
+}
+
+void launch_ugrid32(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
+                    int nbands, int npw, const int *miller_k, const double2 *coef_k,
+                    int band_stride, void *u)
+{
+    ugrid_t(s, plans, fft, mmax, nbands, npw, miller_k, coef_k, band_stride, (float2 *)u);
 }
 
 void launch_fft3d(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,

@@ -271,27 +271,36 @@ template <int CTRL> __device__ __forceinline__ float quad_perm(float v)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// y_r = sum_s i^{r s} v_s across the quad; lane s ends with r = qrow(s)
-template <int Q> __device__ __forceinline__ void quad_dft4(float2 (&x)[Q], int s)
+template <int CTRL> __device__ __forceinline__ double quad_perm(double v)
 {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// y_r = sum_s i^{r s} v_s across the quad; lane s ends with r = qrow(s)
+template <int Q, typename C> __device__ __forceinline__ void quad_dft4(C (&x)[Q], int s)
+{
+    typedef typename CxT<C>::T T;
     // step 1, partner s ^ 2: lanes with bit 1 clear keep own + partner, the
     // others partner - own; step 2, partner s ^ 1, after lane 3 (odd s, r
     // bit 0 set) has multiplied its value by i
-    const float sg1 = (s & 2) ? -1.f : 1.f, sg0 = (s & 1) ? -1.f : 1.f;
+    const T sg1 = (s & 2) ? (T)-1 : (T)1, sg0 = (s & 1) ? (T)-1 : (T)1;
     const bool rot = s == 3;
 #pragma unroll
     for (int k = 0; k < Q; k++) {
-        const float px = quad_perm<0x4E>(x[k].x), py = quad_perm<0x4E>(x[k].y);
-        const float vx = px + sg1 * x[k].x, vy = py + sg1 * x[k].y;
-        const float rx = rot ? -vy : vx, ry = rot ? vx : vy;
-        const float qx = quad_perm<0xB1>(rx), qy = quad_perm<0xB1>(ry);
-        x[k] = make_float2(qx + sg0 * rx, qy + sg0 * ry);
+        const T px = quad_perm<0x4E>(x[k].x), py = quad_perm<0x4E>(x[k].y);
+        const T vx = px + sg1 * x[k].x, vy = py + sg1 * x[k].y;
+        const T rx = rot ? -vy : vx, ry = rot ? vx : vy;
+        const T qx = quad_perm<0xB1>(rx), qy = quad_perm<0xB1>(ry);
+        x[k] = mkc<C>(qx + sg0 * rx, qy + sg0 * ry);
     }
 }
 
 // twQ[t] = e^{2 pi i t/Q}, t < Q; twN[t] = e^{2 pi i t/N}, t < N
-template <int Q>
-__device__ __forceinline__ void quad_fft(float2 (&x)[Q], const float2 *twQ, const float2 *twN, int s)
+template <int Q, typename C>
+__device__ __forceinline__ void quad_fft(C (&x)[Q], const C *twQ, const C *twN, int s)
 {
     quad_dft4<Q>(x, s);
     const int r = quad_row(s);

@@ -252,10 +252,14 @@ __device__ __forceinline__ void lds_sync()
     asm volatile("" ::: "memory");
 }
 
-// widest m3 window the quad form holds in LDS
-template <int N> constexpr int quad_l3max() { return N >= 48 ? N / 2 : N; }
+// widest m3 window the quad form holds in LDS (FP32 2x2 pair blocks, FP64
+// 2x1 pair blocks: either way under 80 KB, two workgroups per CU)
+template <typename C, int N> constexpr int quad_l3max()
+{
+    return sizeof(C) == 8 ? (N >= 48 ? N / 2 : N) : (N >= 48 ? N / 3 : (N >= 32 ? 24 : N));
+}
 
-// Quad-FFT form (FP32), the path for N2 = N3 in {16, 24, 32, 48}.  Per plane
+// Quad-FFT form (FP32 or FP64), the path for N2 = N3 in {16, 24, 32, 48}.  Per plane
 // j1: (A) each quad of lanes (pair q, row j2) loads its two grid rows (each
 // lane a contiguous quarter, in 16-byte loads), forms the product and
 // transforms it along j3 (quad_fft), keeping the m3 window; (B) each quad
@@ -267,14 +271,13 @@ template <int N> constexpr int quad_l3max() { return N >= 48 ? N / 2 : N; }
 // read plane j1's window in phase C: two barriers per plane.  LDS stays under
 // half a CU's, so two workgroups share a CU and cover each other's load and
 // barrier waits.
-template <int N, int NA, int NB, int MAXG>
+template <typename C, int N, int NA, int NB, int MAXG>
 __global__ void __launch_bounds__(256, 2)
-k_pair_quad(const float2 *__restrict__ u_occ, const float2 *__restrict__ u_emp, int nO, int nE, int N1, int ng,
+k_pair_quad(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int nE, int N1, int ng,
             const int *__restrict__ gsph, int g01, int g02, int g03, int lo3, int L3, double2 *__restrict__ M)
 {
-    typedef float2 C;
     constexpr int Q = N / 4, NP = NA * NB;
-    constexpr int L3M = quad_l3max<N>();
+    constexpr int L3M = quad_l3max<C, N>();
     constexpr int TA = (NP * N + 63) / 64;    // phase-A lines per quad
     __shared__ C win0[NP * N * L3M];          // [NP][N][L3]
     __shared__ C win1[NP * N * L3M];
@@ -316,14 +319,19 @@ k_pair_quad(const float2 *__restrict__ u_occ, const float2 *__restrict__ u_emp, 
             if (task < NP * N) {
                 const int q = task / N, j2 = task - q * N;
                 const long off = ((long)j1 * N + j2) * N + Q * s;
-                const float4 *ra = (const float4 *)(u_emp + (long)min(a0 + q / NB, nE - 1) * nr + off);
-                const float4 *rb = (const float4 *)(u_occ + (long)min(b0 + q % NB, nO - 1) * nr + off);
+                const C *ra = u_emp + (long)min(a0 + q / NB, nE - 1) * nr + off;
+                const C *rb = u_occ + (long)min(b0 + q % NB, nO - 1) * nr + off;
                 C x[Q];
+                if constexpr (sizeof(C) == 8) {   // two FP32 complex values per 16-byte load
 #pragma unroll
-                for (int n = 0; n < Q / 2; n++) {
-                    const float4 va = ra[n], vb = rb[n];
-                    x[2 * n] = cmulc(make_float2(va.x, va.y), make_float2(vb.x, vb.y));
-                    x[2 * n + 1] = cmulc(make_float2(va.z, va.w), make_float2(vb.z, vb.w));
+                    for (int n = 0; n < Q / 2; n++) {
+                        const float4 va = ((const float4 *)ra)[n], vb = ((const float4 *)rb)[n];
+                        x[2 * n] = cmulc(mkc<C>(va.x, va.y), mkc<C>(vb.x, vb.y));
+                        x[2 * n + 1] = cmulc(mkc<C>(va.z, va.w), mkc<C>(vb.z, vb.w));
+                    }
+                } else {
+#pragma unroll
+                    for (int n = 0; n < Q; n++) x[n] = cmulc(ra[n], rb[n]);
                 }
                 quad_fft<Q>(x, twQ, twN, s);
                 C *dst = B + ((size_t)q * N + j2) * L3;
@@ -386,13 +394,13 @@ k_pair_quad(const float2 *__restrict__ u_occ, const float2 *__restrict__ u_emp, 
     }
 }
 
-template <int N, int NA, int NB>
-void launch_pair_quad(hipStream_t s, int N1, const float2 *u_occ, const float2 *u_emp, int nO, int nE, int ng,
+template <typename C, int N, int NA, int NB>
+void launch_pair_quad(hipStream_t s, int N1, const C *u_occ, const C *u_emp, int nO, int nE, int ng,
                       const int *gsph, const int g0[3], int lo3, int L3, double2 *M)
 {
     const unsigned nblk = (unsigned)(((nE + NA - 1) / NA) * ((nO + NB - 1) / NB));
 #define RP_PAIRQ(G)                                                                                          \
-    hipLaunchKernelGGL((k_pair_quad<N, NA, NB, G>), dim3(nblk), dim3(256), 0, s, u_occ, u_emp, nO, nE, N1,   \
+    hipLaunchKernelGGL((k_pair_quad<C, N, NA, NB, G>), dim3(nblk), dim3(256), 0, s, u_occ, u_emp, nO, nE, N1,\
                        ng, gsph, g0[0], g0[1], g0[2], lo3, L3, M)
     if (ng <= 512) RP_PAIRQ(2);
     else if (ng <= 1024) RP_PAIRQ(4);
@@ -434,12 +442,6 @@ void launch_pair_t(hipStream_t s, const FftPlan plans[3], const int fft[3], cons
 #undef RP_PAIR
 }
 
-__global__ void k_to_f32(const double2 *__restrict__ in, float2 *__restrict__ out, long n)
-{
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long st = (long)gridDim.x * blockDim.x;
-    for (; i < n; i += st) out[i] = make_float2((float)in[i].x, (float)in[i].y);
-}
 
 }  // namespace
 
@@ -465,14 +467,14 @@ bool pair_reg_supported(const int fft[3], int ng, bool fp32)
 
 // the quad form: N2 = N3 in {16, 24, 32, 48}, N1 <= 256, ng <= 2048, and the
 // m3 window within its LDS plan
-static bool pair_quad_supported(const int fft[3], int ng, int L3)
+template <typename C> static bool pair_quad_supported(const int fft[3], int ng, int L3)
 {
     if (fft[0] > 256 || fft[1] != fft[2] || ng > 2048) return false;
     switch (fft[1]) {
-    case 16: return L3 <= quad_l3max<16>();
-    case 24: return L3 <= quad_l3max<24>();
-    case 32: return L3 <= quad_l3max<32>();
-    case 48: return L3 <= quad_l3max<48>();
+    case 16: return L3 <= quad_l3max<C, 16>();
+    case 24: return L3 <= quad_l3max<C, 24>();
+    case 32: return L3 <= quad_l3max<C, 32>();
+    case 48: return L3 <= quad_l3max<C, 48>();
     default: return false;
     }
 }
@@ -481,35 +483,25 @@ void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], cons
                    const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3], int lo3,
                    int L3, bool fp32, double2 *M)
 {
-    if (fp32 && pair_quad_supported(fft, ng, L3)) {
+    if (fp32 && pair_quad_supported<float2>(fft, ng, L3)) {
         const float2 *uo = (const float2 *)u_occ, *ue = (const float2 *)u_emp;
         switch (fft[1]) {
-        case 16: launch_pair_quad<16, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
-        case 24: launch_pair_quad<24, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
-        case 32: launch_pair_quad<32, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
-        case 48: launch_pair_quad<48, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+        case 16: launch_pair_quad<float2, 16, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+        case 24: launch_pair_quad<float2, 24, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+        case 32: launch_pair_quad<float2, 32, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+        case 48: launch_pair_quad<float2, 48, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
         default: break;
         }
     }
-    if (pair_reg_supported(fft, ng, fp32)) {
-#define RP_REG(NN)                                                                                             \
-    case NN:                                                                                                 \
-        if (fp32)                                                                                            \
-            launch_pair_reg<float2, NN, 2, 2>(s, fft[0], (const float2 *)u_occ, (const float2 *)u_emp, nO, nE, \
-                                              ng, gsph, g0, lo3, L3, M);                                      \
-        else                                                                                                 \
-            launch_pair_reg<double2, (NN < 48 ? NN : 16), 2, 1>(s, fft[0], (const double2 *)u_occ,         \
-                                                                (const double2 *)u_emp, nO, nE, ng, gsph, g0,  \
-                                                                lo3, L3, M);                                   \
-        return;
+    if (!fp32 && pair_quad_supported<double2>(fft, ng, L3)) {
+        const double2 *uo = (const double2 *)u_occ, *ue = (const double2 *)u_emp;
         switch (fft[1]) {
-            RP_REG(16)
-            RP_REG(24)
-            RP_REG(32)
-            RP_REG(48)
+        case 16: launch_pair_quad<double2, 16, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+        case 24: launch_pair_quad<double2, 24, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+        case 32: launch_pair_quad<double2, 32, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+        case 48: launch_pair_quad<double2, 48, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
         default: break;
         }
-#undef RP_REG
     }
     if (fp32)
         launch_pair_t<float2, 2, 2>(s, plans, fft, (const float2 *)u_occ, (const float2 *)u_emp, nO, nE, ng,
@@ -519,10 +511,5 @@ void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], cons
                                      ng, gsph, g0, lo3, L3, M);
 }
 
-void launch_to_f32(hipStream_t s, const double2 *in, void *out, long n)
-{
-    const unsigned nb = (unsigned)std::min<long>((n + 255) / 256, 16384);
-    hipLaunchKernelGGL(k_to_f32, dim3(nb), dim3(256), 0, s, in, (float2 *)out, n);
-}
 
 }  // namespace rp

@@ -339,7 +339,7 @@ rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int
     if (pair_lds_bytes(g.fft, L3max, pair_rows(g.fft), fp32 ? 8 : 16, 4) > 160 * 1024)
         return fail(ctx, RP_E_UNSUPPORTED, "grid %dx%dx%d too large for the pair kernel's LDS plan",
                     g.fft[0], g.fft[1], g.fft[2]);
-    if ((st = ensure(ctx, ctx->ugrid, sizeof(double2) * nr * (nO + nE))) != RP_OK) return st;
+    if (!fp32 && (st = ensure(ctx, ctx->ugrid, sizeof(double2) * nr * (nO + nE))) != RP_OK) return st;
     if (fp32 && (st = ensure(ctx, ctx->ugrid32, sizeof(float2) * nr * (nO + nE))) != RP_OK) return st;
     if ((st = upload(ctx, ctx->glist, gsph, sizeof(int) * 3 * ng)) != RP_OK) return st;
     double2 *u_occ = (double2 *)ctx->ugrid.p;
@@ -358,11 +358,18 @@ rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int
         const double2 *cf = (const double2 *)coef;
         {
             StageTimer t(ctx, RP_STAGE_UGRID);
-            launch_ugrid(ctx->stream, plans, g.fft, mmax, nO, npw[k], miller + (long)k * npw_max * 3,
-                         cf + ((long)k * nband + o0) * npw_max, npw_max, u_occ);
-            launch_ugrid(ctx->stream, plans, g.fft, mmax, nE, npw[kp], miller + (long)kp * npw_max * 3,
-                         cf + ((long)kp * nband + e0) * npw_max, npw_max, u_emp);
-            if (fp32) launch_to_f32(ctx->stream, u_occ, ctx->ugrid32.p, nr * (nO + nE));
+            if (fp32) {
+                float2 *v = (float2 *)ctx->ugrid32.p;
+                launch_ugrid32(ctx->stream, plans, g.fft, mmax, nO, npw[k], miller + (long)k * npw_max * 3,
+                               cf + ((long)k * nband + o0) * npw_max, npw_max, v);
+                launch_ugrid32(ctx->stream, plans, g.fft, mmax, nE, npw[kp], miller + (long)kp * npw_max * 3,
+                               cf + ((long)kp * nband + e0) * npw_max, npw_max, v + nr * nO);
+            } else {
+                launch_ugrid(ctx->stream, plans, g.fft, mmax, nO, npw[k], miller + (long)k * npw_max * 3,
+                             cf + ((long)k * nband + o0) * npw_max, npw_max, u_occ);
+                launch_ugrid(ctx->stream, plans, g.fft, mmax, nE, npw[kp], miller + (long)kp * npw_max * 3,
+                             cf + ((long)kp * nband + e0) * npw_max, npw_max, u_emp);
+            }
         }
         const int lo3 = lo[2] + g0[2];
         double2 *Mk = (double2 *)M + (long)(k - k0) * nE * nO * ng;

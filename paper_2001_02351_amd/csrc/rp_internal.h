@@ -102,6 +102,11 @@ void launch_ugrid(hipStream_t s, const FftPlan plans[3], const int fft[3], const
                   int nbands, int npw, const int *miller_k, const double2 *coef_k,
                   int band_stride, double2 *u);
 
+// fft.hip: the same grids in FP32 (float2) for the split-precision path.
+void launch_ugrid32(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
+                    int nbands, int npw, const int *miller_k, const double2 *coef_k,
+                    int band_stride, void *u);
+
 // fft.hip: in-place batched positive-exponent transform of whole grids.
 void launch_fft3d(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,
                   double2 *data);
@@ -112,7 +117,6 @@ int pair_rows(const int fft[3]);
 void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], const void *u_occ,
                    const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3],
                    int lo3, int L3, bool fp32, double2 *M);
-void launch_to_f32(hipStream_t s, const double2 *in, void *out, long n);
 
 // tetra.hip: weights of a pair range.
 void launch_weights(hipStream_t s, const int kmesh[3], const int iq[3], int nband,

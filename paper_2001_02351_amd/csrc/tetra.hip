@@ -14,25 +14,78 @@
 // textbook X(omega) of Eq. Xakqbk.
 //
 // Divided differences are evaluated top-down on sorted nodes: a set of
-// nodes whose spread is at most a quarter of its distance to z is summed as a
-// Taylor series of g about the set's midpoint; any other set is split by the
-// recurrence (g[x1..xn] - g[x0..x(n-1)]) / (xn - x0), whose denominator is
-// then large enough that nothing cancels.  This replaces the degeneracy
-// thresholds delta_a, delta_r the paper's tetrahedron routine takes.
+// nodes whose deviation from its median node is at most a quarter of that
+// node's distance to z is summed as a Taylor series of g about the median
+// node; any other set is split by the recurrence
+// (g[x1..xn] - g[x0..x(n-1)]) / (xn - x0), whose denominator is then large
+// enough that nothing cancels.  This replaces the degeneracy thresholds
+// delta_a, delta_r the paper's tetrahedron routine takes.  Every series is
+// centred on a node, so the only logarithms are log(z - e_j) at the 15
+// distinct corners of the 24 tetrahedra around k: they are computed once per
+// (pair, frequency) and kept in LDS, and each tetrahedron is pure arithmetic.
 #include "fft_lds.h"
 
 namespace rp {
 
 namespace {
 
+// The 24 tetrahedra around a mesh point (each mesh cell cut into 6 around its
+// (0,0,0)-(1,1,1) diagonal): corners as slots into the 15 distinct
+// neighbours, neighbour offsets as codes (d1+1)*9 + (d2+1)*3 + (d3+1).
 struct TetraTable {
-    // for each of the 24 tetrahedra around a mesh point: neighbour codes
-    // (d1+1)*9 + (d2+1)*3 + (d3+1) of its 4 corners and the corner that is k
-    int nb[24][4];
-    int self[24];
+    int slot[24][4];
+    int nbr[15];
+    int self;   // slot of k itself (code 13)
+    int ntet, nnbr;
 };
 
-__constant__ TetraTable c_tetra;
+constexpr TetraTable make_tetra_table()
+{
+    TetraTable tb{};
+    int codes[24][4] = {};
+    int cnt = 0;
+    const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (int s = 0; s < 8; s++) {                 // k = cell corner + s
+        const int so[3] = {(s >> 2) & 1, (s >> 1) & 1, s & 1};
+        for (int pi = 0; pi < 6; pi++) {
+            int corner[4][3] = {};
+            for (int v = 1; v < 4; v++) {
+                for (int d = 0; d < 3; d++) corner[v][d] = corner[v - 1][d];
+                corner[v][perms[pi][v - 1]] = 1;
+            }
+            bool has = false;
+            for (int v = 0; v < 4; v++)
+                if (corner[v][0] == so[0] && corner[v][1] == so[1] && corner[v][2] == so[2]) has = true;
+            if (!has) continue;
+            for (int v = 0; v < 4; v++)
+                codes[cnt][v] = (corner[v][0] - so[0] + 1) * 9 + (corner[v][1] - so[1] + 1) * 3 +
+                                (corner[v][2] - so[2] + 1);
+            cnt++;
+        }
+    }
+    int n = 0;
+    for (int t = 0; t < 24; t++)
+        for (int v = 0; v < 4; v++) {
+            int found = -1;
+            for (int j = 0; j < n; j++)
+                if (tb.nbr[j] == codes[t][v]) found = j;
+            if (found < 0 && n < 15) {
+                tb.nbr[n] = codes[t][v];
+                found = n++;
+            }
+            tb.slot[t][v] = found;
+        }
+    for (int j = 0; j < n; j++)
+        if (tb.nbr[j] == 13) tb.self = j;
+    tb.ntet = cnt;
+    tb.nnbr = n;
+    return tb;
+}
+
+constexpr TetraTable kTet = make_tetra_table();
+static_assert(kTet.ntet == 24 && kTet.nnbr == 15, "24 tetrahedra over 15 distinct corners expected");
+
+__constant__ TetraTable c_tetra = kTet;
 
 __device__ __forceinline__ double2 clog_d(double2 w)
 {
@@ -47,12 +100,12 @@ __device__ __forceinline__ double2 crecip(double2 w)
     return make_double2(w.x * s, -w.y * s);
 }
 
-// sum_{m>=n} g^(m)(c)/m! * h_{m-n}(x_0-c, .., x_n-c) over the n+1 nodes x[a..a+n]
-__device__ double2 dd_series(double2 z, const double *x, int a, int n)
+// sum_{m>=n} g^(m)(c)/m! * h_{m-n}(x_0-c, .., x_n-c) over the n+1 nodes
+// x[a..a+n], about the node c = x[cm] with lw = log(z - c)
+__device__ double2 dd_series(double2 z, const double *x, int a, int n, int cm, double2 lw)
 {
-    const double c = 0.5 * (x[a] + x[a + n]);
+    const double c = x[cm];
     const double2 w = make_double2(z.x - c, z.y);
-    const double2 lw = clog_d(w);
     const double2 wi = crecip(w);
     double y[5], P[5];
 #pragma unroll
@@ -74,7 +127,7 @@ __device__ double2 dd_series(double2 z, const double *x, int a, int n)
     double2 wp = make_double2(1.0, 0.0);  // w^-(m-3) for m >= 4
     double2 sum = make_double2(0.0, 0.0);
     int quiet = 0;
-    for (int m = n; m < n + 64; m++) {
+    for (int m = n; m < n + 80; m++) {
         const int k = m - n;
         if (k > 0) {
             // raise P to degree k: h_k(y_0..y_i) = h_k(y_0..y_{i-1}) + y_i h_{k-1}(y_0..y_i)
@@ -106,14 +159,9 @@ __device__ double2 dd_series(double2 z, const double *x, int a, int n)
     return sum;
 }
 
-__device__ __forceinline__ double2 g_at(double2 z, double xv)
-{
-    const double2 w = make_double2(z.x - xv, z.y);
-    return cmul(cmul(cmul(w, w), w), clog_d(w));
-}
-
-// fourth divided difference of g over five sorted nodes
-__device__ double2 dd4_sorted(double2 z, const double *x)
+// fourth divided difference of g over five sorted nodes x with lw[i] =
+// log(z - x[i])
+__device__ double2 dd4_sorted(double2 z, const double *x, const double2 *lw)
 {
     // entry (a, n) = g[x_a .. x_{a+n}] at slot id(a,n) = 5n - n(n-1)/2 + a
     bool need[15], ser[15];
@@ -127,10 +175,10 @@ __device__ double2 dd4_sorted(double2 z, const double *x)
         for (int a = 0; a + n <= 4; a++) {
             const int id = 5 * n - n * (n - 1) / 2 + a;
             if (!need[id]) continue;
-            const double spread = x[a + n] - x[a];
-            const double c = 0.5 * (x[a] + x[a + n]);
-            const double dz = hypot(z.x - c, z.y);
-            if (4.0 * spread <= dz) {
+            const int cm = a + n / 2;
+            const double dev = fmax(x[a + n] - x[cm], x[cm] - x[a]);
+            const double dz = hypot(z.x - x[cm], z.y);
+            if (4.0 * dev <= dz) {
                 ser[id] = true;
             } else {
                 const int lid = 5 * (n - 1) - (n - 1) * (n - 2) / 2 + a;
@@ -146,9 +194,10 @@ __device__ double2 dd4_sorted(double2 z, const double *x)
             const int id = 5 * n - n * (n - 1) / 2 + a;
             if (!need[id]) continue;
             if (n == 0) {
-                val[id] = g_at(z, x[a]);
+                const double2 w = make_double2(z.x - x[a], z.y);
+                val[id] = cmul(cmul(cmul(w, w), w), lw[a]);
             } else if (ser[id]) {
-                val[id] = dd_series(z, x, a, n);
+                val[id] = dd_series(z, x, a, n, a + n / 2, lw[a + n / 2]);
             } else {
                 const int lid = 5 * (n - 1) - (n - 1) * (n - 2) / 2 + a;
                 val[id] = cdiv_real(csub(val[lid + 1], val[lid]), x[a + n] - x[a]);
@@ -158,26 +207,23 @@ __device__ double2 dd4_sorted(double2 z, const double *x)
     return val[14];
 }
 
-// I_v(z) for corner energies e[4] (hartree)
-__device__ double2 vertex_integral(double2 z, const double *e, int v)
-{
-    double x[5] = {e[0], e[1], e[2], e[3], e[v]};
-    // sorting network on five keys
-#define RP_CSWAP(i, j) { double lo_ = fmin(x[i], x[j]), hi_ = fmax(x[i], x[j]); x[i] = lo_; x[j] = hi_; }
-    RP_CSWAP(0, 1) RP_CSWAP(3, 4) RP_CSWAP(2, 4) RP_CSWAP(2, 3) RP_CSWAP(0, 3)
-    RP_CSWAP(0, 2) RP_CSWAP(1, 4) RP_CSWAP(1, 3) RP_CSWAP(1, 2)
-#undef RP_CSWAP
-    return dd4_sorted(z, x);
-}
-
 __device__ __forceinline__ int mesh_wrap(int n, int K) { return pmod(n, K); }
 
-__global__ void __launch_bounds__(256)
+constexpr int kWThreads = 128;
+
+// One thread per (pair, frequency).  The corner energies e_j and log(z - e_j)
+// of the 15 distinct corners live in LDS ([slot][thread]); each of the 24
+// tetrahedra sorts its five nodes (four corners, k's corner doubled) together
+// with their logarithms and evaluates I_v(z) and I_v(z').
+__global__ void __launch_bounds__(kWThreads)
 k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const double *E, const double *T,
           int o0, int nO, int e0, int nE, int k0, long npair, int nfreq, const double2 *freq,
           double delta, int mode, double2 *w)
 {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double sE[15][kWThreads];
+    __shared__ double2 sL[15][kWThreads];
+    const int tid = threadIdx.x;
+    const long t = (long)blockIdx.x * blockDim.x + tid;
     if (t >= npair * nfreq) return;
     const int f = (int)(t / npair);
     const long p = t - (long)f * npair;
@@ -196,55 +242,52 @@ k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const doubl
         const double e = (E[(long)kq * nband + a] - E[(long)k * nband + b]) * ha;
         x = cadd(crecip(make_double2(z.x - e, z.y)), crecip(make_double2(zp.x - e, zp.y)));
     } else {
-        x = make_double2(0.0, 0.0);
-        for (int tt = 0; tt < 24; tt++) {
-            double e[4];
 #pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int code = c_tetra.nb[tt][v];
-                const int d1 = code / 9 - 1, d2 = (code / 3) % 3 - 1, d3 = code % 3 - 1;
-                const int m1 = n1 + d1, m2 = n2 + d2, m3 = n3 + d3;
-                const int kv = (mesh_wrap(m1, K1) * K2 + mesh_wrap(m2, K2)) * K3 + mesh_wrap(m3, K3);
-                const int kvq = (mesh_wrap(m1 + q1, K1) * K2 + mesh_wrap(m2 + q2, K2)) * K3 +
-                                mesh_wrap(m3 + q3, K3);
-                e[v] = (E[(long)kvq * nband + a] - E[(long)kv * nband + b]) * ha;
+        for (int j = 0; j < 15; j++) {
+            const int code = kTet.nbr[j];
+            const int m1 = n1 + code / 9 - 1, m2 = n2 + (code / 3) % 3 - 1, m3 = n3 + code % 3 - 1;
+            const int kv = (mesh_wrap(m1, K1) * K2 + mesh_wrap(m2, K2)) * K3 + mesh_wrap(m3, K3);
+            const int kvq = (mesh_wrap(m1 + q1, K1) * K2 + mesh_wrap(m2 + q2, K2)) * K3 + mesh_wrap(m3 + q3, K3);
+            sE[j][tid] = (E[(long)kvq * nband + a] - E[(long)kv * nband + b]) * ha;
+        }
+        x = make_double2(0.0, 0.0);
+        for (int zi = 0; zi < 2; zi++) {
+            const double2 zz = zi ? zp : z;
+#pragma unroll
+            for (int j = 0; j < 15; j++) sL[j][tid] = clog_d(make_double2(zz.x - sE[j][tid], zz.y));
+            for (int tt = 0; tt < 24; tt++) {
+                double xs[5];
+                double2 ls[5];
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int sl = c_tetra.slot[tt][v];
+                    xs[v] = sE[sl][tid];
+                    ls[v] = sL[sl][tid];
+                }
+                xs[4] = sE[kTet.self][tid];
+                ls[4] = sL[kTet.self][tid];
+                // sorting network on five keys, carrying the logarithms
+#define RP_CSWAP(i, j)                                                                             \
+    {                                                                                              \
+        const bool sw_ = xs[j] < xs[i];                                                            \
+        const double xi_ = xs[i], xj_ = xs[j];                                                     \
+        const double2 li_ = ls[i], lj_ = ls[j];                                                    \
+        xs[i] = sw_ ? xj_ : xi_;                                                                   \
+        xs[j] = sw_ ? xi_ : xj_;                                                                   \
+        ls[i] = sw_ ? lj_ : li_;                                                                   \
+        ls[j] = sw_ ? li_ : lj_;                                                                   \
+    }
+                RP_CSWAP(0, 1) RP_CSWAP(3, 4) RP_CSWAP(2, 4) RP_CSWAP(2, 3) RP_CSWAP(0, 3)
+                RP_CSWAP(0, 2) RP_CSWAP(1, 4) RP_CSWAP(1, 3) RP_CSWAP(1, 2)
+#undef RP_CSWAP
+                x = cadd(x, dd4_sorted(zz, xs, ls));
             }
-            const int sv = c_tetra.self[tt];
-            x = cadd(x, cadd(vertex_integral(z, e, sv), vertex_integral(zp, e, sv)));
         }
         x = cscale(x, 1.0 / 6.0);
     }
     double fac = 2.0 / (double)(K1 * K2 * K3);
     if (T) fac *= 1.0 - T[(long)kq * nband + a] * T[(long)k * nband + b];
     w[t] = cscale(x, fac);
-}
-
-TetraTable build_table()
-{
-    TetraTable tb{};
-    int cnt = 0;
-    const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-    for (int s = 0; s < 8; s++) {                 // k = cell corner + s
-        const int so[3] = {(s >> 2) & 1, (s >> 1) & 1, s & 1};
-        for (int pi = 0; pi < 6; pi++) {
-            int corner[4][3] = {{0, 0, 0}};
-            for (int v = 1; v < 4; v++) {
-                for (int d = 0; d < 3; d++) corner[v][d] = corner[v - 1][d];
-                corner[v][perms[pi][v - 1]] = 1;
-            }
-            int self = -1;
-            for (int v = 0; v < 4; v++)
-                if (corner[v][0] == so[0] && corner[v][1] == so[1] && corner[v][2] == so[2]) self = v;
-            if (self < 0) continue;
-            for (int v = 0; v < 4; v++) {
-                const int d1 = corner[v][0] - so[0], d2 = corner[v][1] - so[1], d3 = corner[v][2] - so[2];
-                tb.nb[cnt][v] = (d1 + 1) * 9 + (d2 + 1) * 3 + (d3 + 1);
-            }
-            tb.self[cnt] = self;
-            cnt++;
-        }
-    }
-    return tb;  // cnt == 24
 }
 
 }  // namespace
@@ -254,21 +297,11 @@ void launch_weights(hipStream_t s, const int kmesh[3], const int iq[3], int nban
                     int k0, int k1, int nfreq, const double2 *freq_eV, double delta_eV,
                     int mode, double2 *w)
 {
-    static bool uploaded = false;
-    static int uploaded_dev = -1;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    if (!uploaded || uploaded_dev != dev) {
-        TetraTable tb = build_table();
-        (void)hipMemcpyToSymbol(HIP_SYMBOL(c_tetra), &tb, sizeof(tb), 0, hipMemcpyHostToDevice);
-        uploaded = true;
-        uploaded_dev = dev;
-    }
     const long npair = (long)(k1 - k0) * (e1 - e0) * (o1 - o0);
     const long tot = npair * nfreq;
     if (tot == 0) return;
-    hipLaunchKernelGGL(k_weights, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, kmesh[0],
-                       kmesh[1], kmesh[2], iq[0], iq[1], iq[2], nband, E_eV, T, o0, o1 - o0, e0,
+    hipLaunchKernelGGL(k_weights, dim3((unsigned)((tot + kWThreads - 1) / kWThreads)), dim3(kWThreads), 0, s,
+                       kmesh[0], kmesh[1], kmesh[2], iq[0], iq[1], iq[2], nband, E_eV, T, o0, o1 - o0, e0,
                        e1 - e0, k0, npair, nfreq, freq_eV, delta_eV, mode, w);
 }
 

@@ -12,7 +12,8 @@ from .gen import (  # noqa: F401
     BOHR_ANGSTROM,
     HARTREE_EV,
     Problem,
-    make_config,
     make_problem,
     mesh_fractions,
+    parity_workload,
+    srvo3_workload,
 )

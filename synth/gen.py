@@ -270,31 +270,29 @@ def make_problem(*, name: str, a_bohr: float, fft, kmesh, iq, nocc: int, nemp: i
                    alpha=alpha, gpsi=float(gpsi), seed=seed)
 
 
-def make_config(i: int, seed: Optional[int] = None,
-                workers: Optional[int] = None) -> Problem:
-    """The workload configurations.
-
-    1: 16^3 grid, 4^3 k, 8+24 bands, N_G = 89, 10 real frequencies on
-       [0,20] eV, delta = 0.1 eV, 3 Wannier Gaussians (small parity case).
-    2: 48^3 grid, 8^3 k, 40+200 bands, 100 Ry wavefunction cutoff, N_G = 1500,
-       20 real frequencies on [0,20] eV, delta = 0.1 eV, 10 Wannier Gaussians
-       (the paper's SrVO3 shapes; the measured workload).
-    3: config 1's arrays (used with the split-BF16 contraction).
-    """
+def parity_workload(seed: Optional[int] = None, workers: Optional[int] = None) -> Problem:
+    """The small parity workload: 16^3 grid, 4^3 k mesh, q = (1/4, 0, 0),
+    8 + 24 bands, N_G = 89, 10 real frequencies on [0, 20] eV, delta =
+    0.1 eV, 3 Wannier Gaussians.  The oracle finishes it in seconds."""
     a = A_SRVO3_BOHR
     b = 2.0 * math.pi / a
-    if i in (1, 3):
-        return make_problem(name=f"config{i}", a_bohr=a, fft=(16, 16, 16),
-                            kmesh=(4, 4, 4), iq=(1, 0, 0), nocc=8, nemp=24,
-                            gpsi=4.153 * b, ng=89,
-                            freq_eV=np.linspace(0.0, 20.0, 10), delta_eV=0.1,
-                            nwan=3, alpha_range=(1.0, 2.0),
-                            seed=1 if seed is None else seed, workers=workers)
-    if i == 2:
-        return make_problem(name="config2", a_bohr=a, fft=(48, 48, 48),
-                            kmesh=(8, 8, 8), iq=(1, 0, 0), nocc=40, nemp=200,
-                            gpsi=math.sqrt(2.0 * 50.0), ng=1500,
-                            freq_eV=np.linspace(0.0, 20.0, 20), delta_eV=0.1,
-                            nwan=10, alpha_range=(1.1, 1.9),
-                            seed=2 if seed is None else seed, workers=workers)
-    raise ValueError(f"unknown config {i}")
+    return make_problem(name="parity_16cube_4k_32bands", a_bohr=a, fft=(16, 16, 16),
+                        kmesh=(4, 4, 4), iq=(1, 0, 0), nocc=8, nemp=24,
+                        gpsi=4.153 * b, ng=89,
+                        freq_eV=np.linspace(0.0, 20.0, 10), delta_eV=0.1,
+                        nwan=3, alpha_range=(1.0, 2.0),
+                        seed=1 if seed is None else seed, workers=workers)
+
+
+def srvo3_workload(seed: Optional[int] = None, workers: Optional[int] = None) -> Problem:
+    """The SrVO3-shaped q-point: cubic a = 3.8425 A, 48^3 grid, 8^3 k mesh,
+    q = (1/8, 0, 0), 40 + 200 bands, 100 Ry wavefunction cutoff, N_G = 1500,
+    20 real frequencies on [0, 20] eV, delta = 0.1 eV, 10 Wannier Gaussians
+    (the measured workload)."""
+    a = A_SRVO3_BOHR
+    return make_problem(name="srvo3_48cube_8k_240bands", a_bohr=a, fft=(48, 48, 48),
+                        kmesh=(8, 8, 8), iq=(1, 0, 0), nocc=40, nemp=200,
+                        gpsi=math.sqrt(2.0 * 50.0), ng=1500,
+                        freq_eV=np.linspace(0.0, 20.0, 20), delta_eV=0.1,
+                        nwan=10, alpha_range=(1.1, 1.9),
+                        seed=2 if seed is None else seed, workers=workers)

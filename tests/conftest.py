@@ -14,6 +14,6 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session")
-def config1():
-    from synth import make_config
-    return make_config(1)
+def parity_problem():
+    from synth import parity_workload
+    return parity_workload()

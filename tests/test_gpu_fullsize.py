@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import make_config
+from synth import srvo3_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,7 @@ def ctx(rp):
 @pytest.fixture(scope="module")
 def c2():
     print("[fullsize] generating the 48^3 / 8^3 k / 240-band workload", flush=True)
-    return make_config(2)
+    return srvo3_workload()
 
 
 @pytest.fixture(scope="module")

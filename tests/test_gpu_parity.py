@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import make_config, make_problem
+from synth import make_problem, parity_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -45,8 +45,8 @@ def ctx(rp):
 
 @pytest.fixture(scope="module")
 def c1():
-    p = make_config(1)
-    print("[oracle] config1 path", flush=True)
+    p = parity_workload()
+    print("[oracle] parity-workload path", flush=True)
     ref = oracle.run_path(p)
     return p, ref
 
