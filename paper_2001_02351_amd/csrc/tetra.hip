@@ -100,60 +100,74 @@ __device__ __forceinline__ double2 crecip(double2 w)
     return make_double2(w.x * s, -w.y * s);
 }
 
-// sum_{m>=n} g^(m)(c)/m! * h_{m-n}(x_0-c, .., x_n-c) over the n+1 nodes
-// x[a..a+n], about the node c = x[cm] with lw = log(z - c)
-__device__ double2 dd_series(double2 z, const double *x, int a, int n, int cm, double2 lw)
+// Series coefficients 6 / (m (m-1) (m-2) (m-3)) of the m-th Taylor term,
+// m = 4 .. kSeriesMax - 1 (the m-th entry; entries below 4 unused).
+constexpr int kSeriesMax = 4 + 96;
+struct SeriesTable {
+    double f[kSeriesMax];
+};
+constexpr SeriesTable make_series_table()
+{
+    SeriesTable t{};
+    for (int m = 4; m < kSeriesMax; m++) t.f[m] = 6.0 / ((double)m * (m - 1) * (m - 2) * (m - 3));
+    return t;
+}
+__constant__ SeriesTable c_series = make_series_table();
+
+// sum_{m>=N} g^(m)(c)/m! * h_{m-N}(x_0-c, .., x_N-c) over the N+1 nodes
+// x[a..a+N], about the node c = x[cm] with lw = log(z - c)
+template <int N>
+__device__ __forceinline__ double2 dd_series(double2 z, const double *x, int a, int cm, double2 lw)
 {
     const double c = x[cm];
     const double2 w = make_double2(z.x - c, z.y);
     const double2 wi = crecip(w);
-    double y[5], P[5];
+    double y[N + 1], P[N + 1];
 #pragma unroll
-    for (int i = 0; i < 5; i++) {
-        y[i] = (i <= n) ? x[a + i] - c : 0.0;
+    for (int i = 0; i <= N; i++) {
+        y[i] = x[a + i] - c;
         P[i] = 1.0;
     }
     // Taylor coefficients of g(x) = (z-x)^3 log(z-x) about c, with w = z - c:
     // m=0: w^3 L, 1: -(3w^2 L + w^2), 2: (6wL + 5w)/2, 3: -(6L + 11)/6,
     // m>=4: 6 / (m(m-1)(m-2)(m-3)) w^-(m-3)
-    const double2 w2 = cmul(w, w);
-    double2 lo[4];
-    lo[0] = cmul(cmul(w2, w), lw);
-    lo[1] = make_double2(-(3.0 * (w2.x * lw.x - w2.y * lw.y) + w2.x),
-                         -(3.0 * (w2.x * lw.y + w2.y * lw.x) + w2.y));
-    lo[2] = make_double2(0.5 * (6.0 * (w.x * lw.x - w.y * lw.y) + 5.0 * w.x),
-                         0.5 * (6.0 * (w.x * lw.y + w.y * lw.x) + 5.0 * w.y));
-    lo[3] = make_double2(-(6.0 * lw.x + 11.0) / 6.0, -(6.0 * lw.y) / 6.0);
-    double2 wp = make_double2(1.0, 0.0);  // w^-(m-3) for m >= 4
     double2 sum = make_double2(0.0, 0.0);
-    int quiet = 0;
-    for (int m = n; m < n + 80; m++) {
-        const int k = m - n;
-        if (k > 0) {
-            // raise P to degree k: h_k(y_0..y_i) = h_k(y_0..y_{i-1}) + y_i h_{k-1}(y_0..y_i)
+    const double2 w2 = cmul(w, w);
+#pragma unroll
+    for (int m = N; m < 4; m++) {
+        if (m > N) {
             P[0] *= y[0];
 #pragma unroll
-            for (int i = 1; i < 5; i++)
-                if (i <= n) P[i] = P[i - 1] + y[i] * P[i];
+            for (int i = 1; i <= N; i++) P[i] = P[i - 1] + y[i] * P[i];
         }
-        const double h = P[n];
         double2 coef;
-        if (m < 4) {
-            coef = lo[m];
-        } else {
-            wp = cmul(wp, wi);
-            const double f = 6.0 / ((double)m * (m - 1) * (m - 2) * (m - 3));
-            coef = make_double2(f * wp.x, f * wp.y);
+        if (m == 0) coef = cmul(cmul(w2, w), lw);
+        else if (m == 1)
+            coef = make_double2(-(3.0 * (w2.x * lw.x - w2.y * lw.y) + w2.x), -(3.0 * (w2.x * lw.y + w2.y * lw.x) + w2.y));
+        else if (m == 2)
+            coef = make_double2(0.5 * (6.0 * (w.x * lw.x - w.y * lw.y) + 5.0 * w.x),
+                                0.5 * (6.0 * (w.x * lw.y + w.y * lw.x) + 5.0 * w.y));
+        else coef = make_double2(-(6.0 * lw.x + 11.0) / 6.0, -lw.y);
+        sum = make_double2(sum.x + coef.x * P[N], sum.y + coef.y * P[N]);
+    }
+    double2 wp = make_double2(1.0, 0.0);  // w^-(m-3)
+    int quiet = 0;
+    for (int m = 4; m < kSeriesMax; m++) {
+        if (m > N) {
+            // raise P to degree m - N: h_k(y_0..y_i) = h_k(y_0..y_{i-1}) + y_i h_{k-1}(y_0..y_i)
+            P[0] *= y[0];
+#pragma unroll
+            for (int i = 1; i <= N; i++) P[i] = P[i - 1] + y[i] * P[i];
         }
-        const double2 t = make_double2(coef.x * h, coef.y * h);
+        wp = cmul(wp, wi);
+        const double fh = c_series.f[m] * P[N];
+        const double2 t = make_double2(wp.x * fh, wp.y * fh);
         sum = cadd(sum, t);
-        if (m >= 4) {
-            const double tm = fabs(t.x) + fabs(t.y), sm = fabs(sum.x) + fabs(sum.y);
-            if (tm <= 1e-18 * sm) {
-                if (++quiet == 2) break;
-            } else {
-                quiet = 0;
-            }
+        const double tm = fabs(t.x) + fabs(t.y), sm = fabs(sum.x) + fabs(sum.y);
+        if (tm <= 1e-18 * sm) {
+            if (++quiet == 2) break;
+        } else {
+            quiet = 0;
         }
     }
     return sum;
@@ -169,6 +183,7 @@ __device__ double2 dd4_sorted(double2 z, const double *x, const double2 *lw)
 #pragma unroll
     for (int i = 0; i < 15; i++) { need[i] = false; ser[i] = false; }
     need[14] = true;
+    const double zy2 = z.y * z.y;
 #pragma unroll
     for (int n = 4; n >= 1; n--) {
 #pragma unroll
@@ -177,8 +192,8 @@ __device__ double2 dd4_sorted(double2 z, const double *x, const double2 *lw)
             if (!need[id]) continue;
             const int cm = a + n / 2;
             const double dev = fmax(x[a + n] - x[cm], x[cm] - x[a]);
-            const double dz = hypot(z.x - x[cm], z.y);
-            if (4.0 * dev <= dz) {
+            const double dx = z.x - x[cm];
+            if (16.0 * dev * dev <= dx * dx + zy2) {   // 4 dev <= |z - x_cm|
                 ser[id] = true;
             } else {
                 const int lid = 5 * (n - 1) - (n - 1) * (n - 2) / 2 + a;
@@ -197,7 +212,10 @@ __device__ double2 dd4_sorted(double2 z, const double *x, const double2 *lw)
                 const double2 w = make_double2(z.x - x[a], z.y);
                 val[id] = cmul(cmul(cmul(w, w), w), lw[a]);
             } else if (ser[id]) {
-                val[id] = dd_series(z, x, a, n, a + n / 2, lw[a + n / 2]);
+                if (n == 1) val[id] = dd_series<1>(z, x, a, a + n / 2, lw[a + n / 2]);
+                else if (n == 2) val[id] = dd_series<2>(z, x, a, a + n / 2, lw[a + n / 2]);
+                else if (n == 3) val[id] = dd_series<3>(z, x, a, a + n / 2, lw[a + n / 2]);
+                else val[id] = dd_series<4>(z, x, a, a + n / 2, lw[a + n / 2]);
             } else {
                 const int lid = 5 * (n - 1) - (n - 1) * (n - 2) / 2 + a;
                 val[id] = cdiv_real(csub(val[lid + 1], val[lid]), x[a + n] - x[a]);
