@@ -171,8 +171,10 @@ rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], 
 /*
  * Steps a7-a9: eps = I - v^1/2 chi v^1/2 with v^1/2_G = sqrt(4 pi/Omega)/|q+G|
  * (Eq. epsGG), eps^-1 per frequency by FP64 Gauss-Jordan elimination with
- * partial pivoting, and W = v^1/2 eps^-1 v^1/2 in eV (Eq. Wq, inside S_eps).
+ * partial pivoting (blocked in panels of 64 columns), and W = v^1/2 eps^-1
+ * v^1/2 in eV (Eq. Wq, inside S_eps).
  *
+ * ng              : 1 .. 6144 (RP_E_UNSUPPORTED above)
  * gsph    (host)  : int[ng][3], |q+G| > 0 for every entry
  * chi     (dev)   : c128[nfreq][ng][ng]
  * eps_inv (dev)   : c128[nfreq][ng][ng] output, or NULL
@@ -180,7 +182,8 @@ rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], 
  * A pivot of magnitude below 1e-13 (eps is dimensionless with a unit-scale
  * diagonal, so this means a condition number beyond ~1e13) is reported by
  * rp_synchronize as RP_E_SINGULAR; a non-finite value as RP_E_RANGE.
- * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE, RP_E_NOMEM, RP_E_DEVICE.
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE, RP_E_UNSUPPORTED, RP_E_NOMEM,
+ * RP_E_DEVICE.
  */
 rp_status rp_screen_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int ng,
                       const int *gsph, int nfreq, const double *chi, double *eps_inv,

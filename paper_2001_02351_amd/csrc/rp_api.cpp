@@ -481,6 +481,7 @@ rp_status rp_screen_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int ng,
     if (st != RP_OK) return st;
     if (!chi) return fail(ctx, RP_E_NULL, "chi is NULL");
     if (ng < 1 || nfreq < 1) return fail(ctx, RP_E_SHAPE, "ng and nfreq must be >= 1");
+    if (ng > 6144) return fail(ctx, RP_E_UNSUPPORTED, "ng = %d above 6144", ng);
     if ((st = check_gsph(ctx, g, ng, gsph, "gsph")) != RP_OK) return st;
     const size_t mat = sizeof(double2) * (size_t)ng * ng * nfreq;
     double2 *a = (double2 *)eps_inv;
@@ -491,7 +492,7 @@ rp_status rp_screen_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int ng,
     if ((st = upload(ctx, ctx->glist, gsph, sizeof(int) * 3 * ng)) != RP_OK) return st;
     if ((st = ensure(ctx, ctx->vsqrt, sizeof(double) * ng)) != RP_OK) return st;
     if ((st = ensure(ctx, ctx->piv, sizeof(int) * (size_t)ng * nfreq)) != RP_OK) return st;
-    if ((st = ensure(ctx, ctx->rho, sizeof(double2) * (size_t)ng * nfreq)) != RP_OK) return st;
+    if ((st = ensure(ctx, ctx->rho, invert_scratch_bytes(ng, nfreq))) != RP_OK) return st;
     double *vs = (double *)ctx->vsqrt.p;
     StageTimer t(ctx, RP_STAGE_SCREEN);
     launch_vsqrt(ctx->stream, g, ng, (const int *)ctx->glist.p, vs, ctx->flag);

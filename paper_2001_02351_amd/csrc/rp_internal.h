@@ -141,8 +141,8 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
 void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, double *vs, int *flag);
 void launch_eps(hipStream_t s, int nfreq, int ng, const double *vs, const double2 *chi,
                 double2 *eps, int *flag);
-void launch_invert(hipStream_t s, int nfreq, int ng, double2 *a, double2 *col, int *piv,
-                   int *flag);
+size_t invert_scratch_bytes(int ng, int nfreq);
+void launch_invert(hipStream_t s, int nfreq, int ng, double2 *a, double2 *scratch, int *piv, int *flag);
 void launch_W(hipStream_t s, int nfreq, int ng, const double *vs, const double2 *einv,
               double2 *W);
 

@@ -1,8 +1,8 @@
 // Steps a7-a9 (Eqs. epsGG, Wq):
 //   eps_GG'(w)   = delta_GG' - v^1/2_G chi_GG'(w) v^1/2_G',  v^1/2_G = sqrt(4 pi/Omega)/|q+G|
 //   eps^-1(w)    by in-place Gauss-Jordan elimination with partial (row)
-//                pivoting, all frequencies of a q-point in one batched launch
-//                per elimination step, FP64 throughout
+//                pivoting, blocked, all frequencies of a q-point batched,
+//                FP64 throughout
 //   W_GG'(w)     = HA * v^1/2_G eps^-1_GG'(w) v^1/2_G'   (eV)
 //
 // Elimination step c (per matrix): pick the row r >= c of largest |a_rc|,
@@ -10,6 +10,17 @@
 // subtract a_ic * row c from every other row i (leaving -a_ic/a_cc in column
 // c).  After the last step the recorded row swaps are undone as column swaps
 // in reverse order, which leaves A^-1 in place.
+//
+// Blocked form: the steps of a panel of columns K = [c0, c0 + nb) are run on
+// the panel's columns only (after the full-row swaps), and the other columns
+// R are brought up to date afterwards in one pass.  The steps on K act on the
+// matrix as the sweep on block K: with P the panel columns after the panel
+// steps (rows K: A_KK^-1, other rows: -A_OK A_KK^-1) and A_KR the pivot rows
+// of R before the panel, the updated R columns are
+//     A[:, R] = P A_KR + (rows outside K: A[:, R] as they were),
+// a complex matrix product with an inner dimension of nb, run on the FP64
+// matrix cores.  The arithmetic is that of the unblocked steps regrouped, and
+// the pivots are the same.
 //
 // eps is dimensionless with a unit-scale diagonal, so a pivot below
 // kPivotFloor (a condition number beyond ~1e13, where an FP64 inverse has no
@@ -51,74 +62,157 @@ __global__ void k_eps(int nfreq, int ng, const double *vs, const double2 *chi, d
     eps[t] = make_double2((g == h ? 1.0 : 0.0) - s * c.x, -s * c.y);
 }
 
-// pivot search, row swap and pivot-row scaling for step c; one block per matrix
-__global__ void __launch_bounds__(256) k_gj_pivot(int ng, int c, double2 *a, double2 *col, int *piv,
-                                                  int *flag)
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGjNb = 64;       // panel width
+constexpr int kGjPanelThreads = 1024;
+constexpr int kGjMaxNg = 6144;  // largest N_G the panel kernel's LDS holds
+
+// The steps of panel [c0, c0 + nb) on the panel's columns; one block per
+// matrix.  Per step: pivot search over rows >= c of column c, swap of the
+// full rows, scaling of the pivot row's panel entries, elimination of the
+// other rows' panel entries.  At the end the panel's pivot rows (all
+// columns) are saved to rk [nb][ng] for the update of the other columns.
+__global__ void __launch_bounds__(kGjPanelThreads)
+k_gj_panel(int ng, int c0, int nb, double2 *a, double2 *rk, int *piv, int *flag)
 {
-    __shared__ double bv[256];
-    __shared__ int bi[256];
+    __shared__ double2 fcol[kGjMaxNg];   // column c after the swap
+    __shared__ double2 prow[kGjNb];      // scaled pivot row, panel columns
+    __shared__ double bv[kGjPanelThreads];
+    __shared__ int bi[kGjPanelThreads];
     const int f = blockIdx.x, tid = threadIdx.x;
     double2 *A = a + (long)f * ng * ng;
-    double best = -1.0;
-    int bidx = c;
-    for (int i = c + tid; i < ng; i += 256) {
-        const double2 v = A[(long)i * ng + c];
-        const double m = isfinite(v.x) && isfinite(v.y) ? hypot(v.x, v.y) : INFINITY;
-        if (m > best || (m == best && i < bidx)) { best = m; bidx = i; }
-    }
-    bv[tid] = best;
-    bi[tid] = bidx;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) {
-            const double o = bv[tid + s];
-            const int oi = bi[tid + s];
-            if (o > bv[tid] || (o == bv[tid] && oi < bi[tid])) { bv[tid] = o; bi[tid] = oi; }
+    for (int c = c0; c < c0 + nb; c++) {
+        double best = -1.0;
+        int bidx = c;
+        for (int i = c + tid; i < ng; i += kGjPanelThreads) {
+            const double2 v = A[(long)i * ng + c];
+            const double m = isfinite(v.x) && isfinite(v.y) ? hypot(v.x, v.y) : INFINITY;
+            if (m > best || (m == best && i < bidx)) { best = m; bidx = i; }
+        }
+        bv[tid] = best;
+        bi[tid] = bidx;
+        __syncthreads();
+        for (int st = kGjPanelThreads / 2; st > 0; st >>= 1) {
+            if (tid < st) {
+                const double o = bv[tid + st];
+                const int oi = bi[tid + st];
+                if (o > bv[tid] || (o == bv[tid] && oi < bi[tid])) { bv[tid] = o; bi[tid] = oi; }
+            }
+            __syncthreads();
+        }
+        const int r = bi[0];
+        const double pm = bv[0];
+        if (tid == 0) {
+            piv[(long)f * ng + c] = r;
+            if (!isfinite(pm)) atomicOr(flag, kFlagNonFinite);
+            else if (!(pm > kPivotFloor)) atomicOr(flag, kFlagZeroPivot);
+        }
+        if (r != c) {
+            for (int j = tid; j < ng; j += kGjPanelThreads) {
+                const double2 t = A[(long)c * ng + j];
+                A[(long)c * ng + j] = A[(long)r * ng + j];
+                A[(long)r * ng + j] = t;
+            }
+        }
+        __syncthreads();
+        const double2 p = A[(long)c * ng + c];
+        const double den = p.x * p.x + p.y * p.y;
+        const double2 ip = make_double2(p.x / den, -p.y / den);
+        for (int i = tid; i < ng; i += kGjPanelThreads) fcol[i] = A[(long)i * ng + c];
+        for (int jj = tid; jj < nb; jj += kGjPanelThreads) {
+            const int j = c0 + jj;
+            prow[jj] = (j == c) ? ip : cmul(A[(long)c * ng + j], ip);
+        }
+        __syncthreads();
+        for (long e = tid; e < (long)ng * nb; e += kGjPanelThreads) {
+            const int i = (int)(e / nb), jj = (int)(e - (long)i * nb), j = c0 + jj;
+            double2 *x = A + (long)i * ng + j;
+            if (i == c) {
+                *x = prow[jj];
+            } else {
+                const double2 fi = fcol[i];
+                *x = (j == c) ? cmul(make_double2(-fi.x, -fi.y), ip) : csub(*x, cmul(fi, prow[jj]));
+            }
         }
         __syncthreads();
     }
-    const int r = bi[0];
-    const double pm = bv[0];
-    if (tid == 0) {
-        piv[(long)f * ng + c] = r;
-        if (!isfinite(pm)) atomicOr(flag, kFlagNonFinite);
-        else if (!(pm > kPivotFloor)) atomicOr(flag, kFlagZeroPivot);
-    }
-    if (r != c) {
-        for (int j = tid; j < ng; j += 256) {
-            const double2 t = A[(long)c * ng + j];
-            A[(long)c * ng + j] = A[(long)r * ng + j];
-            A[(long)r * ng + j] = t;
-        }
-    }
-    __syncthreads();
-    const double2 p = A[(long)c * ng + c];
-    const double den = p.x * p.x + p.y * p.y;
-    const double2 ip = make_double2(p.x / den, -p.y / den);
-    // save column c (after the swap) for the elimination kernel
-    for (int i = tid; i < ng; i += 256) col[(long)f * ng + i] = A[(long)i * ng + c];
-    __syncthreads();
-    for (int j = tid; j < ng; j += 256) {
-        const double2 v = (j == c) ? make_double2(1.0, 0.0) : A[(long)c * ng + j];
-        A[(long)c * ng + j] = cmul(v, ip);
+    double2 *R = rk + (long)f * kGjNb * ng;
+    for (long e = tid; e < (long)nb * ng; e += kGjPanelThreads) {
+        const int kk = (int)(e / ng), j = (int)(e - (long)kk * ng);
+        R[(long)kk * ng + j] = A[(long)(c0 + kk) * ng + j];
     }
 }
 
-// rows i != c: a_ij -= a_ic a_cj (j != c), a_ic = -a_ic a_cc
-__global__ void k_gj_elim(int ng, int c, double2 *a, const double2 *col)
+__device__ __forceinline__ d4 mfma64(double x, double y, d4 c)
 {
-    const int f = blockIdx.z;
-    const int i = blockIdx.y;
-    if (i == c) return;
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+}
+
+// Update of the columns outside panel [c0, c0 + nb) (see the header):
+//   A[i][j] = sum_k A[i][c0 + k] rk[k][j] + (i outside the panel rows ? A[i][j] : 0)
+// A 256-thread block owns a 64x64 tile of one matrix; each wave a 32x32
+// sub-tile (2x2 blocks of 16x16) on v_mfma_f64_16x16x4f64 (A operand lane
+// i + 16k, B operand lane j + 16k, result register r of lane l at row
+// l / 16 + 4 r, column l % 16).  The panel columns of the tile's rows and the
+// pivot rows of its columns are staged in LDS.
+__global__ void __launch_bounds__(256)
+k_gj_update(int ng, int c0, int nb, double2 *a, const double2 *rk)
+{
+    __shared__ double2 sP[64][kGjNb + 1];
+    __shared__ double2 sR[kGjNb][64];
+    const int f = blockIdx.z, tid = threadIdx.x;
+    const int rt0 = blockIdx.y * 64, ct0 = blockIdx.x * 64;
+    if (ct0 >= c0 && ct0 + 64 <= c0 + nb) return;   // tile inside the panel columns
     double2 *A = a + (long)f * ng * ng;
-    const double2 fi = col[(long)f * ng + i];
-    if (fi.x == 0.0 && fi.y == 0.0) return;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ng; j += gridDim.x * blockDim.x) {
-        const double2 pc = A[(long)c * ng + j];
-        const double2 prod = cmul(fi, pc);
-        if (j == c) A[(long)i * ng + j] = make_double2(-prod.x, -prod.y);
-        else A[(long)i * ng + j] = csub(A[(long)i * ng + j], prod);
+    const double2 *R = rk + (long)f * kGjNb * ng;
+    for (int e = tid; e < 64 * kGjNb; e += 256) {
+        const int rr = e / kGjNb, k = e - rr * kGjNb, i = rt0 + rr;
+        sP[rr][k] = (i < ng && k < nb) ? A[(long)i * ng + c0 + k] : make_double2(0.0, 0.0);
     }
+    for (int e = tid; e < kGjNb * 64; e += 256) {
+        const int k = e >> 6, cc = e & 63, j = ct0 + cc;
+        sR[k][cc] = (k < nb && j < ng) ? R[(long)k * ng + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    d4 accR[2][2], accI[2][2];
+#pragma unroll
+    for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++) {
+            accR[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+            accI[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+    for (int k0 = 0; k0 < nb; k0 += 4) {
+        double2 x[2], y[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; rb++) x[rb] = sP[wr + rb * 16 + li][k0 + lk];
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++) y[cb] = sR[k0 + lk][wc + cb * 16 + li];
+#pragma unroll
+        for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+            for (int cb = 0; cb < 2; cb++) {
+                accR[rb][cb] = mfma64(x[rb].x, y[cb].x, accR[rb][cb]);
+                accR[rb][cb] = mfma64(-x[rb].y, y[cb].y, accR[rb][cb]);
+                accI[rb][cb] = mfma64(x[rb].x, y[cb].y, accI[rb][cb]);
+                accI[rb][cb] = mfma64(x[rb].y, y[cb].x, accI[rb][cb]);
+            }
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int i = rt0 + wr + rb * 16 + lk + 4 * r, j = ct0 + wc + cb * 16 + li;
+                if (i >= ng || j >= ng || (j >= c0 && j < c0 + nb)) continue;
+                double2 v = make_double2(accR[rb][cb][r], accI[rb][cb][r]);
+                if (i < c0 || i >= c0 + nb) v = cadd(v, A[(long)i * ng + j]);
+                A[(long)i * ng + j] = v;
+            }
 }
 
 // undo the row swaps as column swaps in reverse order; one thread per row
@@ -168,12 +262,16 @@ void launch_eps(hipStream_t s, int nfreq, int ng, const double *vs, const double
                        eps, flag);
 }
 
-void launch_invert(hipStream_t s, int nfreq, int ng, double2 *a, double2 *col, int *piv, int *flag)
+size_t invert_scratch_bytes(int ng, int nfreq) { return sizeof(double2) * (size_t)kGjNb * ng * nfreq; }
+
+void launch_invert(hipStream_t s, int nfreq, int ng, double2 *a, double2 *scratch, int *piv, int *flag)
 {
-    const unsigned xb = (unsigned)std::min(8, (ng + 255) / 256);
-    for (int c = 0; c < ng; c++) {
-        hipLaunchKernelGGL(k_gj_pivot, dim3(nfreq), dim3(256), 0, s, ng, c, a, col, piv, flag);
-        hipLaunchKernelGGL(k_gj_elim, dim3(xb, ng, nfreq), dim3(256), 0, s, ng, c, a, col);
+    const unsigned t = (unsigned)((ng + 63) / 64);
+    for (int c0 = 0; c0 < ng; c0 += kGjNb) {
+        const int nb = std::min(kGjNb, ng - c0);
+        hipLaunchKernelGGL(k_gj_panel, dim3(nfreq), dim3(kGjPanelThreads), 0, s, ng, c0, nb, a, scratch, piv,
+                           flag);
+        hipLaunchKernelGGL(k_gj_update, dim3(t, t, nfreq), dim3(256), 0, s, ng, c0, nb, a, scratch);
     }
     const long rows = (long)nfreq * ng;
     hipLaunchKernelGGL(k_gj_unswap, dim3((unsigned)((rows + 127) / 128)), dim3(128), 0, s, nfreq, ng, a,
