@@ -73,40 +73,49 @@ constexpr int kGjMaxNg = 6144;  // largest N_G the panel kernel's LDS holds
 // full rows, scaling of the pivot row's panel entries, elimination of the
 // other rows' panel entries.  At the end the panel's pivot rows (all
 // columns) are saved to rk [nb][ng] for the update of the other columns.
+// (|v|, row) of the larger pivot candidate; ties go to the lower row
+__device__ __forceinline__ void pivot_max(double &m, int &r, double om, int orow)
+{
+    if (om > m || (om == m && orow < r)) { m = om; r = orow; }
+}
+
 __global__ void __launch_bounds__(kGjPanelThreads)
 k_gj_panel(int ng, int c0, int nb, double2 *a, double2 *rk, int *piv, int *flag)
 {
+    constexpr int NWV = kGjPanelThreads / 64;
     __shared__ double2 fcol[kGjMaxNg];   // column c after the swap
     __shared__ double2 prow[kGjNb];      // scaled pivot row, panel columns
-    __shared__ double bv[kGjPanelThreads];
-    __shared__ int bi[kGjPanelThreads];
-    const int f = blockIdx.x, tid = threadIdx.x;
+    __shared__ double bv[NWV];
+    __shared__ int bi[NWV];
+    const int f = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int jj = tid % kGjNb, rs = tid / kGjNb;   // panel column and row lane of the elimination
+    constexpr int RSTEP = kGjPanelThreads / kGjNb;
     double2 *A = a + (long)f * ng * ng;
     for (int c = c0; c < c0 + nb; c++) {
+        // pivot: largest |a_ic| over rows i >= c (wave shuffles, then across waves)
         double best = -1.0;
         int bidx = c;
         for (int i = c + tid; i < ng; i += kGjPanelThreads) {
             const double2 v = A[(long)i * ng + c];
             const double m = isfinite(v.x) && isfinite(v.y) ? hypot(v.x, v.y) : INFINITY;
-            if (m > best || (m == best && i < bidx)) { best = m; bidx = i; }
+            pivot_max(best, bidx, m, i);
         }
-        bv[tid] = best;
-        bi[tid] = bidx;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) pivot_max(best, bidx, __shfl_xor(best, o), __shfl_xor(bidx, o));
+        if (lane == 0) {
+            bv[wave] = best;
+            bi[wave] = bidx;
+        }
         __syncthreads();
-        for (int st = kGjPanelThreads / 2; st > 0; st >>= 1) {
-            if (tid < st) {
-                const double o = bv[tid + st];
-                const int oi = bi[tid + st];
-                if (o > bv[tid] || (o == bv[tid] && oi < bi[tid])) { bv[tid] = o; bi[tid] = oi; }
-            }
-            __syncthreads();
-        }
-        const int r = bi[0];
-        const double pm = bv[0];
+        best = bv[0];
+        bidx = bi[0];
+#pragma unroll
+        for (int w = 1; w < NWV; w++) pivot_max(best, bidx, bv[w], bi[w]);
+        const int r = bidx;
         if (tid == 0) {
             piv[(long)f * ng + c] = r;
-            if (!isfinite(pm)) atomicOr(flag, kFlagNonFinite);
-            else if (!(pm > kPivotFloor)) atomicOr(flag, kFlagZeroPivot);
+            if (!isfinite(best)) atomicOr(flag, kFlagNonFinite);
+            else if (!(best > kPivotFloor)) atomicOr(flag, kFlagZeroPivot);
         }
         if (r != c) {
             for (int j = tid; j < ng; j += kGjPanelThreads) {
@@ -120,28 +129,29 @@ k_gj_panel(int ng, int c0, int nb, double2 *a, double2 *rk, int *piv, int *flag)
         const double den = p.x * p.x + p.y * p.y;
         const double2 ip = make_double2(p.x / den, -p.y / den);
         for (int i = tid; i < ng; i += kGjPanelThreads) fcol[i] = A[(long)i * ng + c];
-        for (int jj = tid; jj < nb; jj += kGjPanelThreads) {
-            const int j = c0 + jj;
-            prow[jj] = (j == c) ? ip : cmul(A[(long)c * ng + j], ip);
+        if (tid < nb) {
+            const int j = c0 + tid;
+            prow[tid] = (j == c) ? ip : cmul(A[(long)c * ng + j], ip);
         }
         __syncthreads();
-        for (long e = tid; e < (long)ng * nb; e += kGjPanelThreads) {
-            const int i = (int)(e / nb), jj = (int)(e - (long)i * nb), j = c0 + jj;
-            double2 *x = A + (long)i * ng + j;
-            if (i == c) {
-                *x = prow[jj];
-            } else {
-                const double2 fi = fcol[i];
-                *x = (j == c) ? cmul(make_double2(-fi.x, -fi.y), ip) : csub(*x, cmul(fi, prow[jj]));
+        if (jj < nb) {
+            const int j = c0 + jj;
+            const double2 pj = prow[jj];
+            for (int i = rs; i < ng; i += RSTEP) {
+                double2 *x = A + (long)i * ng + j;
+                if (i == c) {
+                    *x = pj;
+                } else {
+                    const double2 fi = fcol[i];
+                    *x = (j == c) ? cmul(make_double2(-fi.x, -fi.y), ip) : csub(*x, cmul(fi, pj));
+                }
             }
         }
         __syncthreads();
     }
     double2 *R = rk + (long)f * kGjNb * ng;
-    for (long e = tid; e < (long)nb * ng; e += kGjPanelThreads) {
-        const int kk = (int)(e / ng), j = (int)(e - (long)kk * ng);
-        R[(long)kk * ng + j] = A[(long)(c0 + kk) * ng + j];
-    }
+    for (int kk = 0; kk < nb; kk++)
+        for (int j = tid; j < ng; j += kGjPanelThreads) R[(long)kk * ng + j] = A[(long)(c0 + kk) * ng + j];
 }
 
 __device__ __forceinline__ d4 mfma64(double x, double y, d4 c)

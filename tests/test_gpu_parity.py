@@ -182,6 +182,9 @@ def test_abi_errors(ctx, rp, c1, d1):
         rp.rp_screen_W(ctx, d.cell, (0, 0, 0), 4, g_with_zero, 1, chi, None, None)
     assert e.value.status == 3            # RP_E_RANGE: |q+G| = 0
     with pytest.raises(rp.RpError) as e:
+        rp.rp_screen_W(ctx, d.cell, p.iq, 6145, np.ones((6145, 3), np.int32), 1, chi, None, None)
+    assert e.value.status == 8            # RP_E_UNSUPPORTED: N_G above the inversion's LDS plan
+    with pytest.raises(rp.RpError) as e:
         rp.rp_weights(ctx, d.cell, p.iq, d.nband, d.energy, None, 0, 1, 1, 2, 0, 1, 1, [0.0],
                       -0.1, 0, torch.empty((1, 1, 2), dtype=torch.float64, device="cuda"))
     assert e.value.status == 3            # delta < 0
