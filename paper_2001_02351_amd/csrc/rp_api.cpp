@@ -334,9 +334,10 @@ rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int
     const int nO = o1 - o0, nE = e1 - e0, nK = k1 - k0;
     if ((long)nO * nE * nK == 0) return RP_OK;
     const long nr = (long)g.fft[0] * g.fft[1] * g.fft[2];
-    // LDS budget of the pair kernel (window along m3 is at most hi-lo+2)
+    // LDS budget of the generic pair kernel (window along m3 is at most
+    // hi-lo+2; band blocks of 2x2 in FP32, 1x1 in FP64)
     const int L3max = hi[2] - lo[2] + 2;
-    if (pair_lds_bytes(g.fft, L3max, pair_rows(g.fft), fp32 ? 8 : 16, 4) > 160 * 1024)
+    if (pair_lds_bytes(g.fft, L3max, pair_rows(g.fft), fp32 ? 8 : 16, fp32 ? 4 : 1) > 160 * 1024)
         return fail(ctx, RP_E_UNSUPPORTED, "grid %dx%dx%d too large for the pair kernel's LDS plan",
                     g.fft[0], g.fft[1], g.fft[2]);
     if (!fp32 && (st = ensure(ctx, ctx->ugrid, sizeof(double2) * nr * (nO + nE))) != RP_OK) return st;

@@ -14,6 +14,8 @@ from .gen import (  # noqa: F401
     Problem,
     make_problem,
     mesh_fractions,
+    batch_system,
     parity_workload,
     srvo3_workload,
+    supercell_workload,
 )

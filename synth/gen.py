@@ -296,3 +296,50 @@ def srvo3_workload(seed: Optional[int] = None, workers: Optional[int] = None) ->
                         freq_eV=np.linspace(0.0, 20.0, 20), delta_eV=0.1,
                         nwan=10, alpha_range=(1.1, 1.9),
                         seed=2 if seed is None else seed, workers=workers)
+
+
+BATCH_EDGES = (24, 25, 27, 30, 32, 36, 40)
+
+
+def batch_system(s: int, iq_index: int = 0, workers: Optional[int] = None) -> Problem:
+    """System s (0 <= s < 24) of the batched uneven workload, at its
+    iq_index-th q-point (0 <= iq_index < 4).  Drawn from seed 400 + s: cubic
+    grid edge from BATCH_EDGES, cell edge scaled with it (a = a_SrVO3 edge/48),
+    k-mesh edge in 2..6, 16..64 occupied + 48..256 empty bands, plane-wave
+    spheres of about max(300, 1.25 n_band) vectors, N_G in 300..1200; the
+    q-points are the first four non-Gamma mesh points in lexicographic order;
+    16 imaginary frequencies i nu, nu in {0} and geomspace(0.1, 100, 15) eV,
+    delta = 0, generalized tetrahedron."""
+    if not 0 <= s < 24 or not 0 <= iq_index < 4:
+        raise ValueError("system index in 0..23, q index in 0..3")
+    rng = np.random.default_rng(400 + s)
+    edge = int(rng.choice(BATCH_EDGES))
+    kedge = int(rng.integers(2, 7))
+    nocc = int(rng.integers(16, 65))
+    nemp = int(rng.integers(48, 257))
+    ng = int(rng.integers(300, 1201))
+    a = A_SRVO3_BOHR * edge / 48.0
+    b = 2.0 * math.pi / a
+    npw_target = max(300, int(1.25 * (nocc + nemp)))
+    gpsi = b * (3.0 * npw_target / (4.0 * math.pi)) ** (1.0 / 3.0)
+    qs = [(i, j, k) for i in range(kedge) for j in range(kedge) for k in range(kedge)
+          if (i, j, k) != (0, 0, 0)]
+    nu = np.concatenate([[0.0], np.geomspace(0.1, 100.0, 15)])
+    return make_problem(name=f"batch_system_{s}_q{iq_index}", a_bohr=a, fft=(edge, edge, edge),
+                        kmesh=(kedge, kedge, kedge), iq=qs[iq_index], nocc=nocc, nemp=nemp,
+                        gpsi=gpsi, ng=ng, freq_eV=1j * nu, delta_eV=0.0, nwan=0,
+                        seed=400 + s, workers=workers)
+
+
+def supercell_workload(nocc: int = 600, nemp: int = 1200, workers: Optional[int] = None) -> Problem:
+    """A 4x4x4 supercell of the SrVO3-shaped cell (a = 29.045 bohr): 96^3
+    grid, Gamma-only k mesh, q = 0 (G = 0 dropped), 600 + 1200 bands,
+    plane-wave sphere of radius 8.31 (2 pi/a) (about 2 400 vectors),
+    N_G = 6000, 16 real frequencies on [0, 20] eV, delta = 0.1 eV (sampling
+    weights, N_k = 1), 20 Wannier Gaussians with alpha in [0.1, 0.45]."""
+    a = 4.0 * A_SRVO3_BOHR
+    b = 2.0 * math.pi / a
+    return make_problem(name="supercell_96cube_gamma", a_bohr=a, fft=(96, 96, 96), kmesh=(1, 1, 1),
+                        iq=(0, 0, 0), nocc=nocc, nemp=nemp, gpsi=8.31 * b, ng=6000,
+                        freq_eV=np.linspace(0.0, 20.0, 16), delta_eV=0.1, nwan=20,
+                        alpha_range=(0.1, 0.45), seed=5, workers=workers)
