@@ -19,7 +19,12 @@ Inputs are resident in HBM before the timed region.
                 HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE
                 counters, scaled by what they read for a plain copy, as
                 recorded in profiles/k_chi_bf16_traffic.md (reported only
-                while the kernel source matches the recorded hash)
+                while the kernel source matches the recorded hash), and
+                mfma_counter_frac the executed MFMA flops from the BF16
+                MOPS counter recorded there
+  hbm_a2_a4     HBM bytes of the pair kernel and the u-grid kernels from
+                profiles/pair_stage_hbm_counters.md over their stage times,
+                with the algorithmic bytes (u-grids once + M) beside them
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload
 
 Counter runs use two extra modes: --copy-calibration (a plain 1 GiB device
@@ -42,28 +47,56 @@ if ROOT not in sys.path:
 METRIC = "χ0 build TFLOP/s + s/q-point, split-BF16 vs FP64, at rel err ≤1e-5 vs oracle"
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_chi_bf16_traffic.md")
 CHI_SOURCE = os.path.join(ROOT, "paper_2001_02351_amd", "csrc", "chi_bf16.hip")
 
 
-def recorded_traffic():
-    """HBM bytes per k_chi_bf16 launch from the committed counter summary, or
-    None when there is none or the kernel source changed since it was taken."""
+PAIR_FILE = os.path.join(ROOT, "profiles", "pair_stage_hbm_counters.md")
+
+
+def _sha(path):
     import hashlib
-    if not os.path.exists(TRAFFIC_FILE):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _recorded(path, keys):
+    """key: value lines of a committed counter summary (None if absent)."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             line = line.strip().strip("`")
-            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
-                k, v = line.split(":", 1)
-                vals[k.strip()] = v.strip()
-    with open(CHI_SOURCE, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if vals.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+            k = line.split(":", 1)[0].strip()
+            if ":" in line and k in keys:
+                vals[k] = line.split(":", 1)[1].strip()
+    return vals
+
+
+def recorded_traffic():
+    """HBM bytes and BF16 MFMA ops per k_chi_bf16 launch from the committed
+    counter summary, or None when there is none or the kernel source changed
+    since it was taken."""
+    vals = _recorded(TRAFFIC_FILE, ("traffic_bytes_per_launch", "mfma_mops_per_launch",
+                                    "kernel_source_sha256"))
+    if not vals or vals.get("kernel_source_sha256") != _sha(CHI_SOURCE) or \
+            "traffic_bytes_per_launch" not in vals:
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    return {k: float(v) for k, v in vals.items() if k != "kernel_source_sha256"}
+
+
+def recorded_pair_counters():
+    """HBM bytes of the pair kernel (per launch = per k-point) and of the u-grid
+    kernels (per k-point), or None when the sources changed."""
+    vals = _recorded(PAIR_FILE, ("pair_bytes_per_launch", "ugrid_bytes_per_k", "pair_source_sha256",
+                                 "fft_source_sha256"))
+    csrc = os.path.join(ROOT, "paper_2001_02351_amd", "csrc")
+    if not vals or vals.get("pair_source_sha256") != _sha(os.path.join(csrc, "pair.hip")) or \
+            vals.get("fft_source_sha256") != _sha(os.path.join(csrc, "fft.hip")):
+        return None
+    return {k: float(vals[k]) for k in ("pair_bytes_per_launch", "ugrid_bytes_per_k")}
 
 
 def copy_calibration():
@@ -165,7 +198,7 @@ def run_leg(rp, path, ctx, d, prec, steps, warmup, kbatch):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--fp64-warmup", type=int, default=0)
@@ -197,6 +230,7 @@ def main():
         baseline = cpu_baseline(prob)
         log(f"oracle sample: {baseline['sample']}")
 
+    import numpy as np
     import torch
 
     import paper_2001_02351_amd as rp
@@ -245,6 +279,22 @@ def main():
 
     npair_total = d.nk * prob.nocc * prob.nemp
     achieved = split["chi_kernel_flops_per_launch"] / (split["chi_kernel_ms_per_launch"] / 1e3) / 1e12
+    rec = recorded_traffic()
+    pc = recorded_pair_counters()
+    hbm = None
+    if pc is not None:
+        t_pair = split["stage_ms_per_step"]["pair"] / d.nk / 1e3      # s per k-point (one launch)
+        t_ugrid = split["stage_ms_per_step"]["ugrid"] / d.nk / 1e3
+        alg = (prob.nocc + prob.nemp) * int(np.prod(prob.fft)) * 8 + prob.nocc * prob.nemp * d.ng * 16
+        hbm = {
+            "pair_kernel": {"bytes_per_launch": pc["pair_bytes_per_launch"], "ms_per_launch": t_pair * 1e3,
+                            "achieved_GB_s": pc["pair_bytes_per_launch"] / t_pair / 1e9,
+                            "algorithmic_bytes_per_launch": alg,
+                            "algorithmic_GB_s": alg / t_pair / 1e9, "peak_GB_s": PEAK_HBM_GBS},
+            "ugrid_kernels": {"bytes_per_k": pc["ugrid_bytes_per_k"], "ms_per_k": t_ugrid * 1e3,
+                              "achieved_GB_s": pc["ugrid_bytes_per_k"] / t_ugrid / 1e9,
+                              "peak_GB_s": PEAK_HBM_GBS},
+        }
     out = {
         "metric": METRIC,
         "value": split["chi0_tflops"],
@@ -279,10 +329,14 @@ def main():
             "peak": PEAK_BF16_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_BF16_TFLOPS,
-            "traffic": recorded_traffic(),
+            "traffic": None if rec is None else rec["traffic_bytes_per_launch"],
             "kernel": "k_chi_bf16 (chi0 contraction, split-BF16)",
             "mfma_executed_frac": 3.0 * achieved / PEAK_BF16_TFLOPS,
+            "mfma_counter_frac": None if rec is None or "mfma_mops_per_launch" not in rec else
+            rec["mfma_mops_per_launch"] * 512.0 / (split["chi_kernel_ms_per_launch"] / 1e3) / 1e12 /
+            PEAK_BF16_TFLOPS,
         },
+        "hbm_a2_a4": hbm,
         "cpu_baseline": None if baseline is None else {k: baseline[k] for k in
                                                         ("value", "unit", "cores", "kind", "sample")},
     }
