@@ -169,6 +169,59 @@ rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], 
                              rp_precision prec, int accumulate, double *chi);
 
 /*
+ * Steps a2-a6 for a batch of independent chi0 problems (section "Parallel
+ * calculation": q-points are independent, and chi of one q is a sum of
+ * band-pair blocks), enqueued as one HIP graph launch.  Each problem carries
+ * the arguments of rp_pair_density and rp_chi0_accumulate; its k range
+ * [k0, k1) is processed kbatch k-points at a time: the pair densities of a
+ * batch go to a context-owned buffer, then their weights and contraction are
+ * added into the problem's chi (the first batch overwrites chi when
+ * accumulate = 0).  A problem with no pairs only clears chi (accumulate = 0).
+ * Problems may differ in cell, grid, k mesh, bands, N_G and frequencies;
+ * they run one after the other on the context's stream, sharing workspace.
+ *
+ * The first call captures every launch of the batch into a graph and
+ * launches it.  A later call with the same problems (the same scalars and
+ * pointers, and the same contents of the host arrays npw, gsph and freq_eV)
+ * relaunches that graph without capturing again; any difference captures a
+ * new graph.  The device arrays are read when the graph runs.
+ *
+ * Fields of rp_problem, as in rp_pair_density and rp_chi0_accumulate:
+ *   npw (host int[Nk]), mmax, miller (dev), coef (dev), energy_eV (dev),
+ *   T (dev or NULL), gsph (host int[ng][3]), freq_eV (host c128[nfreq]),
+ *   chi (dev c128[nfreq][ng][ng] output, hartree^-1).
+ * kbatch >= 1 sets the pair-density buffer: 16*kbatch*(o1-o0)*(e1-e0)*ng
+ * bytes for the largest problem.
+ * prec applies to every problem.
+ * Errors: those of rp_pair_density and rp_chi0_accumulate, with "problem i:"
+ * in the message; RP_E_SHAPE for kbatch < 1 or nprob < 0.  On a non-OK
+ * status nothing has been launched.
+ */
+typedef struct rp_problem {
+    rp_cell cell;
+    int iq[3];
+    int nband, npw_max;
+    const int *npw;
+    int mmax[3];
+    const int *miller;
+    const double *coef;
+    const double *energy_eV;
+    const double *T;
+    int o0, o1, e0, e1, k0, k1;
+    int ng;
+    const int *gsph;
+    int nfreq;
+    const double *freq_eV;
+    double delta_eV;
+    rp_weight_mode wm;
+    int kbatch;
+    int accumulate;
+    double *chi;
+} rp_problem;
+
+rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_precision prec);
+
+/*
  * Steps a7-a9: eps = I - v^1/2 chi v^1/2 with v^1/2_G = sqrt(4 pi/Omega)/|q+G|
  * (Eq. epsGG), eps^-1 per frequency by FP64 Gauss-Jordan elimination with
  * partial pivoting (blocked in panels of 64 columns), and W = v^1/2 eps^-1
@@ -221,6 +274,8 @@ rp_status rp_wannier_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nw
  *   RP_STAGE_CHI      chi contraction kernel (FP64 or split-BF16), a6
  *   RP_STAGE_SCREEN   eps, inversion and W, a7-a9
  *   RP_STAGE_WANNIER  Wannier densities and projection, a10
+ *   RP_STAGE_BATCH    one rp_chi0_batch graph launch, a2-a6 of every problem
+ *                     (the per-stage timers do not run inside the graph)
  * rp_profile(ctx, 1) enables and resets; rp_profile(ctx, 0) disables.
  * rp_profile_read synchronizes the stream and returns, per stage, the summed
  * milliseconds and the number of timed launches (arrays of RP_NSTAGE).
@@ -233,7 +288,8 @@ enum {
     RP_STAGE_CHI = 4,
     RP_STAGE_SCREEN = 5,
     RP_STAGE_WANNIER = 6,
-    RP_NSTAGE = 7
+    RP_STAGE_BATCH = 7,
+    RP_NSTAGE = 8
 };
 
 rp_status rp_profile(rp_ctx *ctx, int enable);

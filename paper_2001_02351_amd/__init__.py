@@ -18,6 +18,8 @@ from ._rp import (  # noqa: F401
     load,
     make_cell,
     rp_chi0_accumulate,
+    rp_chi0_batch,
+    rp_problem,
     rp_last_error,
     rp_pair_density,
     rp_profile,

@@ -27,10 +27,10 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_E_NULL", 2: "RP_E_SHAPE", 3: "RP_E_RANGE", 4:
                 5: "RP_E_NOMEM", 6: "RP_E_DEVICE", 7: "RP_E_SINGULAR", 8: "RP_E_UNSUPPORTED"}
 
 EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pair_density",
-            "rp_weights", "rp_chi0_accumulate", "rp_screen_W", "rp_wannier_W", "rp_profile",
-            "rp_profile_read"]
+            "rp_weights", "rp_chi0_accumulate", "rp_chi0_batch", "rp_screen_W", "rp_wannier_W",
+            "rp_profile", "rp_profile_read"]
 
-STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier"]
+STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier", "batch"]
 
 
 class RpError(RuntimeError):
@@ -42,6 +42,18 @@ class RpError(RuntimeError):
 class rp_cell(ctypes.Structure):
     _fields_ = [("lat", (ctypes.c_double * 3) * 3), ("fft", ctypes.c_int * 3),
                 ("kmesh", ctypes.c_int * 3)]
+
+
+class rp_problem(ctypes.Structure):
+    """One chi0 problem of rp_chi0_batch (the C struct of the same name)."""
+    _fields_ = [("cell", rp_cell), ("iq", ctypes.c_int * 3), ("nband", ctypes.c_int),
+                ("npw_max", ctypes.c_int), ("npw", ctypes.c_void_p), ("mmax", ctypes.c_int * 3),
+                ("miller", ctypes.c_void_p), ("coef", ctypes.c_void_p), ("energy_eV", ctypes.c_void_p),
+                ("T", ctypes.c_void_p), ("o0", ctypes.c_int), ("o1", ctypes.c_int), ("e0", ctypes.c_int),
+                ("e1", ctypes.c_int), ("k0", ctypes.c_int), ("k1", ctypes.c_int), ("ng", ctypes.c_int),
+                ("gsph", ctypes.c_void_p), ("nfreq", ctypes.c_int), ("freq_eV", ctypes.c_void_p),
+                ("delta_eV", ctypes.c_double), ("wm", ctypes.c_int), ("kbatch", ctypes.c_int),
+                ("accumulate", ctypes.c_int), ("chi", ctypes.c_void_p)]
 
 
 def make_cell(lat, fft, kmesh) -> rp_cell:
@@ -77,6 +89,7 @@ def load(path: Optional[str] = None):
         "rp_pair_density": [P, cellp, P, I, I, P, P, P, P, I, I, I, I, I, I, I, P, I, P],
         "rp_weights": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, D, I, P],
         "rp_chi0_accumulate": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, I, P, D, I, I, I, P],
+        "rp_chi0_batch": [P, I, ctypes.POINTER(rp_problem), I],
         "rp_screen_W": [P, cellp, P, I, P, I, P, P, P],
         "rp_wannier_W": [P, cellp, P, I, P, P, I, P, I, P, I, P, P],
         "rp_profile": [P, I],
@@ -190,6 +203,35 @@ def rp_chi0_accumulate(ctx: Context, cell: rp_cell, iq, nband, energy_eV, T, o0,
                                     int(accumulate), _dp(chi))
     ctx._leave()
     ctx._check(st, "rp_chi0_accumulate")
+
+
+def rp_chi0_batch(ctx: Context, problems, prec):
+    """problems: a sequence of dicts with the rp_problem fields; "cell" is an
+    rp_cell, host arrays (npw, mmax, gsph, freq_eV) are numpy-convertible,
+    device arrays (miller, coef, energy_eV, T, chi) are torch tensors."""
+    keep = []
+    arr = (rp_problem * max(1, len(problems)))()
+    for i, q in enumerate(problems):
+        r = arr[i]
+        r.cell = q["cell"]
+        for a in range(3):
+            r.iq[a] = int(q["iq"][a])
+        npw_h, mm_h = _host(q["npw"], np.int32), _host(q["mmax"], np.int32)
+        g_h, f_h = _host(q["gsph"], np.int32), _host(q["freq_eV"], np.complex128)
+        keep += [npw_h, g_h, f_h]
+        for a in range(3):
+            r.mmax[a] = int(mm_h[a])
+        r.npw, r.gsph, r.freq_eV = _hp(npw_h), _hp(g_h), _hp(f_h)
+        r.miller, r.coef = _dp(q["miller"]), _dp(q["coef"])
+        r.energy_eV, r.T, r.chi = _dp(q["energy_eV"]), _dp(q.get("T")), _dp(q["chi"])
+        for name in ("nband", "npw_max", "o0", "o1", "e0", "e1", "k0", "k1", "ng", "nfreq", "wm",
+                     "kbatch", "accumulate"):
+            setattr(r, name, int(q[name]))
+        r.delta_eV = float(q["delta_eV"])
+    ctx._enter()
+    st = ctx.lib.rp_chi0_batch(ctx.handle, len(problems), arr, int(prec))
+    ctx._leave()
+    ctx._check(st, "rp_chi0_batch")
 
 
 def rp_screen_W(ctx: Context, cell: rp_cell, iq, ng, gsph, nfreq, chi, eps_inv, W):

@@ -117,7 +117,7 @@ static hipEvent_t take_event(rp_ctx *ctx)
 
 StageTimer::StageTimer(rp_ctx *ctx, int stage) : ctx_(ctx), stage_(stage)
 {
-    if (!ctx_->profiling) return;
+    if (!ctx_->profiling || ctx_->capturing) return;
     a_ = take_event(ctx_);
     if (a_) (void)hipEventRecord(a_, ctx_->stream);
 }
@@ -179,6 +179,260 @@ static rp_status check_gsph(rp_ctx *ctx, const Geometry &g, int ng, const int *g
             return fail(ctx, RP_E_RANGE, "%s[%d]: |q+G| = 0 (drop G = 0 at q = 0)", name, i);
     return RP_OK;
 }
+
+// ---- steps a2-a4: validated pair-density work, enqueued without allocation --
+
+// Host-side description of one pair-density request after validation.
+struct PairJob {
+    Geometry g;
+    FftPlan plans[3];
+    int nband = 0, npw_max = 0;
+    const int *npw = nullptr;       // host [Nk]
+    int mmax[3] = {0, 0, 0};
+    const int *miller = nullptr;    // device [Nk][npw_max][3]
+    const double2 *coef = nullptr;  // device [Nk][nband][npw_max]
+    int o0 = 0, o1 = 0, e0 = 0, e1 = 0;
+    int ng = 0;
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    bool fp32 = false;
+    bool empty = true;  // no band pairs in the requested ranges
+};
+
+static bool valid_prec(rp_precision prec)
+{
+    return prec == RP_FP64 || prec == RP_SPLIT_BF16 || prec == RP_SPLIT_BF16_X6;
+}
+
+static rp_status pair_check(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband, int npw_max,
+                            const int *npw, const int mmax[3], const int *miller, const double *coef, int o0,
+                            int o1, int e0, int e1, int k0, int k1, int ng, const int *gsph, rp_precision prec,
+                            PairJob *j)
+{
+    rp_status st = geometry(ctx, cell, iq, &j->g);
+    if (st != RP_OK) return st;
+    const Geometry &g = j->g;
+    if (!npw || !mmax || !miller || !coef) return fail(ctx, RP_E_NULL, "NULL array argument");
+    if ((st = check_ranges(ctx, g, nband, o0, o1, e0, e1, k0, k1)) != RP_OK) return st;
+    if (ng < 1 || ng > 6144) return fail(ctx, RP_E_UNSUPPORTED, "ng = %d outside [1, 6144]", ng);
+    if ((st = check_gsph(ctx, g, ng, gsph, "gsph")) != RP_OK) return st;
+    if (npw_max < 1) return fail(ctx, RP_E_SHAPE, "npw_max must be >= 1");
+    if (!valid_prec(prec)) return fail(ctx, RP_E_RANGE, "unknown precision");
+    j->fp32 = prec != RP_FP64;
+    if ((st = plans3(ctx, g, j->plans)) != RP_OK) return st;
+    for (int k = 0; k < g.nk; k++)
+        if (npw[k] < 0 || npw[k] > npw_max) return fail(ctx, RP_E_SHAPE, "npw[%d] outside [0, npw_max]", k);
+    // alias-free condition per axis: N > 2 mmax + max |m + G0|, G0 in {0, 1} when iq > 0
+    for (int a = 0; a < 3; a++) {
+        int lo = 1 << 30, hi = -(1 << 30);
+        for (int i = 0; i < ng; i++) {
+            lo = std::min(lo, gsph[3 * i + a]);
+            hi = std::max(hi, gsph[3 * i + a]);
+        }
+        j->lo[a] = lo;
+        j->hi[a] = hi;
+        const int up = hi + (iq[a] > 0 ? 1 : 0);
+        const int gmax = std::max(std::abs(lo), std::abs(up));
+        if (mmax[a] < 0) return fail(ctx, RP_E_SHAPE, "mmax[%d] < 0", a);
+        if (g.fft[a] <= 2 * mmax[a] + gmax)
+            return fail(ctx, RP_E_ALIAS, "axis %d: N=%d <= 2*mmax+|G|max = %d (pair products alias)", a,
+                        g.fft[a], 2 * mmax[a] + gmax);
+        j->mmax[a] = mmax[a];
+    }
+    j->nband = nband;
+    j->npw_max = npw_max;
+    j->npw = npw;
+    j->miller = miller;
+    j->coef = (const double2 *)coef;
+    j->o0 = o0;
+    j->o1 = o1;
+    j->e0 = e0;
+    j->e1 = e1;
+    j->ng = ng;
+    j->empty = (long)(o1 - o0) * (e1 - e0) * (k1 - k0) == 0;
+    if (j->empty) return RP_OK;
+    // LDS budget of the generic pair kernel (window along m3 is at most
+    // hi-lo+2; band blocks of 2x2 in FP32, 1x1 in FP64)
+    const int L3max = j->hi[2] - j->lo[2] + 2;
+    if (pair_lds_bytes(g.fft, L3max, pair_rows(g.fft), j->fp32 ? 8 : 16, j->fp32 ? 4 : 1) > 160 * 1024)
+        return fail(ctx, RP_E_UNSUPPORTED, "grid %dx%dx%d too large for the pair kernel's LDS plan", g.fft[0],
+                    g.fft[1], g.fft[2]);
+    return RP_OK;
+}
+
+// u-grid workspace of one k: the occupied and the empty bands' grids.
+static size_t pair_grid_bytes(const PairJob &j)
+{
+    const long nr = (long)j.g.fft[0] * j.g.fft[1] * j.g.fft[2];
+    return (size_t)nr * (size_t)((j.o1 - j.o0) + (j.e1 - j.e0)) * (j.fp32 ? sizeof(float2) : sizeof(double2));
+}
+
+// Enqueues steps a2-a4 for k in [k0, k1): per k, the u-grids of the occupied
+// bands at k and of the empty bands at k+q (into `grid`), then the pair
+// kernel into M[k - k0].  dg is the device copy of the G list.  No
+// allocation, copy or synchronization.
+static rp_status pair_enqueue(rp_ctx *ctx, const PairJob &j, int k0, int k1, const int *dg, void *grid,
+                              double2 *M)
+{
+    const Geometry &g = j.g;
+    const int nO = j.o1 - j.o0, nE = j.e1 - j.e0;
+    if ((long)nO * nE * (k1 - k0) == 0) return RP_OK;
+    const long nr = (long)g.fft[0] * g.fft[1] * g.fft[2];
+    const int L3 = j.hi[2] - j.lo[2] + 1;
+    for (int k = k0; k < k1; k++) {
+        const int n1 = k / (g.kmesh[1] * g.kmesh[2]), n2 = (k / g.kmesh[2]) % g.kmesh[1], n3 = k % g.kmesh[2];
+        const int s[3] = {n1 + g.iq[0], n2 + g.iq[1], n3 + g.iq[2]};
+        int r[3], g0[3];
+        for (int a = 0; a < 3; a++) {
+            r[a] = s[a] % g.kmesh[a];
+            g0[a] = s[a] / g.kmesh[a];
+        }
+        const int kp = (r[0] * g.kmesh[1] + r[1]) * g.kmesh[2] + r[2];
+        const int *mil_k = j.miller + (long)k * j.npw_max * 3, *mil_kp = j.miller + (long)kp * j.npw_max * 3;
+        const double2 *c_k = j.coef + ((long)k * j.nband + j.o0) * j.npw_max;
+        const double2 *c_kp = j.coef + ((long)kp * j.nband + j.e0) * j.npw_max;
+        {
+            StageTimer t(ctx, RP_STAGE_UGRID);
+            if (j.fp32) {
+                float2 *v = (float2 *)grid;
+                launch_ugrid32(ctx->stream, j.plans, g.fft, j.mmax, nO, j.npw[k], mil_k, c_k, j.npw_max, v);
+                launch_ugrid32(ctx->stream, j.plans, g.fft, j.mmax, nE, j.npw[kp], mil_kp, c_kp, j.npw_max,
+                               v + nr * nO);
+            } else {
+                double2 *u = (double2 *)grid;
+                launch_ugrid(ctx->stream, j.plans, g.fft, j.mmax, nO, j.npw[k], mil_k, c_k, j.npw_max, u);
+                launch_ugrid(ctx->stream, j.plans, g.fft, j.mmax, nE, j.npw[kp], mil_kp, c_kp, j.npw_max,
+                             u + nr * nO);
+            }
+        }
+        const int lo3 = j.lo[2] + g0[2];
+        double2 *Mk = M + (long)(k - k0) * nE * nO * j.ng;
+        {
+            StageTimer t(ctx, RP_STAGE_PAIR);
+            if (j.fp32) {
+                const float2 *v = (const float2 *)grid;
+                launch_pair_k(ctx->stream, j.plans, g.fft, v, v + nr * nO, nO, nE, j.ng, dg, g0, lo3, L3, true, Mk);
+            } else {
+                const double2 *u = (const double2 *)grid;
+                launch_pair_k(ctx->stream, j.plans, g.fft, u, u + nr * nO, nO, nE, j.ng, dg, g0, lo3, L3, false,
+                              Mk);
+            }
+        }
+        rp_status st = check_launch(ctx, "pair density");
+        if (st != RP_OK) return st;
+    }
+    return RP_OK;
+}
+
+// ---- steps a5-a6: validated weight and contraction work -------------------
+
+struct ChiJob {
+    Geometry g;
+    int nband = 0;
+    const double *E = nullptr, *T = nullptr;  // device [Nk][nband]
+    int o0 = 0, o1 = 0, e0 = 0, e1 = 0;
+    int ng = 0;
+    int nfreq = 0;
+    double delta = 0.0;
+    rp_weight_mode wm = RP_W_TETRA;
+    rp_precision prec = RP_FP64;
+};
+
+static rp_status weights_check(rp_ctx *ctx, const double *E, int nfreq, const double *freq_eV, double delta_eV,
+                               rp_weight_mode wm)
+{
+    if (!E || !freq_eV) return fail(ctx, RP_E_NULL, "NULL energy or frequency array");
+    if (nfreq < 1) return fail(ctx, RP_E_SHAPE, "nfreq must be >= 1");
+    if (!(delta_eV >= 0.0) || !std::isfinite(delta_eV)) return fail(ctx, RP_E_RANGE, "delta must be >= 0");
+    if (wm != RP_W_TETRA && wm != RP_W_SAMPLING) return fail(ctx, RP_E_RANGE, "unknown weight mode");
+    for (int f = 0; f < 2 * nfreq; f++)
+        if (!std::isfinite(freq_eV[f])) return fail(ctx, RP_E_RANGE, "non-finite frequency");
+    return RP_OK;
+}
+
+static rp_status chi_check(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband, const double *E,
+                           const double *T, int o0, int o1, int e0, int e1, int k0, int k1, int ng, int nfreq,
+                           const double *freq_eV, double delta_eV, rp_weight_mode wm, rp_precision prec,
+                           int accumulate, ChiJob *c)
+{
+    rp_status st = geometry(ctx, cell, iq, &c->g);
+    if (st != RP_OK) return st;
+    if ((st = check_ranges(ctx, c->g, nband, o0, o1, e0, e1, k0, k1)) != RP_OK) return st;
+    if (ng < 1) return fail(ctx, RP_E_SHAPE, "ng must be >= 1");
+    if (!valid_prec(prec)) return fail(ctx, RP_E_RANGE, "unknown precision");
+    if (accumulate != 0 && accumulate != 1) return fail(ctx, RP_E_RANGE, "accumulate must be 0 or 1");
+    if ((st = weights_check(ctx, E, nfreq, freq_eV, delta_eV, wm)) != RP_OK) return st;
+    c->nband = nband;
+    c->E = E;
+    c->T = T;
+    c->o0 = o0;
+    c->o1 = o1;
+    c->e0 = e0;
+    c->e1 = e1;
+    c->ng = ng;
+    c->nfreq = nfreq;
+    c->delta = delta_eV;
+    c->wm = wm;
+    c->prec = prec;
+    return RP_OK;
+}
+
+// Workspace of one contraction over npair pairs.
+struct ChiBytes {
+    size_t w = 0, a = 0, b = 0, sw = 0;
+};
+
+static ChiBytes chi_bytes(const ChiJob &c, long npair)
+{
+    ChiBytes b;
+    b.w = sizeof(double2) * (size_t)std::max(1L, npair) * c.nfreq;
+    if (c.prec != RP_FP64) {
+        b.a = split_a_bytes(npair, c.ng);
+        b.b = split_b_bytes(npair, c.ng);
+        b.sw = split_w_bytes(npair, c.nfreq);
+    }
+    return b;
+}
+
+struct ChiBufs {
+    double2 *w;
+    void *a, *b, *sw;
+};
+
+// Enqueues the weights of the pairs of k in [k0, k1) into bufs.w (dfreq is the
+// device copy of the frequencies) and the contraction of M into chi.  No
+// allocation, copy or synchronization.
+static rp_status chi_enqueue(rp_ctx *ctx, const ChiJob &c, int k0, int k1, const double2 *M,
+                             const double2 *dfreq, const ChiBufs &bufs, int accumulate, double2 *chi)
+{
+    const long npair = (long)(k1 - k0) * (c.e1 - c.e0) * (c.o1 - c.o0);
+    rp_status st;
+    if (npair > 0) {
+        {
+            StageTimer t(ctx, RP_STAGE_WEIGHTS);
+            launch_weights(ctx->stream, c.g.kmesh, c.g.iq, c.nband, c.E, c.T, c.o0, c.o1, c.e0, c.e1, k0, k1,
+                           c.nfreq, dfreq, c.delta, (int)c.wm, bufs.w);
+        }
+        if ((st = check_launch(ctx, "weights")) != RP_OK) return st;
+    }
+    if (c.prec == RP_FP64) {
+        StageTimer t(ctx, RP_STAGE_CHI);
+        launch_chi_f64(ctx->stream, npair, c.ng, M, c.nfreq, bufs.w, accumulate, chi);
+    } else {
+        const int nterm = c.prec == RP_SPLIT_BF16 ? 2 : 3;
+        {
+            StageTimer t(ctx, RP_STAGE_PREP);
+            launch_split_prep(ctx->stream, nterm, npair, c.ng, c.nfreq, M, bufs.w, bufs.a, bufs.b, bufs.sw);
+        }
+        StageTimer t(ctx, RP_STAGE_CHI);
+        launch_chi_bf16(ctx->stream, nterm, npair, c.ng, c.nfreq, accumulate, chi, bufs.a, bufs.b, bufs.sw);
+    }
+    return check_launch(ctx, "chi0 contraction");
+}
+
+// Launch arguments of a batch, serialized to decide whether a graph can be reused.
+static void key_put(std::string &key, const void *p, size_t n) { key.append((const char *)p, n); }
+
+template <typename T> static void key_val(std::string &key, const T &v) { key_put(key, &v, sizeof v); }
 
 }  // namespace rp
 
@@ -265,7 +519,9 @@ rp_status rp_destroy(rp_ctx *ctx)
     for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
     ctx->spare.clear();
     DevBuf *bufs[] = {&ctx->ugrid, &ctx->ugrid32, &ctx->weights, &ctx->glist, &ctx->freq,  &ctx->kinfo, &ctx->vsqrt,
-                      &ctx->work,  &ctx->split_a, &ctx->split_b, &ctx->split_w, &ctx->rho, &ctx->piv};
+                      &ctx->work,  &ctx->split_a, &ctx->split_b, &ctx->split_w, &ctx->rho, &ctx->piv,
+                      &ctx->mbuf,  &ctx->bstage};
+    if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->flag) (void)hipFree(ctx->flag);
@@ -300,113 +556,16 @@ rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int
 {
     if (!ctx) return RP_E_NULL;
     (void)hipSetDevice(ctx->device);
-    Geometry g;
-    rp_status st = geometry(ctx, cell, iq, &g);
+    PairJob j;
+    rp_status st = pair_check(ctx, cell, iq, nband, npw_max, npw, mmax, miller, coef, o0, o1, e0, e1, k0, k1, ng,
+                              gsph, prec, &j);
     if (st != RP_OK) return st;
-    if (!npw || !mmax || !miller || !coef || !M) return fail(ctx, RP_E_NULL, "NULL array argument");
-    if ((st = check_ranges(ctx, g, nband, o0, o1, e0, e1, k0, k1)) != RP_OK) return st;
-    if (ng < 1 || ng > 6144) return fail(ctx, RP_E_UNSUPPORTED, "ng = %d outside [1, 6144]", ng);
-    if ((st = check_gsph(ctx, g, ng, gsph, "gsph")) != RP_OK) return st;
-    if (npw_max < 1) return fail(ctx, RP_E_SHAPE, "npw_max must be >= 1");
-    if (prec != RP_FP64 && prec != RP_SPLIT_BF16 && prec != RP_SPLIT_BF16_X6)
-        return fail(ctx, RP_E_RANGE, "unknown precision");
-    const bool fp32 = prec != RP_FP64;
-    FftPlan plans[3];
-    if ((st = plans3(ctx, g, plans)) != RP_OK) return st;
-    for (int k = 0; k < g.nk; k++)
-        if (npw[k] < 0 || npw[k] > npw_max) return fail(ctx, RP_E_SHAPE, "npw[%d] outside [0, npw_max]", k);
-    // alias-free condition per axis: N > 2 mmax + max |m + G0|, G0 in {0, 1} when iq > 0
-    int lo[3], hi[3];
-    for (int a = 0; a < 3; a++) {
-        lo[a] = 1 << 30;
-        hi[a] = -(1 << 30);
-        for (int i = 0; i < ng; i++) {
-            lo[a] = std::min(lo[a], gsph[3 * i + a]);
-            hi[a] = std::max(hi[a], gsph[3 * i + a]);
-        }
-        const int up = hi[a] + (iq[a] > 0 ? 1 : 0);
-        const int gmax = std::max(std::abs(lo[a]), std::abs(up));
-        if (mmax[a] < 0) return fail(ctx, RP_E_SHAPE, "mmax[%d] < 0", a);
-        if (g.fft[a] <= 2 * mmax[a] + gmax)
-            return fail(ctx, RP_E_ALIAS, "axis %d: N=%d <= 2*mmax+|G|max = %d (pair products alias)", a,
-                        g.fft[a], 2 * mmax[a] + gmax);
-    }
-    const int nO = o1 - o0, nE = e1 - e0, nK = k1 - k0;
-    if ((long)nO * nE * nK == 0) return RP_OK;
-    const long nr = (long)g.fft[0] * g.fft[1] * g.fft[2];
-    // LDS budget of the generic pair kernel (window along m3 is at most
-    // hi-lo+2; band blocks of 2x2 in FP32, 1x1 in FP64)
-    const int L3max = hi[2] - lo[2] + 2;
-    if (pair_lds_bytes(g.fft, L3max, pair_rows(g.fft), fp32 ? 8 : 16, fp32 ? 4 : 1) > 160 * 1024)
-        return fail(ctx, RP_E_UNSUPPORTED, "grid %dx%dx%d too large for the pair kernel's LDS plan",
-                    g.fft[0], g.fft[1], g.fft[2]);
-    if (!fp32 && (st = ensure(ctx, ctx->ugrid, sizeof(double2) * nr * (nO + nE))) != RP_OK) return st;
-    if (fp32 && (st = ensure(ctx, ctx->ugrid32, sizeof(float2) * nr * (nO + nE))) != RP_OK) return st;
+    if (!M) return fail(ctx, RP_E_NULL, "M is NULL");
+    if (j.empty) return RP_OK;
+    DevBuf &grid = j.fp32 ? ctx->ugrid32 : ctx->ugrid;
+    if ((st = ensure(ctx, grid, pair_grid_bytes(j))) != RP_OK) return st;
     if ((st = upload(ctx, ctx->glist, gsph, sizeof(int) * 3 * ng)) != RP_OK) return st;
-    double2 *u_occ = (double2 *)ctx->ugrid.p;
-    double2 *u_emp = u_occ + nr * nO;
-    const int *dg = (const int *)ctx->glist.p;
-    const int L3 = hi[2] - lo[2] + 1;
-    for (int k = k0; k < k1; k++) {
-        const int n1 = k / (g.kmesh[1] * g.kmesh[2]), n2 = (k / g.kmesh[2]) % g.kmesh[1], n3 = k % g.kmesh[2];
-        const int s[3] = {n1 + iq[0], n2 + iq[1], n3 + iq[2]};
-        int r[3], g0[3];
-        for (int a = 0; a < 3; a++) {
-            r[a] = s[a] % g.kmesh[a];
-            g0[a] = s[a] / g.kmesh[a];
-        }
-        const int kp = (r[0] * g.kmesh[1] + r[1]) * g.kmesh[2] + r[2];
-        const double2 *cf = (const double2 *)coef;
-        {
-            StageTimer t(ctx, RP_STAGE_UGRID);
-            if (fp32) {
-                float2 *v = (float2 *)ctx->ugrid32.p;
-                launch_ugrid32(ctx->stream, plans, g.fft, mmax, nO, npw[k], miller + (long)k * npw_max * 3,
-                               cf + ((long)k * nband + o0) * npw_max, npw_max, v);
-                launch_ugrid32(ctx->stream, plans, g.fft, mmax, nE, npw[kp], miller + (long)kp * npw_max * 3,
-                               cf + ((long)kp * nband + e0) * npw_max, npw_max, v + nr * nO);
-            } else {
-                launch_ugrid(ctx->stream, plans, g.fft, mmax, nO, npw[k], miller + (long)k * npw_max * 3,
-                             cf + ((long)k * nband + o0) * npw_max, npw_max, u_occ);
-                launch_ugrid(ctx->stream, plans, g.fft, mmax, nE, npw[kp], miller + (long)kp * npw_max * 3,
-                             cf + ((long)kp * nband + e0) * npw_max, npw_max, u_emp);
-            }
-        }
-        const int lo3 = lo[2] + g0[2];
-        double2 *Mk = (double2 *)M + (long)(k - k0) * nE * nO * ng;
-        {
-            StageTimer t(ctx, RP_STAGE_PAIR);
-            if (fp32) {
-                const float2 *v = (const float2 *)ctx->ugrid32.p;
-                launch_pair_k(ctx->stream, plans, g.fft, v, v + nr * nO, nO, nE, ng, dg, g0, lo3, L3, true, Mk);
-            } else {
-                launch_pair_k(ctx->stream, plans, g.fft, u_occ, u_emp, nO, nE, ng, dg, g0, lo3, L3, false, Mk);
-            }
-        }
-        if ((st = check_launch(ctx, "pair density")) != RP_OK) return st;
-    }
-    return RP_OK;
-}
-
-static rp_status weights_common(rp_ctx *ctx, const Geometry &g, int nband, const double *E,
-                                const double *T, int o0, int o1, int e0, int e1, int k0, int k1,
-                                int nfreq, const double *freq_eV, double delta_eV, rp_weight_mode wm,
-                                double2 *w)
-{
-    rp_status st;
-    if (!E || !freq_eV) return fail(ctx, RP_E_NULL, "NULL energy or frequency array");
-    if (nfreq < 1) return fail(ctx, RP_E_SHAPE, "nfreq must be >= 1");
-    if (!(delta_eV >= 0.0) || !std::isfinite(delta_eV)) return fail(ctx, RP_E_RANGE, "delta must be >= 0");
-    if (wm != RP_W_TETRA && wm != RP_W_SAMPLING) return fail(ctx, RP_E_RANGE, "unknown weight mode");
-    for (int f = 0; f < 2 * nfreq; f++)
-        if (!std::isfinite(freq_eV[f])) return fail(ctx, RP_E_RANGE, "non-finite frequency");
-    if ((st = upload(ctx, ctx->freq, freq_eV, sizeof(double2) * nfreq)) != RP_OK) return st;
-    {
-        StageTimer t(ctx, RP_STAGE_WEIGHTS);
-        launch_weights(ctx->stream, g.kmesh, g.iq, nband, E, T, o0, o1, e0, e1, k0, k1, nfreq,
-                       (const double2 *)ctx->freq.p, delta_eV, (int)wm, w);
-    }
-    return check_launch(ctx, "weights");
+    return pair_enqueue(ctx, j, k0, k1, (const int *)ctx->glist.p, grid.p, (double2 *)M);
 }
 
 rp_status rp_weights(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband,
@@ -421,8 +580,14 @@ rp_status rp_weights(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nban
     if (st != RP_OK) return st;
     if ((st = check_ranges(ctx, g, nband, o0, o1, e0, e1, k0, k1)) != RP_OK) return st;
     if (!w) return fail(ctx, RP_E_NULL, "w is NULL");
-    return weights_common(ctx, g, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, nfreq, freq_eV, delta_eV,
-                          wm, (double2 *)w);
+    if ((st = weights_check(ctx, energy_eV, nfreq, freq_eV, delta_eV, wm)) != RP_OK) return st;
+    if ((st = upload(ctx, ctx->freq, freq_eV, sizeof(double2) * nfreq)) != RP_OK) return st;
+    {
+        StageTimer t(ctx, RP_STAGE_WEIGHTS);
+        launch_weights(ctx->stream, g.kmesh, g.iq, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, nfreq,
+                       (const double2 *)ctx->freq.p, delta_eV, (int)wm, (double2 *)w);
+    }
+    return check_launch(ctx, "weights");
 }
 
 rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband,
@@ -433,43 +598,173 @@ rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], 
 {
     if (!ctx) return RP_E_NULL;
     (void)hipSetDevice(ctx->device);
-    Geometry g;
-    rp_status st = geometry(ctx, cell, iq, &g);
+    ChiJob c;
+    rp_status st = chi_check(ctx, cell, iq, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, ng, nfreq, freq_eV,
+                             delta_eV, wm, prec, accumulate, &c);
     if (st != RP_OK) return st;
-    if ((st = check_ranges(ctx, g, nband, o0, o1, e0, e1, k0, k1)) != RP_OK) return st;
     if (!M || !chi) return fail(ctx, RP_E_NULL, "NULL M or chi");
-    if (ng < 1) return fail(ctx, RP_E_SHAPE, "ng must be >= 1");
-    if (prec != RP_FP64 && prec != RP_SPLIT_BF16 && prec != RP_SPLIT_BF16_X6)
-        return fail(ctx, RP_E_RANGE, "unknown precision");
-    if (accumulate != 0 && accumulate != 1) return fail(ctx, RP_E_RANGE, "accumulate must be 0 or 1");
     const long npair = (long)(k1 - k0) * (e1 - e0) * (o1 - o0);
-    if ((st = ensure(ctx, ctx->weights, sizeof(double2) * std::max(1L, npair) * nfreq)) != RP_OK) return st;
-    double2 *w = (double2 *)ctx->weights.p;
-    if (npair > 0) {
-        st = weights_common(ctx, g, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, nfreq, freq_eV, delta_eV,
-                            wm, w);
-        if (st != RP_OK) return st;
-    } else if (!energy_eV || !freq_eV) {
-        return fail(ctx, RP_E_NULL, "NULL energy or frequency array");
+    const ChiBytes nb = chi_bytes(c, npair);
+    if ((st = ensure(ctx, ctx->weights, nb.w)) != RP_OK) return st;
+    if (prec != RP_FP64) {
+        if ((st = ensure(ctx, ctx->split_a, nb.a)) != RP_OK) return st;
+        if ((st = ensure(ctx, ctx->split_b, nb.b)) != RP_OK) return st;
+        if ((st = ensure(ctx, ctx->split_w, nb.sw)) != RP_OK) return st;
     }
-    if (prec == RP_FP64) {
-        StageTimer t(ctx, RP_STAGE_CHI);
-        launch_chi_f64(ctx->stream, npair, ng, (const double2 *)M, nfreq, w, accumulate, (double2 *)chi);
-    } else {
-        const int nterm = prec == RP_SPLIT_BF16 ? 2 : 3;
-        if ((st = ensure(ctx, ctx->split_a, split_a_bytes(npair, ng))) != RP_OK) return st;
-        if ((st = ensure(ctx, ctx->split_b, split_b_bytes(npair, ng))) != RP_OK) return st;
-        if ((st = ensure(ctx, ctx->split_w, split_w_bytes(npair, nfreq))) != RP_OK) return st;
-        {
-            StageTimer t(ctx, RP_STAGE_PREP);
-            launch_split_prep(ctx->stream, nterm, npair, ng, nfreq, (const double2 *)M, w, ctx->split_a.p,
-                              ctx->split_b.p, ctx->split_w.p);
+    if ((st = upload(ctx, ctx->freq, freq_eV, sizeof(double2) * nfreq)) != RP_OK) return st;
+    const ChiBufs bufs{(double2 *)ctx->weights.p, ctx->split_a.p, ctx->split_b.p, ctx->split_w.p};
+    return chi_enqueue(ctx, c, k0, k1, (const double2 *)M, (const double2 *)ctx->freq.p, bufs, accumulate,
+                       (double2 *)chi);
+}
+
+// ---- batch of chi0 problems as one graph launch ----------------------------
+
+rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_precision prec)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    if (nprob < 0) return fail(ctx, RP_E_SHAPE, "nprob < 0");
+    if (nprob > 0 && !probs) return fail(ctx, RP_E_NULL, "probs is NULL");
+    if (!valid_prec(prec)) return fail(ctx, RP_E_RANGE, "unknown precision");
+    if (nprob == 0) return RP_OK;
+    std::vector<PairJob> pj(nprob);
+    std::vector<ChiJob> cj(nprob);
+    std::vector<size_t> goff(nprob), foff(nprob);
+    size_t grid_b = 0, m_b = 0, stage_b = 0;
+    ChiBytes cb;
+    auto round_up = [](size_t n) { return (n + 255) / 256 * 256; };
+    for (int i = 0; i < nprob; i++) {
+        const rp_problem &p = probs[i];
+        rp_status st = pair_check(ctx, &p.cell, p.iq, p.nband, p.npw_max, p.npw, p.mmax, p.miller, p.coef, p.o0,
+                                  p.o1, p.e0, p.e1, p.k0, p.k1, p.ng, p.gsph, prec, &pj[i]);
+        if (st == RP_OK)
+            st = chi_check(ctx, &p.cell, p.iq, p.nband, p.energy_eV, p.T, p.o0, p.o1, p.e0, p.e1, p.k0, p.k1, p.ng,
+                           p.nfreq, p.freq_eV, p.delta_eV, p.wm, prec, p.accumulate, &cj[i]);
+        if (st == RP_OK && p.kbatch < 1) st = fail(ctx, RP_E_SHAPE, "kbatch must be >= 1");
+        if (st == RP_OK && !p.chi) st = fail(ctx, RP_E_NULL, "chi is NULL");
+        if (st != RP_OK) {
+            ctx->err = "problem " + std::to_string(i) + ": " + ctx->err;
+            return st;
         }
-        StageTimer t(ctx, RP_STAGE_CHI);
-        launch_chi_bf16(ctx->stream, nterm, npair, ng, nfreq, accumulate, (double2 *)chi, ctx->split_a.p,
-                        ctx->split_b.p, ctx->split_w.p);
+        const long npk = (long)(p.o1 - p.o0) * (p.e1 - p.e0);
+        const long npair = npk * std::min(p.kbatch, std::max(1, p.k1 - p.k0));
+        if (!pj[i].empty) {
+            grid_b = std::max(grid_b, pair_grid_bytes(pj[i]));
+            m_b = std::max(m_b, sizeof(double2) * (size_t)npair * p.ng);
+        }
+        const ChiBytes b = chi_bytes(cj[i], pj[i].empty ? 0 : npair);
+        cb.w = std::max(cb.w, b.w);
+        cb.a = std::max(cb.a, b.a);
+        cb.b = std::max(cb.b, b.b);
+        cb.sw = std::max(cb.sw, b.sw);
+        goff[i] = stage_b;
+        stage_b += round_up(sizeof(int) * 3 * p.ng);
+        foff[i] = stage_b;
+        stage_b += round_up(sizeof(double2) * p.nfreq);
     }
-    return check_launch(ctx, "chi0 contraction");
+    const bool fp32 = prec != RP_FP64;
+    DevBuf &grid = fp32 ? ctx->ugrid32 : ctx->ugrid;
+    rp_status st;
+    if ((st = ensure(ctx, grid, grid_b)) != RP_OK) return st;
+    if ((st = ensure(ctx, ctx->mbuf, m_b)) != RP_OK) return st;
+    if ((st = ensure(ctx, ctx->weights, cb.w)) != RP_OK) return st;
+    if (fp32) {
+        if ((st = ensure(ctx, ctx->split_a, cb.a)) != RP_OK) return st;
+        if ((st = ensure(ctx, ctx->split_b, cb.b)) != RP_OK) return st;
+        if ((st = ensure(ctx, ctx->split_w, cb.sw)) != RP_OK) return st;
+    }
+    // host staging of every G list and frequency list, one copy to the device
+    std::vector<char> stage(stage_b, 0);
+    for (int i = 0; i < nprob; i++) {
+        memcpy(stage.data() + goff[i], probs[i].gsph, sizeof(int) * 3 * probs[i].ng);
+        memcpy(stage.data() + foff[i], probs[i].freq_eV, sizeof(double2) * probs[i].nfreq);
+    }
+    // the graph depends on every launch argument: the problems' scalars and
+    // pointers, the host arrays read at enqueue time, and the workspaces
+    std::string key;
+    key_val(key, prec);
+    key_val(key, nprob);
+    for (int i = 0; i < nprob; i++) {
+        const rp_problem &p = probs[i];
+        key_val(key, p.cell);
+        key_put(key, p.iq, sizeof p.iq);
+        const int ints[] = {p.nband, p.npw_max, p.o0, p.o1, p.e0, p.e1, p.k0, p.k1, p.ng, p.nfreq, (int)p.wm,
+                            p.kbatch, p.accumulate};
+        key_put(key, ints, sizeof ints);
+        key_put(key, p.mmax, sizeof p.mmax);
+        key_put(key, p.npw, sizeof(int) * pj[i].g.nk);
+        const void *ptrs[] = {p.miller, p.coef, p.energy_eV, p.T, p.chi};
+        key_put(key, ptrs, sizeof ptrs);
+        key_val(key, p.delta_eV);
+    }
+    key_put(key, stage.data(), stage.size());
+    const void *ws[] = {grid.p, ctx->mbuf.p, ctx->weights.p, ctx->split_a.p, ctx->split_b.p, ctx->split_w.p};
+    key_put(key, ws, sizeof ws);
+
+    if (!ctx->batch_exec || key != ctx->batch_key) {
+        if (ctx->batch_exec) {
+            if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+                return fail(ctx, RP_E_DEVICE, "stream synchronize failed before replacing the batch graph");
+            (void)hipGraphExecDestroy(ctx->batch_exec);
+            ctx->batch_exec = nullptr;
+            ctx->batch_key.clear();
+        }
+        if ((st = upload(ctx, ctx->bstage, stage.data(), stage.size())) != RP_OK) return st;
+        const char *dstage = (const char *)ctx->bstage.p;
+        const ChiBufs bufs{(double2 *)ctx->weights.p, ctx->split_a.p, ctx->split_b.p, ctx->split_w.p};
+        if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, RP_E_DEVICE, "stream capture could not begin");
+        }
+        ctx->capturing = true;
+        for (int i = 0; i < nprob && st == RP_OK; i++) {
+            const rp_problem &p = probs[i];
+            const int *dg = (const int *)(dstage + goff[i]);
+            const double2 *df = (const double2 *)(dstage + foff[i]);
+            double2 *chi = (double2 *)p.chi;
+            if (pj[i].empty) {
+                // no pairs: chi is overwritten with zero or left as it is
+                st = chi_enqueue(ctx, cj[i], p.k0, p.k0, nullptr, df, bufs, p.accumulate, chi);
+                continue;
+            }
+            for (int ka = p.k0; ka < p.k1 && st == RP_OK; ka += p.kbatch) {
+                const int kb = std::min(p.k1, ka + p.kbatch);
+                double2 *M = (double2 *)ctx->mbuf.p;
+                st = pair_enqueue(ctx, pj[i], ka, kb, dg, grid.p, M);
+                if (st == RP_OK)
+                    st = chi_enqueue(ctx, cj[i], ka, kb, M, df, bufs, ka == p.k0 ? p.accumulate : 1, chi);
+            }
+        }
+        ctx->capturing = false;
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
+        if (st != RP_OK || ec != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            if (st != RP_OK) {
+                ctx->err = "batch capture: " + ctx->err;
+                return st;
+            }
+            return fail(ctx, RP_E_DEVICE, "stream capture failed: %s", hipGetErrorString(ec));
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, RP_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+        }
+        ctx->batch_exec = exec;
+        ctx->batch_key = key;
+    }
+    {
+        StageTimer t(ctx, RP_STAGE_BATCH);
+        if (hipGraphLaunch(ctx->batch_exec, ctx->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, RP_E_DEVICE, "graph launch failed");
+        }
+    }
+    return RP_OK;
 }
 
 rp_status rp_screen_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int ng, const int *gsph,

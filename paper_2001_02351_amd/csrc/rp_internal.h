@@ -66,6 +66,12 @@ struct rp_ctx {
     rp::DevBuf split_w;             // split-BF16 weights (FP32)
     rp::DevBuf rho;                 // Wannier densities
     rp::DevBuf piv;                 // pivots
+    rp::DevBuf mbuf;                // pair densities of one k batch (batch entry point)
+    rp::DevBuf bstage;              // device copies of a batch's G and frequency lists
+    // the last batch's graph and the launch arguments it was captured with
+    hipGraphExec_t batch_exec = nullptr;
+    std::string batch_key;
+    bool capturing = false;         // stage timers stay off while a graph is captured
     // stage timers
     bool profiling = false;
     struct Mark {

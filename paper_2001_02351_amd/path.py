@@ -95,6 +95,28 @@ def chi0(ctx, d: DeviceInputs, prec: int = _rp.RP_FP64, kbatch: int = 1, k0: int
     return chi
 
 
+def batch_problem(d: DeviceInputs, chi, kbatch: int = 1, o=None, e=None, k=None, accumulate: int = 0):
+    """The rp_chi0_batch description of chi0 of one problem (all bands and k
+    unless band or k ranges are given)."""
+    p = d.prob
+    o0, o1 = o if o else (0, p.nocc)
+    e0, e1 = e if e else (p.nocc, p.nocc + p.nemp)
+    k0, k1 = k if k else (0, d.nk)
+    return dict(cell=d.cell, iq=p.iq, nband=d.nband, npw_max=p.miller.shape[1], npw=p.npw, mmax=d.mmax,
+                miller=d.miller, coef=d.coef, energy_eV=d.energy, T=d.T, o0=o0, o1=o1, e0=e0, e1=e1, k0=k0,
+                k1=k1, ng=d.ng, gsph=p.gsph, nfreq=d.nfreq, freq_eV=p.freq_eV, delta_eV=p.delta_eV,
+                wm=weight_mode(p), kbatch=kbatch, accumulate=accumulate, chi=chi)
+
+
+def chi0_batch(ctx, ds, prec: int = _rp.RP_FP64, kbatch: int = 1, chis=None):
+    """chi0 of several problems (DeviceInputs) in one rp_chi0_batch call."""
+    import torch
+    if chis is None:
+        chis = [torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device=d.device) for d in ds]
+    _rp.rp_chi0_batch(ctx, [batch_problem(d, c, kbatch) for d, c in zip(ds, chis)], prec)
+    return chis
+
+
 def screen(ctx, d: DeviceInputs, chi, want_eps_inv: bool = True, want_W: bool = True):
     import torch
     p = d.prob

@@ -41,6 +41,32 @@ def test_cell_marshalling():
     assert list(c.fft) == [16, 18, 20] and list(c.kmesh) == [4, 3, 2]
 
 
+def test_problem_struct_layout_matches_the_header(tmp_path):
+    """The ctypes rp_problem has the size and field offsets of the C struct
+    (compiled from include/rp.h with the host compiler)."""
+    import shutil
+    import subprocess
+
+    import paper_2001_02351_amd as rp
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        import pytest
+        pytest.skip("no host C compiler")
+    fields = [f[0] for f in rp.rp_problem._fields_]
+    src = ['#include <stddef.h>', '#include <stdio.h>', '#include "rp.h"', "int main(void) {",
+           '  printf("%zu\\n", sizeof(rp_problem));']
+    src += [f'  printf("%zu\\n", offsetof(rp_problem, {f}));' for f in fields]
+    src += ["  return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(rp.rp_problem)
+    assert out[1:] == [getattr(rp.rp_problem, f).offset for f in fields]
+
+
 def test_product_does_not_import_the_oracle():
     pkg = os.path.join(ROOT, "paper_2001_02351_amd")
     for dirpath, _, files in os.walk(pkg):

@@ -86,3 +86,87 @@ def test_batch_system_parity(ctx, rp, s):
                 assert _rel(c, c.conj().T) < 1e-13
                 ev = np.linalg.eigvalsh((c + c.conj().T) / 2)
                 assert ev.max() < 1e-10 * np.abs(ev).max()
+
+
+def _per_problem(ctx, rp, d, o, e, prec, kbatch, k=None):
+    """chi0 of one problem through rp_pair_density + rp_chi0_accumulate, k
+    batches of kbatch k-points (the reference for the batch entry point)."""
+    from paper_2001_02351_amd import path
+    p = d.prob
+    k0, k1 = k if k else (0, d.nk)
+    npk = (o[1] - o[0]) * (e[1] - e[0])
+    chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device="cuda")
+    M = torch.empty((kbatch * npk, d.ng, 2), dtype=torch.float64, device="cuda")
+    for ka in range(k0, k1, kbatch):
+        kb = min(k1, ka + kbatch)
+        Mk = M[: (kb - ka) * npk]
+        path.pair_density(ctx, d, ka, kb, o=o, e=e, out=Mk, prec=prec)
+        rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, d.T, *o, *e, ka, kb, d.ng, Mk, d.nfreq,
+                              p.freq_eV, p.delta_eV, path.weight_mode(p), prec, 0 if ka == k0 else 1, chi)
+    return chi
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_chi0_batch_graph_matches_per_problem_calls(ctx, rp, prec):
+    """rp_chi0_batch over uneven problems (three systems, two q-points of one,
+    a k sub-range, and an empty problem) equals the per-problem calls; the
+    graph is relaunched on an unchanged batch and re-captured on a changed one."""
+    from paper_2001_02351_amd import path
+    systems = [(21, 0), (21, 1), (7, 0), (4, 0)]
+    ds = [path.DeviceInputs(batch_system(s, iq)) for s, iq in systems]
+    bands = [((0, 8), (d.prob.nocc, d.prob.nocc + 16)) for d in ds]
+    kr = [None, (2, 7), None, None]
+    kbatch = 3
+    chis = [torch.full((d.nfreq, d.ng, d.ng, 2), float("nan"), dtype=torch.float64, device="cuda")
+            for d in ds]
+    probs = [path.batch_problem(d, c, kbatch, o=o, e=e, k=k) for d, c, (o, e), k in zip(ds, chis, bands, kr)]
+    # an empty problem (no k) clears its chi
+    zero = torch.full((ds[2].nfreq, ds[2].ng, ds[2].ng, 2), 5.0, dtype=torch.float64, device="cuda")
+    probs.append(path.batch_problem(ds[2], zero, kbatch, o=bands[2][0], e=bands[2][1], k=(3, 3)))
+    print(f"[batch graph] prec={prec}: {len(probs)} problems", flush=True)
+    rp.rp_chi0_batch(ctx, probs, prec)
+    rp.rp_synchronize(ctx)
+    assert float(zero.abs().max()) == 0.0
+    ref = [_per_problem(ctx, rp, d, o, e, prec, kbatch, k) for d, (o, e), k in zip(ds, bands, kr)]
+    for i, (c, r) in enumerate(zip(chis, ref)):
+        err = float(torch.linalg.norm(c - r) / torch.linalg.norm(r))
+        print(f"[batch graph] problem {i}: rel diff {err:.1e} (exact: {bool(torch.equal(c, r))})", flush=True)
+        assert err <= 1e-14
+    # unchanged batch: the same graph again, same result
+    before = [c.clone() for c in chis]
+    for c in chis:
+        c.fill_(float("nan"))
+    rp.rp_chi0_batch(ctx, probs, prec)
+    rp.rp_synchronize(ctx)
+    for c, b in zip(chis, before):
+        assert torch.equal(c, b)
+    # changed batch (accumulate into chi of problem 0 only): a new capture
+    rp.rp_chi0_batch(ctx, [dict(probs[0], accumulate=1)], prec)
+    rp.rp_synchronize(ctx)
+    assert float(torch.linalg.norm(chis[0] - 2 * before[0]) / torch.linalg.norm(before[0])) <= 1e-14
+    # and the oracle on sampled columns of problem 2
+    d, (o, e) = ds[2], bands[2]
+    M = oracle.pair_densities(d.prob, *o, *e, 0, d.nk)
+    w = oracle.prob_weights(d.prob, *o, *e, 0, d.nk)
+    cols = np.unique(np.concatenate([np.random.default_rng(9).choice(d.ng, 30, replace=False), [d.ng - 1]]))
+    want = oracle.chi0(M[:, cols], w)
+    got = path.to_complex(chis[2])
+    err = max(_rel(got[f][cols][:, cols], want[f]) for f in range(d.nfreq))
+    assert err < (1e-10 if prec == 0 else 1e-5)
+
+
+def test_chi0_batch_rejects_bad_problems(ctx, rp):
+    from paper_2001_02351_amd import path
+    d = path.DeviceInputs(batch_system(21, 0))
+    chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device="cuda")
+    good = path.batch_problem(d, chi, 2)
+    with pytest.raises(rp.RpError) as e:
+        rp.rp_chi0_batch(ctx, [good, dict(good, kbatch=0)], 0)
+    assert e.value.status == 2 and "problem 1" in str(e.value)
+    with pytest.raises(rp.RpError) as e:
+        rp.rp_chi0_batch(ctx, [dict(good, k1=d.nk + 1)], 0)
+    assert e.value.status == 2 and "problem 0" in str(e.value)
+    with pytest.raises(rp.RpError) as e:
+        rp.rp_chi0_batch(ctx, [good], 7)
+    assert e.value.status == 3
+    rp.rp_chi0_batch(ctx, [], 0)   # an empty batch is a no-op
