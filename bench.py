@@ -30,6 +30,12 @@ Inputs are resident in HBM before the timed region.
 Counter runs use two extra modes: --copy-calibration (a plain 1 GiB device
 copy, three times) and --profile-k N (the split chi0 build over the first N
 k-points in the launch configuration of the timed legs).
+
+--batch measures the batched uneven workload instead (24 systems x 4
+q-points, 16 imaginary frequencies, split-BF16 chi0) through rp_chi0_batch,
+one graph launch per step, beside the same problems through per-problem
+calls; its rate counts the Hermitian half of Eq. chi, F = 4 N_G^2 P N_w per
+problem (real weights on the imaginary axis).
 """
 
 from __future__ import annotations
@@ -195,6 +201,106 @@ def run_leg(rp, path, ctx, d, prec, steps, warmup, kbatch):
     return res, chi, einv, Wij
 
 
+def batch_leg(args):
+    """The batched uneven workload through rp_chi0_batch (one JSON line)."""
+    import copy
+
+    import torch
+
+    import paper_2001_02351_amd as rp
+    from paper_2001_02351_amd import path
+    from synth import batch_system_qpoints
+    nsys = args.batch_systems
+    log(f"generating {nsys} uneven systems x 4 q-points")
+    t0 = time.perf_counter()
+    probs = []
+    for s in range(nsys):
+        probs += batch_system_qpoints(s)
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    rp.load()
+    ctx = rp.Context(0)
+    ds = []
+    for i, p in enumerate(probs):
+        if i % 4 == 0:
+            base = path.DeviceInputs(p)
+            ds.append(base)
+        else:
+            d = copy.copy(base)
+            d.prob = p
+            ds.append(d)
+    chis = [torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device=d.device) for d in ds]
+    torch.cuda.synchronize()
+    log("inputs resident on the device")
+    prec = rp.RP_SPLIT_BF16
+    # k batches of about 40 000 pairs (at least one k-point)
+    descs = []
+    for d, c in zip(ds, chis):
+        npk = d.prob.nocc * d.prob.nemp
+        kb = max(1, min(d.nk, args.batch_pairs // npk))
+        descs.append(path.batch_problem(d, c, kb))
+    pairs = [d.nk * d.prob.nocc * d.prob.nemp for d in ds]
+    f_herm = sum(4.0 * d.ng ** 2 * P * d.nfreq for d, P in zip(ds, pairs))
+    t = time.perf_counter()
+    rp.rp_chi0_batch(ctx, descs, prec)
+    rp.rp_synchronize(ctx)
+    log(f"first batch call (capture + instantiate + run) {time.perf_counter() - t:.2f} s")
+    for i in range(args.warmup):
+        rp.rp_chi0_batch(ctx, descs, prec)
+        rp.rp_synchronize(ctx)
+    times = []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rp.rp_chi0_batch(ctx, descs, prec)
+        rp.rp_synchronize(ctx)
+        times.append(time.perf_counter() - t)
+        log(f"batch step {i}: {times[-1]:.3f} s")
+    tb = sorted(times)[len(times) // 2]
+    # the same problems through per-problem calls, with per-stage timers
+    rp.rp_profile(ctx, True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for d, c, q in zip(ds, chis, descs):
+        path.chi0(ctx, d, prec=prec, kbatch=q["kbatch"], chi=c)
+    rp.rp_synchronize(ctx)
+    tu = time.perf_counter() - t
+    stages = rp.rp_profile_read(ctx)
+    rp.rp_profile(ctx, False)
+    log(f"per-problem calls: {tu:.3f} s")
+    ctx.close()
+    out = {
+        "metric": METRIC,
+        "value": f_herm / tb / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": tb * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched uneven systems: {nsys} systems x 4 q-points, grids 24^3-40^3, k meshes "
+                        "2^3-6^3, 16-64 + 48-256 bands, N_G 300-1200, 16 imaginary frequencies, delta=0, "
+                        "generalized tetrahedron, split-BF16 chi0, one rp_chi0_batch graph per step",
+            "problems": len(ds),
+            "pairs": sum(pairs),
+            "flops_hermitian_half": f_herm,
+            "pairs_per_k_batch": args.batch_pairs,
+        },
+        "s_per_batch": tb,
+        "per_problem_calls_s": tu,
+        "per_problem_stage_ms": {k: v[0] for k, v in stages.items()},
+        "per_problem_stage_launches": {k: v[1] for k, v in stages.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +314,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--profile-k", type=int, default=0)
+    ap.add_argument("--batch", action="store_true")
+    ap.add_argument("--batch-systems", type=int, default=24)
+    ap.add_argument("--batch-pairs", type=int, default=40000)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -216,6 +325,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.batch:
+        batch_leg(args)
         return
 
     from synth import srvo3_workload

@@ -309,4 +309,49 @@ __device__ __forceinline__ void quad_fft(C (&x)[Q], const C *twQ, const C *twN, 
     reg_fft<Q>(x, twQ);
 }
 
+// ---------------------------------------------------------------------------
+// Lane-group FFT: a line of length N = G Q over G adjacent lanes, G in
+// {1, 2, 4} (the group's lanes are active together).  G = 4 is the quad form
+// above; G = 2 is the same decimation in frequency with a 2-point DFT across
+// the lane pair (DPP swap of lanes s and s ^ 1): lane s holds x[Q s + n] and
+// ends with X[2k + s] in x[k]; G = 1 is the register FFT of the whole line.
+// group_row<G>(s) is the output residue of lane s: X[G k + group_row(s)].
+
+template <int G> __device__ __forceinline__ int group_row(int s)
+{
+    if constexpr (G == 4) return quad_row(s & 3);
+    else if constexpr (G == 2) return s & 1;
+    else return 0;
+}
+
+// lane 0 ends with x0 + x1, lane 1 with x0 - x1 (x_s the value of lane s)
+template <int Q, typename C> __device__ __forceinline__ void pair_dft2(C (&x)[Q], int s)
+{
+    typedef typename CxT<C>::T T;
+    const T sg = (s & 1) ? (T)-1 : (T)1;
+#pragma unroll
+    for (int k = 0; k < Q; k++) {
+        const T px = quad_perm<0xB1>(x[k].x), py = quad_perm<0xB1>(x[k].y);
+        x[k] = mkc<C>(px + sg * x[k].x, py + sg * x[k].y);
+    }
+}
+
+// twQ[t] = e^{2 pi i t/Q}, t < Q; twN[t] = e^{2 pi i t/N}, t < N (for G = 1
+// the two tables are the same length and only twQ is read)
+template <int G, int Q, typename C>
+__device__ __forceinline__ void group_fft(C (&x)[Q], const C *twQ, const C *twN, int s)
+{
+    if constexpr (G == 4) {
+        quad_fft<Q>(x, twQ, twN, s);
+    } else if constexpr (G == 2) {
+        pair_dft2<Q>(x, s);
+        const int r = s & 1;
+#pragma unroll
+        for (int n = 1; n < Q; n++) x[n] = cmul(x[n], twN[r * n]);
+        reg_fft<Q>(x, twQ);
+    } else {
+        reg_fft<Q>(x, twQ);
+    }
+}
+
 }  // namespace rp

@@ -135,113 +135,6 @@ k_pair(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int nE,
     (void)sizeof(T);
 }
 
-// Register-FFT form for compile-time N2 = N3 = N: per plane, (A) thread
-// (pair q, row j2) forms the product row and transforms it along j3 in
-// registers, keeping the m3 window; (B) thread (q, column t3) transforms along
-// j2 in registers, in place; (C) every sphere point accumulates its j1 phase.
-// The window buffer is double-buffered across planes: two barriers per plane.
-template <typename C, int N, int NA, int NB, int MAXG>
-__global__ void __launch_bounds__(256)
-k_pair_reg(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int nE, int N1, int ng,
-           const int *__restrict__ gsph, int g01, int g02, int g03, int lo3, int L3, double2 *__restrict__ M)
-{
-    constexpr int NP = NA * NB;
-    extern __shared__ double2 smem_d[];
-    C *smem = (C *)smem_d;
-    const int tid = threadIdx.x;
-    const int nbB = (nO + NB - 1) / NB;
-    const int a0 = (blockIdx.x / nbB) * NA, b0 = (blockIdx.x % nbB) * NB;
-    const long nr = (long)N1 * N * N;
-
-    C *tw1 = smem;
-    C *twN = tw1 + N1;
-    C *buf0 = twN + N;                                       // two [NP][N][L3] windows
-    fill_twiddles(tw1, N1, tid, 256);
-    fill_twiddles(twN, N, tid, 256);
-
-    C acc[NP][MAXG];
-    int cidx[MAXG], step1[MAXG], ph[MAXG];
-#pragma unroll
-    for (int t = 0; t < MAXG; t++) {
-        const int g = tid + t * 256;
-#pragma unroll
-        for (int q = 0; q < NP; q++) acc[q][t] = mkc<C>(0, 0);
-        cidx[t] = 0;
-        step1[t] = 0;
-        ph[t] = 0;
-        if (g < ng) {
-            const int m1 = gsph[3 * g] + g01, m2 = gsph[3 * g + 1] + g02, m3 = gsph[3 * g + 2] + g03;
-            cidx[t] = pmod(m2, N) * L3 + (m3 - lo3);
-            step1[t] = pmod(m1, N1);
-        }
-    }
-    __syncthreads();
-
-    for (int j1 = 0; j1 < N1; j1++) {
-        C *B = buf0 + (size_t)(j1 & 1) * NP * N * L3;
-        // (A) rows along j3
-        for (int L = tid; L < NP * N; L += 256) {
-            const int q = L / N, j2 = L - q * N;
-            const int a = min(a0 + q / NB, nE - 1), b = min(b0 + q % NB, nO - 1);
-            const long off = ((long)j1 * N + j2) * N;
-            const C *ra = u_emp + (long)a * nr + off;
-            const C *rb = u_occ + (long)b * nr + off;
-            C x[N];
-#pragma unroll
-            for (int i = 0; i < N; i++) x[i] = cmulc(ra[i], rb[i]);
-            reg_fft<N>(x, twN);
-            C *dst = B + ((size_t)q * N + j2) * L3;
-#pragma unroll
-            for (int i = 0; i < N; i++) {
-                int t3 = i - lo3;
-                t3 = t3 < 0 ? t3 + N : (t3 >= N ? t3 - N : t3);
-                if (t3 < L3) dst[t3] = x[i];
-            }
-        }
-        __syncthreads();
-        // (B) columns along j2, in place
-        for (int L = tid; L < NP * L3; L += 256) {
-            const int q = L / L3, t3 = L - q * L3;
-            C *col = B + (size_t)q * N * L3 + t3;
-            C y[N];
-#pragma unroll
-            for (int j2 = 0; j2 < N; j2++) y[j2] = col[j2 * L3];
-            reg_fft<N>(y, twN);
-#pragma unroll
-            for (int m2 = 0; m2 < N; m2++) col[m2 * L3] = y[m2];
-        }
-        __syncthreads();
-        // (C) sphere points
-#pragma unroll
-        for (int t = 0; t < MAXG; t++) {
-            const int g = tid + t * 256;
-            if (g < ng) {
-                const C e = tw1[ph[t]];
-#pragma unroll
-                for (int q = 0; q < NP; q++) {
-                    const C v = B[(size_t)q * N * L3 + cidx[t]];
-                    acc[q][t].x += v.x * e.x - v.y * e.y;
-                    acc[q][t].y += v.x * e.y + v.y * e.x;
-                }
-                ph[t] += step1[t];
-                if (ph[t] >= N1) ph[t] -= N1;
-            }
-        }
-    }
-    const double inv = 1.0 / (double)nr;
-#pragma unroll
-    for (int q = 0; q < NP; q++) {
-        const int a = a0 + q / NB, b = b0 + q % NB;
-        if (a >= nE || b >= nO) continue;
-        double2 *out = M + ((long)a * nO + b) * ng;
-#pragma unroll
-        for (int t = 0; t < MAXG; t++) {
-            const int g = tid + t * 256;
-            if (g < ng) out[g] = make_double2((double)acc[q][t].x * inv, (double)acc[q][t].y * inv);
-        }
-    }
-}
-
 // Workgroup barrier over LDS only: waits for this wave's LDS operations, not
 // for global-to-LDS DMAs still in flight (which __syncthreads would drain).
 __device__ __forceinline__ void lds_sync()
@@ -252,20 +145,26 @@ __device__ __forceinline__ void lds_sync()
     asm volatile("" ::: "memory");
 }
 
-// widest m3 window the quad form holds in LDS (FP32 2x2 pair blocks, FP64
-// 2x1 pair blocks: either way under 80 KB, two workgroups per CU)
-template <typename C, int N> constexpr int quad_l3max()
+// lanes per line for the lane-group form: 4 when N is a multiple of 4, else
+// 2 when even, else 1
+template <int N> constexpr int pair_group() { return N % 4 == 0 ? 4 : (N % 2 == 0 ? 2 : 1); }
+
+// widest m3 window the lane-group form holds in LDS: two windows of
+// [NP][N][L3M] under 72 KB (FP32) or 48 KB (FP64), so two workgroups share a CU
+template <typename C, int N, int NP> constexpr int lanes_l3max()
 {
-    return sizeof(C) == 8 ? (N >= 48 ? N / 2 : N) : (N >= 48 ? N / 3 : (N >= 32 ? 24 : N));
+    constexpr int budget = sizeof(C) == 8 ? 73728 : 49152;
+    constexpr int m = budget / (2 * NP * N * (int)sizeof(C));
+    return m < N ? m : N;
 }
 
-// Quad-FFT form (FP32 or FP64), the path for N2 = N3 in {16, 24, 32, 48}.  Per plane
-// j1: (A) each quad of lanes (pair q, row j2) loads its two grid rows (each
-// lane a contiguous quarter, in 16-byte loads), forms the product and
-// transforms it along j3 (quad_fft), keeping the m3 window; (B) each quad
-// (q, column t3) transforms along j2 in place; (C) every sphere point
-// accumulates its j1 phase in registers.  All four waves share phases A and B
-// evenly, and a lane holds N/4 points of a line instead of N, which leaves
+// Lane-group form (FP32 or FP64), the path for N2 = N3 = N with a compile-time
+// instantiation.  Per plane j1: (A) each group of G lanes (pair q, row j2)
+// loads its two grid rows (each lane a contiguous 1/G of the row), forms the
+// product and transforms it along j3 (group_fft), keeping the m3 window;
+// (B) each group (q, column t3) transforms along j2 in place; (C) every
+// sphere point accumulates its j1 phase in registers.  All four waves share
+// phases A and B evenly, and a lane holds N/G points of a line, which leaves
 // room for the sphere accumulators.  The two m3-window buffers alternate
 // between planes, so phase A of plane j1+1 may start while other waves still
 // read plane j1's window in phase C: two barriers per plane.  LDS stays under
@@ -273,19 +172,20 @@ template <typename C, int N> constexpr int quad_l3max()
 // barrier waits.
 template <typename C, int N, int NA, int NB, int MAXG>
 __global__ void __launch_bounds__(256, 2)
-k_pair_quad(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int nE, int N1, int ng,
-            const int *__restrict__ gsph, int g01, int g02, int g03, int lo3, int L3, double2 *__restrict__ M)
+k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int nE, int N1, int ng,
+             const int *__restrict__ gsph, int g01, int g02, int g03, int lo3, int L3, double2 *__restrict__ M)
 {
-    constexpr int Q = N / 4, NP = NA * NB;
-    constexpr int L3M = quad_l3max<C, N>();
-    constexpr int TA = (NP * N + 63) / 64;    // phase-A lines per quad
+    constexpr int G = pair_group<N>(), Q = N / G, NP = NA * NB;
+    constexpr int NGRP = 256 / G;             // lane groups per workgroup
+    constexpr int L3M = lanes_l3max<C, N, NP>();
+    constexpr int TA = (NP * N + NGRP - 1) / NGRP;    // phase-A lines per group
     __shared__ C win0[NP * N * L3M];          // [NP][N][L3]
     __shared__ C win1[NP * N * L3M];
     __shared__ C tw1[256];
     __shared__ C twN[N];
     __shared__ C twQ[Q];
     const int tid = threadIdx.x;
-    const int s = tid & 3, quad = tid >> 2, r = quad_row(s);
+    const int s = tid & (G - 1), grp = tid / G, r = group_row<G>(s);
     const int nbB = (nO + NB - 1) / NB;
     const int a0 = (blockIdx.x / nbB) * NA, b0 = (blockIdx.x % nbB) * NB;
     const long nr = (long)N1 * N * N;
@@ -315,14 +215,16 @@ k_pair_quad(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, in
         // (A) product rows along j3
 #pragma unroll 1
         for (int it = 0; it < TA; it++) {
-            const int task = quad + 64 * it;
+            const int task = grp + NGRP * it;
             if (task < NP * N) {
                 const int q = task / N, j2 = task - q * N;
                 const long off = ((long)j1 * N + j2) * N + Q * s;
                 const C *ra = u_emp + (long)min(a0 + q / NB, nE - 1) * nr + off;
                 const C *rb = u_occ + (long)min(b0 + q % NB, nO - 1) * nr + off;
                 C x[Q];
-                if constexpr (sizeof(C) == 8) {   // two FP32 complex values per 16-byte load
+                if constexpr (sizeof(C) == 8 && N % 2 == 0 && Q % 2 == 0) {
+                    // two FP32 complex values per 16-byte load (row and lane
+                    // offsets are even, grids 16-byte aligned)
 #pragma unroll
                     for (int n = 0; n < Q / 2; n++) {
                         const float4 va = ((const float4 *)ra)[n], vb = ((const float4 *)rb)[n];
@@ -333,28 +235,28 @@ k_pair_quad(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, in
 #pragma unroll
                     for (int n = 0; n < Q; n++) x[n] = cmulc(ra[n], rb[n]);
                 }
-                quad_fft<Q>(x, twQ, twN, s);
+                group_fft<G, Q>(x, twQ, twN, s);
                 C *dst = B + ((size_t)q * N + j2) * L3;
 #pragma unroll
                 for (int k = 0; k < Q; k++) {
-                    int t3 = 4 * k + r - lo3;
+                    int t3 = G * k + r - lo3;
                     t3 = t3 < 0 ? t3 + N : (t3 >= N ? t3 - N : t3);
                     if (t3 < L3) dst[t3] = x[k];
                 }
             }
         }
         lds_sync();
-        // (B) columns along j2, in place (a quad reads its whole column
+        // (B) columns along j2, in place (a group reads its whole column
         // before any of its lanes writes)
-        for (int task = quad; task < NP * L3; task += 64) {
+        for (int task = grp; task < NP * L3; task += NGRP) {
             const int qq = task / L3, t3 = task - qq * L3;
             C *col = B + (size_t)qq * N * L3 + t3;
             C y[Q];
 #pragma unroll
             for (int n = 0; n < Q; n++) y[n] = col[(Q * s + n) * L3];
-            quad_fft<Q>(y, twQ, twN, s);
+            group_fft<G, Q>(y, twQ, twN, s);
 #pragma unroll
-            for (int k = 0; k < Q; k++) col[(4 * k + r) * L3] = y[k];
+            for (int k = 0; k < Q; k++) col[(G * k + r) * L3] = y[k];
         }
         lds_sync();
         // (C) sphere points
@@ -395,33 +297,18 @@ k_pair_quad(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, in
 }
 
 template <typename C, int N, int NA, int NB>
-void launch_pair_quad(hipStream_t s, int N1, const C *u_occ, const C *u_emp, int nO, int nE, int ng,
-                      const int *gsph, const int g0[3], int lo3, int L3, double2 *M)
+void launch_pair_lanes(hipStream_t s, int N1, const C *u_occ, const C *u_emp, int nO, int nE, int ng,
+                       const int *gsph, const int g0[3], int lo3, int L3, double2 *M)
 {
     const unsigned nblk = (unsigned)(((nE + NA - 1) / NA) * ((nO + NB - 1) / NB));
-#define RP_PAIRQ(G)                                                                                          \
-    hipLaunchKernelGGL((k_pair_quad<C, N, NA, NB, G>), dim3(nblk), dim3(256), 0, s, u_occ, u_emp, nO, nE, N1,\
-                       ng, gsph, g0[0], g0[1], g0[2], lo3, L3, M)
-    if (ng <= 512) RP_PAIRQ(2);
-    else if (ng <= 1024) RP_PAIRQ(4);
-    else if (ng <= 1536) RP_PAIRQ(6);
-    else RP_PAIRQ(8);
-#undef RP_PAIRQ
-}
-
-template <typename C, int N, int NA, int NB>
-void launch_pair_reg(hipStream_t s, int N1, const C *u_occ, const C *u_emp, int nO, int nE, int ng,
-                     const int *gsph, const int g0[3], int lo3, int L3, double2 *M)
-{
-    const size_t shm = sizeof(C) * ((size_t)N1 + N + 2 * (size_t)NA * NB * N * L3);
-    const unsigned nblk = (unsigned)(((nE + NA - 1) / NA) * ((nO + NB - 1) / NB));
-#define RP_PAIRR(G)                                                                                            \
-    hipLaunchKernelGGL((k_pair_reg<C, N, NA, NB, G>), dim3(nblk), dim3(256), shm, s, u_occ, u_emp, nO, nE, N1, \
-                       ng, gsph, g0[0], g0[1], g0[2], lo3, L3, M)
-    if (ng <= 512) RP_PAIRR(2);
-    else if (ng <= 1024) RP_PAIRR(4);
-    else RP_PAIRR(8);
-#undef RP_PAIRR
+#define RP_PAIRL(G)                                                                                          \
+    hipLaunchKernelGGL((k_pair_lanes<C, N, NA, NB, G>), dim3(nblk), dim3(256), 0, s, u_occ, u_emp, nO, nE,   \
+                       N1, ng, gsph, g0[0], g0[1], g0[2], lo3, L3, M)
+    if (ng <= 512) RP_PAIRL(2);
+    else if (ng <= 1024) RP_PAIRL(4);
+    else if (ng <= 1536) RP_PAIRL(6);
+    else RP_PAIRL(8);
+#undef RP_PAIRL
 }
 
 template <typename C, int NA, int NB>
@@ -453,53 +340,65 @@ size_t pair_lds_bytes(const int fft[3], int L3, int rows, size_t csize, int npai
 
 int pair_rows(const int fft[3]) { return std::max(1, std::min(fft[1], 768 / fft[2])); }
 
-// lengths with a register-FFT instantiation (FP64 lines of 48 do not fit in
-// registers and use the LDS form)
-bool pair_reg_supported(const int fft[3], int ng, bool fp32)
+// The lane-group form's lengths: N2 = N3 = N in these lists, N1 <= 256,
+// ng <= 2048, and the m3 window within its LDS plan.  The band blocks are
+// 2x2 pairs in FP32 and 2x1 in FP64.  FP64 lines of 25, 27 and 30 (one or two
+// lanes per line) do not fit in registers and use the generic form.
+#define RP_LANE_LENGTHS_F32(X) X(16) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(48)
+#define RP_LANE_LENGTHS_F64(X) X(16) X(24) X(32) X(36) X(40) X(48)
+
+static bool pair_lanes_f32(const int fft[3], int ng, int L3)
 {
-    if (ng > 2048 || fft[1] != fft[2]) return false;
+    if (fft[0] > 256 || fft[1] != fft[2] || ng > 2048) return false;
     switch (fft[1]) {
-    case 16: case 24: case 32: return true;
-    case 48: return fp32;
+#define RP_CASE(n) \
+    case n: return L3 <= lanes_l3max<float2, n, 4>();
+        RP_LANE_LENGTHS_F32(RP_CASE)
+#undef RP_CASE
     default: return false;
     }
 }
 
-// the quad form: N2 = N3 in {16, 24, 32, 48}, N1 <= 256, ng <= 2048, and the
-// m3 window within its LDS plan
-template <typename C> static bool pair_quad_supported(const int fft[3], int ng, int L3)
+static bool pair_lanes_f64(const int fft[3], int ng, int L3)
 {
     if (fft[0] > 256 || fft[1] != fft[2] || ng > 2048) return false;
     switch (fft[1]) {
-    case 16: return L3 <= quad_l3max<C, 16>();
-    case 24: return L3 <= quad_l3max<C, 24>();
-    case 32: return L3 <= quad_l3max<C, 32>();
-    case 48: return L3 <= quad_l3max<C, 48>();
+#define RP_CASE(n) \
+    case n: return L3 <= lanes_l3max<double2, n, 2>();
+        RP_LANE_LENGTHS_F64(RP_CASE)
+#undef RP_CASE
     default: return false;
     }
+}
+
+bool pair_supported(const int fft[3], int ng, int L3, bool fp32)
+{
+    if (fp32 ? pair_lanes_f32(fft, ng, L3) : pair_lanes_f64(fft, ng, L3)) return true;
+    // the generic form's LDS plan (band blocks of 2x2 in FP32, 1x1 in FP64)
+    return pair_lds_bytes(fft, L3, pair_rows(fft), fp32 ? 8 : 16, fp32 ? 4 : 1) <= 160 * 1024;
 }
 
 void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], const void *u_occ,
                    const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3], int lo3,
                    int L3, bool fp32, double2 *M)
 {
-    if (fp32 && pair_quad_supported<float2>(fft, ng, L3)) {
+    if (fp32 && pair_lanes_f32(fft, ng, L3)) {
         const float2 *uo = (const float2 *)u_occ, *ue = (const float2 *)u_emp;
         switch (fft[1]) {
-        case 16: launch_pair_quad<float2, 16, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
-        case 24: launch_pair_quad<float2, 24, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
-        case 32: launch_pair_quad<float2, 32, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
-        case 48: launch_pair_quad<float2, 48, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+#define RP_CASE(n) \
+        case n: launch_pair_lanes<float2, n, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+            RP_LANE_LENGTHS_F32(RP_CASE)
+#undef RP_CASE
         default: break;
         }
     }
-    if (!fp32 && pair_quad_supported<double2>(fft, ng, L3)) {
+    if (!fp32 && pair_lanes_f64(fft, ng, L3)) {
         const double2 *uo = (const double2 *)u_occ, *ue = (const double2 *)u_emp;
         switch (fft[1]) {
-        case 16: launch_pair_quad<double2, 16, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
-        case 24: launch_pair_quad<double2, 24, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
-        case 32: launch_pair_quad<double2, 32, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
-        case 48: launch_pair_quad<double2, 48, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+#define RP_CASE(n) \
+        case n: launch_pair_lanes<double2, n, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+            RP_LANE_LENGTHS_F64(RP_CASE)
+#undef RP_CASE
         default: break;
         }
     }
@@ -510,6 +409,5 @@ void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], cons
         launch_pair_t<double2, 1, 1>(s, plans, fft, (const double2 *)u_occ, (const double2 *)u_emp, nO, nE,
                                      ng, gsph, g0, lo3, L3, M);
 }
-
 
 }  // namespace rp

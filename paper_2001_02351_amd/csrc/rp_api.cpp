@@ -250,10 +250,8 @@ static rp_status pair_check(rp_ctx *ctx, const rp_cell *cell, const int iq[3], i
     j->ng = ng;
     j->empty = (long)(o1 - o0) * (e1 - e0) * (k1 - k0) == 0;
     if (j->empty) return RP_OK;
-    // LDS budget of the generic pair kernel (window along m3 is at most
-    // hi-lo+2; band blocks of 2x2 in FP32, 1x1 in FP64)
-    const int L3max = j->hi[2] - j->lo[2] + 2;
-    if (pair_lds_bytes(g.fft, L3max, pair_rows(g.fft), j->fp32 ? 8 : 16, j->fp32 ? 4 : 1) > 160 * 1024)
+    // the pair kernels' LDS plans (m3 window of the sphere, hi - lo + 1)
+    if (!pair_supported(g.fft, ng, j->hi[2] - j->lo[2] + 1, j->fp32))
         return fail(ctx, RP_E_UNSUPPORTED, "grid %dx%dx%d too large for the pair kernel's LDS plan", g.fft[0],
                     g.fft[1], g.fft[2]);
     return RP_OK;

@@ -120,6 +120,8 @@ void launch_fft3d(hipStream_t s, const FftPlan plans[3], const int fft[3], int n
 // pair.hip: pair densities of one k (grids in FP64, or FP32 when fp32).
 size_t pair_lds_bytes(const int fft[3], int L3, int rows, size_t csize, int npairs);
 int pair_rows(const int fft[3]);
+// whether a pair kernel can run this grid, sphere size and m3 window
+bool pair_supported(const int fft[3], int ng, int L3, bool fp32);
 void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], const void *u_occ,
                    const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3],
                    int lo3, int L3, bool fp32, double2 *M);

@@ -15,6 +15,7 @@ from .gen import (  # noqa: F401
     make_problem,
     mesh_fractions,
     batch_system,
+    batch_system_qpoints,
     parity_workload,
     srvo3_workload,
     supercell_workload,

@@ -331,6 +331,29 @@ def batch_system(s: int, iq_index: int = 0, workers: Optional[int] = None) -> Pr
                         seed=400 + s, workers=workers)
 
 
+def batch_system_qpoints(s: int, workers: Optional[int] = None) -> list:
+    """The four q-points of batch system s as four problems that share one
+    set of coefficient, Miller and energy arrays (only iq, the G sphere and
+    its tail differ): the same inputs as batch_system(s, 0..3)."""
+    import dataclasses
+    p0 = batch_system(s, 0, workers=workers)
+    kedge = p0.kmesh[0]
+    qs = [(i, j, k) for i in range(kedge) for j in range(kedge) for k in range(kedge)
+          if (i, j, k) != (0, 0, 0)][:4]
+    recip = 2.0 * math.pi * np.linalg.inv(p0.lat).T
+    out = [p0]
+    for n, iq in enumerate(qs[1:], start=1):
+        qf = np.array(iq, dtype=np.float64) / np.array(p0.kmesh, dtype=np.float64)
+        gsph = _sphere(recip, qf, None, count=int(p0.gsph.shape[0]))
+        full = _sphere(recip, qf, p0.gpsi)
+        in_eps = {tuple(m) for m in gsph.tolist()}
+        gtail = np.array([m for m in full.tolist() if tuple(m) not in in_eps],
+                         dtype=np.int32).reshape(-1, 3)
+        out.append(dataclasses.replace(p0, name=f"batch_system_{s}_q{n}", iq=tuple(iq), gsph=gsph,
+                                       gtail=gtail))
+    return out
+
+
 def supercell_workload(nocc: int = 600, nemp: int = 1200, workers: Optional[int] = None) -> Problem:
     """A 4x4x4 supercell of the SrVO3-shaped cell (a = 29.045 bohr): 96^3
     grid, Gamma-only k mesh, q = 0 (G = 0 dropped), 600 + 1200 bands,
