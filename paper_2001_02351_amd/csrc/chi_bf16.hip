@@ -25,6 +25,8 @@
 // pairs stream through two LDS buffers (32 KB of A and 16 NT KB of B each)
 // by global_load_lds DMA, so the next step's operands arrive while the matrix
 // cores work on the current one.
+#include <algorithm>
+
 #include "fft_lds.h"
 
 namespace rp {
@@ -103,7 +105,9 @@ __global__ void k_split_prep(long npair, int ng, int npg, int NGP, const double2
     for (int s = 0; s < 2 * NT; s++) Bp[s * plane + t] = pl[s];
 }
 
-__global__ void k_weight_prep(long npair, long KP, int nfreq, const double2 *__restrict__ w,
+// real_w: the weights are real (imaginary frequencies, no broadening) and
+// their imaginary parts, rounding residue only, are dropped
+__global__ void k_weight_prep(long npair, long KP, int nfreq, const double2 *__restrict__ w, int real_w,
                               float2 *__restrict__ wq)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -112,13 +116,36 @@ __global__ void k_weight_prep(long npair, long KP, int nfreq, const double2 *__r
     const long p = t - (long)f * KP;
     double2 v = make_double2(0.0, 0.0);
     if (p < npair) v = w[(long)f * npair + p];
-    wq[t] = make_float2((float)v.x, (float)v.y);
+    wq[t] = make_float2((float)v.x, real_w ? 0.f : (float)v.y);
 }
 
+// Tile (rt, ct) of block index id: row-major over the t x t tiles, or over
+// the upper triangle rt <= ct when only that half is formed.
+__device__ __forceinline__ void tile_of(int id, int t, int herm, int &rt, int &ct)
+{
+    if (!herm) {
+        rt = id / t;
+        ct = id - rt * t;
+        return;
+    }
+    rt = 0;
+    while (id >= t - rt) {
+        id -= t - rt;
+        rt++;
+    }
+    ct = rt + id;
+}
+
+// Grid: x = tile (all t x t tiles, or the upper triangle when herm), y = slice
+// of the pair steps (sps steps each), z = frequency group.  With one slice the
+// block adds its tile into chi (and, for an off-diagonal tile of a Hermitian
+// chi, the conjugate transpose into the mirrored tile); with several slices
+// it writes its FP32 partial tile to part[slice][f][NGP][NGP] for k_chi_reduce.
 template <int NT>
 __global__ void __launch_bounds__(256)
 k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, const bf8 *__restrict__ Bp,
-           int nfreq, const float2 *__restrict__ wq, int accumulate, double2 *__restrict__ chi)
+           int nfreq, const float2 *__restrict__ wq, int accumulate, double2 *__restrict__ chi, int herm,
+           int sps, float2 *__restrict__ part)
 {
     constexpr int NW = kNW;
     constexpr int NPL = 2 * NT;  // B planes
@@ -130,11 +157,14 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
-    const int rt0 = blockIdx.y * kTile, ct0 = blockIdx.x * kTile;
+    int rt, ct;
+    tile_of(blockIdx.x, NGP / kTile, herm, rt, ct);
+    const int rt0 = rt * kTile, ct0 = ct * kTile;
     const int wr = wave >> 1, wc = wave & 1;
     const int f0 = blockIdx.z * NW;
     const long plane = (long)npg * NGP;
-    const int nstep = npg / 4;
+    const int step0 = blockIdx.y * sps;
+    const int nstep = min(sps, npg / 4 - step0);
 
     // DMA segments of 1 KB; wave w moves pair group kg = w: its 8 A row
     // blocks and its NPL x 2 B half-rows
@@ -263,8 +293,8 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     // together with that DMA, so no wait inside a step covers the DMA.
     float2 wcur[NW][8], wnext[NW][8];
     if (nstep > 0) {
-        wload(0, wnext);
-        issue(sA[0], sB[0], 0);
+        wload(step0, wnext);
+        issue(sA[0], sB[0], 4 * step0);
     }
     for (int t = 0; t < nstep; t++) {
         const int stg = t & 1;
@@ -275,11 +305,30 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
 #pragma unroll
             for (int j = 0; j < 8; j++) wcur[iw][j] = wnext[iw][j];
         const bool more = t + 1 < nstep;
-        if (more) wload(t + 1, wnext);
-        step(sA[stg ^ 1], sB[stg ^ 1], sA[stg], sB[stg], more ? 4 * (t + 1) : -1, wcur);
+        if (more) wload(step0 + t + 1, wnext);
+        step(sA[stg ^ 1], sB[stg ^ 1], sA[stg], sB[stg], more ? 4 * (step0 + t + 1) : -1, wcur);
     }
 
     // result register r of lane (li, lk) holds row 4 lk + r, column li of a 16x16 block
+    if (part) {
+#pragma unroll
+        for (int iw = 0; iw < NW; iw++) {
+            if (f0 + iw >= nfreq) continue;
+            float2 *P = part + ((long)blockIdx.y * nfreq + f0 + iw) * NGP * NGP;
+#pragma unroll
+            for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+                for (int cb = 0; cb < 4; cb++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int i = rt0 + wr * 64 + rb * 16 + 4 * lk + r;
+                        const int j = ct0 + wc * 64 + cb * 16 + li;
+                        P[(long)i * NGP + j] = make_float2(accR[iw][rb][cb][r], accI[iw][rb][cb][r]);
+                    }
+        }
+        return;
+    }
+    const bool mirror = herm && rt != ct;
 #pragma unroll
     for (int iw = 0; iw < NW; iw++) {
         if (f0 + iw >= nfreq) continue;
@@ -293,12 +342,64 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
                     const int i = rt0 + wr * 64 + rb * 16 + 4 * lk + r;
                     const int j = ct0 + wc * 64 + cb * 16 + li;
                     if (i < ng && j < ng) {
-                        double2 v = make_double2((double)accR[iw][rb][cb][r], (double)accI[iw][rb][cb][r]);
+                        const double2 a = make_double2((double)accR[iw][rb][cb][r], (double)accI[iw][rb][cb][r]);
                         const long idx = (long)i * ng + j;
-                        if (accumulate) v = cadd(C[idx], v);
-                        C[idx] = v;
+                        C[idx] = accumulate ? cadd(C[idx], a) : a;
+                        if (mirror) {
+                            const long jdx = (long)j * ng + i;
+                            const double2 b = make_double2(a.x, -a.y);
+                            C[jdx] = accumulate ? cadd(C[jdx], b) : b;
+                        }
                     }
                 }
+    }
+}
+
+// chi (+)= sum over slices of the partial tiles, in FP64, for the computed
+// tiles; for an off-diagonal tile of a Hermitian chi the conjugate transpose
+// goes to the mirrored tile through LDS.  Block: 32 x 32 elements of one
+// frequency (grid x over the NGP/32 x NGP/32 chunks, z over frequencies).
+__global__ void __launch_bounds__(256)
+k_chi_reduce(int nslice, int nfreq, int ng, int NGP, const float2 *__restrict__ part, int accumulate, int herm,
+             double2 *__restrict__ chi)
+{
+    __shared__ double2 tr[32][33];
+    const int nc = NGP / 32;
+    const int ci = blockIdx.x / nc, cj = blockIdx.x - ci * nc;
+    const int rt = ci / (kTile / 32), ct = cj / (kTile / 32);
+    if (herm && rt > ct) return;
+    const int f = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const long plane = (long)NGP * NGP;
+    double2 *C = chi + (long)f * ng * ng;
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        const int i = ci * 32 + ty + 8 * m, j = cj * 32 + tx;
+        const float2 *src = part + (long)f * plane + (long)i * NGP + j;
+        double2 v = make_double2(0.0, 0.0);
+        for (int sl = 0; sl < nslice; sl++) {
+            const float2 x = src[(long)sl * nfreq * plane];
+            v.x += (double)x.x;
+            v.y += (double)x.y;
+        }
+        if (i < ng && j < ng) {
+            const long idx = (long)i * ng + j;
+            C[idx] = accumulate ? cadd(C[idx], v) : v;
+        }
+        tr[ty + 8 * m][tx] = v;
+    }
+    if (!(herm && rt < ct)) return;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        // element (row cj*32 + ty + 8m, column ci*32 + tx) of the mirrored tile
+        const int i = cj * 32 + ty + 8 * m, j = ci * 32 + tx;
+        const double2 a = tr[tx][ty + 8 * m];
+        const double2 v = make_double2(a.x, -a.y);
+        if (i < ng && j < ng) {
+            const long idx = (long)i * ng + j;
+            C[idx] = accumulate ? cadd(C[idx], v) : v;
+        }
     }
 }
 
@@ -311,8 +412,34 @@ size_t split_a_bytes(long npair, int ng) { return (size_t)pad_pairs(npair) * pad
 size_t split_b_bytes(long npair, int ng) { return (size_t)6 * pad_pairs(npair) * pad_ng(ng) * 2; }
 size_t split_w_bytes(long npair, int nfreq) { return (size_t)pad_pairs(npair) * nfreq * sizeof(float2); }
 
+// Slices of the pair steps for one contraction: enough blocks to fill the
+// chip twice over (two blocks per CU), each slice at least 8 steps.
+static void chi_slices(long npair, int ng, int nfreq, bool herm, int *nslice, int *sps)
+{
+    const int t = pad_ng(ng) / kTile;
+    const long tiles = herm ? (long)t * (t + 1) / 2 : (long)t * t;
+    const long blocks = tiles * ((nfreq + kNW - 1) / kNW);
+    const int nstep = (int)(pad_pairs(npair) / kStep);
+    int S = 1;
+    if (blocks < 512 && nstep >= 16) {
+        S = (int)std::min<long>((1024 + blocks - 1) / blocks, nstep / 8);
+        S = std::max(1, std::min(S, 64));
+    }
+    const int per = std::max(1, (nstep + S - 1) / S);
+    *sps = per;
+    *nslice = std::max(1, (nstep + per - 1) / per);
+}
+
+size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm)
+{
+    int S, sps;
+    chi_slices(npair, ng, nfreq, herm, &S, &sps);
+    if (S == 1) return 0;
+    return (size_t)S * nfreq * (size_t)pad_ng(ng) * pad_ng(ng) * sizeof(float2);
+}
+
 void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, const double2 *M,
-                       const double2 *w, void *split_a, void *split_b, void *split_w)
+                       const double2 *w, bool herm, void *split_a, void *split_b, void *split_w)
 {
     const long KP = pad_pairs(npair);
     const int NGP = pad_ng(ng);
@@ -328,23 +455,32 @@ void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, 
                            (bf8 *)split_b);
     const long nw = KP * nfreq;
     hipLaunchKernelGGL(k_weight_prep, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, npair, KP, nfreq, w,
-                       (float2 *)split_w);
+                       (int)herm, (float2 *)split_w);
 }
 
 void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, int accumulate, double2 *chi,
-                     const void *split_a, const void *split_b, const void *split_w)
+                     const void *split_a, const void *split_b, const void *split_w, bool herm, void *part)
 {
     const long KP = pad_pairs(npair);
     const int NGP = pad_ng(ng);
     const int npg = (int)(KP / 8);
-    const unsigned t = (unsigned)(NGP / kTile);
-    const dim3 grid(t, t, (nfreq + kNW - 1) / kNW);
+    const int t = NGP / kTile;
+    int S, sps;
+    chi_slices(npair, ng, nfreq, herm, &S, &sps);
+    const unsigned tiles = herm ? (unsigned)(t * (t + 1) / 2) : (unsigned)(t * t);
+    const dim3 grid(tiles, (unsigned)S, (nfreq + kNW - 1) / kNW);
+    float2 *P = S > 1 ? (float2 *)part : nullptr;
     if (nterm == 2)
         hipLaunchKernelGGL(k_chi_bf16<2>, grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a,
-                           (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi);
+                           (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P);
     else
         hipLaunchKernelGGL(k_chi_bf16<3>, grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a,
-                           (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi);
+                           (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P);
+    if (S > 1) {
+        const int nc = NGP / 32;
+        hipLaunchKernelGGL(k_chi_reduce, dim3((unsigned)(nc * nc), 1, (unsigned)nfreq), dim3(256), 0, s, S, nfreq, ng,
+                           NGP, (const float2 *)P, accumulate, (int)herm, chi);
+    }
 }
 
 }  // namespace rp

@@ -37,10 +37,31 @@ __device__ __forceinline__ void dma16(const void *src, void *lds)
     __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
 }
 
+// Tile (rt, ct) of block index id: row-major over the t x t tiles, or over
+// the upper triangle rt <= ct when only that half is formed.
+__device__ __forceinline__ void tile_of(int id, int t, int herm, int &rt, int &ct)
+{
+    if (!herm) {
+        rt = id / t;
+        ct = id - rt * t;
+        return;
+    }
+    rt = 0;
+    while (id >= t - rt) {
+        id -= t - rt;
+        rt++;
+    }
+    ct = rt + id;
+}
+
+// herm: the weights are real (imaginary frequencies, no broadening), so chi
+// is Hermitian: their imaginary parts (rounding residue) are dropped, only
+// the tiles rt <= ct are formed, and an off-diagonal tile also writes its
+// conjugate transpose into the mirrored tile.
 template <int NW>
 __global__ void __launch_bounds__(256)
 k_chi_f64(long npair, int ng, const double2 *__restrict__ M, int nfreq, const double2 *__restrict__ w,
-          int accumulate, double2 *__restrict__ chi)
+          int accumulate, int herm, double2 *__restrict__ chi)
 {
     // [stage][A rows | B cols][pair][64] double2, then [stage][NW][pair] weights
     __shared__ double2 sm[2][2][kKC][kT];
@@ -48,7 +69,9 @@ k_chi_f64(long npair, int ng, const double2 *__restrict__ M, int nfreq, const do
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
-    const int rt0 = blockIdx.y * kT, ct0 = blockIdx.x * kT;
+    int rt, ct;
+    tile_of(blockIdx.x, (ng + kT - 1) / kT, herm, rt, ct);
+    const int rt0 = rt * kT, ct0 = ct * kT;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int f0 = blockIdx.z * NW;
     const long nchunk = (npair + kKC - 1) / kKC;
@@ -69,7 +92,10 @@ k_chi_f64(long npair, int ng, const double2 *__restrict__ M, int nfreq, const do
     const int wiw = tid / kKC, wpp = tid % kKC;
     auto wload = [&](long c) -> double2 {
         const long p = c * kKC + wpp;
-        if (tid < NW * kKC && p < npair && f0 + wiw < nfreq) return w[(long)(f0 + wiw) * npair + p];
+        if (tid < NW * kKC && p < npair && f0 + wiw < nfreq) {
+            const double2 v = w[(long)(f0 + wiw) * npair + p];
+            return make_double2(v.x, herm ? 0.0 : v.y);
+        }
         return make_double2(0.0, 0.0);
     };
 
@@ -132,6 +158,7 @@ k_chi_f64(long npair, int ng, const double2 *__restrict__ M, int nfreq, const do
     }
 
     // result register r of lane (li, lk) holds row lk + 4 r, column li of a 16x16 block
+    const bool mirror = herm && rt != ct;
 #pragma unroll
     for (int iw = 0; iw < NW; iw++) {
         if (f0 + iw >= nfreq) continue;
@@ -145,10 +172,14 @@ k_chi_f64(long npair, int ng, const double2 *__restrict__ M, int nfreq, const do
                     const int i = rt0 + wr + rb * 16 + lk + 4 * r;
                     const int j = ct0 + wc + cb * 16 + li;
                     if (i < ng && j < ng) {
-                        double2 v = make_double2(accR[iw][rb][cb][r], accI[iw][rb][cb][r]);
+                        const double2 a = make_double2(accR[iw][rb][cb][r], accI[iw][rb][cb][r]);
                         const long idx = (long)i * ng + j;
-                        if (accumulate) v = cadd(C[idx], v);
-                        C[idx] = v;
+                        C[idx] = accumulate ? cadd(C[idx], a) : a;
+                        if (mirror) {
+                            const long jdx = (long)j * ng + i;
+                            const double2 b = make_double2(a.x, -a.y);
+                            C[jdx] = accumulate ? cadd(C[jdx], b) : b;
+                        }
                     }
                 }
     }
@@ -157,11 +188,12 @@ k_chi_f64(long npair, int ng, const double2 *__restrict__ M, int nfreq, const do
 }  // namespace
 
 void launch_chi_f64(hipStream_t s, long npair, int ng, const double2 *M, int nfreq, const double2 *w,
-                    int accumulate, double2 *chi)
+                    int accumulate, bool herm, double2 *chi)
 {
     const unsigned t = (unsigned)((ng + kT - 1) / kT);
-    hipLaunchKernelGGL(k_chi_f64<kNW>, dim3(t, t, (nfreq + kNW - 1) / kNW), dim3(256), 0, s, npair, ng, M,
-                       nfreq, w, accumulate, chi);
+    const unsigned tiles = herm ? t * (t + 1) / 2 : t * t;
+    hipLaunchKernelGGL(k_chi_f64<kNW>, dim3(tiles, 1, (nfreq + kNW - 1) / kNW), dim3(256), 0, s, npair, ng, M,
+                       nfreq, w, accumulate, (int)herm, chi);
 }
 
 }  // namespace rp

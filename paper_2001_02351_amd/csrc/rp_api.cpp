@@ -333,6 +333,7 @@ struct ChiJob {
     double delta = 0.0;
     rp_weight_mode wm = RP_W_TETRA;
     rp_precision prec = RP_FP64;
+    bool herm = false;  // real weights: chi Hermitian
 };
 
 static rp_status weights_check(rp_ctx *ctx, const double *E, int nfreq, const double *freq_eV, double delta_eV,
@@ -371,12 +372,18 @@ static rp_status chi_check(rp_ctx *ctx, const rp_cell *cell, const int iq[3], in
     c->delta = delta_eV;
     c->wm = wm;
     c->prec = prec;
+    // on the imaginary axis (w = i nu) without broadening, z = i nu and
+    // z' = -i nu = z* in Eqs. Xakqbk and tetrahedron, whose two terms are then
+    // complex conjugates: the weights are real and chi is Hermitian
+    c->herm = delta_eV == 0.0;
+    for (int f = 0; f < nfreq; f++)
+        if (freq_eV[2 * f] != 0.0) c->herm = false;
     return RP_OK;
 }
 
 // Workspace of one contraction over npair pairs.
 struct ChiBytes {
-    size_t w = 0, a = 0, b = 0, sw = 0;
+    size_t w = 0, a = 0, b = 0, sw = 0, part = 0;
 };
 
 static ChiBytes chi_bytes(const ChiJob &c, long npair)
@@ -387,13 +394,14 @@ static ChiBytes chi_bytes(const ChiJob &c, long npair)
         b.a = split_a_bytes(npair, c.ng);
         b.b = split_b_bytes(npair, c.ng);
         b.sw = split_w_bytes(npair, c.nfreq);
+        b.part = chi_part_bytes(npair, c.ng, c.nfreq, c.herm);
     }
     return b;
 }
 
 struct ChiBufs {
     double2 *w;
-    void *a, *b, *sw;
+    void *a, *b, *sw, *part;
 };
 
 // Enqueues the weights of the pairs of k in [k0, k1) into bufs.w (dfreq is the
@@ -414,15 +422,17 @@ static rp_status chi_enqueue(rp_ctx *ctx, const ChiJob &c, int k0, int k1, const
     }
     if (c.prec == RP_FP64) {
         StageTimer t(ctx, RP_STAGE_CHI);
-        launch_chi_f64(ctx->stream, npair, c.ng, M, c.nfreq, bufs.w, accumulate, chi);
+        launch_chi_f64(ctx->stream, npair, c.ng, M, c.nfreq, bufs.w, accumulate, c.herm, chi);
     } else {
         const int nterm = c.prec == RP_SPLIT_BF16 ? 2 : 3;
         {
             StageTimer t(ctx, RP_STAGE_PREP);
-            launch_split_prep(ctx->stream, nterm, npair, c.ng, c.nfreq, M, bufs.w, bufs.a, bufs.b, bufs.sw);
+            launch_split_prep(ctx->stream, nterm, npair, c.ng, c.nfreq, M, bufs.w, c.herm, bufs.a, bufs.b,
+                              bufs.sw);
         }
         StageTimer t(ctx, RP_STAGE_CHI);
-        launch_chi_bf16(ctx->stream, nterm, npair, c.ng, c.nfreq, accumulate, chi, bufs.a, bufs.b, bufs.sw);
+        launch_chi_bf16(ctx->stream, nterm, npair, c.ng, c.nfreq, accumulate, chi, bufs.a, bufs.b, bufs.sw, c.herm,
+                        bufs.part);
     }
     return check_launch(ctx, "chi0 contraction");
 }
@@ -518,7 +528,7 @@ rp_status rp_destroy(rp_ctx *ctx)
     ctx->spare.clear();
     DevBuf *bufs[] = {&ctx->ugrid, &ctx->ugrid32, &ctx->weights, &ctx->glist, &ctx->freq,  &ctx->kinfo, &ctx->vsqrt,
                       &ctx->work,  &ctx->split_a, &ctx->split_b, &ctx->split_w, &ctx->rho, &ctx->piv,
-                      &ctx->mbuf,  &ctx->bstage};
+                      &ctx->mbuf,  &ctx->bstage,  &ctx->chi_part};
     if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -608,9 +618,11 @@ rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], 
         if ((st = ensure(ctx, ctx->split_a, nb.a)) != RP_OK) return st;
         if ((st = ensure(ctx, ctx->split_b, nb.b)) != RP_OK) return st;
         if ((st = ensure(ctx, ctx->split_w, nb.sw)) != RP_OK) return st;
+        if ((st = ensure(ctx, ctx->chi_part, nb.part)) != RP_OK) return st;
     }
     if ((st = upload(ctx, ctx->freq, freq_eV, sizeof(double2) * nfreq)) != RP_OK) return st;
-    const ChiBufs bufs{(double2 *)ctx->weights.p, ctx->split_a.p, ctx->split_b.p, ctx->split_w.p};
+    const ChiBufs bufs{(double2 *)ctx->weights.p, ctx->split_a.p, ctx->split_b.p, ctx->split_w.p,
+                       ctx->chi_part.p};
     return chi_enqueue(ctx, c, k0, k1, (const double2 *)M, (const double2 *)ctx->freq.p, bufs, accumulate,
                        (double2 *)chi);
 }
@@ -655,6 +667,7 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
         cb.a = std::max(cb.a, b.a);
         cb.b = std::max(cb.b, b.b);
         cb.sw = std::max(cb.sw, b.sw);
+        cb.part = std::max(cb.part, b.part);
         goff[i] = stage_b;
         stage_b += round_up(sizeof(int) * 3 * p.ng);
         foff[i] = stage_b;
@@ -670,6 +683,7 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
         if ((st = ensure(ctx, ctx->split_a, cb.a)) != RP_OK) return st;
         if ((st = ensure(ctx, ctx->split_b, cb.b)) != RP_OK) return st;
         if ((st = ensure(ctx, ctx->split_w, cb.sw)) != RP_OK) return st;
+        if ((st = ensure(ctx, ctx->chi_part, cb.part)) != RP_OK) return st;
     }
     // host staging of every G list and frequency list, one copy to the device
     std::vector<char> stage(stage_b, 0);
@@ -696,7 +710,8 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
         key_val(key, p.delta_eV);
     }
     key_put(key, stage.data(), stage.size());
-    const void *ws[] = {grid.p, ctx->mbuf.p, ctx->weights.p, ctx->split_a.p, ctx->split_b.p, ctx->split_w.p};
+    const void *ws[] = {grid.p,          ctx->mbuf.p,    ctx->weights.p, ctx->split_a.p,
+                        ctx->split_b.p, ctx->split_w.p, ctx->chi_part.p};
     key_put(key, ws, sizeof ws);
 
     if (!ctx->batch_exec || key != ctx->batch_key) {
@@ -709,7 +724,8 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
         }
         if ((st = upload(ctx, ctx->bstage, stage.data(), stage.size())) != RP_OK) return st;
         const char *dstage = (const char *)ctx->bstage.p;
-        const ChiBufs bufs{(double2 *)ctx->weights.p, ctx->split_a.p, ctx->split_b.p, ctx->split_w.p};
+        const ChiBufs bufs{(double2 *)ctx->weights.p, ctx->split_a.p, ctx->split_b.p, ctx->split_w.p,
+                           ctx->chi_part.p};
         if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             (void)hipGetLastError();
             return fail(ctx, RP_E_DEVICE, "stream capture could not begin");

@@ -64,6 +64,7 @@ struct rp_ctx {
     rp::DevBuf split_a;             // split-BF16 row operand (FP32 complex)
     rp::DevBuf split_b;             // split-BF16 column operand (BF16 planes)
     rp::DevBuf split_w;             // split-BF16 weights (FP32)
+    rp::DevBuf chi_part;            // split-BF16 partial tiles of sliced pair steps
     rp::DevBuf rho;                 // Wannier densities
     rp::DevBuf piv;                 // pivots
     rp::DevBuf mbuf;                // pair densities of one k batch (batch entry point)
@@ -132,18 +133,22 @@ void launch_weights(hipStream_t s, const int kmesh[3], const int iq[3], int nban
                     int k0, int k1, int nfreq, const double2 *freq_eV, double delta_eV,
                     int mode, double2 *w);
 
-// chi_f64.hip: chi += sum_p w_p M_p M_p^H on FP64 matrix cores.
+// chi_f64.hip: chi += sum_p w_p M_p M_p^H on FP64 matrix cores.  herm: the
+// weights are real and only the upper tiles are formed (chi Hermitian).
 void launch_chi_f64(hipStream_t s, long npair, int ng, const double2 *M, int nfreq,
-                    const double2 *w, int accumulate, double2 *chi);
+                    const double2 *w, int accumulate, bool herm, double2 *chi);
 
-// chi_bf16.hip: split-BF16 contraction.
+// chi_bf16.hip: split-BF16 contraction (herm as above; part holds the
+// partial tiles when the pair steps are sliced, chi_part_bytes of them).
 size_t split_a_bytes(long npair, int ng);
 size_t split_b_bytes(long npair, int ng);
 size_t split_w_bytes(long npair, int nfreq);
+size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm);
 void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, const double2 *M,
-                       const double2 *w, void *split_a, void *split_b, void *split_w);
+                       const double2 *w, bool herm, void *split_a, void *split_b, void *split_w);
 void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, int accumulate,
-                     double2 *chi, const void *split_a, const void *split_b, const void *split_w);
+                     double2 *chi, const void *split_a, const void *split_b, const void *split_w,
+                     bool herm, void *part);
 
 // screen.hip
 void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, double *vs, int *flag);
