@@ -259,6 +259,21 @@ def batch_leg(args):
         times.append(time.perf_counter() - t)
         log(f"batch step {i}: {times[-1]:.3f} s")
     tb = sorted(times)[len(times) // 2]
+    # the same batch with the library's default launch shapes (no table)
+    untuned = None
+    if ctx.tuning is not None:
+        rp.rp_set_tuning(ctx, [])
+        rp.rp_chi0_batch(ctx, descs, prec)
+        rp.rp_synchronize(ctx)
+        ut = []
+        for i in range(max(1, args.steps // 2)):
+            t = time.perf_counter()
+            rp.rp_chi0_batch(ctx, descs, prec)
+            rp.rp_synchronize(ctx)
+            ut.append(time.perf_counter() - t)
+        untuned = sorted(ut)[len(ut) // 2]
+        log(f"default launch shapes: {untuned:.3f} s")
+        rp.rp_set_tuning(ctx, rp.load_tuning(ctx.tuning))
     # the same problems through per-problem calls, with per-stage timers
     rp.rp_profile(ctx, True)
     torch.cuda.synchronize()
@@ -294,6 +309,8 @@ def batch_leg(args):
             "pairs_per_k_batch": args.batch_pairs,
         },
         "s_per_batch": tb,
+        "tuning_table": None if ctx.tuning is None else os.path.relpath(ctx.tuning, ROOT),
+        "s_per_batch_default_shapes": untuned,
         "per_problem_calls_s": tu,
         "per_problem_stage_ms": {k: v[0] for k, v in stages.items()},
         "per_problem_stage_launches": {k: v[1] for k, v in stages.items()},

@@ -264,6 +264,33 @@ rp_status rp_wannier_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nw
                        double *Wij);
 
 /*
+ * Launch-shape tuning per size class (the autotuner in the Python package
+ * measures the candidates and installs its table with this call).  A call
+ * with N_G sphere vectors and largest FFT edge E uses the first entry with
+ * ng_max >= N_G and grid_max >= E; with no match, or no table, the defaults
+ * apply.  The table is copied; n = 0 clears it.
+ *   chi_nw     frequencies per workgroup of the split-BF16 contraction, 1 or
+ *              2 (0: the default, 2)
+ *   chi_fill   workgroups the slicing of the pair steps aims for when the
+ *              tiles alone give fewer than half of it (0: never slice, -1:
+ *              the default, 1024)
+ *   fft_lines  lines per workgroup of the u-grid transforms, 1..64 (0: 32,
+ *              16 or 8 by length)
+ * Only launch shapes change: every choice computes the same sums (the
+ * contraction's FP32 partial sums are grouped differently when sliced).
+ * Errors: RP_E_NULL, RP_E_RANGE.
+ */
+typedef struct {
+    int ng_max;
+    int grid_max;
+    int chi_nw;
+    int chi_fill;
+    int fft_lines;
+} rp_tune_entry;
+
+rp_status rp_set_tuning(rp_ctx *ctx, int n, const rp_tune_entry *table);
+
+/*
  * Stage timers.  While enabled, the context records a pair of HIP events on
  * its stream around every kernel launch of a stage and accumulates the
  * elapsed device time per stage.  Stages:

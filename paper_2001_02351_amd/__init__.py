@@ -16,6 +16,7 @@ from ._rp import (  # noqa: F401
     Context,
     RpError,
     load,
+    load_tuning,
     make_cell,
     rp_chi0_accumulate,
     rp_chi0_batch,
@@ -25,6 +26,8 @@ from ._rp import (  # noqa: F401
     rp_profile,
     rp_profile_read,
     rp_screen_W,
+    rp_set_tuning,
+    rp_tune_entry,
     rp_synchronize,
     rp_wannier_W,
     rp_weights,

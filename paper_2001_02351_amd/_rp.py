@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_E_NULL", 2: "RP_E_SHAPE", 3: "RP_E_RANGE", 4:
 
 EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pair_density",
             "rp_weights", "rp_chi0_accumulate", "rp_chi0_batch", "rp_screen_W", "rp_wannier_W",
-            "rp_profile", "rp_profile_read"]
+            "rp_set_tuning", "rp_profile", "rp_profile_read"]
 
 STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier", "batch"]
 
@@ -54,6 +54,15 @@ class rp_problem(ctypes.Structure):
                 ("gsph", ctypes.c_void_p), ("nfreq", ctypes.c_int), ("freq_eV", ctypes.c_void_p),
                 ("delta_eV", ctypes.c_double), ("wm", ctypes.c_int), ("kbatch", ctypes.c_int),
                 ("accumulate", ctypes.c_int), ("chi", ctypes.c_void_p)]
+
+
+class rp_tune_entry(ctypes.Structure):
+    """One size class of the launch-shape table (the C struct of the same name)."""
+    _fields_ = [("ng_max", ctypes.c_int), ("grid_max", ctypes.c_int), ("chi_nw", ctypes.c_int),
+                ("chi_fill", ctypes.c_int), ("fft_lines", ctypes.c_int)]
+
+
+TUNE_FIELDS = [f[0] for f in rp_tune_entry._fields_]
 
 
 def make_cell(lat, fft, kmesh) -> rp_cell:
@@ -92,6 +101,7 @@ def load(path: Optional[str] = None):
         "rp_chi0_batch": [P, I, ctypes.POINTER(rp_problem), I],
         "rp_screen_W": [P, cellp, P, I, P, I, P, P, P],
         "rp_wannier_W": [P, cellp, P, I, P, P, I, P, I, P, I, P, P],
+        "rp_set_tuning": [P, I, ctypes.POINTER(rp_tune_entry)],
         "rp_profile": [P, I],
         "rp_profile_read": [P, P, P],
     }
@@ -124,10 +134,28 @@ def _dp(t) -> Optional[int]:
     return t.data_ptr()
 
 
-class Context:
-    """An rp_ctx bound to a dedicated default-priority torch stream."""
+DEFAULT_TUNING = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json")
 
-    def __init__(self, device: int = 0):
+
+def load_tuning(path: str) -> list:
+    """The entries of a tuning table written by the autotuner."""
+    import json
+    with open(path) as f:
+        table = json.load(f)
+    entries = table["entries"]
+    for e in entries:
+        if sorted(e) != sorted(TUNE_FIELDS):
+            raise ValueError(f"{path}: entry fields {sorted(e)} != {sorted(TUNE_FIELDS)}")
+    return entries
+
+
+class Context:
+    """An rp_ctx bound to a dedicated default-priority torch stream.
+
+    tuning: "default" installs the package's measured table when it exists,
+    a path installs that table, None leaves the library's defaults."""
+
+    def __init__(self, device: int = 0, tuning: Optional[str] = "default"):
         import torch
         self.lib = load()
         self.device = device
@@ -137,6 +165,11 @@ class Context:
         if st != RP_OK:
             raise RpError(st, "rp_create", "context creation failed")
         self.handle = h
+        self.tuning = None
+        path = DEFAULT_TUNING if tuning == "default" else tuning
+        if path is not None and (tuning != "default" or os.path.exists(path)):
+            rp_set_tuning(self, load_tuning(path))
+            self.tuning = path
 
     def close(self):
         if getattr(self, "handle", None):
@@ -253,6 +286,15 @@ def rp_wannier_W(ctx: Context, cell: rp_cell, iq, nwan, phi, centre_frac, ng, gs
                               int(ng), _hp(g_h), int(ntail), _hp(t_h), int(nfreq), _dp(eps_inv), _dp(Wij))
     ctx._leave()
     ctx._check(st, "rp_wannier_W")
+
+
+def rp_set_tuning(ctx: Context, entries):
+    """entries: a sequence of dicts with the rp_tune_entry fields (empty clears)."""
+    arr = (rp_tune_entry * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        for name in TUNE_FIELDS:
+            setattr(arr[i], name, int(e[name]))
+    ctx._check(ctx.lib.rp_set_tuning(ctx.handle, len(entries), arr), "rp_set_tuning")
 
 
 def rp_profile(ctx: Context, enable: bool):

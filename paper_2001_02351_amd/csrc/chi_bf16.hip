@@ -20,8 +20,8 @@
 //   Wq: FP32 weights [nfreq][KP]
 // with KP = pairs padded to 32 and NGP = ng padded to 128 (zeros).
 //
-// Tiling: a 256-thread block owns a 128x128 tile of (G, G') for NW = 2
-// frequencies; each wave a 64x64 sub-tile (4x4 blocks of 16x16).  Steps of 32
+// Tiling: a 256-thread block owns a 128x128 tile of (G, G') for NW = 1 or 2
+// frequencies (a tuning choice); each wave a 64x64 sub-tile (4x4 blocks of 16x16).  Steps of 32
 // pairs stream through two LDS buffers (32 KB of A and 16 NT KB of B each)
 // by global_load_lds DMA, so the next step's operands arrive while the matrix
 // cores work on the current one.
@@ -39,7 +39,6 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 128;
 constexpr int kStep = 32;  // pairs per matrix-core step
-constexpr int kNW = 2;     // frequencies per block
 
 __device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c)
 {
@@ -141,13 +140,12 @@ __device__ __forceinline__ void tile_of(int id, int t, int herm, int &rt, int &c
 // block adds its tile into chi (and, for an off-diagonal tile of a Hermitian
 // chi, the conjugate transpose into the mirrored tile); with several slices
 // it writes its FP32 partial tile to part[slice][f][NGP][NGP] for k_chi_reduce.
-template <int NT>
+template <int NT, int NW>
 __global__ void __launch_bounds__(256)
 k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, const bf8 *__restrict__ Bp,
            int nfreq, const float2 *__restrict__ wq, int accumulate, double2 *__restrict__ chi, int herm,
            int sps, float2 *__restrict__ part)
 {
-    constexpr int NW = kNW;
     constexpr int NPL = 2 * NT;  // B planes
     // per stage: A [4 kg][8 row blocks][4 q][16][2] float2 (32 KB) and
     //            B [NPL planes][4 kg][128 cols] bf8 (8 NPL KB)
@@ -412,17 +410,18 @@ size_t split_a_bytes(long npair, int ng) { return (size_t)pad_pairs(npair) * pad
 size_t split_b_bytes(long npair, int ng) { return (size_t)6 * pad_pairs(npair) * pad_ng(ng) * 2; }
 size_t split_w_bytes(long npair, int nfreq) { return (size_t)pad_pairs(npair) * nfreq * sizeof(float2); }
 
-// Slices of the pair steps for one contraction: enough blocks to fill the
-// chip twice over (two blocks per CU), each slice at least 8 steps.
-static void chi_slices(long npair, int ng, int nfreq, bool herm, int *nslice, int *sps)
+// Slices of the pair steps for one contraction: with fill > 0, enough slices
+// that the grid holds about `fill` blocks (one block per CU fits), each slice
+// at least 8 steps; fill = 0 never slices.
+static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fill, int *nslice, int *sps)
 {
     const int t = pad_ng(ng) / kTile;
     const long tiles = herm ? (long)t * (t + 1) / 2 : (long)t * t;
-    const long blocks = tiles * ((nfreq + kNW - 1) / kNW);
+    const long blocks = tiles * ((nfreq + nw - 1) / nw);
     const int nstep = (int)(pad_pairs(npair) / kStep);
     int S = 1;
-    if (blocks < 512 && nstep >= 16) {
-        S = (int)std::min<long>((1024 + blocks - 1) / blocks, nstep / 8);
+    if (fill > 0 && blocks < fill / 2 && nstep >= 16) {
+        S = (int)std::min<long>((fill + blocks - 1) / blocks, nstep / 8);
         S = std::max(1, std::min(S, 64));
     }
     const int per = std::max(1, (nstep + S - 1) / S);
@@ -430,10 +429,10 @@ static void chi_slices(long npair, int ng, int nfreq, bool herm, int *nslice, in
     *nslice = std::max(1, (nstep + per - 1) / per);
 }
 
-size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm)
+size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill)
 {
     int S, sps;
-    chi_slices(npair, ng, nfreq, herm, &S, &sps);
+    chi_slices(npair, ng, nfreq, herm, nw, fill, &S, &sps);
     if (S == 1) return 0;
     return (size_t)S * nfreq * (size_t)pad_ng(ng) * pad_ng(ng) * sizeof(float2);
 }
@@ -459,23 +458,30 @@ void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, 
 }
 
 void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, int accumulate, double2 *chi,
-                     const void *split_a, const void *split_b, const void *split_w, bool herm, void *part)
+                     const void *split_a, const void *split_b, const void *split_w, bool herm, int nw, int fill,
+                     void *part)
 {
     const long KP = pad_pairs(npair);
     const int NGP = pad_ng(ng);
     const int npg = (int)(KP / 8);
     const int t = NGP / kTile;
+    nw = nw == 1 ? 1 : 2;
     int S, sps;
-    chi_slices(npair, ng, nfreq, herm, &S, &sps);
+    chi_slices(npair, ng, nfreq, herm, nw, fill, &S, &sps);
     const unsigned tiles = herm ? (unsigned)(t * (t + 1) / 2) : (unsigned)(t * t);
-    const dim3 grid(tiles, (unsigned)S, (nfreq + kNW - 1) / kNW);
+    const dim3 grid(tiles, (unsigned)S, (unsigned)((nfreq + nw - 1) / nw));
     float2 *P = S > 1 ? (float2 *)part : nullptr;
-    if (nterm == 2)
-        hipLaunchKernelGGL(k_chi_bf16<2>, grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a,
-                           (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P);
-    else
-        hipLaunchKernelGGL(k_chi_bf16<3>, grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a,
-                           (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P);
+#define RP_CHI(NT, NW)                                                                                         \
+    hipLaunchKernelGGL((k_chi_bf16<NT, NW>), grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a, \
+                       (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P)
+    if (nterm == 2) {
+        if (nw == 1) RP_CHI(2, 1);
+        else RP_CHI(2, 2);
+    } else {
+        if (nw == 1) RP_CHI(3, 1);
+        else RP_CHI(3, 2);
+    }
+#undef RP_CHI
     if (S > 1) {
         const int nc = NGP / 32;
         hipLaunchKernelGGL(k_chi_reduce, dim3((unsigned)(nc * nc), 1, (unsigned)nfreq), dim3(256), 0, s, S, nfreq, ng,

@@ -96,11 +96,18 @@ __global__ void k_scatter(const int *miller, const double2 *coef, int npw, int b
     u[(long)band * N1 * N2 * N3 + ((long)m1 * N2 + m2) * N3 + m3] = mkc<C>((T)c.x, (T)c.y);
 }
 
-int lines_per_block(int n) { return n <= 64 ? 32 : (n <= 128 ? 16 : 8); }
-
-template <typename C> void run_pass(hipStream_t s, C *data, const LineSet &ls, const FftPlan &plan)
+// lines per block: the tuned count when given (clamped to 64 KB of LDS), else
+// 32, 16 or 8 by length
+template <typename C> int lines_per_block(int n, int tuned)
 {
-    int lpb = lines_per_block(ls.n);
+    int lpb = tuned > 0 ? std::min(tuned, 64) : (n <= 64 ? 32 : (n <= 128 ? 16 : 8));
+    while (lpb > 1 && sizeof(C) * ((size_t)n + 2 * (size_t)lpb * (n + 1)) > 65536) lpb /= 2;
+    return lpb;
+}
+
+template <typename C> void run_pass(hipStream_t s, C *data, const LineSet &ls, const FftPlan &plan, int tuned)
+{
+    int lpb = lines_per_block<C>(ls.n, tuned);
     long nblk = (ls.nlines + lpb - 1) / lpb;
     size_t shm = sizeof(C) * ((size_t)ls.n + 2 * (size_t)lpb * (ls.n + 1));
     hipLaunchKernelGGL(k_fft_lines<C>, dim3((unsigned)nblk), dim3(256), shm, s, data, ls, plan, lpb);
@@ -116,7 +123,7 @@ void axis_box(int mmax, int N, int *B, int *mm)
 
 template <typename C>
 void fft3d_passes(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,
-                  const int mmax[3], C *data)
+                  const int mmax[3], C *data, int lines)
 {
     const int N1 = fft[0], N2 = fft[1], N3 = fft[2];
     const long nr = (long)N1 * N2 * N3;
@@ -125,18 +132,18 @@ void fft3d_passes(hipStream_t s, const FftPlan plans[3], const int fft[3], int n
     axis_box(mmax[1], N2, &B2, &mm2);
     // axis 3: lines (band, j1 in box, j2 in box), contiguous
     LineSet l3{N3, 1, (long)ngrids * B1 * B2, 1, 0, B1, mm1, N1, N2 * N3, B2, mm2, N2, N3, nr};
-    run_pass(s, data, l3, plans[2]);
+    run_pass(s, data, l3, plans[2], lines);
     // axis 2: lines (band, j1 in box, j3), stride N3
     LineSet l2{N2, N3, (long)ngrids * B1 * N3, N3, 1, B1, mm1, N1, N2 * N3, 1, 0, 1, 0, nr};
-    run_pass(s, data, l2, plans[1]);
+    run_pass(s, data, l2, plans[1], lines);
     // axis 1: lines (band, j2, j3), stride N2*N3
     LineSet l1{N1, N2 * N3, (long)ngrids * N2 * N3, N2 * N3, 1, 1, 0, 1, 0, 1, 0, 1, 0, nr};
-    run_pass(s, data, l1, plans[0]);
+    run_pass(s, data, l1, plans[0], lines);
 }
 
 template <typename C>
 void ugrid_t(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3], int nbands, int npw,
-             const int *miller_k, const double2 *coef_k, int band_stride, C *u)
+             const int *miller_k, const double2 *coef_k, int band_stride, C *u, int lines)
 {
     const long nr = (long)fft[0] * fft[1] * fft[2];
     const long tot = nr * nbands;
@@ -145,30 +152,30 @@ void ugrid_t(hipStream_t s, const FftPlan plans[3], const int fft[3], const int 
     long ns = (long)npw * nbands;
     hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, miller_k,
                        coef_k, npw, band_stride, nbands, fft[0], fft[1], fft[2], u);
-    fft3d_passes(s, plans, fft, nbands, mmax, u);
+    fft3d_passes(s, plans, fft, nbands, mmax, u, lines);
 }
 
 }  // namespace
 
 void launch_ugrid(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
                   int nbands, int npw, const int *miller_k, const double2 *coef_k,
-                  int band_stride, double2 *u)
+                  int band_stride, double2 *u, int lines)
 {
-    ugrid_t(s, plans, fft, mmax, nbands, npw, miller_k, coef_k, band_stride, u);
+    ugrid_t(s, plans, fft, mmax, nbands, npw, miller_k, coef_k, band_stride, u, lines);
 }
 
 void launch_ugrid32(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
                     int nbands, int npw, const int *miller_k, const double2 *coef_k,
-                    int band_stride, void *u)
+                    int band_stride, void *u, int lines)
 {
-    ugrid_t(s, plans, fft, mmax, nbands, npw, miller_k, coef_k, band_stride, (float2 *)u);
+    ugrid_t(s, plans, fft, mmax, nbands, npw, miller_k, coef_k, band_stride, (float2 *)u, lines);
 }
 
 void launch_fft3d(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,
                   double2 *data)
 {
     const int full[3] = {-1, -1, -1};
-    fft3d_passes(s, plans, fft, ngrids, full, data);
+    fft3d_passes(s, plans, fft, ngrids, full, data, 0);
 }
 
 }  // namespace rp

@@ -103,6 +103,20 @@ rp_status geometry(rp_ctx *ctx, const rp_cell *cell, const int iq[3], Geometry *
     return RP_OK;
 }
 
+Tune tune_for(const rp_ctx *ctx, int ng, const int fft[3])
+{
+    Tune t;
+    const int edge = std::max(fft[0], std::max(fft[1], fft[2]));
+    for (const rp_tune_entry &e : ctx->tuning) {
+        if (ng > e.ng_max || edge > e.grid_max) continue;
+        if (e.chi_nw) t.chi_nw = e.chi_nw;
+        if (e.chi_fill >= 0) t.chi_fill = e.chi_fill;
+        t.fft_lines = e.fft_lines;
+        break;
+    }
+    return t;
+}
+
 static hipEvent_t take_event(rp_ctx *ctx)
 {
     if (!ctx->spare.empty()) {
@@ -196,6 +210,7 @@ struct PairJob {
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     bool fp32 = false;
     bool empty = true;  // no band pairs in the requested ranges
+    int fft_lines = 0;  // tuned lines per workgroup of the u-grid transforms
 };
 
 static bool valid_prec(rp_precision prec)
@@ -248,6 +263,7 @@ static rp_status pair_check(rp_ctx *ctx, const rp_cell *cell, const int iq[3], i
     j->e0 = e0;
     j->e1 = e1;
     j->ng = ng;
+    j->fft_lines = tune_for(ctx, ng, g.fft).fft_lines;
     j->empty = (long)(o1 - o0) * (e1 - e0) * (k1 - k0) == 0;
     if (j->empty) return RP_OK;
     // the pair kernels' LDS plans (m3 window of the sphere, hi - lo + 1)
@@ -292,14 +308,16 @@ static rp_status pair_enqueue(rp_ctx *ctx, const PairJob &j, int k0, int k1, con
             StageTimer t(ctx, RP_STAGE_UGRID);
             if (j.fp32) {
                 float2 *v = (float2 *)grid;
-                launch_ugrid32(ctx->stream, j.plans, g.fft, j.mmax, nO, j.npw[k], mil_k, c_k, j.npw_max, v);
+                launch_ugrid32(ctx->stream, j.plans, g.fft, j.mmax, nO, j.npw[k], mil_k, c_k, j.npw_max, v,
+                               j.fft_lines);
                 launch_ugrid32(ctx->stream, j.plans, g.fft, j.mmax, nE, j.npw[kp], mil_kp, c_kp, j.npw_max,
-                               v + nr * nO);
+                               v + nr * nO, j.fft_lines);
             } else {
                 double2 *u = (double2 *)grid;
-                launch_ugrid(ctx->stream, j.plans, g.fft, j.mmax, nO, j.npw[k], mil_k, c_k, j.npw_max, u);
+                launch_ugrid(ctx->stream, j.plans, g.fft, j.mmax, nO, j.npw[k], mil_k, c_k, j.npw_max, u,
+                             j.fft_lines);
                 launch_ugrid(ctx->stream, j.plans, g.fft, j.mmax, nE, j.npw[kp], mil_kp, c_kp, j.npw_max,
-                             u + nr * nO);
+                             u + nr * nO, j.fft_lines);
             }
         }
         const int lo3 = j.lo[2] + g0[2];
@@ -334,6 +352,7 @@ struct ChiJob {
     rp_weight_mode wm = RP_W_TETRA;
     rp_precision prec = RP_FP64;
     bool herm = false;  // real weights: chi Hermitian
+    Tune tune;          // contraction launch shape
 };
 
 static rp_status weights_check(rp_ctx *ctx, const double *E, int nfreq, const double *freq_eV, double delta_eV,
@@ -375,6 +394,7 @@ static rp_status chi_check(rp_ctx *ctx, const rp_cell *cell, const int iq[3], in
     // on the imaginary axis (w = i nu) without broadening, z = i nu and
     // z' = -i nu = z* in Eqs. Xakqbk and tetrahedron, whose two terms are then
     // complex conjugates: the weights are real and chi is Hermitian
+    c->tune = tune_for(ctx, ng, c->g.fft);
     c->herm = delta_eV == 0.0;
     for (int f = 0; f < nfreq; f++)
         if (freq_eV[2 * f] != 0.0) c->herm = false;
@@ -394,7 +414,7 @@ static ChiBytes chi_bytes(const ChiJob &c, long npair)
         b.a = split_a_bytes(npair, c.ng);
         b.b = split_b_bytes(npair, c.ng);
         b.sw = split_w_bytes(npair, c.nfreq);
-        b.part = chi_part_bytes(npair, c.ng, c.nfreq, c.herm);
+        b.part = chi_part_bytes(npair, c.ng, c.nfreq, c.herm, c.tune.chi_nw, c.tune.chi_fill);
     }
     return b;
 }
@@ -432,7 +452,7 @@ static rp_status chi_enqueue(rp_ctx *ctx, const ChiJob &c, int k0, int k1, const
         }
         StageTimer t(ctx, RP_STAGE_CHI);
         launch_chi_bf16(ctx->stream, nterm, npair, c.ng, c.nfreq, accumulate, chi, bufs.a, bufs.b, bufs.sw, c.herm,
-                        bufs.part);
+                        c.tune.chi_nw, c.tune.chi_fill, bufs.part);
     }
     return check_launch(ctx, "chi0 contraction");
 }
@@ -627,6 +647,23 @@ rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], 
                        (double2 *)chi);
 }
 
+rp_status rp_set_tuning(rp_ctx *ctx, int n, const rp_tune_entry *table)
+{
+    if (!ctx) return RP_E_NULL;
+    if (n < 0) return fail(ctx, RP_E_RANGE, "n < 0");
+    if (n > 0 && !table) return fail(ctx, RP_E_NULL, "table is NULL");
+    for (int i = 0; i < n; i++) {
+        const rp_tune_entry &e = table[i];
+        if (e.ng_max < 1 || e.grid_max < 1) return fail(ctx, RP_E_RANGE, "entry %d: class bounds must be >= 1", i);
+        if (e.chi_nw < 0 || e.chi_nw > 2) return fail(ctx, RP_E_RANGE, "entry %d: chi_nw must be 0, 1 or 2", i);
+        if (e.chi_fill < -1 || e.chi_fill > (1 << 20))
+            return fail(ctx, RP_E_RANGE, "entry %d: chi_fill outside [-1, 2^20]", i);
+        if (e.fft_lines < 0 || e.fft_lines > 64) return fail(ctx, RP_E_RANGE, "entry %d: fft_lines outside [0, 64]", i);
+    }
+    ctx->tuning.assign(table, table + n);
+    return RP_OK;
+}
+
 // ---- batch of chi0 problems as one graph launch ----------------------------
 
 rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_precision prec)
@@ -708,6 +745,8 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
         const void *ptrs[] = {p.miller, p.coef, p.energy_eV, p.T, p.chi};
         key_put(key, ptrs, sizeof ptrs);
         key_val(key, p.delta_eV);
+        const int tn[] = {cj[i].tune.chi_nw, cj[i].tune.chi_fill, pj[i].fft_lines};
+        key_put(key, tn, sizeof tn);
     }
     key_put(key, stage.data(), stage.size());
     const void *ws[] = {grid.p,          ctx->mbuf.p,    ctx->weights.p, ctx->split_a.p,

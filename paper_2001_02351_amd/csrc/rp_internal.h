@@ -73,6 +73,7 @@ struct rp_ctx {
     hipGraphExec_t batch_exec = nullptr;
     std::string batch_key;
     bool capturing = false;         // stage timers stay off while a graph is captured
+    std::vector<rp_tune_entry> tuning;  // launch shapes per size class, matched in order
     // stage timers
     bool profiling = false;
     struct Mark {
@@ -89,6 +90,16 @@ rp_status fail(rp_ctx *ctx, rp_status st, const char *fmt, ...);
 rp_status ensure(rp_ctx *ctx, DevBuf &b, size_t bytes);
 rp_status check_launch(rp_ctx *ctx, const char *what);
 rp_status geometry(rp_ctx *ctx, const rp_cell *cell, const int iq[3], Geometry *g);
+
+// Launch shapes of one call: the first tuning entry whose class holds N_G and
+// the largest FFT edge, else the defaults (2 frequencies per contraction
+// workgroup, slicing towards 1024 workgroups, FFT lines per block by length).
+struct Tune {
+    int chi_nw = 2;
+    int chi_fill = 1024;
+    int fft_lines = 0;
+};
+Tune tune_for(const rp_ctx *ctx, int ng, const int fft[3]);
 
 // Brackets the launches of one stage with events when profiling is on.
 class StageTimer {
@@ -107,12 +118,12 @@ class StageTimer {
 // fft.hip: u-grids of several bands of one k: scatter + 3-D transform.
 void launch_ugrid(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
                   int nbands, int npw, const int *miller_k, const double2 *coef_k,
-                  int band_stride, double2 *u);
+                  int band_stride, double2 *u, int lines);
 
 // fft.hip: the same grids in FP32 (float2) for the split-precision path.
 void launch_ugrid32(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
                     int nbands, int npw, const int *miller_k, const double2 *coef_k,
-                    int band_stride, void *u);
+                    int band_stride, void *u, int lines);
 
 // fft.hip: in-place batched positive-exponent transform of whole grids.
 void launch_fft3d(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,
@@ -143,12 +154,12 @@ void launch_chi_f64(hipStream_t s, long npair, int ng, const double2 *M, int nfr
 size_t split_a_bytes(long npair, int ng);
 size_t split_b_bytes(long npair, int ng);
 size_t split_w_bytes(long npair, int nfreq);
-size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm);
+size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill);
 void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, const double2 *M,
                        const double2 *w, bool herm, void *split_a, void *split_b, void *split_w);
 void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, int accumulate,
                      double2 *chi, const void *split_a, const void *split_b, const void *split_w,
-                     bool herm, void *part);
+                     bool herm, int nw, int fill, void *part);
 
 // screen.hip
 void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, double *vs, int *flag);

@@ -5,6 +5,7 @@ import os
 import re
 
 import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -41,8 +42,9 @@ def test_cell_marshalling():
     assert list(c.fft) == [16, 18, 20] and list(c.kmesh) == [4, 3, 2]
 
 
-def test_problem_struct_layout_matches_the_header(tmp_path):
-    """The ctypes rp_problem has the size and field offsets of the C struct
+@pytest.mark.parametrize("name", ["rp_problem", "rp_tune_entry"])
+def test_struct_layout_matches_the_header(tmp_path, name):
+    """The ctypes structs have the size and field offsets of the C structs
     (compiled from include/rp.h with the host compiler)."""
     import shutil
     import subprocess
@@ -50,12 +52,12 @@ def test_problem_struct_layout_matches_the_header(tmp_path):
     import paper_2001_02351_amd as rp
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
-        import pytest
         pytest.skip("no host C compiler")
-    fields = [f[0] for f in rp.rp_problem._fields_]
+    cls = getattr(rp, name)
+    fields = [f[0] for f in cls._fields_]
     src = ['#include <stddef.h>', '#include <stdio.h>', '#include "rp.h"', "int main(void) {",
-           '  printf("%zu\\n", sizeof(rp_problem));']
-    src += [f'  printf("%zu\\n", offsetof(rp_problem, {f}));' for f in fields]
+           f'  printf("%zu\\n", sizeof({name}));']
+    src += [f'  printf("%zu\\n", offsetof({name}, {f}));' for f in fields]
     src += ["  return 0;", "}"]
     c = tmp_path / "layout.c"
     c.write_text("\n".join(src) + "\n")
@@ -63,8 +65,40 @@ def test_problem_struct_layout_matches_the_header(tmp_path):
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
     out = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
                                           text=True).stdout.split()]
-    assert out[0] == ctypes.sizeof(rp.rp_problem)
-    assert out[1:] == [getattr(rp.rp_problem, f).offset for f in fields]
+    assert out[0] == ctypes.sizeof(cls)
+    assert out[1:] == [getattr(cls, f).offset for f in fields]
+
+
+def test_tuning_table_loading(tmp_path):
+    import json
+
+    import paper_2001_02351_amd as rp
+    from paper_2001_02351_amd import _rp
+    good = {"entries": [dict(ng_max=512, grid_max=27, chi_nw=1, chi_fill=0, fft_lines=8)]}
+    f = tmp_path / "t.json"
+    f.write_text(json.dumps(good))
+    assert _rp.load_tuning(str(f)) == good["entries"]
+    f.write_text(json.dumps({"entries": [dict(ng_max=512, grid_max=27)]}))
+    with pytest.raises(ValueError):
+        _rp.load_tuning(str(f))
+    if os.path.exists(_rp.DEFAULT_TUNING):      # the committed table is well formed
+        for e in _rp.load_tuning(_rp.DEFAULT_TUNING):
+            assert e["chi_nw"] in (0, 1, 2) and -1 <= e["chi_fill"] and 0 <= e["fft_lines"] <= 64
+    assert rp.rp_tune_entry is _rp.rp_tune_entry
+
+
+def test_autotune_class_problems_are_alias_free():
+    """The tuner's synthetic inputs satisfy the pair kernel's alias-free
+    condition N > 2 mmax + max |m + G0| on every class."""
+    from paper_2001_02351_amd import autotune
+    for edge in autotune.GRID_BUCKETS:
+        for ng in autotune.NG_BUCKETS:
+            p = autotune._ClassProblem(edge=edge, ng=ng, nocc=2, nemp=4)
+            assert p.gsph.shape == (ng, 3) and len({tuple(g) for g in p.gsph.tolist()}) == ng
+            for a in range(3):
+                up = p.gsph[:, a].max() + (1 if p.iq[a] > 0 else 0)
+                gmax = max(abs(int(p.gsph[:, a].min())), int(up))
+                assert edge > 2 * int(p.mmax[a]) + gmax
 
 
 def test_product_does_not_import_the_oracle():

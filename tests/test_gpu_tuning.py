@@ -1,0 +1,99 @@
+"""Launch-shape tuning: every table entry computes the same chi, and the
+autotuner runs end to end.
+
+On batch system 21 (24^3 grid, 2^3 k, N_G = 1132, 16 imaginary frequencies),
+band subset 8 x 16:
+* FP64 chi is bit-identical under every FFT lines-per-workgroup choice (the
+  transforms do the same arithmetic in every partition);
+* split-BF16 chi under each contraction shape (1 or 2 frequencies per
+  workgroup, pair-step slicing off or towards 2048 workgroups) agrees with
+  the default shape to 1e-6 and with the oracle to 1e-5.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import batch_system
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+BIG = 10 ** 6
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def rp():
+    import paper_2001_02351_amd as rp
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rp.load()
+    return rp
+
+
+@pytest.fixture(scope="module")
+def ctx(rp):
+    c = rp.Context(0, tuning=None)
+    yield c
+    c.close()
+
+
+def _entry(**kw):
+    e = dict(ng_max=BIG, grid_max=BIG, chi_nw=0, chi_fill=-1, fft_lines=0)
+    e.update(kw)
+    return e
+
+
+def test_set_tuning_rejects_bad_entries(ctx, rp):
+    for bad in (_entry(chi_nw=3), _entry(chi_fill=-2), _entry(fft_lines=65), _entry(ng_max=0)):
+        with pytest.raises(rp.RpError) as e:
+            rp.rp_set_tuning(ctx, [bad])
+        assert e.value.status == 3
+    rp.rp_set_tuning(ctx, [])
+
+
+def test_tunings_compute_the_same_chi(ctx, rp):
+    from paper_2001_02351_amd import path
+    p = batch_system(21, 0)
+    d = path.DeviceInputs(p)
+    o, e = (0, 8), (p.nocc, p.nocc + 16)
+
+    def chi_for(prec, entries):
+        rp.rp_set_tuning(ctx, entries)
+        M = path.pair_density(ctx, d, 0, d.nk, o=o, e=e, prec=prec)
+        chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device="cuda")
+        rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, d.T, *o, *e, 0, d.nk, d.ng, M, d.nfreq,
+                              p.freq_eV, p.delta_eV, path.weight_mode(p), prec, 0, chi)
+        rp.rp_synchronize(ctx)
+        return chi
+
+    ref64 = chi_for(rp.RP_FP64, [])
+    for lines in (1, 4, 16, 64):
+        assert torch.equal(chi_for(rp.RP_FP64, [_entry(fft_lines=lines)]), ref64), lines
+    ref = path.to_complex(chi_for(rp.RP_SPLIT_BF16, []))
+    M = oracle.pair_densities(p, *o, *e, 0, d.nk)
+    w = oracle.prob_weights(p, *o, *e, 0, d.nk)
+    cols = np.unique(np.concatenate([np.random.default_rng(5).choice(d.ng, 30, replace=False), [d.ng - 1]]))
+    want = oracle.chi0(M[:, cols], w)
+    for nw in (1, 2):
+        for fill in (0, 2048):
+            got = path.to_complex(chi_for(rp.RP_SPLIT_BF16, [_entry(chi_nw=nw, chi_fill=fill, fft_lines=8)]))
+            d_ref = max(_rel(got[f], ref[f]) for f in range(d.nfreq))
+            d_orc = max(_rel(got[f][cols][:, cols], want[f]) for f in range(d.nfreq))
+            print(f"[tuning] nw={nw} fill={fill}: vs default {d_ref:.1e}, vs oracle {d_orc:.1e}", flush=True)
+            assert d_ref < 1e-6 and d_orc < 1e-5
+    rp.rp_set_tuning(ctx, [])
+
+
+def test_autotuner_runs(ctx, rp):
+    from paper_2001_02351_amd import autotune
+    table = autotune.autotune(ctx, ng_buckets=(512,), grid_buckets=(27,), repeats=1)
+    (e,) = table["entries"]
+    assert (e["ng_max"], e["grid_max"]) == (512, 27)
+    assert (e["chi_nw"], e["chi_fill"]) in autotune.CHI_CANDIDATES
+    assert e["fft_lines"] in autotune.FFT_CANDIDATES
