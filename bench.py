@@ -34,7 +34,8 @@ k-points in the launch configuration of the timed legs).
 --batch measures the batched uneven workload instead (24 systems x 4
 q-points, 16 imaginary frequencies, split-BF16 chi0) through rp_chi0_batch,
 one graph launch per step, beside the same problems through per-problem
-calls; its rate counts the Hermitian half of Eq. chi, F = 4 N_G^2 P N_w per
+calls; launch shapes are autotuned on the workload first (one q-point of
+every system) and the default shapes are timed beside; its rate counts the Hermitian half of Eq. chi, F = 4 N_G^2 P N_w per
 problem (real weights on the imaginary axis).
 """
 
@@ -221,7 +222,7 @@ def batch_leg(args):
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     rp.load()
-    ctx = rp.Context(0)
+    ctx = rp.Context(0, tuning=None if args.batch_tuning in ("workload", "none") else args.batch_tuning)
     ds = []
     for i, p in enumerate(probs):
         if i % 4 == 0:
@@ -243,6 +244,21 @@ def batch_leg(args):
         descs.append(path.batch_problem(d, c, kb))
     pairs = [d.nk * d.prob.nocc * d.prob.nemp for d in ds]
     f_herm = sum(4.0 * d.ng ** 2 * P * d.nfreq for d, P in zip(ds, pairs))
+    table, t_tune = None, None
+    if args.batch_tuning == "workload":
+        # launch shapes tuned on the workload: one q-point of every system
+        from paper_2001_02351_amd import autotune
+        t = time.perf_counter()
+        table = autotune.autotune(ctx, samples=[(ds[i], descs[i]["kbatch"]) for i in range(0, len(ds), 4)],
+                                  log=log)
+        t_tune = time.perf_counter() - t
+        rp.rp_set_tuning(ctx, table["entries"])
+        log(f"autotuned on {len(ds) // 4} samples in {t_tune:.1f} s")
+        if args.tuning_out:
+            with open(args.tuning_out, "w") as f:
+                json.dump(table, f, indent=1)
+    elif ctx.tuning is not None:
+        table = {"entries": rp.load_tuning(ctx.tuning), "file": os.path.relpath(ctx.tuning, ROOT)}
     t = time.perf_counter()
     rp.rp_chi0_batch(ctx, descs, prec)
     rp.rp_synchronize(ctx)
@@ -261,7 +277,7 @@ def batch_leg(args):
     tb = sorted(times)[len(times) // 2]
     # the same batch with the library's default launch shapes (no table)
     untuned = None
-    if ctx.tuning is not None:
+    if table is not None:
         rp.rp_set_tuning(ctx, [])
         rp.rp_chi0_batch(ctx, descs, prec)
         rp.rp_synchronize(ctx)
@@ -273,7 +289,7 @@ def batch_leg(args):
             ut.append(time.perf_counter() - t)
         untuned = sorted(ut)[len(ut) // 2]
         log(f"default launch shapes: {untuned:.3f} s")
-        rp.rp_set_tuning(ctx, rp.load_tuning(ctx.tuning))
+        rp.rp_set_tuning(ctx, table["entries"])
     # the same problems through per-problem calls, with per-stage timers
     rp.rp_profile(ctx, True)
     torch.cuda.synchronize()
@@ -309,7 +325,8 @@ def batch_leg(args):
             "pairs_per_k_batch": args.batch_pairs,
         },
         "s_per_batch": tb,
-        "tuning_table": None if ctx.tuning is None else os.path.relpath(ctx.tuning, ROOT),
+        "tuning": None if table is None else {"mode": args.batch_tuning, "seconds": t_tune,
+                                              "entries": table["entries"]},
         "s_per_batch_default_shapes": untuned,
         "per_problem_calls_s": tu,
         "per_problem_stage_ms": {k: v[0] for k, v in stages.items()},
@@ -334,6 +351,9 @@ def main():
     ap.add_argument("--batch", action="store_true")
     ap.add_argument("--batch-systems", type=int, default=24)
     ap.add_argument("--batch-pairs", type=int, default=40000)
+    ap.add_argument("--batch-tuning", default="workload",
+                    help="workload (autotune on the batch first), none, or a table file")
+    ap.add_argument("--tuning-out", default=None)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -21,6 +21,7 @@ import argparse
 import json
 import math
 import time
+from typing import Optional
 
 import numpy as np
 
@@ -28,7 +29,7 @@ from . import _rp
 
 NG_BUCKETS = (512, 768, 1024, 1200)
 GRID_BUCKETS = (27, 32, 40)
-CHI_CANDIDATES = tuple((nw, fill) for nw in (1, 2) for fill in (0, 512, 1024, 2048))
+CHI_CANDIDATES = tuple((nw, fill) for nw in (1, 2) for fill in (0, 256, 512, 1024, 2048, 4096))
 FFT_CANDIDATES = (0, 4, 8, 16, 32)
 
 
@@ -112,59 +113,131 @@ def _timed(ctx, fn, repeats: int) -> float:
     return sorted(times)[len(times) // 2]
 
 
-def autotune(ctx, ng_buckets=NG_BUCKETS, grid_buckets=GRID_BUCKETS, repeats: int = 3, log=print) -> dict:
-    """Measure every candidate per class; returns the table (JSON-ready)."""
+def _bucket(v: int, buckets) -> Optional[int]:
+    for b in buckets:
+        if v <= b:
+            return b
+    return None
+
+
+class _Sample:
+    """A problem the tuner measures: device inputs of the path's DeviceInputs
+    form plus the k batch its contractions use."""
+
+    def __init__(self, d, kbatch: int):
+        p = d.prob
+        self.d, self.kbatch = d, kbatch
+        self.ng, self.nk, self.nfreq = d.ng, d.nk, d.nfreq
+        self.npk, self.edge = p.nocc * p.nemp, max(p.fft)
+
+    def pair(self, ctx, k0, k1, M, prec):
+        d, p = self.d, self.d.prob
+        _rp.rp_pair_density(ctx, d.cell, p.iq, d.nband, p.miller.shape[1], p.npw, d.mmax, d.miller, d.coef,
+                            0, p.nocc, p.nocc, p.nocc + p.nemp, k0, k1, d.ng, p.gsph, prec, M)
+
+    def chi(self, ctx, k1, M, chi, prec):
+        d, p = self.d, self.d.prob
+        wm = _rp.RP_W_SAMPLING if d.nk == 1 else _rp.RP_W_TETRA
+        _rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, d.T, 0, p.nocc, p.nocc, p.nocc + p.nemp,
+                               0, k1, d.ng, M, d.nfreq, p.freq_eV, p.delta_eV, wm, prec, 0, chi)
+
+
+class _Synthetic:
+    """A synthetic class problem in the _Sample form (all k in one batch)."""
+
+    def __init__(self, p: _ClassProblem):
+        self.dev = _Device(p)
+        self.ng, self.nk, self.nfreq = p.ng, p.nk, len(p.freq)
+        self.npk, self.edge, self.kbatch = p.nocc * p.nemp, max(p.fft), p.nk
+
+    def pair(self, ctx, k0, k1, M, prec):
+        self.dev.pair(ctx, k0, k1, M, prec)
+
+    def chi(self, ctx, k1, M, chi, prec):
+        self.dev.chi(ctx, M, chi, prec)
+
+
+def autotune(ctx, samples=None, ng_buckets=NG_BUCKETS, grid_buckets=GRID_BUCKETS, repeats: int = 3,
+             log=print) -> dict:
+    """Measure every candidate per class and keep the fastest; returns the
+    table (JSON-ready).
+
+    samples: optional list of (DeviceInputs, kbatch) of the workload to tune
+    for; each class then sums the device time of its samples' first k batch
+    (contraction) or first two k-points (u-grids).  Without samples, one
+    synthetic problem at the class's upper sizes stands for each class."""
     import torch
     prec = _rp.RP_SPLIT_BF16
     big = 10 ** 6
-    chi_pick, chi_ms = {}, {}
-    for ngb in ng_buckets:
-        p = _ClassProblem(edge=32, ng=ngb)
-        d = _Device(p)
-        npair = p.nk * p.nocc * p.nemp
-        M = torch.empty((npair, p.ng, 2), dtype=torch.float64, device="cuda")
-        chi = torch.empty((len(p.freq), p.ng, p.ng, 2), dtype=torch.float64, device="cuda")
+    if samples:
+        items = [_Sample(d, kb) for d, kb in samples]
+        chi_items = [(_bucket(m.ng, ng_buckets), m) for m in items]
+        fft_items = [(_bucket(m.edge, grid_buckets), m) for m in items]
+    else:
+        chi_items = [(b, _Synthetic(_ClassProblem(edge=32, ng=b))) for b in ng_buckets]
+        fft_items = [(b, _Synthetic(_ClassProblem(edge=b, ng=300))) for b in grid_buckets]
+    chi_tot = {b: {c: 0.0 for c in CHI_CANDIDATES} for b in ng_buckets}
+    for b, smp in chi_items:
+        if b is None:
+            continue
+        k1 = min(smp.nk, smp.kbatch)
+        M = torch.empty((k1 * smp.npk, smp.ng, 2), dtype=torch.float64, device="cuda")
+        chi = torch.empty((smp.nfreq, smp.ng, smp.ng, 2), dtype=torch.float64, device="cuda")
         _rp.rp_set_tuning(ctx, [])
-        d.pair(ctx, 0, p.nk, M, prec)
-        res = {}
-        for nw, fill in CHI_CANDIDATES:
-            _rp.rp_set_tuning(ctx, [dict(ng_max=big, grid_max=big, chi_nw=nw, chi_fill=fill, fft_lines=0)])
-            res[(nw, fill)] = _timed(ctx, lambda: d.chi(ctx, M, chi, prec), repeats)
-        best = min(res, key=res.get)
-        chi_pick[ngb] = best
-        chi_ms[ngb] = {f"nw{nw}_fill{fill}": round(v, 4) for (nw, fill), v in res.items()}
-        log(f"[autotune] N_G <= {ngb} ({npair} pairs, 16 w): " +
-            ", ".join(f"nw={nw} fill={fill}: {v:.3f} ms" for (nw, fill), v in res.items()) +
-            f" -> nw={best[0]} fill={best[1]}")
+        smp.pair(ctx, 0, k1, M, prec)
+        for c in CHI_CANDIDATES:
+            _rp.rp_set_tuning(ctx, [dict(ng_max=big, grid_max=big, chi_nw=c[0], chi_fill=c[1], fft_lines=0)])
+            chi_tot[b][c] += _timed(ctx, lambda: smp.chi(ctx, k1, M, chi, prec), repeats)
         del M, chi
-    fft_pick, fft_ms = {}, {}
-    for gb in grid_buckets:
-        p = _ClassProblem(edge=gb, ng=300)
-        d = _Device(p)
-        M = torch.empty((2 * p.nocc * p.nemp, p.ng, 2), dtype=torch.float64, device="cuda")
-        res = {}
+    chi_pick = {}
+    for b in ng_buckets:
+        res = chi_tot[b]
+        if not any(res.values()):
+            continue
+        best = min(res, key=res.get)
+        chi_pick[b] = best
+        log(f"[autotune] N_G <= {b}: " + ", ".join(f"nw={nw} fill={fill}: {v:.3f} ms"
+                                                   for (nw, fill), v in res.items()) +
+            f" -> nw={best[0]} fill={best[1]}")
+    fft_tot = {b: {c: 0.0 for c in FFT_CANDIDATES} for b in grid_buckets}
+    for b, smp in fft_items:
+        if b is None:
+            continue
+        k1 = min(2, smp.nk)
+        M = torch.empty((k1 * smp.npk, smp.ng, 2), dtype=torch.float64, device="cuda")
         for lines in FFT_CANDIDATES:
             _rp.rp_set_tuning(ctx, [dict(ng_max=big, grid_max=big, chi_nw=0, chi_fill=-1, fft_lines=lines)])
-            d.pair(ctx, 0, 2, M, prec)
+            smp.pair(ctx, 0, k1, M, prec)
             vals = []
             for _ in range(repeats):
                 _rp.rp_profile(ctx, True)
-                d.pair(ctx, 0, 2, M, prec)
+                smp.pair(ctx, 0, k1, M, prec)
                 vals.append(_rp.rp_profile_read(ctx)["ugrid"][0])
                 _rp.rp_profile(ctx, False)
-            res[lines] = sorted(vals)[len(vals) // 2]
+            fft_tot[b][lines] += sorted(vals)[len(vals) // 2]
+        del M
+    fft_pick = {}
+    for b in grid_buckets:
+        res = fft_tot[b]
+        if not any(res.values()):
+            continue
         best = min(res, key=res.get)
-        fft_pick[gb] = best
-        fft_ms[gb] = {f"lines{k}": round(v, 4) for k, v in res.items()}
-        log(f"[autotune] edge <= {gb}: " + ", ".join(f"lines={k}: {v:.3f} ms" for k, v in res.items()) +
+        fft_pick[b] = best
+        log(f"[autotune] edge <= {b}: " + ", ".join(f"lines={k}: {v:.3f} ms" for k, v in res.items()) +
             f" -> lines={best}")
     _rp.rp_set_tuning(ctx, [])
-    entries = [dict(ng_max=ngb, grid_max=gb, chi_nw=chi_pick[ngb][0], chi_fill=chi_pick[ngb][1],
-                    fft_lines=fft_pick[gb]) for ngb in ng_buckets for gb in grid_buckets]
+    default_chi = (0, -1)
+    entries = [dict(ng_max=nb, grid_max=gb, chi_nw=chi_pick.get(nb, default_chi)[0],
+                    chi_fill=chi_pick.get(nb, default_chi)[1], fft_lines=fft_pick.get(gb, 0))
+               for nb in ng_buckets for gb in grid_buckets]
     return {"device": torch.cuda.get_device_name(0), "ng_buckets": list(ng_buckets),
             "grid_buckets": list(grid_buckets), "entries": entries,
-            "measured_ms": {"chi": {str(k): v for k, v in chi_ms.items()},
-                            "ugrid": {str(k): v for k, v in fft_ms.items()}},
+            "tuned_on": "workload samples" if samples else "synthetic class problems",
+            "samples": len(samples) if samples else 0,
+            "measured_ms": {"chi": {str(b): {f"nw{c[0]}_fill{c[1]}": round(v, 4) for c, v in r.items()}
+                                    for b, r in chi_tot.items()},
+                            "ugrid": {str(b): {f"lines{c}": round(v, 4) for c, v in r.items()}
+                                      for b, r in fft_tot.items()}},
             "created": time.strftime("%Y-%m-%d %H:%M:%S")}
 
 
