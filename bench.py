@@ -259,6 +259,17 @@ def batch_leg(args):
                 json.dump(table, f, indent=1)
     elif ctx.tuning is not None:
         table = {"entries": rp.load_tuning(ctx.tuning), "file": os.path.relpath(ctx.tuning, ROOT)}
+    if args.batch_no_graph:
+        # per-problem calls only (for profilers that do not follow graph launches)
+        for i in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for d, c, q in zip(ds, chis, descs):
+                path.chi0(ctx, d, prec=prec, kbatch=q["kbatch"], chi=c)
+            rp.rp_synchronize(ctx)
+            log(f"per-problem calls {i}: {time.perf_counter() - t:.3f} s")
+        ctx.close()
+        return
     t = time.perf_counter()
     rp.rp_chi0_batch(ctx, descs, prec)
     rp.rp_synchronize(ctx)
@@ -354,6 +365,7 @@ def main():
     ap.add_argument("--batch-tuning", default="workload",
                     help="workload (autotune on the batch first), none, or a table file")
     ap.add_argument("--tuning-out", default=None)
+    ap.add_argument("--batch-no-graph", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
