@@ -232,7 +232,8 @@ constexpr int kWThreads = 128;
 // One thread per (pair, frequency).  The corner energies e_j and log(z - e_j)
 // of the 15 distinct corners live in LDS ([slot][thread]); each of the 24
 // tetrahedra sorts its five nodes (four corners, k's corner doubled) together
-// with their logarithms and evaluates I_v(z) and I_v(z').
+// with their logarithms and evaluates I_v(z) and I_v(z') (only I_v(z) when
+// z' = z*).
 __global__ void __launch_bounds__(kWThreads)
 k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const double *E, const double *T,
           int o0, int nO, int e0, int nE, int k0, long npair, int nfreq, const double2 *freq,
@@ -268,8 +269,11 @@ k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const doubl
             const int kvq = (mesh_wrap(m1 + q1, K1) * K2 + mesh_wrap(m2 + q2, K2)) * K3 + mesh_wrap(m3 + q3, K3);
             sE[j][tid] = (E[(long)kvq * nband + a] - E[(long)kv * nband + b]) * ha;
         }
+        // on the imaginary axis without broadening z' = z*, and since the
+        // corner energies are real I_v(z*) = conj(I_v(z)): x = 2 Re sum I_v(z)/6
+        const bool conj_pair = dl == 0.0 && om.x == 0.0;
         x = make_double2(0.0, 0.0);
-        for (int zi = 0; zi < 2; zi++) {
+        for (int zi = 0; zi < (conj_pair ? 1 : 2); zi++) {
             const double2 zz = zi ? zp : z;
 #pragma unroll
             for (int j = 0; j < 15; j++) sL[j][tid] = clog_d(make_double2(zz.x - sE[j][tid], zz.y));
@@ -301,6 +305,7 @@ k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const doubl
                 x = cadd(x, dd4_sorted(zz, xs, ls));
             }
         }
+        if (conj_pair) x = make_double2(2.0 * x.x, 0.0);
         x = cscale(x, 1.0 / 6.0);
     }
     double fac = 2.0 / (double)(K1 * K2 * K3);
