@@ -141,34 +141,40 @@ void fft3d_passes(hipStream_t s, const FftPlan plans[3], const int fft[3], int n
     run_pass(s, data, l1, plans[0], lines);
 }
 
+// The u-grids of two band sets (occupied bands at k, empty bands at k+q) that
+// sit one after the other in u: one zero fill, a scatter per set, and one set
+// of transforms over all nA + nB grids.
 template <typename C>
-void ugrid_t(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3], int nbands, int npw,
-             const int *miller_k, const double2 *coef_k, int band_stride, C *u, int lines)
+void ugrid2_t(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3], int nA, int npwA,
+              const int *millerA, const double2 *coefA, int nB, int npwB, const int *millerB,
+              const double2 *coefB, int band_stride, C *u, int lines)
 {
     const long nr = (long)fft[0] * fft[1] * fft[2];
-    const long tot = nr * nbands;
+    const long tot = nr * (nA + nB);
     unsigned zb = (unsigned)std::min<long>((tot + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero<C>, dim3(zb), dim3(256), 0, s, u, tot);
-    long ns = (long)npw * nbands;
-    hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, miller_k,
-                       coef_k, npw, band_stride, nbands, fft[0], fft[1], fft[2], u);
-    fft3d_passes(s, plans, fft, nbands, mmax, u, lines);
+    const long nsA = (long)npwA * nA, nsB = (long)npwB * nB;
+    if (nsA > 0)
+        hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)((nsA + 255) / 256)), dim3(256), 0, s, millerA, coefA, npwA,
+                           band_stride, nA, fft[0], fft[1], fft[2], u);
+    if (nsB > 0)
+        hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)((nsB + 255) / 256)), dim3(256), 0, s, millerB, coefB, npwB,
+                           band_stride, nB, fft[0], fft[1], fft[2], u + nr * nA);
+    fft3d_passes(s, plans, fft, nA + nB, mmax, u, lines);
 }
 
 }  // namespace
 
-void launch_ugrid(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
-                  int nbands, int npw, const int *miller_k, const double2 *coef_k,
-                  int band_stride, double2 *u, int lines)
+void launch_ugrid2(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3], int nA, int npwA,
+                   const int *millerA, const double2 *coefA, int nB, int npwB, const int *millerB,
+                   const double2 *coefB, int band_stride, void *u, bool fp32, int lines)
 {
-    ugrid_t(s, plans, fft, mmax, nbands, npw, miller_k, coef_k, band_stride, u, lines);
-}
-
-void launch_ugrid32(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
-                    int nbands, int npw, const int *miller_k, const double2 *coef_k,
-                    int band_stride, void *u, int lines)
-{
-    ugrid_t(s, plans, fft, mmax, nbands, npw, miller_k, coef_k, band_stride, (float2 *)u, lines);
+    if (fp32)
+        ugrid2_t(s, plans, fft, mmax, nA, npwA, millerA, coefA, nB, npwB, millerB, coefB, band_stride, (float2 *)u,
+                 lines);
+    else
+        ugrid2_t(s, plans, fft, mmax, nA, npwA, millerA, coefA, nB, npwB, millerB, coefB, band_stride, (double2 *)u,
+                 lines);
 }
 
 void launch_fft3d(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,

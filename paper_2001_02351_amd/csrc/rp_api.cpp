@@ -306,19 +306,8 @@ static rp_status pair_enqueue(rp_ctx *ctx, const PairJob &j, int k0, int k1, con
         const double2 *c_kp = j.coef + ((long)kp * j.nband + j.e0) * j.npw_max;
         {
             StageTimer t(ctx, RP_STAGE_UGRID);
-            if (j.fp32) {
-                float2 *v = (float2 *)grid;
-                launch_ugrid32(ctx->stream, j.plans, g.fft, j.mmax, nO, j.npw[k], mil_k, c_k, j.npw_max, v,
-                               j.fft_lines);
-                launch_ugrid32(ctx->stream, j.plans, g.fft, j.mmax, nE, j.npw[kp], mil_kp, c_kp, j.npw_max,
-                               v + nr * nO, j.fft_lines);
-            } else {
-                double2 *u = (double2 *)grid;
-                launch_ugrid(ctx->stream, j.plans, g.fft, j.mmax, nO, j.npw[k], mil_k, c_k, j.npw_max, u,
-                             j.fft_lines);
-                launch_ugrid(ctx->stream, j.plans, g.fft, j.mmax, nE, j.npw[kp], mil_kp, c_kp, j.npw_max,
-                             u + nr * nO, j.fft_lines);
-            }
+            launch_ugrid2(ctx->stream, j.plans, g.fft, j.mmax, nO, j.npw[k], mil_k, c_k, nE, j.npw[kp], mil_kp, c_kp,
+                          j.npw_max, grid, j.fp32, j.fft_lines);
         }
         const int lo3 = j.lo[2] + g0[2];
         double2 *Mk = M + (long)(k - k0) * nE * nO * j.ng;

@@ -115,15 +115,12 @@ class StageTimer {
 
 // ---- kernel launchers (one translation unit each) --------------------------
 
-// fft.hip: u-grids of several bands of one k: scatter + 3-D transform.
-void launch_ugrid(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
-                  int nbands, int npw, const int *miller_k, const double2 *coef_k,
-                  int band_stride, double2 *u, int lines);
-
-// fft.hip: the same grids in FP32 (float2) for the split-precision path.
-void launch_ugrid32(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3],
-                    int nbands, int npw, const int *miller_k, const double2 *coef_k,
-                    int band_stride, void *u, int lines);
+// fft.hip: u-grids (scatter + pruned 3-D transform) of two band sets stored
+// one after the other in u (nA grids from millerA/coefA, then nB from
+// millerB/coefB), FP32 or FP64.
+void launch_ugrid2(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3], int nA, int npwA,
+                   const int *millerA, const double2 *coefA, int nB, int npwB, const int *millerB,
+                   const double2 *coefB, int band_stride, void *u, bool fp32, int lines);
 
 // fft.hip: in-place batched positive-exponent transform of whole grids.
 void launch_fft3d(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,
