@@ -121,6 +121,17 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(prob, nemp_sample: int = 100, nfreq_sample: int = 4):
     """Time the FP64 oracle on a bounded sample: k = 0, all occupied bands x
     the first `nemp_sample` empty bands, the first `nfreq_sample` frequencies
@@ -146,6 +157,7 @@ def cpu_baseline(prob, nemp_sample: int = 100, nfreq_sample: int = 4):
         "value": flops / (t3 - t0) / 1e12,
         "unit": "TFLOP/s",
         "cores": oracle.threads_used(),
+        "cpu_model": _cpu_model(),
         "kind": "oracle",
         "sample": (f"k=0 only, {p.nocc} occupied x {nemp_sample} empty bands ({npair} pairs), "
                    f"{nfreq_sample} of {prob.nfreq} frequencies, N_G={p.ng}: pair densities "
@@ -218,6 +230,16 @@ def batch_leg(args):
     for s in range(nsys):
         probs += batch_system_qpoints(s)
     log(f"generated in {time.perf_counter() - t0:.1f} s")
+    baseline = None
+    if not args.no_cpu_baseline and not args.batch_no_graph:
+        # the oracle on one problem of the batch (system 21, the fewest pairs
+        # per k-point): k = 0, all occupied x 40 empty bands, 4 frequencies
+        small = [p for p in probs if p.name == "batch_system_21_q0"]
+        if small:
+            log("timing the FP64 oracle on a bounded sample of the batch (host cores)")
+            baseline = cpu_baseline(small[0], nemp_sample=40, nfreq_sample=4)
+            baseline["value"] /= 2.0     # Hermitian-half flops, as the batch rate counts them
+            log(f"oracle sample: {baseline['sample']}")
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
@@ -342,6 +364,9 @@ def batch_leg(args):
         "per_problem_calls_s": tu,
         "per_problem_stage_ms": {k: v[0] for k, v in stages.items()},
         "per_problem_stage_launches": {k: v[1] for k, v in stages.items()},
+        "cpu_baseline": None if baseline is None else {k: baseline[k] for k in
+                                                        ("value", "unit", "cores", "cpu_model", "kind",
+                                                         "sample")},
     }
     print(json.dumps(out), flush=True)
 
@@ -499,7 +524,8 @@ def main():
         },
         "hbm_a2_a4": hbm,
         "cpu_baseline": None if baseline is None else {k: baseline[k] for k in
-                                                        ("value", "unit", "cores", "kind", "sample")},
+                                                        ("value", "unit", "cores", "cpu_model", "kind",
+                                                         "sample")},
     }
     if fp64 is not None:
         a64 = fp64["chi_kernel_flops_per_launch"] / (fp64["chi_kernel_ms_per_launch"] / 1e3) / 1e12
