@@ -233,11 +233,11 @@ def batch_leg(args):
     baseline = None
     if not args.no_cpu_baseline and not args.batch_no_graph:
         # the oracle on one problem of the batch (system 21, the fewest pairs
-        # per k-point): k = 0, all occupied x 40 empty bands, 4 frequencies
+        # per k-point): k = 0, all 29 occupied x 90 empty bands, 16 frequencies
         small = [p for p in probs if p.name == "batch_system_21_q0"]
         if small:
             log("timing the FP64 oracle on a bounded sample of the batch (host cores)")
-            baseline = cpu_baseline(small[0], nemp_sample=40, nfreq_sample=4)
+            baseline = cpu_baseline(small[0], nemp_sample=90, nfreq_sample=16)
             baseline["value"] /= 2.0     # Hermitian-half flops, as the batch rate counts them
             log(f"oracle sample: {baseline['sample']}")
     if not torch.cuda.is_available():
