@@ -276,6 +276,10 @@ rp_status rp_wannier_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nw
  *              the default, 1024)
  *   fft_lines  lines per workgroup of the u-grid transforms, 1..64 (0: 32,
  *              16 or 8 by length)
+ *   chi_kernel split-BF16 contraction form: 0 = 128 x 128 tiles on four
+ *              waves, 1 = 256 x 64 tiles on eight waves (two per SIMD, 32x32
+ *              matrix-core ops; used where N_G pads to a multiple of 256 and
+ *              the weights are complex, else form 0)
  * Only launch shapes change: every choice computes the same sums (the
  * contraction's FP32 partial sums are grouped differently when sliced).
  * Errors: RP_E_NULL, RP_E_RANGE.
@@ -286,6 +290,7 @@ typedef struct {
     int chi_nw;
     int chi_fill;
     int fft_lines;
+    int chi_kernel;
 } rp_tune_entry;
 
 rp_status rp_set_tuning(rp_ctx *ctx, int n, const rp_tune_entry *table);

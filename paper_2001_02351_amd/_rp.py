@@ -59,7 +59,7 @@ class rp_problem(ctypes.Structure):
 class rp_tune_entry(ctypes.Structure):
     """One size class of the launch-shape table (the C struct of the same name)."""
     _fields_ = [("ng_max", ctypes.c_int), ("grid_max", ctypes.c_int), ("chi_nw", ctypes.c_int),
-                ("chi_fill", ctypes.c_int), ("fft_lines", ctypes.c_int)]
+                ("chi_fill", ctypes.c_int), ("fft_lines", ctypes.c_int), ("chi_kernel", ctypes.c_int)]
 
 
 TUNE_FIELDS = [f[0] for f in rp_tune_entry._fields_]

@@ -5,9 +5,10 @@ times the candidate launch shapes on synthetic inputs of the class's upper
 sizes (random coefficients and energies: only the shapes matter for timing)
 and keeps the fastest:
 
-* the split-BF16 contraction (chi_nw frequencies per workgroup, chi_fill
-  workgroups aimed for by slicing the pair steps): timed per N_G bucket on
-  one contraction of about 40 000 pairs with 16 imaginary frequencies;
+* the split-BF16 contraction (chi_kernel form, chi_nw frequencies per
+  workgroup, chi_fill workgroups aimed for by slicing the pair steps): timed
+  per N_G bucket on one contraction of the samples' first k batch (or of
+  about 40 000 pairs with 16 imaginary frequencies for the synthetic classes);
 * the u-grid transforms (fft_lines per workgroup): timed per edge bucket
   with the stage timer of the u-grid kernels.
 
@@ -29,7 +30,8 @@ from . import _rp
 
 NG_BUCKETS = (512, 768, 1024, 1200)
 GRID_BUCKETS = (27, 32, 40)
-CHI_CANDIDATES = tuple((nw, fill) for nw in (1, 2) for fill in (0, 256, 512, 1024, 2048, 4096, 8192))
+CHI_CANDIDATES = tuple((kern, nw, fill) for kern in (0, 1) for nw in (1, 2)
+                       for fill in (0, 256, 512, 1024, 2048, 4096, 8192))
 FFT_CANDIDATES = (0, 4, 8, 16, 32)
 
 
@@ -186,7 +188,8 @@ def autotune(ctx, samples=None, ng_buckets=NG_BUCKETS, grid_buckets=GRID_BUCKETS
         _rp.rp_set_tuning(ctx, [])
         smp.pair(ctx, 0, k1, M, prec)
         for c in CHI_CANDIDATES:
-            _rp.rp_set_tuning(ctx, [dict(ng_max=big, grid_max=big, chi_nw=c[0], chi_fill=c[1], fft_lines=0)])
+            _rp.rp_set_tuning(ctx, [dict(ng_max=big, grid_max=big, chi_nw=c[1], chi_fill=c[2], fft_lines=0,
+                                         chi_kernel=c[0])])
             chi_tot[b][c] += _timed(ctx, lambda: smp.chi(ctx, k1, M, chi, prec), repeats)
         del M, chi
     chi_pick = {}
@@ -196,9 +199,9 @@ def autotune(ctx, samples=None, ng_buckets=NG_BUCKETS, grid_buckets=GRID_BUCKETS
             continue
         best = min(res, key=res.get)
         chi_pick[b] = best
-        log(f"[autotune] N_G <= {b}: " + ", ".join(f"nw={nw} fill={fill}: {v:.3f} ms"
-                                                   for (nw, fill), v in res.items()) +
-            f" -> nw={best[0]} fill={best[1]}")
+        log(f"[autotune] N_G <= {b}: " + ", ".join(f"kernel={k} nw={nw} fill={fill}: {v:.3f} ms"
+                                                   for (k, nw, fill), v in res.items()) +
+            f" -> kernel={best[0]} nw={best[1]} fill={best[2]}")
     fft_tot = {b: {c: 0.0 for c in FFT_CANDIDATES} for b in grid_buckets}
     for b, smp in fft_items:
         if b is None:
@@ -206,7 +209,8 @@ def autotune(ctx, samples=None, ng_buckets=NG_BUCKETS, grid_buckets=GRID_BUCKETS
         k1 = min(2, smp.nk)
         M = torch.empty((k1 * smp.npk, smp.ng, 2), dtype=torch.float64, device="cuda")
         for lines in FFT_CANDIDATES:
-            _rp.rp_set_tuning(ctx, [dict(ng_max=big, grid_max=big, chi_nw=0, chi_fill=-1, fft_lines=lines)])
+            _rp.rp_set_tuning(ctx, [dict(ng_max=big, grid_max=big, chi_nw=0, chi_fill=-1, fft_lines=lines,
+                                         chi_kernel=0)])
             smp.pair(ctx, 0, k1, M, prec)
             vals = []
             for _ in range(repeats):
@@ -226,15 +230,17 @@ def autotune(ctx, samples=None, ng_buckets=NG_BUCKETS, grid_buckets=GRID_BUCKETS
         log(f"[autotune] edge <= {b}: " + ", ".join(f"lines={k}: {v:.3f} ms" for k, v in res.items()) +
             f" -> lines={best}")
     _rp.rp_set_tuning(ctx, [])
-    default_chi = (0, -1)
-    entries = [dict(ng_max=nb, grid_max=gb, chi_nw=chi_pick.get(nb, default_chi)[0],
-                    chi_fill=chi_pick.get(nb, default_chi)[1], fft_lines=fft_pick.get(gb, 0))
+    default_chi = (0, 0, -1)
+    entries = [dict(ng_max=nb, grid_max=gb, chi_kernel=chi_pick.get(nb, default_chi)[0],
+                    chi_nw=chi_pick.get(nb, default_chi)[1], chi_fill=chi_pick.get(nb, default_chi)[2],
+                    fft_lines=fft_pick.get(gb, 0))
                for nb in ng_buckets for gb in grid_buckets]
     return {"device": torch.cuda.get_device_name(0), "ng_buckets": list(ng_buckets),
             "grid_buckets": list(grid_buckets), "entries": entries,
             "tuned_on": "workload samples" if samples else "synthetic class problems",
             "samples": len(samples) if samples else 0,
-            "measured_ms": {"chi": {str(b): {f"nw{c[0]}_fill{c[1]}": round(v, 4) for c, v in r.items()}
+            "measured_ms": {"chi": {str(b): {f"kernel{c[0]}_nw{c[1]}_fill{c[2]}": round(v, 4)
+                                             for c, v in r.items()}
                                     for b, r in chi_tot.items()},
                             "ugrid": {str(b): {f"lines{c}": round(v, 4) for c, v in r.items()}
                                       for b, r in fft_tot.items()}},

@@ -34,6 +34,7 @@ namespace rp {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
@@ -353,6 +354,167 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     }
 }
 
+// Wide form: a 512-thread block owns a 256 x 64 tile of (G, G') for NW
+// frequencies; each of its 8 waves (two per SIMD) owns 32 whole rows of the
+// tile as two 32 x 32 blocks on v_mfma_f32_32x32x16_bf16, so every row of A is
+// weighted and split by one wave only.  Steps of 16 pairs (one pair group of
+// 8 per wave half) stream through two LDS stages (32 KB of A, 2 NT KB of B and
+// the step's weights each) by global_load_lds DMA.  The operand layouts are
+// those of the prep pass above (a block of 16 rows x 8 pairs in quarter
+// order for A; per plane 8 consecutive pairs of one column for B).  The
+// contraction of one (a, b) pair is the same sum of split products as in
+// k_chi_bf16; only the tiling differs.  Not for a Hermitian chi.
+__device__ __forceinline__ f16v mfma32_bf16(bf8 a, bf8 b, f16v c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int NT, int NW>
+__global__ void __launch_bounds__(512)
+k_chi_bf16_wide(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, const bf8 *__restrict__ Bp,
+                int nfreq, const float2 *__restrict__ wq, int accumulate, double2 *__restrict__ chi, int sps,
+                float2 *__restrict__ part)
+{
+    constexpr int NPL = 2 * NT;
+    // per stage: A [2 pair groups][16 row blocks][128] float2 (32 KB),
+    //            B [NPL planes][2 pair groups][64 cols] bf8, W [NW][16 pairs] float2
+    __shared__ float2 sA[2][2 * 16 * 128];
+    __shared__ bf8 sB[2][NPL * 2 * 64];
+    __shared__ float2 sW[2][NW * 16];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int r32 = lane & 31, h = lane >> 5;
+    const int TC = NGP / 64;
+    const int rt0 = (blockIdx.x / TC) * 256, ct0 = (blockIdx.x % TC) * 64;
+    const int f0 = blockIdx.z * NW;
+    const long plane = (long)npg * NGP;
+    const int step0 = blockIdx.y * sps;
+    const int nstep = min(sps, npg / 2 - step0);
+
+    // DMA of step t (pair groups 2t, 2t+1): wave w moves the A blocks of
+    // pair group w/4, row blocks 4(w%4)..4(w%4)+3, then its share of the
+    // 2 NPL B segments; wave 0's first 8 NW lanes move the weights
+    auto issue = [&](float2 *dA, bf8 *dB, float2 *dW, int t) {
+        const int pgw = 2 * t + (wave >> 2);
+        const float2 *a = Ap + ((long)pgw * (NGP / 16) + rt0 / 16 + (wave & 3) * 4) * 128 + lane * 2;
+        float2 *da = dA + ((wave >> 2) * 16 + (wave & 3) * 4) * 128;
+#pragma unroll
+        for (int i = 0; i < 4; i++) dma16(a + i * 128, da + i * 128);
+#pragma unroll
+        for (int sid = wave; sid < 2 * NPL; sid += 8) {
+            const int sp = sid >> 1, g = sid & 1;
+            dma16(Bp + sp * plane + (long)(2 * t + g) * NGP + ct0 + lane, dB + sid * 64);
+        }
+        if (wave == 0 && lane < 8 * NW) {
+            const int f = min(f0 + lane / 8, nfreq - 1);
+            dma16(wq + (long)f * KP + (long)t * 16 + (lane & 7) * 2, dW);
+        }
+    };
+
+    f16v accR[NW][2], accI[NW][2];
+#pragma unroll
+    for (int iw = 0; iw < NW; iw++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int e = 0; e < 16; e++) {
+                accR[iw][cb][e] = 0.f;
+                accI[iw][cb][e] = 0.f;
+            }
+
+    auto step = [&](float2 *__restrict__ nA, bf8 *__restrict__ nB, float2 *__restrict__ nW,
+                    const float2 *__restrict__ cA, const bf8 *__restrict__ cB, const float2 *__restrict__ cW,
+                    int tn) {
+        if (tn >= 0) issue(nA, nB, nW, tn);
+        bf8 B[2][NPL];
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int sp = 0; sp < NPL; sp++) B[cb][sp] = cB[(sp * 2 + h) * 64 + cb * 32 + r32];
+        const float2 *blk = cA + (h * 16 + 2 * wave + (r32 >> 4)) * 128 + (r32 & 15) * 2;
+        float2 araw[8];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const float4 v = *(const float4 *)(blk + q * 32);
+            araw[2 * q] = make_float2(v.x, v.y);
+            araw[2 * q + 1] = make_float2(v.z, v.w);
+        }
+#pragma unroll
+        for (int iw = 0; iw < NW; iw++) {
+            float2 wv[8];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const float4 v = *(const float4 *)(cW + iw * 16 + h * 8 + 2 * q);
+                wv[2 * q] = make_float2(v.x, v.y);
+                wv[2 * q + 1] = make_float2(v.z, v.w);
+            }
+            bf8 ar[NT], ai[NT], an[NT];
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const float2 x = araw[j], y = wv[j];
+                __bf16 tr[NT], ti[NT];
+                split<NT>(x.x * y.x - x.y * y.y, tr);
+                split<NT>(x.x * y.y + x.y * y.x, ti);
+#pragma unroll
+                for (int s2 = 0; s2 < NT; s2++) {
+                    ar[s2][j] = tr[s2];
+                    ai[s2][j] = ti[s2];
+                }
+            }
+#pragma unroll
+            for (int s2 = 0; s2 < NT; s2++) an[s2] = negate(ar[s2]);
+#pragma unroll
+            for (int s2 = 0; s2 < NT; s2++)
+#pragma unroll
+                for (int u = 0; u < NT; u++) {
+                    if (s2 + u >= NT) continue;
+#pragma unroll
+                    for (int cb = 0; cb < 2; cb++) {
+                        accR[iw][cb] = mfma32_bf16(ar[s2], B[cb][u], accR[iw][cb]);
+                        accI[iw][cb] = mfma32_bf16(ai[s2], B[cb][u], accI[iw][cb]);
+                    }
+#pragma unroll
+                    for (int cb = 0; cb < 2; cb++) {
+                        accR[iw][cb] = mfma32_bf16(ai[s2], B[cb][NT + u], accR[iw][cb]);
+                        accI[iw][cb] = mfma32_bf16(an[s2], B[cb][NT + u], accI[iw][cb]);
+                    }
+                }
+        }
+    };
+
+    if (nstep > 0) issue(sA[0], sB[0], sW[0], step0);
+    for (int t = 0; t < nstep; t++) {
+        const int stg = t & 1;
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const bool more = t + 1 < nstep;
+        step(sA[stg ^ 1], sB[stg ^ 1], sW[stg ^ 1], sA[stg], sB[stg], sW[stg], more ? step0 + t + 1 : -1);
+    }
+
+    // result register e of lane (r32, h) holds row 8 (e / 4) + 4 h + e % 4,
+    // column r32 of a 32 x 32 block
+#pragma unroll
+    for (int iw = 0; iw < NW; iw++) {
+        if (f0 + iw >= nfreq) continue;
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int e = 0; e < 16; e++) {
+                const int i = rt0 + 32 * wave + 8 * (e >> 2) + 4 * h + (e & 3);
+                const int j = ct0 + cb * 32 + r32;
+                if (part) {
+                    part[((long)blockIdx.y * nfreq + f0 + iw) * NGP * NGP + (long)i * NGP + j] =
+                        make_float2(accR[iw][cb][e], accI[iw][cb][e]);
+                } else if (i < ng && j < ng) {
+                    const double2 a = make_double2((double)accR[iw][cb][e], (double)accI[iw][cb][e]);
+                    double2 *C = chi + (long)(f0 + iw) * ng * ng + (long)i * ng + j;
+                    *C = accumulate ? cadd(*C, a) : a;
+                }
+            }
+    }
+}
+
 // chi (+)= sum over slices of the partial tiles, in FP64, for the computed
 // tiles; for an off-diagonal tile of a Hermitian chi the conjugate transpose
 // goes to the mirrored tile through LDS.  Block: 32 x 32 elements of one
@@ -410,15 +572,24 @@ size_t split_a_bytes(long npair, int ng) { return (size_t)pad_pairs(npair) * pad
 size_t split_b_bytes(long npair, int ng) { return (size_t)6 * pad_pairs(npair) * pad_ng(ng) * 2; }
 size_t split_w_bytes(long npair, int nfreq) { return (size_t)pad_pairs(npair) * nfreq * sizeof(float2); }
 
+// Whether the wide form can run: real weights' Hermitian half is not
+// supported by it, and its rows come in blocks of 256.
+static bool wide_ok(int ng, bool herm) { return !herm && pad_ng(ng) % 256 == 0; }
+
 // Slices of the pair steps for one contraction: with fill > 0, enough slices
 // that the grid holds about `fill` blocks (one block per CU fits), each slice
 // at least 8 steps; fill = 0 never slices.
-static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fill, int *nslice, int *sps)
+static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fill, bool wide, int *nslice,
+                       int *sps)
 {
     const int t = pad_ng(ng) / kTile;
-    const long tiles = herm ? (long)t * (t + 1) / 2 : (long)t * t;
+    long tiles = herm ? (long)t * (t + 1) / 2 : (long)t * t;
+    int nstep = (int)(pad_pairs(npair) / kStep);
+    if (wide) {
+        tiles = (long)(pad_ng(ng) / 256) * (pad_ng(ng) / 64);
+        nstep = (int)(pad_pairs(npair) / 16);
+    }
     const long blocks = tiles * ((nfreq + nw - 1) / nw);
-    const int nstep = (int)(pad_pairs(npair) / kStep);
     int S = 1;
     if (fill > 0 && blocks < fill / 2 && nstep >= 16) {
         S = (int)std::min<long>((fill + blocks - 1) / blocks, nstep / 8);
@@ -429,10 +600,10 @@ static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fil
     *nslice = std::max(1, (nstep + per - 1) / per);
 }
 
-size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill)
+size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill, int kernel)
 {
     int S, sps;
-    chi_slices(npair, ng, nfreq, herm, nw, fill, &S, &sps);
+    chi_slices(npair, ng, nfreq, herm, nw, fill, kernel == 1 && wide_ok(ng, herm), &S, &sps);
     if (S == 1) return 0;
     return (size_t)S * nfreq * (size_t)pad_ng(ng) * pad_ng(ng) * sizeof(float2);
 }
@@ -459,29 +630,46 @@ void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, 
 
 void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, int accumulate, double2 *chi,
                      const void *split_a, const void *split_b, const void *split_w, bool herm, int nw, int fill,
-                     void *part)
+                     int kernel, void *part)
 {
     const long KP = pad_pairs(npair);
     const int NGP = pad_ng(ng);
     const int npg = (int)(KP / 8);
     const int t = NGP / kTile;
     nw = nw == 1 ? 1 : 2;
+    const bool wide = kernel == 1 && wide_ok(ng, herm);
     int S, sps;
-    chi_slices(npair, ng, nfreq, herm, nw, fill, &S, &sps);
-    const unsigned tiles = herm ? (unsigned)(t * (t + 1) / 2) : (unsigned)(t * t);
-    const dim3 grid(tiles, (unsigned)S, (unsigned)((nfreq + nw - 1) / nw));
+    chi_slices(npair, ng, nfreq, herm, nw, fill, wide, &S, &sps);
     float2 *P = S > 1 ? (float2 *)part : nullptr;
+    const unsigned nfg = (unsigned)((nfreq + nw - 1) / nw);
+    if (wide) {
+        const dim3 grid((unsigned)((NGP / 256) * (NGP / 64)), (unsigned)S, nfg);
+#define RP_CHIW(NT, NW)                                                                                          \
+    hipLaunchKernelGGL((k_chi_bf16_wide<NT, NW>), grid, dim3(512), 0, s, npg, NGP, KP, ng, (const float2 *)split_a, \
+                       (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, sps, P)
+        if (nterm == 2) {
+            if (nw == 1) RP_CHIW(2, 1);
+            else RP_CHIW(2, 2);
+        } else {
+            if (nw == 1) RP_CHIW(3, 1);
+            else RP_CHIW(3, 2);
+        }
+#undef RP_CHIW
+    } else {
+        const unsigned tiles = herm ? (unsigned)(t * (t + 1) / 2) : (unsigned)(t * t);
+        const dim3 grid(tiles, (unsigned)S, nfg);
 #define RP_CHI(NT, NW)                                                                                         \
     hipLaunchKernelGGL((k_chi_bf16<NT, NW>), grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a, \
                        (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P)
-    if (nterm == 2) {
-        if (nw == 1) RP_CHI(2, 1);
-        else RP_CHI(2, 2);
-    } else {
-        if (nw == 1) RP_CHI(3, 1);
-        else RP_CHI(3, 2);
-    }
+        if (nterm == 2) {
+            if (nw == 1) RP_CHI(2, 1);
+            else RP_CHI(2, 2);
+        } else {
+            if (nw == 1) RP_CHI(3, 1);
+            else RP_CHI(3, 2);
+        }
 #undef RP_CHI
+    }
     if (S > 1) {
         const int nc = NGP / 32;
         hipLaunchKernelGGL(k_chi_reduce, dim3((unsigned)(nc * nc), 1, (unsigned)nfreq), dim3(256), 0, s, S, nfreq, ng,

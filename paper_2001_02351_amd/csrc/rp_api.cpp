@@ -112,6 +112,7 @@ Tune tune_for(const rp_ctx *ctx, int ng, const int fft[3])
         if (e.chi_nw) t.chi_nw = e.chi_nw;
         if (e.chi_fill >= 0) t.chi_fill = e.chi_fill;
         t.fft_lines = e.fft_lines;
+        t.chi_kernel = e.chi_kernel;
         break;
     }
     return t;
@@ -403,7 +404,7 @@ static ChiBytes chi_bytes(const ChiJob &c, long npair)
         b.a = split_a_bytes(npair, c.ng);
         b.b = split_b_bytes(npair, c.ng);
         b.sw = split_w_bytes(npair, c.nfreq);
-        b.part = chi_part_bytes(npair, c.ng, c.nfreq, c.herm, c.tune.chi_nw, c.tune.chi_fill);
+        b.part = chi_part_bytes(npair, c.ng, c.nfreq, c.herm, c.tune.chi_nw, c.tune.chi_fill, c.tune.chi_kernel);
     }
     return b;
 }
@@ -441,7 +442,7 @@ static rp_status chi_enqueue(rp_ctx *ctx, const ChiJob &c, int k0, int k1, const
         }
         StageTimer t(ctx, RP_STAGE_CHI);
         launch_chi_bf16(ctx->stream, nterm, npair, c.ng, c.nfreq, accumulate, chi, bufs.a, bufs.b, bufs.sw, c.herm,
-                        c.tune.chi_nw, c.tune.chi_fill, bufs.part);
+                        c.tune.chi_nw, c.tune.chi_fill, c.tune.chi_kernel, bufs.part);
     }
     return check_launch(ctx, "chi0 contraction");
 }
@@ -648,6 +649,7 @@ rp_status rp_set_tuning(rp_ctx *ctx, int n, const rp_tune_entry *table)
         if (e.chi_fill < -1 || e.chi_fill > (1 << 20))
             return fail(ctx, RP_E_RANGE, "entry %d: chi_fill outside [-1, 2^20]", i);
         if (e.fft_lines < 0 || e.fft_lines > 64) return fail(ctx, RP_E_RANGE, "entry %d: fft_lines outside [0, 64]", i);
+        if (e.chi_kernel < 0 || e.chi_kernel > 1) return fail(ctx, RP_E_RANGE, "entry %d: chi_kernel must be 0 or 1", i);
     }
     ctx->tuning.assign(table, table + n);
     return RP_OK;
@@ -734,7 +736,7 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
         const void *ptrs[] = {p.miller, p.coef, p.energy_eV, p.T, p.chi};
         key_put(key, ptrs, sizeof ptrs);
         key_val(key, p.delta_eV);
-        const int tn[] = {cj[i].tune.chi_nw, cj[i].tune.chi_fill, pj[i].fft_lines};
+        const int tn[] = {cj[i].tune.chi_nw, cj[i].tune.chi_fill, cj[i].tune.chi_kernel, pj[i].fft_lines};
         key_put(key, tn, sizeof tn);
     }
     key_put(key, stage.data(), stage.size());

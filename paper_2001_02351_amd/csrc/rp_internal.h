@@ -98,6 +98,7 @@ struct Tune {
     int chi_nw = 2;
     int chi_fill = 1024;
     int fft_lines = 0;
+    int chi_kernel = 0;
 };
 Tune tune_for(const rp_ctx *ctx, int ng, const int fft[3]);
 
@@ -151,12 +152,12 @@ void launch_chi_f64(hipStream_t s, long npair, int ng, const double2 *M, int nfr
 size_t split_a_bytes(long npair, int ng);
 size_t split_b_bytes(long npair, int ng);
 size_t split_w_bytes(long npair, int nfreq);
-size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill);
+size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill, int kernel);
 void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, const double2 *M,
                        const double2 *w, bool herm, void *split_a, void *split_b, void *split_w);
 void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, int accumulate,
                      double2 *chi, const void *split_a, const void *split_b, const void *split_w,
-                     bool herm, int nw, int fill, void *part);
+                     bool herm, int nw, int fill, int kernel, void *part);
 
 // screen.hip
 void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, double *vs, int *flag);

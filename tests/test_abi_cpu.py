@@ -74,7 +74,7 @@ def test_tuning_table_loading(tmp_path):
 
     import paper_2001_02351_amd as rp
     from paper_2001_02351_amd import _rp
-    good = {"entries": [dict(ng_max=512, grid_max=27, chi_nw=1, chi_fill=0, fft_lines=8)]}
+    good = {"entries": [dict(ng_max=512, grid_max=27, chi_nw=1, chi_fill=0, fft_lines=8, chi_kernel=1)]}
     f = tmp_path / "t.json"
     f.write_text(json.dumps(good))
     assert _rp.load_tuning(str(f)) == good["entries"]
@@ -84,6 +84,7 @@ def test_tuning_table_loading(tmp_path):
     if os.path.exists(_rp.DEFAULT_TUNING):      # the committed table is well formed
         for e in _rp.load_tuning(_rp.DEFAULT_TUNING):
             assert e["chi_nw"] in (0, 1, 2) and -1 <= e["chi_fill"] and 0 <= e["fft_lines"] <= 64
+            assert e["chi_kernel"] in (0, 1)
     assert rp.rp_tune_entry is _rp.rp_tune_entry
 
 

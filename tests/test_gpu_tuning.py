@@ -44,13 +44,14 @@ def ctx(rp):
 
 
 def _entry(**kw):
-    e = dict(ng_max=BIG, grid_max=BIG, chi_nw=0, chi_fill=-1, fft_lines=0)
+    e = dict(ng_max=BIG, grid_max=BIG, chi_nw=0, chi_fill=-1, fft_lines=0, chi_kernel=0)
     e.update(kw)
     return e
 
 
 def test_set_tuning_rejects_bad_entries(ctx, rp):
-    for bad in (_entry(chi_nw=3), _entry(chi_fill=-2), _entry(fft_lines=65), _entry(ng_max=0)):
+    for bad in (_entry(chi_nw=3), _entry(chi_fill=-2), _entry(fft_lines=65), _entry(ng_max=0),
+                _entry(chi_kernel=2)):
         with pytest.raises(rp.RpError) as e:
             rp.rp_set_tuning(ctx, [bad])
         assert e.value.status == 3
@@ -95,5 +96,35 @@ def test_autotuner_runs(ctx, rp):
     table = autotune.autotune(ctx, ng_buckets=(512,), grid_buckets=(27,), repeats=1)
     (e,) = table["entries"]
     assert (e["ng_max"], e["grid_max"]) == (512, 27)
-    assert (e["chi_nw"], e["chi_fill"]) in autotune.CHI_CANDIDATES
+    assert (e["chi_kernel"], e["chi_nw"], e["chi_fill"]) in autotune.CHI_CANDIDATES
     assert e["fft_lines"] in autotune.FFT_CANDIDATES
+
+
+def test_wide_contraction_form_matches(ctx, rp):
+    """The 256 x 64 eight-wave contraction form (chi_kernel = 1) on complex
+    weights (real frequencies, delta > 0) with N_G = 200 (padded to 256):
+    against the default form to 1e-6 and the oracle to 1e-5, with one or two
+    frequencies per workgroup and with the pair steps sliced."""
+    from paper_2001_02351_amd import path
+    from synth import make_problem
+    p = make_problem(name="wide", a_bohr=7.26, fft=(16, 16, 16), kmesh=(2, 2, 2), iq=(1, 0, 0), nocc=8,
+                     nemp=24, gpsi=2.4, ng=200, freq_eV=np.linspace(0.0, 20.0, 5), delta_eV=0.1, seed=23)
+    d = path.DeviceInputs(p)
+    M = oracle.pair_densities(p, 0, p.nocc, p.nocc, p.nband, 0, d.nk)
+    w = oracle.prob_weights(p, 0, p.nocc, p.nocc, p.nband, 0, d.nk)
+    want = oracle.chi0(M, w)
+
+    def chi_for(entries):
+        rp.rp_set_tuning(ctx, entries)
+        return path.to_complex(path.chi0(ctx, d, prec=rp.RP_SPLIT_BF16, kbatch=d.nk))
+
+    ref = chi_for([])
+    assert max(_rel(ref[f], want[f]) for f in range(d.nfreq)) < 1e-5
+    for nw in (1, 2):
+        for fill in (0, 4096):
+            got = chi_for([_entry(chi_nw=nw, chi_fill=fill, chi_kernel=1)])
+            d_ref = max(_rel(got[f], ref[f]) for f in range(d.nfreq))
+            d_orc = max(_rel(got[f], want[f]) for f in range(d.nfreq))
+            print(f"[tuning] wide nw={nw} fill={fill}: vs default {d_ref:.1e}, vs oracle {d_orc:.1e}", flush=True)
+            assert d_ref < 1e-6 and d_orc < 1e-5
+    rp.rp_set_tuning(ctx, [])
