@@ -278,8 +278,10 @@ rp_status rp_wannier_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nw
  *              16 or 8 by length)
  *   chi_kernel split-BF16 contraction form: 0 = 128 x 128 tiles on four
  *              waves, 1 = 256 x 64 tiles on eight waves (two per SIMD, 32x32
- *              matrix-core ops; used where N_G pads to a multiple of 256 and
- *              the weights are complex, else form 0)
+ *              matrix-core ops), 2 = 256 x 128 tiles on eight waves, one
+ *              frequency per workgroup (RP_SPLIT_BF16 only, else form 1).
+ *              Forms 1 and 2 run where N_G pads to a multiple of 256 and the
+ *              weights are complex; elsewhere form 0 runs.
  * Only launch shapes change: every choice computes the same sums (the
  * contraction's FP32 partial sums are grouped differently when sliced).
  * Errors: RP_E_NULL, RP_E_RANGE.

@@ -30,8 +30,8 @@ from . import _rp
 
 NG_BUCKETS = (512, 768, 1024, 1200)
 GRID_BUCKETS = (27, 32, 40)
-CHI_CANDIDATES = tuple((kern, nw, fill) for kern in (0, 1) for nw in (1, 2)
-                       for fill in (0, 256, 512, 1024, 2048, 4096, 8192))
+CHI_CANDIDATES = tuple((kern, nw, fill) for kern in (0, 1, 2) for nw in (1, 2)
+                       for fill in (0, 256, 512, 1024, 2048, 4096, 8192) if not (kern == 2 and nw == 2))
 FFT_CANDIDATES = (0, 4, 8, 16, 32)
 
 

@@ -354,47 +354,55 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     }
 }
 
-// Wide form: a 512-thread block owns a 256 x 64 tile of (G, G') for NW
-// frequencies; each of its 8 waves (two per SIMD) owns 32 whole rows of the
-// tile as two 32 x 32 blocks on v_mfma_f32_32x32x16_bf16, so every row of A is
+// Wide form: a 512-thread block owns a 256 x 32 CB tile of (G, G') for NW
+// frequencies (CB = 2: 256 x 64, NW = 1 or 2; CB = 4: 256 x 128, NW = 1); each
+// of its 8 waves (two per SIMD) owns 32 whole rows of the tile as CB 32 x 32
+// blocks on v_mfma_f32_32x32x16_bf16, so every row of A is
 // weighted and split by one wave only.  Steps of 16 pairs (one pair group of
 // 8 per wave half) stream through two LDS stages (32 KB of A, 2 NT KB of B and
 // the step's weights each) by global_load_lds DMA.  The operand layouts are
 // those of the prep pass above (a block of 16 rows x 8 pairs in quarter
 // order for A; per plane 8 consecutive pairs of one column for B).  The
 // contraction of one (a, b) pair is the same sum of split products as in
-// k_chi_bf16; only the tiling differs.  Not for a Hermitian chi.
+// k_chi_bf16; only the tiling differs.  Not for a Hermitian chi.  Three LDS
+// stages (120 KB) let a step's DMA run two steps ahead of its use.
 __device__ __forceinline__ f16v mfma32_bf16(bf8 a, bf8 b, f16v c)
 {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-template <int NT, int NW>
+template <int NT, int NW, int CB>
 __global__ void __launch_bounds__(512)
 k_chi_bf16_wide(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, const bf8 *__restrict__ Bp,
                 int nfreq, const float2 *__restrict__ wq, int accumulate, double2 *__restrict__ chi, int sps,
                 float2 *__restrict__ part)
 {
     constexpr int NPL = 2 * NT;
+    constexpr int TN = 32 * CB;               // tile columns
+    constexpr int NBH = NPL * 2 * (TN / 32) / 8;   // B half-segments (512 B) per wave per step
+    constexpr int NOPS = 4 + NBH + 1;         // DMA operations per wave per step
     // per stage: A [2 pair groups][16 row blocks][128] float2 (32 KB),
     //            B [NPL planes][2 pair groups][64 cols] bf8, W [NW][16 pairs] float2
-    __shared__ float2 sA[2][2 * 16 * 128];
-    __shared__ bf8 sB[2][NPL * 2 * 64];
-    __shared__ float2 sW[2][NW * 16];
+    // three stages as distinct objects, so the compiler sees that a stage's
+    // reads never touch the two stages whose DMA is in flight
+    __shared__ float2 sA0[2 * 16 * 128], sA1[2 * 16 * 128], sA2[2 * 16 * 128];
+    __shared__ bf8 sB0[NPL * 2 * TN], sB1[NPL * 2 * TN], sB2[NPL * 2 * TN];
+    __shared__ float2 sW0[2 * 16], sW1[2 * 16], sW2[2 * 16];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int r32 = lane & 31, h = lane >> 5;
-    const int TC = NGP / 64;
-    const int rt0 = (blockIdx.x / TC) * 256, ct0 = (blockIdx.x % TC) * 64;
+    const int TC = NGP / TN;
+    const int rt0 = (blockIdx.x / TC) * 256, ct0 = (blockIdx.x % TC) * TN;
     const int f0 = blockIdx.z * NW;
     const long plane = (long)npg * NGP;
     const int step0 = blockIdx.y * sps;
     const int nstep = min(sps, npg / 2 - step0);
 
-    // DMA of step t (pair groups 2t, 2t+1): wave w moves the A blocks of
-    // pair group w/4, row blocks 4(w%4)..4(w%4)+3, then its share of the
-    // 2 NPL B segments; wave 0's first 8 NW lanes move the weights
+    // DMA of step t (pair groups 2t, 2t+1), the same number of operations in
+    // every wave: wave w moves the A blocks of pair group w/4, row blocks
+    // 4(w%4)..4(w%4)+3, NBH of the 4 NPL half-segments of B (32 lanes each),
+    // and two of the 16 weight chunks of 16 B (2 lanes; two frequencies)
     auto issue = [&](float2 *dA, bf8 *dB, float2 *dW, int t) {
         const int pgw = 2 * t + (wave >> 2);
         const float2 *a = Ap + ((long)pgw * (NGP / 16) + rt0 / 16 + (wave & 3) * 4) * 128 + lane * 2;
@@ -402,21 +410,25 @@ k_chi_bf16_wide(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap
 #pragma unroll
         for (int i = 0; i < 4; i++) dma16(a + i * 128, da + i * 128);
 #pragma unroll
-        for (int sid = wave; sid < 2 * NPL; sid += 8) {
+        for (int i = 0; i < NBH; i++) {
+            const int hs = wave * NBH + i;            // half-segment: plane, pair group, 32 columns
+            const int sid = hs / (TN / 32), c32 = hs % (TN / 32);
             const int sp = sid >> 1, g = sid & 1;
-            dma16(Bp + sp * plane + (long)(2 * t + g) * NGP + ct0 + lane, dB + sid * 64);
+            if (lane < 32)
+                dma16(Bp + sp * plane + (long)(2 * t + g) * NGP + ct0 + c32 * 32 + lane, dB + sid * TN + c32 * 32);
         }
-        if (wave == 0 && lane < 8 * NW) {
-            const int f = min(f0 + lane / 8, nfreq - 1);
-            dma16(wq + (long)f * KP + (long)t * 16 + (lane & 7) * 2, dW);
+        if (lane < 2) {
+            const int c = wave * 2 + lane;           // chunk: frequency c / 8, pairs 2 (c % 8)
+            const int f = min(f0 + min(c / 8, NW - 1), nfreq - 1);
+            dma16(wq + (long)f * KP + (long)t * 16 + (c & 7) * 2, dW + wave * 4);
         }
     };
 
-    f16v accR[NW][2], accI[NW][2];
+    f16v accR[NW][CB], accI[NW][CB];
 #pragma unroll
     for (int iw = 0; iw < NW; iw++)
 #pragma unroll
-        for (int cb = 0; cb < 2; cb++)
+        for (int cb = 0; cb < CB; cb++)
 #pragma unroll
             for (int e = 0; e < 16; e++) {
                 accR[iw][cb][e] = 0.f;
@@ -427,11 +439,6 @@ k_chi_bf16_wide(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap
                     const float2 *__restrict__ cA, const bf8 *__restrict__ cB, const float2 *__restrict__ cW,
                     int tn) {
         if (tn >= 0) issue(nA, nB, nW, tn);
-        bf8 B[2][NPL];
-#pragma unroll
-        for (int cb = 0; cb < 2; cb++)
-#pragma unroll
-            for (int sp = 0; sp < NPL; sp++) B[cb][sp] = cB[(sp * 2 + h) * 64 + cb * 32 + r32];
         const float2 *blk = cA + (h * 16 + 2 * wave + (r32 >> 4)) * 128 + (r32 & 15) * 2;
         float2 araw[8];
 #pragma unroll
@@ -464,32 +471,42 @@ k_chi_bf16_wide(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap
             }
 #pragma unroll
             for (int s2 = 0; s2 < NT; s2++) an[s2] = negate(ar[s2]);
+            // column blocks one at a time (their B planes loaded just before use)
 #pragma unroll
-            for (int s2 = 0; s2 < NT; s2++)
+            for (int cb = 0; cb < CB; cb++) {
+                bf8 B[NPL];
 #pragma unroll
-                for (int u = 0; u < NT; u++) {
-                    if (s2 + u >= NT) continue;
+                for (int sp = 0; sp < NPL; sp++) B[sp] = cB[(sp * 2 + h) * TN + cb * 32 + r32];
+                f16v cr = accR[iw][cb], ci = accI[iw][cb];
 #pragma unroll
-                    for (int cb = 0; cb < 2; cb++) {
-                        accR[iw][cb] = mfma32_bf16(ar[s2], B[cb][u], accR[iw][cb]);
-                        accI[iw][cb] = mfma32_bf16(ai[s2], B[cb][u], accI[iw][cb]);
+                for (int s2 = 0; s2 < NT; s2++)
+#pragma unroll
+                    for (int u = 0; u < NT; u++) {
+                        if (s2 + u >= NT) continue;
+                        cr = mfma32_bf16(ar[s2], B[u], cr);
+                        ci = mfma32_bf16(ai[s2], B[u], ci);
+                        cr = mfma32_bf16(ai[s2], B[NT + u], cr);
+                        ci = mfma32_bf16(an[s2], B[NT + u], ci);
                     }
-#pragma unroll
-                    for (int cb = 0; cb < 2; cb++) {
-                        accR[iw][cb] = mfma32_bf16(ai[s2], B[cb][NT + u], accR[iw][cb]);
-                        accI[iw][cb] = mfma32_bf16(an[s2], B[cb][NT + u], accI[iw][cb]);
-                    }
-                }
+                accR[iw][cb] = cr;
+                accI[iw][cb] = ci;
+            }
         }
     };
 
-    if (nstep > 0) issue(sA[0], sB[0], sW[0], step0);
-    for (int t = 0; t < nstep; t++) {
-        const int stg = t & 1;
-        __builtin_amdgcn_s_waitcnt(0);
+    auto body = [&](int t, float2 *__restrict__ nA, bf8 *__restrict__ nB, float2 *__restrict__ nW,
+                    const float2 *__restrict__ cA, const bf8 *__restrict__ cB, const float2 *__restrict__ cW) {
+        if (t + 1 < nstep) __builtin_amdgcn_s_waitcnt(0x0f70 | (NOPS & 0xf) | ((NOPS >> 4) << 14));
+        else __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        const bool more = t + 1 < nstep;
-        step(sA[stg ^ 1], sB[stg ^ 1], sW[stg ^ 1], sA[stg], sB[stg], sW[stg], more ? step0 + t + 1 : -1);
+        step(nA, nB, nW, cA, cB, cW, t + 2 < nstep ? step0 + t + 2 : -1);
+    };
+    if (nstep > 0) issue(sA0, sB0, sW0, step0);
+    if (nstep > 1) issue(sA1, sB1, sW1, step0 + 1);
+    for (int t = 0; t < nstep; t += 3) {
+        body(t, sA2, sB2, sW2, sA0, sB0, sW0);
+        if (t + 1 < nstep) body(t + 1, sA0, sB0, sW0, sA1, sB1, sW1);
+        if (t + 2 < nstep) body(t + 2, sA1, sB1, sW1, sA2, sB2, sW2);
     }
 
     // result register e of lane (r32, h) holds row 8 (e / 4) + 4 h + e % 4,
@@ -498,7 +515,7 @@ k_chi_bf16_wide(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap
     for (int iw = 0; iw < NW; iw++) {
         if (f0 + iw >= nfreq) continue;
 #pragma unroll
-        for (int cb = 0; cb < 2; cb++)
+        for (int cb = 0; cb < CB; cb++)
 #pragma unroll
             for (int e = 0; e < 16; e++) {
                 const int i = rt0 + 32 * wave + 8 * (e >> 2) + 4 * h + (e & 3);
@@ -572,21 +589,29 @@ size_t split_a_bytes(long npair, int ng) { return (size_t)pad_pairs(npair) * pad
 size_t split_b_bytes(long npair, int ng) { return (size_t)6 * pad_pairs(npair) * pad_ng(ng) * 2; }
 size_t split_w_bytes(long npair, int nfreq) { return (size_t)pad_pairs(npair) * nfreq * sizeof(float2); }
 
-// Whether the wide form can run: real weights' Hermitian half is not
-// supported by it, and its rows come in blocks of 256.
-static bool wide_ok(int ng, bool herm) { return !herm && pad_ng(ng) % 256 == 0; }
+// The contraction form that runs for a requested one: the wide forms take
+// complex weights only (no Hermitian half) and rows in blocks of 256, and the
+// 256 x 128 form needs the two-term split (three stages of the six-plane B
+// operand would not fit in LDS); otherwise the 128 x 128 form.
+static int eff_kernel(int kernel, int ng, bool herm, int nterm)
+{
+    if (kernel == 0 || herm || pad_ng(ng) % 256 != 0) return 0;
+    return (kernel == 2 && nterm == 2) ? 2 : 1;
+}
 
 // Slices of the pair steps for one contraction: with fill > 0, enough slices
 // that the grid holds about `fill` blocks (one block per CU fits), each slice
 // at least 8 steps; fill = 0 never slices.
-static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fill, bool wide, int *nslice,
+static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fill, int wide, int *nslice,
                        int *sps)
 {
     const int t = pad_ng(ng) / kTile;
     long tiles = herm ? (long)t * (t + 1) / 2 : (long)t * t;
     int nstep = (int)(pad_pairs(npair) / kStep);
     if (wide) {
-        tiles = (long)(pad_ng(ng) / 256) * (pad_ng(ng) / 64);
+        const int tn = wide == 2 ? 128 : 64;
+        if (wide == 2) nw = 1;
+        tiles = (long)(pad_ng(ng) / 256) * (pad_ng(ng) / tn);
         nstep = (int)(pad_pairs(npair) / 16);
     }
     const long blocks = tiles * ((nfreq + nw - 1) / nw);
@@ -600,10 +625,10 @@ static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fil
     *nslice = std::max(1, (nstep + per - 1) / per);
 }
 
-size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill, int kernel)
+size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill, int kernel, int nterm)
 {
     int S, sps;
-    chi_slices(npair, ng, nfreq, herm, nw, fill, kernel == 1 && wide_ok(ng, herm), &S, &sps);
+    chi_slices(npair, ng, nfreq, herm, nw == 1 ? 1 : 2, fill, eff_kernel(kernel, ng, herm, nterm), &S, &sps);
     if (S == 1) return 0;
     return (size_t)S * nfreq * (size_t)pad_ng(ng) * pad_ng(ng) * sizeof(float2);
 }
@@ -637,22 +662,28 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
     const int npg = (int)(KP / 8);
     const int t = NGP / kTile;
     nw = nw == 1 ? 1 : 2;
-    const bool wide = kernel == 1 && wide_ok(ng, herm);
+    const int wide = eff_kernel(kernel, ng, herm, nterm);
     int S, sps;
     chi_slices(npair, ng, nfreq, herm, nw, fill, wide, &S, &sps);
     float2 *P = S > 1 ? (float2 *)part : nullptr;
     const unsigned nfg = (unsigned)((nfreq + nw - 1) / nw);
     if (wide) {
-        const dim3 grid((unsigned)((NGP / 256) * (NGP / 64)), (unsigned)S, nfg);
-#define RP_CHIW(NT, NW)                                                                                          \
-    hipLaunchKernelGGL((k_chi_bf16_wide<NT, NW>), grid, dim3(512), 0, s, npg, NGP, KP, ng, (const float2 *)split_a, \
-                       (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, sps, P)
-        if (nterm == 2) {
-            if (nw == 1) RP_CHIW(2, 1);
-            else RP_CHIW(2, 2);
+        const int CBW = wide == 2 ? 4 : 2;
+        if (CBW == 4) nw = 1;
+        const dim3 grid((unsigned)((NGP / 256) * (NGP / (32 * CBW))), (unsigned)S,
+                        (unsigned)((nfreq + nw - 1) / nw));
+#define RP_CHIW(NT, NW, CB)                                                                                      \
+    hipLaunchKernelGGL((k_chi_bf16_wide<NT, NW, CB>), grid, dim3(512), 0, s, npg, NGP, KP, ng,                   \
+                       (const float2 *)split_a, (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, \
+                       chi, sps, P)
+        if (CBW == 4) {
+            RP_CHIW(2, 1, 4);
+        } else if (nterm == 2) {
+            if (nw == 1) RP_CHIW(2, 1, 2);
+            else RP_CHIW(2, 2, 2);
         } else {
-            if (nw == 1) RP_CHIW(3, 1);
-            else RP_CHIW(3, 2);
+            if (nw == 1) RP_CHIW(3, 1, 2);
+            else RP_CHIW(3, 2, 2);
         }
 #undef RP_CHIW
     } else {

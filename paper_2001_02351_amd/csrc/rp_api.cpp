@@ -404,7 +404,8 @@ static ChiBytes chi_bytes(const ChiJob &c, long npair)
         b.a = split_a_bytes(npair, c.ng);
         b.b = split_b_bytes(npair, c.ng);
         b.sw = split_w_bytes(npair, c.nfreq);
-        b.part = chi_part_bytes(npair, c.ng, c.nfreq, c.herm, c.tune.chi_nw, c.tune.chi_fill, c.tune.chi_kernel);
+        b.part = chi_part_bytes(npair, c.ng, c.nfreq, c.herm, c.tune.chi_nw, c.tune.chi_fill, c.tune.chi_kernel,
+                                c.prec == RP_SPLIT_BF16 ? 2 : 3);
     }
     return b;
 }
@@ -649,7 +650,7 @@ rp_status rp_set_tuning(rp_ctx *ctx, int n, const rp_tune_entry *table)
         if (e.chi_fill < -1 || e.chi_fill > (1 << 20))
             return fail(ctx, RP_E_RANGE, "entry %d: chi_fill outside [-1, 2^20]", i);
         if (e.fft_lines < 0 || e.fft_lines > 64) return fail(ctx, RP_E_RANGE, "entry %d: fft_lines outside [0, 64]", i);
-        if (e.chi_kernel < 0 || e.chi_kernel > 1) return fail(ctx, RP_E_RANGE, "entry %d: chi_kernel must be 0 or 1", i);
+        if (e.chi_kernel < 0 || e.chi_kernel > 2) return fail(ctx, RP_E_RANGE, "entry %d: chi_kernel must be 0, 1 or 2", i);
     }
     ctx->tuning.assign(table, table + n);
     return RP_OK;

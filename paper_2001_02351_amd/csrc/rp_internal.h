@@ -152,7 +152,7 @@ void launch_chi_f64(hipStream_t s, long npair, int ng, const double2 *M, int nfr
 size_t split_a_bytes(long npair, int ng);
 size_t split_b_bytes(long npair, int ng);
 size_t split_w_bytes(long npair, int nfreq);
-size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill, int kernel);
+size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill, int kernel, int nterm);
 void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, const double2 *M,
                        const double2 *w, bool herm, void *split_a, void *split_b, void *split_w);
 void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, int accumulate,

@@ -51,7 +51,7 @@ def _entry(**kw):
 
 def test_set_tuning_rejects_bad_entries(ctx, rp):
     for bad in (_entry(chi_nw=3), _entry(chi_fill=-2), _entry(fft_lines=65), _entry(ng_max=0),
-                _entry(chi_kernel=2)):
+                _entry(chi_kernel=3)):
         with pytest.raises(rp.RpError) as e:
             rp.rp_set_tuning(ctx, [bad])
         assert e.value.status == 3
@@ -101,8 +101,9 @@ def test_autotuner_runs(ctx, rp):
 
 
 def test_wide_contraction_form_matches(ctx, rp):
-    """The 256 x 64 eight-wave contraction form (chi_kernel = 1) on complex
-    weights (real frequencies, delta > 0) with N_G = 200 (padded to 256):
+    """The eight-wave contraction forms (chi_kernel = 1: 256 x 64 tiles,
+    2: 256 x 128 tiles) on complex weights (real frequencies, delta > 0) with
+    N_G = 200 (padded to 256):
     against the default form to 1e-6 and the oracle to 1e-5, with one or two
     frequencies per workgroup and with the pair steps sliced."""
     from paper_2001_02351_amd import path
@@ -120,11 +121,12 @@ def test_wide_contraction_form_matches(ctx, rp):
 
     ref = chi_for([])
     assert max(_rel(ref[f], want[f]) for f in range(d.nfreq)) < 1e-5
-    for nw in (1, 2):
+    for kern, nw in ((1, 1), (1, 2), (2, 1)):
         for fill in (0, 4096):
-            got = chi_for([_entry(chi_nw=nw, chi_fill=fill, chi_kernel=1)])
+            got = chi_for([_entry(chi_nw=nw, chi_fill=fill, chi_kernel=kern)])
             d_ref = max(_rel(got[f], ref[f]) for f in range(d.nfreq))
             d_orc = max(_rel(got[f], want[f]) for f in range(d.nfreq))
-            print(f"[tuning] wide nw={nw} fill={fill}: vs default {d_ref:.1e}, vs oracle {d_orc:.1e}", flush=True)
+            print(f"[tuning] wide form {kern} nw={nw} fill={fill}: vs default {d_ref:.1e}, "
+                  f"vs oracle {d_orc:.1e}", flush=True)
             assert d_ref < 1e-6 and d_orc < 1e-5
     rp.rp_set_tuning(ctx, [])
