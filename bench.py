@@ -31,6 +31,9 @@ Counter runs use two extra modes: --copy-calibration (a plain 1 GiB device
 copy, three times) and --profile-k N (the split chi0 build over the first N
 k-points in the launch configuration of the timed legs).
 
+--tune OUT writes the launch-shape table tuned on both workloads (the
+package's tuning_mi355x.json comes from it).
+
 --batch measures the batched uneven workload instead (24 systems x 4
 q-points, 16 imaginary frequencies, split-BF16 chi0) through rp_chi0_batch,
 one graph launch per step, beside the same problems through per-problem
@@ -371,6 +374,40 @@ def batch_leg(args):
     print(json.dumps(out), flush=True)
 
 
+def tune_leg(args):
+    """Launch shapes tuned on the 48^3 workload's first k batch and on one
+    q-point of every batched system, merged into one table (--tune OUT)."""
+
+    import torch
+
+    import paper_2001_02351_amd as rp
+    from paper_2001_02351_amd import autotune, path
+    from synth import batch_system_qpoints, srvo3_workload
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    rp.load()
+    ctx = rp.Context(0, tuning=None)
+    log("tuning on the 48^3 workload (first k batch)")
+    d = path.DeviceInputs(srvo3_workload())
+    t48 = autotune.autotune(ctx, samples=[(d, args.kbatch)], ng_buckets=(1536,), grid_buckets=(48,), log=log)
+    del d
+    torch.cuda.empty_cache()
+    log(f"tuning on the batched workload ({args.batch_systems} systems, one q-point each)")
+    samples = []
+    for s in range(args.batch_systems):
+        p = batch_system_qpoints(s)[0]
+        dd = path.DeviceInputs(p)
+        npk = p.nocc * p.nemp
+        samples.append((dd, max(1, min(dd.nk, args.batch_pairs // npk))))
+    tb = autotune.autotune(ctx, samples=samples, log=log)
+    ctx.close()
+    table = autotune.merge(tb, t48)
+    with open(args.tune, "w") as f:
+        json.dump(table, f, indent=1)
+    print(json.dumps({"tuning_table": args.tune, "entries": table["entries"]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,6 +428,8 @@ def main():
                     help="workload (autotune on the batch first), none, or a table file")
     ap.add_argument("--tuning-out", default=None)
     ap.add_argument("--batch-no-graph", action="store_true")
+    ap.add_argument("--tune", default=None, metavar="OUT",
+                    help="autotune the launch shapes on both workloads and write the table")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -399,6 +438,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.tune:
+        tune_leg(args)
         return
     if args.batch:
         batch_leg(args)

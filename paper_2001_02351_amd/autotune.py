@@ -3,7 +3,8 @@
 Size classes are N_G buckets x FFT-edge buckets.  For each class the tuner
 times the candidate launch shapes on synthetic inputs of the class's upper
 sizes (random coefficients and energies: only the shapes matter for timing)
-and keeps the fastest:
+and keeps the fastest (the library's default shape unless a candidate beats
+it by more than 1%):
 
 * the split-BF16 contraction (chi_kernel form, chi_nw frequencies per
   workgroup, chi_fill workgroups aimed for by slicing the pair steps): timed
@@ -27,6 +28,12 @@ from typing import Optional
 import numpy as np
 
 from . import _rp
+
+# a candidate replaces the library's default shape only when it is faster by
+# more than this fraction (timings of equal shapes differ by about that much)
+MARGIN = 0.01
+CHI_DEFAULT = (0, 2, 1024)
+FFT_DEFAULT = 0
 
 NG_BUCKETS = (512, 768, 1024, 1200)
 GRID_BUCKETS = (27, 32, 40)
@@ -131,6 +138,9 @@ class _Sample:
         self.d, self.kbatch = d, kbatch
         self.ng, self.nk, self.nfreq = d.ng, d.nk, d.nfreq
         self.npk, self.edge = p.nocc * p.nemp, max(p.fft)
+        # real weights (imaginary frequencies, no broadening): the library
+        # forms the Hermitian half with the 128 x 128 form whatever is asked
+        self.real_w = p.delta_eV == 0.0 and bool(np.all(np.real(p.freq_eV) == 0.0))
 
     def pair(self, ctx, k0, k1, M, prec):
         d, p = self.d, self.d.prob
@@ -151,6 +161,7 @@ class _Synthetic:
         self.dev = _Device(p)
         self.ng, self.nk, self.nfreq = p.ng, p.nk, len(p.freq)
         self.npk, self.edge, self.kbatch = p.nocc * p.nemp, max(p.fft), p.nk
+        self.real_w = True
 
     def pair(self, ctx, k0, k1, M, prec):
         self.dev.pair(ctx, k0, k1, M, prec)
@@ -188,6 +199,9 @@ def autotune(ctx, samples=None, ng_buckets=NG_BUCKETS, grid_buckets=GRID_BUCKETS
         _rp.rp_set_tuning(ctx, [])
         smp.pair(ctx, 0, k1, M, prec)
         for c in CHI_CANDIDATES:
+            if smp.real_w and c[0] != 0:
+                chi_tot[b][c] = float("inf")    # the same launches as form 0
+                continue
             _rp.rp_set_tuning(ctx, [dict(ng_max=big, grid_max=big, chi_nw=c[1], chi_fill=c[2], fft_lines=0,
                                          chi_kernel=c[0])])
             chi_tot[b][c] += _timed(ctx, lambda: smp.chi(ctx, k1, M, chi, prec), repeats)
@@ -195,9 +209,11 @@ def autotune(ctx, samples=None, ng_buckets=NG_BUCKETS, grid_buckets=GRID_BUCKETS
     chi_pick = {}
     for b in ng_buckets:
         res = chi_tot[b]
-        if not any(res.values()):
+        if not any(v for v in res.values() if v != float("inf")):
             continue
         best = min(res, key=res.get)
+        if res[CHI_DEFAULT] <= res[best] * (1.0 + MARGIN):
+            best = CHI_DEFAULT
         chi_pick[b] = best
         log(f"[autotune] N_G <= {b}: " + ", ".join(f"kernel={k} nw={nw} fill={fill}: {v:.3f} ms"
                                                    for (k, nw, fill), v in res.items()) +
@@ -226,6 +242,8 @@ def autotune(ctx, samples=None, ng_buckets=NG_BUCKETS, grid_buckets=GRID_BUCKETS
         if not any(res.values()):
             continue
         best = min(res, key=res.get)
+        if res[FFT_DEFAULT] <= res[best] * (1.0 + MARGIN):
+            best = FFT_DEFAULT
         fft_pick[b] = best
         log(f"[autotune] edge <= {b}: " + ", ".join(f"lines={k}: {v:.3f} ms" for k, v in res.items()) +
             f" -> lines={best}")
@@ -240,11 +258,35 @@ def autotune(ctx, samples=None, ng_buckets=NG_BUCKETS, grid_buckets=GRID_BUCKETS
             "tuned_on": "workload samples" if samples else "synthetic class problems",
             "samples": len(samples) if samples else 0,
             "measured_ms": {"chi": {str(b): {f"kernel{c[0]}_nw{c[1]}_fill{c[2]}": round(v, 4)
-                                             for c, v in r.items()}
+                                             for c, v in r.items() if v != float("inf")}
                                     for b, r in chi_tot.items()},
                             "ugrid": {str(b): {f"lines{c}": round(v, 4) for c, v in r.items()}
                                       for b, r in fft_tot.items()}},
             "created": time.strftime("%Y-%m-%d %H:%M:%S")}
+
+
+def merge(*tables) -> dict:
+    """One table from several: the classes of every table that measured
+    them, ordered by N_G bound then edge bound (a class measured by an
+    earlier table is kept)."""
+    seen, entries = set(), []
+    for t in tables:
+        measured = {int(b) for b, r in t["measured_ms"]["chi"].items() if r} | \
+                   {int(b) for b, r in t["measured_ms"]["ugrid"].items() if any(r.values())}
+        for e in t["entries"]:
+            key = (e["ng_max"], e["grid_max"])
+            if key in seen or (e["ng_max"] not in measured and e["grid_max"] not in measured):
+                continue
+            seen.add(key)
+            entries.append(e)
+    entries.sort(key=lambda e: (e["ng_max"], e["grid_max"]))
+    out = dict(tables[0])
+    out["entries"] = entries
+    out["merged_from"] = [{"tuned_on": t.get("tuned_on"), "samples": t.get("samples"),
+                           "ng_buckets": t["ng_buckets"], "grid_buckets": t["grid_buckets"],
+                           "measured_ms": t["measured_ms"]} for t in tables]
+    out.pop("measured_ms", None)
+    return out
 
 
 def main():
