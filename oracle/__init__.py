@@ -12,6 +12,8 @@ marshals numpy arrays and strings the steps together in the paper's order:
   a6  chi0 = sum_p w_p M_p M_p^H                Eq. chi
   a7-a9 eps, eps^-1, W                          Eqs. epsGG, Wq
   a10 Wannier densities and W_ij                Eqs. matrix_U, rhoiqG
+  q -> 0 head, wings and optics (oracle.head)  Eqs. eps00-cRPA, momentum, epsilonM,
+                                               eels, optical-conductivity, reflectance
 
 Parity status of each function is listed in its docstring.
 """
@@ -311,3 +313,5 @@ def threads_used() -> int:
     except AttributeError:  # pragma: no cover
         return os.cpu_count() or 1
 
+
+from . import head  # noqa: E402,F401  (q -> 0 head, wings and optics)
