@@ -264,6 +264,53 @@ rp_status rp_wannier_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nw
                        double *Wij);
 
 /*
+ * The q -> 0 head (section "Response function with random phase
+ * approximation", Eqs. eps00-cRPA and momentum): for an empty band a and an
+ * occupied band b at the same k, the G = 0 pair density tends to
+ * q . p_ab(k) / (E_a(k) - E_b(k)) with p_ab = <psi_a| -i grad |psi_b> (the
+ * non-local pseudopotential term dropped, as in the paper).  This call writes
+ * the head density h_ab = qhat . p_ab / (E_a - E_b) (bohr, hartree) into
+ * column col of M (c128 [npair][ng], the layout of rp_pair_density), so that
+ * M holds M(q, G) for G != 0 and lim M(q, 0)/|q| in that column; the
+ * contraction of such an M gives lim chi_00 / q^2 and lim chi_0G / q.
+ * The usual use is rp_pair_density at iq = 0 with G = 0 in gsph at index
+ * col, then this call, then rp_chi0_accumulate and rp_screen_head.
+ *
+ * npw (host int[Nk]), miller (dev), coef (dev): as rp_pair_density;
+ * energy_eV (dev double[Nk][nband]).
+ * qhat (host double[3]): direction of q, Cartesian, normalized here.
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE, RP_E_NOMEM, RP_E_DEVICE; a pair
+ * with E_a = E_b is flagged non-finite (rp_synchronize) and gets 0.
+ */
+rp_status rp_head_density(rp_ctx *ctx, const rp_cell *cell, int nband, int npw_max, const int *npw,
+                          const int *miller, const double *coef, const double *energy_eV, int o0,
+                          int o1, int e0, int e1, int k0, int k1, const double qhat[3], int ng,
+                          int col, double *M);
+
+/*
+ * eps at q -> 0 with head and wings, its inverse, and the optical quantities
+ * (Eqs. eps00-cRPA, epsilonM, eels, optical-conductivity, reflectance):
+ * eps_GG' = delta_GG' - v^1/2_G chi_GG' v^1/2_G' with v^1/2_0 = sqrt(4 pi/Omega)
+ * (the q factors of head and wings are in chi, see rp_head_density) and
+ * v^1/2_G = sqrt(4 pi/Omega)/|G| otherwise; then per frequency
+ *   optics[f] = {Re eps_M, Im eps_M, L, Re sigma, R}
+ * with eps_M = 1/eps^-1_00, L = -Im eps^-1_00, Re sigma = (w/4 pi) Im eps_M
+ * (w = Re freq in hartree, sigma in atomic units) and the reflectance
+ * R = |(sqrt(eps_M) - 1)/(sqrt(eps_M) + 1)|^2.  No intraband (Drude) term:
+ * the plasma-frequency term of Eq. eps00 is not included.
+ *
+ * gsph     (host) : int[ng][3], G = 0 first, no other zero vector
+ * freq_eV  (host) : c128[nfreq]
+ * chi      (dev)  : c128[nfreq][ng][ng] with the head row and column
+ * eps_inv  (dev)  : c128[nfreq][ng][ng] output, or NULL
+ * optics   (dev)  : double[nfreq][5] output, or NULL
+ * Errors: as rp_screen_W; a zero pivot surfaces in rp_synchronize.
+ */
+rp_status rp_screen_head(rp_ctx *ctx, const rp_cell *cell, int ng, const int *gsph, int nfreq,
+                         const double *freq_eV, const double *chi, double *eps_inv,
+                         double *optics);
+
+/*
  * Launch-shape tuning per size class (the autotuner in the Python package
  * measures the candidates and installs its table with this call).  A call
  * with N_G sphere vectors and largest FFT edge E uses the first entry with

@@ -20,12 +20,14 @@ from ._rp import (  # noqa: F401
     make_cell,
     rp_chi0_accumulate,
     rp_chi0_batch,
+    rp_head_density,
     rp_problem,
     rp_last_error,
     rp_pair_density,
     rp_profile,
     rp_profile_read,
     rp_screen_W,
+    rp_screen_head,
     rp_set_tuning,
     rp_tune_entry,
     rp_synchronize,

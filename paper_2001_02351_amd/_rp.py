@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_E_NULL", 2: "RP_E_SHAPE", 3: "RP_E_RANGE", 4:
 
 EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pair_density",
             "rp_weights", "rp_chi0_accumulate", "rp_chi0_batch", "rp_screen_W", "rp_wannier_W",
-            "rp_set_tuning", "rp_profile", "rp_profile_read"]
+            "rp_set_tuning", "rp_head_density", "rp_screen_head", "rp_profile", "rp_profile_read"]
 
 STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier", "batch"]
 
@@ -102,6 +102,8 @@ def load(path: Optional[str] = None):
         "rp_screen_W": [P, cellp, P, I, P, I, P, P, P],
         "rp_wannier_W": [P, cellp, P, I, P, P, I, P, I, P, I, P, P],
         "rp_set_tuning": [P, I, ctypes.POINTER(rp_tune_entry)],
+        "rp_head_density": [P, cellp, I, I, P, P, P, P, I, I, I, I, I, I, P, I, I, P],
+        "rp_screen_head": [P, cellp, I, P, I, P, P, P, P],
         "rp_profile": [P, I],
         "rp_profile_read": [P, P, P],
     }
@@ -265,6 +267,26 @@ def rp_chi0_batch(ctx: Context, problems, prec):
     st = ctx.lib.rp_chi0_batch(ctx.handle, len(problems), arr, int(prec))
     ctx._leave()
     ctx._check(st, "rp_chi0_batch")
+
+
+def rp_head_density(ctx: Context, cell: rp_cell, nband, npw_max, npw, miller, coef, energy_eV, o0, o1, e0, e1,
+                    k0, k1, qhat, ng, col, M):
+    npw_h, q_h = _host(npw, np.int32), _host(qhat, np.float64)
+    ctx._enter()
+    st = ctx.lib.rp_head_density(ctx.handle, ctypes.byref(cell), int(nband), int(npw_max), _hp(npw_h), _dp(miller),
+                                 _dp(coef), _dp(energy_eV), o0, o1, e0, e1, k0, k1, _hp(q_h), int(ng), int(col),
+                                 _dp(M))
+    ctx._leave()
+    ctx._check(st, "rp_head_density")
+
+
+def rp_screen_head(ctx: Context, cell: rp_cell, ng, gsph, nfreq, freq_eV, chi, eps_inv, optics):
+    g_h, f_h = _host(gsph, np.int32), _host(freq_eV, np.complex128)
+    ctx._enter()
+    st = ctx.lib.rp_screen_head(ctx.handle, ctypes.byref(cell), int(ng), _hp(g_h), int(nfreq), _hp(f_h), _dp(chi),
+                                _dp(eps_inv), _dp(optics))
+    ctx._leave()
+    ctx._check(st, "rp_screen_head")
 
 
 def rp_screen_W(ctx: Context, cell: rp_cell, iq, ng, gsph, nfreq, chi, eps_inv, W):

@@ -28,7 +28,7 @@ FLAGS = [
     "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function",
 ]
 
-SOURCES = ["rp_api.cpp", "fft.hip", "pair.hip", "tetra.hip", "chi_f64.hip", "chi_bf16.hip",
+SOURCES = ["rp_api.cpp", "fft.hip", "pair.hip", "tetra.hip", "chi_f64.hip", "chi_bf16.hip", "head.hip",
            "screen.hip", "wannier.hip"]
 
 

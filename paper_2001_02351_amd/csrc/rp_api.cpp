@@ -230,7 +230,9 @@ static rp_status pair_check(rp_ctx *ctx, const rp_cell *cell, const int iq[3], i
     if (!npw || !mmax || !miller || !coef) return fail(ctx, RP_E_NULL, "NULL array argument");
     if ((st = check_ranges(ctx, g, nband, o0, o1, e0, e1, k0, k1)) != RP_OK) return st;
     if (ng < 1 || ng > 6144) return fail(ctx, RP_E_UNSUPPORTED, "ng = %d outside [1, 6144]", ng);
-    if ((st = check_gsph(ctx, g, ng, gsph, "gsph")) != RP_OK) return st;
+    // (G = 0 at q = 0 is allowed here: the pair density there is an overlap;
+    // the Coulomb factor that forbids it belongs to the screening step)
+    if (!gsph) return fail(ctx, RP_E_NULL, "gsph is NULL");
     if (npw_max < 1) return fail(ctx, RP_E_SHAPE, "npw_max must be >= 1");
     if (!valid_prec(prec)) return fail(ctx, RP_E_RANGE, "unknown precision");
     j->fp32 = prec != RP_FP64;
@@ -841,6 +843,71 @@ rp_status rp_screen_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int ng,
     launch_invert(ctx->stream, nfreq, ng, a, (double2 *)ctx->rho.p, (int *)ctx->piv.p, ctx->flag);
     if (W) launch_W(ctx->stream, nfreq, ng, vs, a, (double2 *)W);
     return check_launch(ctx, "screen");
+}
+
+rp_status rp_head_density(rp_ctx *ctx, const rp_cell *cell, int nband, int npw_max, const int *npw,
+                          const int *miller, const double *coef, const double *energy_eV, int o0, int o1, int e0,
+                          int e1, int k0, int k1, const double qhat[3], int ng, int col, double *M)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    Geometry g;
+    const int iq0[3] = {0, 0, 0};
+    rp_status st = geometry(ctx, cell, iq0, &g);
+    if (st != RP_OK) return st;
+    if (!npw || !miller || !coef || !energy_eV || !qhat || !M) return fail(ctx, RP_E_NULL, "NULL array argument");
+    if ((st = check_ranges(ctx, g, nband, o0, o1, e0, e1, k0, k1)) != RP_OK) return st;
+    if (npw_max < 1) return fail(ctx, RP_E_SHAPE, "npw_max must be >= 1");
+    for (int k = 0; k < g.nk; k++)
+        if (npw[k] < 0 || npw[k] > npw_max) return fail(ctx, RP_E_SHAPE, "npw[%d] outside [0, npw_max]", k);
+    if (ng < 1 || col < 0 || col >= ng) return fail(ctx, RP_E_SHAPE, "col = %d outside [0, ng = %d)", col, ng);
+    const double qn = std::sqrt(qhat[0] * qhat[0] + qhat[1] * qhat[1] + qhat[2] * qhat[2]);
+    if (!(qn > 0.0) || !std::isfinite(qn)) return fail(ctx, RP_E_RANGE, "qhat must be a finite non-zero vector");
+    if ((long)(o1 - o0) * (e1 - e0) * (k1 - k0) == 0) return RP_OK;
+    const double qu[3] = {qhat[0] / qn, qhat[1] / qn, qhat[2] / qn};
+    if ((st = upload(ctx, ctx->kinfo, npw, sizeof(int) * g.nk)) != RP_OK) return st;
+    {
+        StageTimer t(ctx, RP_STAGE_PAIR);
+        launch_head(ctx->stream, g, miller, (const double2 *)coef, energy_eV, (const int *)ctx->kinfo.p, nband,
+                    npw_max, o0, o1, e0, e1, k0, k1, qu, ng, col, (double2 *)M, ctx->flag);
+    }
+    return check_launch(ctx, "head density");
+}
+
+rp_status rp_screen_head(rp_ctx *ctx, const rp_cell *cell, int ng, const int *gsph, int nfreq,
+                         const double *freq_eV, const double *chi, double *eps_inv, double *optics)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    Geometry g;
+    const int iq0[3] = {0, 0, 0};
+    rp_status st = geometry(ctx, cell, iq0, &g);
+    if (st != RP_OK) return st;
+    if (!chi || !gsph || !freq_eV) return fail(ctx, RP_E_NULL, "NULL array argument");
+    if (ng < 1 || nfreq < 1) return fail(ctx, RP_E_SHAPE, "ng and nfreq must be >= 1");
+    if (ng > 6144) return fail(ctx, RP_E_UNSUPPORTED, "ng = %d above 6144", ng);
+    if (gsph[0] != 0 || gsph[1] != 0 || gsph[2] != 0) return fail(ctx, RP_E_RANGE, "gsph[0] must be G = 0");
+    if ((st = check_gsph(ctx, g, ng - 1, gsph + 3, "gsph[1:]")) != RP_OK) return st;
+    for (int f = 0; f < 2 * nfreq; f++)
+        if (!std::isfinite(freq_eV[f])) return fail(ctx, RP_E_RANGE, "non-finite frequency");
+    const size_t mat = sizeof(double2) * (size_t)ng * ng * nfreq;
+    double2 *a = (double2 *)eps_inv;
+    if (!a) {
+        if ((st = ensure(ctx, ctx->work, mat)) != RP_OK) return st;
+        a = (double2 *)ctx->work.p;
+    }
+    if ((st = upload(ctx, ctx->glist, gsph, sizeof(int) * 3 * ng)) != RP_OK) return st;
+    if ((st = upload(ctx, ctx->freq, freq_eV, sizeof(double2) * nfreq)) != RP_OK) return st;
+    if ((st = ensure(ctx, ctx->vsqrt, sizeof(double) * ng)) != RP_OK) return st;
+    if ((st = ensure(ctx, ctx->piv, sizeof(int) * (size_t)ng * nfreq)) != RP_OK) return st;
+    if ((st = ensure(ctx, ctx->rho, invert_scratch_bytes(ng, nfreq))) != RP_OK) return st;
+    double *vs = (double *)ctx->vsqrt.p;
+    StageTimer t(ctx, RP_STAGE_SCREEN);
+    launch_vsqrt(ctx->stream, g, ng, (const int *)ctx->glist.p, vs, ctx->flag, true);
+    launch_eps(ctx->stream, nfreq, ng, vs, (const double2 *)chi, a, ctx->flag);
+    launch_invert(ctx->stream, nfreq, ng, a, (double2 *)ctx->rho.p, (int *)ctx->piv.p, ctx->flag);
+    if (optics) launch_optics(ctx->stream, nfreq, ng, a, (const double2 *)ctx->freq.p, optics);
+    return check_launch(ctx, "screen head");
 }
 
 rp_status rp_wannier_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nwan, const double *phi,

@@ -160,13 +160,22 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
                      bool herm, int nw, int fill, int kernel, void *part);
 
 // screen.hip
-void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, double *vs, int *flag);
+void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, double *vs, int *flag,
+                  bool head = false);
 void launch_eps(hipStream_t s, int nfreq, int ng, const double *vs, const double2 *chi,
                 double2 *eps, int *flag);
 size_t invert_scratch_bytes(int ng, int nfreq);
 void launch_invert(hipStream_t s, int nfreq, int ng, double2 *a, double2 *scratch, int *piv, int *flag);
 void launch_W(hipStream_t s, int nfreq, int ng, const double *vs, const double2 *einv,
               double2 *W);
+
+// head.hip: q -> 0 head densities into column col of M (row stride ldm),
+// and the optical quantities {Re eps_M, Im eps_M, L, Re sigma, R} per
+// frequency from eps^-1_00.
+void launch_head(hipStream_t s, const Geometry &g, const int *miller, const double2 *coef, const double *E,
+                 const int *npw_dev, int nband, int npw_max, int o0, int o1, int e0, int e1, int k0, int k1,
+                 const double qhat[3], int ldm, int col, double2 *M, int *flag);
+void launch_optics(hipStream_t s, int nfreq, int ng, const double2 *einv, const double2 *freq, double *out);
 
 // wannier.hip
 void launch_wannier_density(hipStream_t s, const Geometry &g, const FftPlan plans[3], int nwan,

@@ -34,9 +34,11 @@ namespace {
 
 constexpr double kPivotFloor = 1e-13;
 
+// vs[i] = sqrt(4 pi / Omega) / |q + G_i|; with head set, the q -> 0 form:
+// |q + G| = 0 (G = 0) takes sqrt(4 pi / Omega), the q factor being in chi
 __global__ void k_vsqrt(int ng, const int *g, double r0, double r1, double r2, double r3, double r4,
                         double r5, double r6, double r7, double r8, double q1, double q2, double q3,
-                        double pref, double *vs, int *flag)
+                        double pref, int head, double *vs, int *flag)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ng) return;
@@ -45,6 +47,10 @@ __global__ void k_vsqrt(int ng, const int *g, double r0, double r1, double r2, d
     const double y = f1 * r1 + f2 * r4 + f3 * r7;
     const double z = f1 * r2 + f2 * r5 + f3 * r8;
     const double qg = sqrt(x * x + y * y + z * z);
+    if (head && qg == 0.0) {
+        vs[i] = pref;
+        return;
+    }
     vs[i] = pref / qg;
     if (!(qg > 0.0)) atomicOr(flag, kFlagNonFinite);
 }
@@ -255,13 +261,13 @@ __global__ void k_W(int nfreq, int ng, const double *vs, const double2 *einv, do
 
 }  // namespace
 
-void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, double *vs, int *flag)
+void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, double *vs, int *flag, bool head)
 {
     const double pref = sqrt(4.0 * kPi / g.volume);
     hipLaunchKernelGGL(k_vsqrt, dim3((ng + 255) / 256), dim3(256), 0, s, ng, gsph, g.rec[0], g.rec[1],
                        g.rec[2], g.rec[3], g.rec[4], g.rec[5], g.rec[6], g.rec[7], g.rec[8],
                        (double)g.iq[0] / g.kmesh[0], (double)g.iq[1] / g.kmesh[1],
-                       (double)g.iq[2] / g.kmesh[2], pref, vs, flag);
+                       (double)g.iq[2] / g.kmesh[2], pref, (int)head, vs, flag);
 }
 
 void launch_eps(hipStream_t s, int nfreq, int ng, const double *vs, const double2 *chi, double2 *eps,

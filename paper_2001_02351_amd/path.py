@@ -117,6 +117,43 @@ def chi0_batch(ctx, ds, prec: int = _rp.RP_FP64, kbatch: int = 1, chis=None):
     return chis
 
 
+def chi0_head(ctx, d: DeviceInputs, qhat, prec: int = _rp.RP_FP64, kbatch: int = 1):
+    """chi at q -> 0 (iq = 0) over all k and bands with G = 0 first in the
+    sphere and the head density of direction qhat in its row and column.
+    Returns (chi, G list)."""
+    import torch
+    p = d.prob
+    if tuple(int(x) for x in p.iq) != (0, 0, 0):
+        raise ValueError("the q -> 0 head needs iq = 0")
+    gaug = np.ascontiguousarray(np.concatenate([np.zeros((1, 3), np.int32), np.asarray(p.gsph, np.int32)]))
+    ng = int(gaug.shape[0])
+    npk = p.nocc * p.nemp
+    chi = torch.empty((d.nfreq, ng, ng, 2), dtype=torch.float64, device=d.device)
+    M = torch.empty((kbatch * npk, ng, 2), dtype=torch.float64, device=d.device)
+    o0, o1, e0, e1 = 0, p.nocc, p.nocc, p.nocc + p.nemp
+    for ka in range(0, d.nk, kbatch):
+        kb = min(d.nk, ka + kbatch)
+        Mk = M[: (kb - ka) * npk]
+        _rp.rp_pair_density(ctx, d.cell, p.iq, d.nband, p.miller.shape[1], p.npw, d.mmax, d.miller, d.coef,
+                            o0, o1, e0, e1, ka, kb, ng, gaug, prec, Mk)
+        _rp.rp_head_density(ctx, d.cell, d.nband, p.miller.shape[1], p.npw, d.miller, d.coef, d.energy,
+                            o0, o1, e0, e1, ka, kb, qhat, ng, 0, Mk)
+        _rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, d.T, o0, o1, e0, e1, ka, kb, ng, Mk,
+                               d.nfreq, p.freq_eV, p.delta_eV, weight_mode(p), prec, 0 if ka == 0 else 1, chi)
+    return chi, gaug
+
+
+def screen_head(ctx, d: DeviceInputs, chi, gaug):
+    """eps^-1 at q -> 0 with head and wings, and the optical quantities
+    {Re eps_M, Im eps_M, L, Re sigma, R} per frequency."""
+    import torch
+    p = d.prob
+    einv = torch.empty_like(chi)
+    optics = torch.empty((d.nfreq, 5), dtype=torch.float64, device=d.device)
+    _rp.rp_screen_head(ctx, d.cell, int(gaug.shape[0]), gaug, d.nfreq, p.freq_eV, chi, einv, optics)
+    return einv, optics
+
+
 def screen(ctx, d: DeviceInputs, chi, want_eps_inv: bool = True, want_W: bool = True):
     import torch
     p = d.prob
