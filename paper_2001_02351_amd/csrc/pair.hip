@@ -179,8 +179,7 @@ k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, i
     constexpr int NGRP = 256 / G;             // lane groups per workgroup
     constexpr int L3M = lanes_l3max<C, N, NP>();
     constexpr int TA = (NP * N + NGRP - 1) / NGRP;    // phase-A lines per group
-    __shared__ C win0[NP * N * L3M];          // [NP][N][L3]
-    __shared__ C win1[NP * N * L3M];
+    __shared__ C win[2][NP * N * L3M];        // two windows [NP][N][L3]
     __shared__ C tw1[256];
     __shared__ C twN[N];
     __shared__ C twQ[Q];
@@ -211,55 +210,47 @@ k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, i
     }
     __syncthreads();
 
-    auto plane = [&](int j1, C *B) {
-        // (A) product rows along j3
-#pragma unroll 1
-        for (int it = 0; it < TA; it++) {
-            const int task = grp + NGRP * it;
-            if (task < NP * N) {
-                const int q = task / N, j2 = task - q * N;
-                const long off = ((long)j1 * N + j2) * N + Q * s;
-                const C *ra = u_emp + (long)min(a0 + q / NB, nE - 1) * nr + off;
-                const C *rb = u_occ + (long)min(b0 + q % NB, nO - 1) * nr + off;
-                C x[Q];
-                if constexpr (sizeof(C) == 8 && N % 2 == 0 && Q % 2 == 0) {
-                    // two FP32 complex values per 16-byte load (row and lane
-                    // offsets are even, grids 16-byte aligned)
+    // (A) one product row along j3 (line task q, j2 of plane j1) into window B
+    auto row_task = [&](int j1, int q, int j2, C *B) {
+        const long off = ((long)j1 * N + j2) * N + Q * s;
+        const C *ra = u_emp + (long)min(a0 + q / NB, nE - 1) * nr + off;
+        const C *rb = u_occ + (long)min(b0 + q % NB, nO - 1) * nr + off;
+        C x[Q];
+        if constexpr (sizeof(C) == 8 && N % 2 == 0 && Q % 2 == 0) {
+            // two FP32 complex values per 16-byte load (row and lane offsets
+            // are even, grids 16-byte aligned)
 #pragma unroll
-                    for (int n = 0; n < Q / 2; n++) {
-                        const float4 va = ((const float4 *)ra)[n], vb = ((const float4 *)rb)[n];
-                        x[2 * n] = cmulc(mkc<C>(va.x, va.y), mkc<C>(vb.x, vb.y));
-                        x[2 * n + 1] = cmulc(mkc<C>(va.z, va.w), mkc<C>(vb.z, vb.w));
-                    }
-                } else {
-#pragma unroll
-                    for (int n = 0; n < Q; n++) x[n] = cmulc(ra[n], rb[n]);
-                }
-                group_fft<G, Q>(x, twQ, twN, s);
-                C *dst = B + ((size_t)q * N + j2) * L3;
-#pragma unroll
-                for (int k = 0; k < Q; k++) {
-                    int t3 = G * k + r - lo3;
-                    t3 = t3 < 0 ? t3 + N : (t3 >= N ? t3 - N : t3);
-                    if (t3 < L3) dst[t3] = x[k];
-                }
+            for (int n = 0; n < Q / 2; n++) {
+                const float4 va = ((const float4 *)ra)[n], vb = ((const float4 *)rb)[n];
+                x[2 * n] = cmulc(mkc<C>(va.x, va.y), mkc<C>(vb.x, vb.y));
+                x[2 * n + 1] = cmulc(mkc<C>(va.z, va.w), mkc<C>(vb.z, vb.w));
             }
-        }
-        lds_sync();
-        // (B) columns along j2, in place (a group reads its whole column
-        // before any of its lanes writes)
-        for (int task = grp; task < NP * L3; task += NGRP) {
-            const int qq = task / L3, t3 = task - qq * L3;
-            C *col = B + (size_t)qq * N * L3 + t3;
-            C y[Q];
+        } else {
 #pragma unroll
-            for (int n = 0; n < Q; n++) y[n] = col[(Q * s + n) * L3];
-            group_fft<G, Q>(y, twQ, twN, s);
-#pragma unroll
-            for (int k = 0; k < Q; k++) col[(G * k + r) * L3] = y[k];
+            for (int n = 0; n < Q; n++) x[n] = cmulc(ra[n], rb[n]);
         }
-        lds_sync();
-        // (C) sphere points
+        group_fft<G, Q>(x, twQ, twN, s);
+        C *dst = B + ((size_t)q * N + j2) * L3;
+#pragma unroll
+        for (int k = 0; k < Q; k++) {
+            int t3 = G * k + r - lo3;
+            t3 = t3 < 0 ? t3 + N : (t3 >= N ? t3 - N : t3);
+            if (t3 < L3) dst[t3] = x[k];
+        }
+    };
+    // (B) one column along j2, in place (a group reads its whole column
+    // before any of its lanes writes)
+    auto col_task = [&](int qq, int t3, C *B) {
+        C *col = B + (size_t)qq * N * L3 + t3;
+        C y[Q];
+#pragma unroll
+        for (int n = 0; n < Q; n++) y[n] = col[(Q * s + n) * L3];
+        group_fft<G, Q>(y, twQ, twN, s);
+#pragma unroll
+        for (int k = 0; k < Q; k++) col[(G * k + r) * L3] = y[k];
+    };
+    // (C) the sphere points accumulate one plane's window with its j1 phase
+    auto sphere = [&](const C *B) {
 #pragma unroll
         for (int t = 0; t < MAXG; t++) {
             const int g = tid + t * 256;
@@ -276,11 +267,50 @@ k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, i
             }
         }
     };
-    // window j1 & 1 is rewritten by phase A of plane j1 + 2, which every
-    // thread starts only after the barriers of plane j1 + 1
-    for (int j1 = 0; j1 < N1; j1 += 2) {
-        plane(j1, win0);
-        if (j1 + 1 < N1) plane(j1 + 1, win1);
+    if constexpr (G <= 2) {
+        // one or two lanes per line leave too few line tasks in one plane to
+        // occupy the workgroup: phases A and B take two planes at a time, and
+        // a third barrier keeps the next pair's rows out of the windows until
+        // every sphere point has read them
+        constexpr int TA2 = (2 * NP * N + NGRP - 1) / NGRP;
+        for (int j1 = 0; j1 < N1; j1 += 2) {
+            const int npl = min(2, N1 - j1);
+#pragma unroll 1
+            for (int it = 0; it < TA2; it++) {
+                const int task = grp + NGRP * it;
+                if (task < npl * NP * N) {
+                    const int pl = task / (NP * N), t2 = task - pl * (NP * N);
+                    row_task(j1 + pl, t2 / N, t2 % N, win[pl]);
+                }
+            }
+            lds_sync();
+            for (int task = grp; task < npl * NP * L3; task += NGRP) {
+                const int pl = task / (NP * L3), t2 = task - pl * (NP * L3);
+                col_task(t2 / L3, t2 % L3, win[pl]);
+            }
+            lds_sync();
+            sphere(win[0]);
+            if (npl == 2) sphere(win[1]);
+            lds_sync();
+        }
+    } else {
+        auto plane = [&](int j1, C *B) {
+#pragma unroll 1
+            for (int it = 0; it < TA; it++) {
+                const int task = grp + NGRP * it;
+                if (task < NP * N) row_task(j1, task / N, task % N, B);
+            }
+            lds_sync();
+            for (int task = grp; task < NP * L3; task += NGRP) col_task(task / L3, task % L3, B);
+            lds_sync();
+            sphere(B);
+        };
+        // window j1 & 1 is rewritten by phase A of plane j1 + 2, which every
+        // thread starts only after the barriers of plane j1 + 1
+        for (int j1 = 0; j1 < N1; j1 += 2) {
+            plane(j1, win[0]);
+            if (j1 + 1 < N1) plane(j1 + 1, win[1]);
+        }
     }
     const double inv = 1.0 / (double)nr;
 #pragma unroll
