@@ -31,6 +31,10 @@ Counter runs use two extra modes: --copy-calibration (a plain 1 GiB device
 copy, three times) and --profile-k N (the split chi0 build over the first N
 k-points in the launch configuration of the timed legs).
 
+--supercell measures the large-supercell shape (96^3, N_G = 6000, 720 000
+pairs over 16 frequencies streamed in blocks of empty bands; rate counts the
+full Eq. chi, 8 N_G^2 P N_w).
+
 --tune OUT writes the launch-shape table tuned on both workloads (the
 package's tuning_mi355x.json comes from it).
 
@@ -374,6 +378,98 @@ def batch_leg(args):
     print(json.dumps(out), flush=True)
 
 
+def supercell_leg(args):
+    """The large-supercell shape (96^3, Gamma only, q = 0, 600 + 1200 bands,
+    N_G = 6000, 16 real frequencies, 20 Wannier orbitals): split-BF16 chi0
+    streamed over blocks of empty bands, FP64 eps^-1 and W, W_ij (one JSON
+    line)."""
+    import torch
+
+    import paper_2001_02351_amd as rp
+    from paper_2001_02351_amd import path
+    from synth import supercell_workload
+    log("generating the supercell workload (96^3, 600 + 1200 bands, N_G = 6000)")
+    t0 = time.perf_counter()
+    p = supercell_workload()
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    rp.load()
+    ctx = rp.Context(0)
+    d = path.DeviceInputs(p)
+    eb = args.sc_emp_block
+    nblk = (p.nemp + eb - 1) // eb
+    nrun = nblk if args.sc_blocks <= 0 else min(nblk, args.sc_blocks)
+    prec = rp.RP_SPLIT_BF16
+    chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device=d.device)
+    M = torch.empty((p.nocc * eb, d.ng, 2), dtype=torch.float64, device=d.device)
+    torch.cuda.synchronize()
+    log("inputs resident on the device")
+
+    def block(i, acc):
+        e0 = p.nocc + i * eb
+        e1 = min(p.nocc + p.nemp, e0 + eb)
+        Mk = M[: p.nocc * (e1 - e0)]
+        path.pair_density(ctx, d, 0, 1, o=(0, p.nocc), e=(e0, e1), out=Mk, prec=prec)
+        rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, d.T, 0, p.nocc, e0, e1, 0, 1, d.ng, Mk,
+                              d.nfreq, p.freq_eV, p.delta_eV, path.weight_mode(p), prec, acc, chi)
+
+    block(0, 0)                                      # warm-up (kernel loading)
+    rp.rp_synchronize(ctx)
+    rp.rp_profile(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(nrun):
+        block(i, 0 if i == 0 else 1)
+    rp.rp_synchronize(ctx)
+    t_chi = time.perf_counter() - t0
+    log(f"chi0 over {nrun} of {nblk} empty-band blocks: {t_chi:.2f} s")
+    t0 = time.perf_counter()
+    einv, W = path.screen(ctx, d, chi)
+    rp.rp_synchronize(ctx)
+    t_scr = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    path.wannier(ctx, d, einv)
+    rp.rp_synchronize(ctx)
+    t_wan = time.perf_counter() - t0
+    stages = rp.rp_profile_read(ctx)
+    rp.rp_profile(ctx, False)
+    ctx.close()
+    pairs = p.nocc * min(p.nemp, nrun * eb)
+    flops = 8.0 * d.ng ** 2 * pairs * d.nfreq
+    scale = (p.nocc * p.nemp) / pairs
+    out = {
+        "metric": METRIC,
+        "value": flops / t_chi / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": (t_chi * scale + t_scr + t_wan) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": "supercell q-point: 96^3 grid, Gamma-only k, q = 0 (G = 0 dropped), 600 + 1200 bands, "
+                        "N_G = 6000, 16 real frequencies, delta = 0.1 eV, sampling weights, 20 Wannier orbitals; "
+                        f"pair densities streamed in blocks of {eb} empty bands",
+            "pairs_timed": pairs,
+            "pairs_total": p.nocc * p.nemp,
+            "ng": d.ng,
+            "nfreq": d.nfreq,
+        },
+        "t_chi0_s_timed": t_chi,
+        "t_chi0_s_per_qpoint": t_chi * scale,
+        "t_screen_s": t_scr,
+        "t_wannier_s": t_wan,
+        "stage_ms": {k: v[0] for k, v in stages.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def tune_leg(args):
     """Launch shapes tuned on the 48^3 workload's first k batch and on one
     q-point of every batched system, merged into one table (--tune OUT)."""
@@ -428,6 +524,9 @@ def main():
                     help="workload (autotune on the batch first), none, or a table file")
     ap.add_argument("--tuning-out", default=None)
     ap.add_argument("--batch-no-graph", action="store_true")
+    ap.add_argument("--supercell", action="store_true")
+    ap.add_argument("--sc-emp-block", type=int, default=100)
+    ap.add_argument("--sc-blocks", type=int, default=0, help="empty-band blocks to time (0: all)")
     ap.add_argument("--tune", default=None, metavar="OUT",
                     help="autotune the launch shapes on both workloads and write the table")
     args = ap.parse_args()
@@ -441,6 +540,9 @@ def main():
         return
     if args.tune:
         tune_leg(args)
+        return
+    if args.supercell:
+        supercell_leg(args)
         return
     if args.batch:
         batch_leg(args)

@@ -311,7 +311,7 @@ __device__ __forceinline__ void quad_fft(C (&x)[Q], const C *twQ, const C *twN, 
 
 // ---------------------------------------------------------------------------
 // Lane-group FFT: a line of length N = G Q over G adjacent lanes, G in
-// {1, 2, 4} (the group's lanes are active together).  G = 4 is the quad form
+// {1, 2, 4, 8} (the group's lanes are active together).  G = 4 is the quad form
 // above; G = 2 is the same decimation in frequency with a 2-point DFT across
 // the lane pair (DPP swap of lanes s and s ^ 1): lane s holds x[Q s + n] and
 // ends with X[2k + s] in x[k]; G = 1 is the register FFT of the whole line.
@@ -319,7 +319,8 @@ __device__ __forceinline__ void quad_fft(C (&x)[Q], const C *twQ, const C *twN, 
 
 template <int G> __device__ __forceinline__ int group_row(int s)
 {
-    if constexpr (G == 4) return quad_row(s & 3);
+    if constexpr (G == 8) return 2 * quad_row(s & 3) + ((s >> 2) & 1);
+    else if constexpr (G == 4) return quad_row(s & 3);
     else if constexpr (G == 2) return s & 1;
     else return 0;
 }
@@ -338,10 +339,41 @@ template <int Q, typename C> __device__ __forceinline__ void pair_dft2(C (&x)[Q]
 
 // twQ[t] = e^{2 pi i t/Q}, t < Q; twN[t] = e^{2 pi i t/N}, t < N (for G = 1
 // the two tables are the same length and only twQ is read)
+// G = 8: a radix-2 step across lanes s and s ^ 4 (lanes 0-3 keep x_s + x_s+4,
+// lanes 4-7 take (x_s-4 - x_s) e^{2 pi i (s-4)/8}), then a 4-point DFT across
+// each quad: lane s ends with output residue 2 qrow(s & 3) + (s >> 2 & 1).
+template <int Q, typename C> __device__ __forceinline__ void oct_dft2(C (&x)[Q], int s)
+{
+    typedef typename CxT<C>::T T;
+    const bool hi = (s & 4) != 0;
+    const int m = s & 3;
+    // e^{2 pi i m / 8}, m < 4
+    const T h = (T)0.70710678118654752440;
+    const T wr = m == 0 ? (T)1 : (m == 1 ? h : (m == 2 ? (T)0 : -h));
+    const T wi = m == 0 ? (T)0 : (m == 1 ? h : (m == 2 ? (T)1 : h));
+#pragma unroll
+    for (int k = 0; k < Q; k++) {
+        const T px = __shfl_xor(x[k].x, 4), py = __shfl_xor(x[k].y, 4);
+        if (!hi) {
+            x[k] = mkc<C>(x[k].x + px, x[k].y + py);
+        } else {
+            const T dx = px - x[k].x, dy = py - x[k].y;
+            x[k] = mkc<C>(dx * wr - dy * wi, dx * wi + dy * wr);
+        }
+    }
+}
+
 template <int G, int Q, typename C>
 __device__ __forceinline__ void group_fft(C (&x)[Q], const C *twQ, const C *twN, int s)
 {
-    if constexpr (G == 4) {
+    if constexpr (G == 8) {
+        oct_dft2<Q>(x, s);
+        quad_dft4<Q>(x, s & 3);
+        const int r = group_row<8>(s);
+#pragma unroll
+        for (int n = 1; n < Q; n++) x[n] = cmul(x[n], twN[r * n]);
+        reg_fft<Q>(x, twQ);
+    } else if constexpr (G == 4) {
         quad_fft<Q>(x, twQ, twN, s);
     } else if constexpr (G == 2) {
         pair_dft2<Q>(x, s);

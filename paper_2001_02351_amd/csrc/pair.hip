@@ -145,9 +145,13 @@ __device__ __forceinline__ void lds_sync()
     asm volatile("" ::: "memory");
 }
 
-// lanes per line for the lane-group form: 4 when N is a multiple of 4, else
-// 2 when even, else 1
-template <int N> constexpr int pair_group() { return N % 4 == 0 ? 4 : (N % 2 == 0 ? 2 : 1); }
+// lanes per line for the lane-group form: 8 for the 96-point lines (12
+// points per lane keep the registers for large spheres), else 4 when N is a
+// multiple of 4, 2 when even, 1 when odd
+template <int N> constexpr int pair_group()
+{
+    return N == 96 ? 8 : (N % 4 == 0 ? 4 : (N % 2 == 0 ? 2 : 1));
+}
 
 // widest m3 window the lane-group form holds in LDS: two windows of
 // [NP][N][L3M] under 72 KB (FP32) or 48 KB (FP64), so two workgroups share a CU
@@ -193,19 +197,19 @@ k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, i
     fill_twiddles(twQ, Q, tid, 256);
 
     C acc[NP][MAXG];
-    int cidx[MAXG], step1[MAXG], ph[MAXG];
+    // per sphere point, packed into one register: bits 0-13 the window index
+    // (m2 mod N) L3 + m3 - lo3 (< N L3M <= 2304), bits 14-21 the j1 phase step
+    // m1 mod N1, bits 22-29 the running phase index (N1 <= 256)
+    unsigned pk[MAXG];
 #pragma unroll
     for (int t = 0; t < MAXG; t++) {
         const int g = tid + t * 256;
 #pragma unroll
         for (int q = 0; q < NP; q++) acc[q][t] = mkc<C>(0, 0);
-        cidx[t] = 0;
-        step1[t] = 0;
-        ph[t] = 0;
+        pk[t] = 0;
         if (g < ng) {
             const int m1 = gsph[3 * g] + g01, m2 = gsph[3 * g + 1] + g02, m3 = gsph[3 * g + 2] + g03;
-            cidx[t] = pmod(m2, N) * L3 + (m3 - lo3);
-            step1[t] = pmod(m1, N1);
+            pk[t] = (unsigned)(pmod(m2, N) * L3 + (m3 - lo3)) | ((unsigned)pmod(m1, N1) << 14);
         }
     }
     __syncthreads();
@@ -255,15 +259,19 @@ k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, i
         for (int t = 0; t < MAXG; t++) {
             const int g = tid + t * 256;
             if (g < ng) {
-                const C e = tw1[ph[t]];
+                const unsigned u = pk[t];
+                const int ci = (int)(u & 0x3fffu), st = (int)((u >> 14) & 0xffu);
+                int ph = (int)(u >> 22);
+                const C e = tw1[ph];
 #pragma unroll
                 for (int qq = 0; qq < NP; qq++) {
-                    const C v = B[(size_t)qq * N * L3 + cidx[t]];
+                    const C v = B[(size_t)qq * N * L3 + ci];
                     acc[qq][t].x += v.x * e.x - v.y * e.y;
                     acc[qq][t].y += v.x * e.y + v.y * e.x;
                 }
-                ph[t] += step1[t];
-                if (ph[t] >= N1) ph[t] -= N1;
+                ph += st;
+                if (ph >= N1) ph -= N1;
+                pk[t] = (u & 0x3fffffu) | ((unsigned)ph << 22);
             }
         }
     };
@@ -334,10 +342,17 @@ void launch_pair_lanes(hipStream_t s, int N1, const C *u_occ, const C *u_emp, in
 #define RP_PAIRL(G)                                                                                          \
     hipLaunchKernelGGL((k_pair_lanes<C, N, NA, NB, G>), dim3(nblk), dim3(256), 0, s, u_occ, u_emp, nO, nE,   \
                        N1, ng, gsph, g0[0], g0[1], g0[2], lo3, L3, M)
-    if (ng <= 512) RP_PAIRL(2);
-    else if (ng <= 1024) RP_PAIRL(4);
-    else if (ng <= 1536) RP_PAIRL(6);
-    else RP_PAIRL(8);
+    if constexpr (N >= 96) {
+        // large grids come with large spheres: 2048, 4096 or 6144 points
+        if (ng <= 2048) RP_PAIRL(8);
+        else if (ng <= 4096) RP_PAIRL(16);
+        else RP_PAIRL(24);
+    } else {
+        if (ng <= 512) RP_PAIRL(2);
+        else if (ng <= 1024) RP_PAIRL(4);
+        else if (ng <= 1536) RP_PAIRL(6);
+        else RP_PAIRL(8);
+    }
 #undef RP_PAIRL
 }
 
@@ -372,14 +387,17 @@ int pair_rows(const int fft[3]) { return std::max(1, std::min(fft[1], 768 / fft[
 
 // The lane-group form's lengths: N2 = N3 = N in these lists, N1 <= 256,
 // ng <= 2048, and the m3 window within its LDS plan.  The band blocks are
-// 2x2 pairs in FP32 and 2x1 in FP64.  FP64 lines of 25, 27 and 30 (one or two
+// 2x2 pairs in FP32 and 2x1 in FP64.  FP32 N = 96 (the supercell grid) takes
+// 2x1 blocks, so that a window of 24 fits, and spheres up to 6144 points.  FP64 lines of 25, 27 and 30 (one or two
 // lanes per line) do not fit in registers and use the generic form.
 #define RP_LANE_LENGTHS_F32(X) X(16) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(48)
 #define RP_LANE_LENGTHS_F64(X) X(16) X(24) X(32) X(36) X(40) X(48)
 
 static bool pair_lanes_f32(const int fft[3], int ng, int L3)
 {
-    if (fft[0] > 256 || fft[1] != fft[2] || ng > 2048) return false;
+    if (fft[0] > 256 || fft[1] != fft[2]) return false;
+    if (fft[1] == 96) return ng <= 6144 && L3 <= lanes_l3max<float2, 96, 2>();
+    if (ng > 2048) return false;
     switch (fft[1]) {
 #define RP_CASE(n) \
     case n: return L3 <= lanes_l3max<float2, n, 4>();
@@ -419,6 +437,7 @@ void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], cons
         case n: launch_pair_lanes<float2, n, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
             RP_LANE_LENGTHS_F32(RP_CASE)
 #undef RP_CASE
+        case 96: launch_pair_lanes<float2, 96, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
         default: break;
         }
     }
