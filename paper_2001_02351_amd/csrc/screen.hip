@@ -175,22 +175,16 @@ __device__ __forceinline__ d4 mfma64(double x, double y, d4 c)
 __global__ void __launch_bounds__(256)
 k_gj_update(int ng, int c0, int nb, double2 *a, const double2 *rk)
 {
-    __shared__ double2 sP[64][kGjNb + 1];
-    __shared__ double2 sR[kGjNb][64];
+    // the panel's 64 columns pass through LDS in chunks of 16, so that a CU
+    // holds several workgroups and one's loads overlap another's matrix work
+    constexpr int KC = 16;
+    __shared__ double2 sP[64][KC + 1];
+    __shared__ double2 sR[KC][64];
     const int f = blockIdx.z, tid = threadIdx.x;
     const int rt0 = blockIdx.y * 64, ct0 = blockIdx.x * 64;
     if (ct0 >= c0 && ct0 + 64 <= c0 + nb) return;   // tile inside the panel columns
     double2 *A = a + (long)f * ng * ng;
     const double2 *R = rk + (long)f * kGjNb * ng;
-    for (int e = tid; e < 64 * kGjNb; e += 256) {
-        const int rr = e / kGjNb, k = e - rr * kGjNb, i = rt0 + rr;
-        sP[rr][k] = (i < ng && k < nb) ? A[(long)i * ng + c0 + k] : make_double2(0.0, 0.0);
-    }
-    for (int e = tid; e < kGjNb * 64; e += 256) {
-        const int k = e >> 6, cc = e & 63, j = ct0 + cc;
-        sR[k][cc] = (k < nb && j < ng) ? R[(long)k * ng + j] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
     const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     d4 accR[2][2], accI[2][2];
@@ -201,21 +195,34 @@ k_gj_update(int ng, int c0, int nb, double2 *a, const double2 *rk)
             accR[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
             accI[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
         }
-    for (int k0 = 0; k0 < nb; k0 += 4) {
-        double2 x[2], y[2];
+    for (int kc = 0; kc < nb; kc += KC) {
+        for (int e = tid; e < 64 * KC; e += 256) {
+            const int rr = e / KC, k = e - rr * KC, i = rt0 + rr;
+            sP[rr][k] = (i < ng && kc + k < nb) ? A[(long)i * ng + c0 + kc + k] : make_double2(0.0, 0.0);
+        }
+        for (int e = tid; e < KC * 64; e += 256) {
+            const int k = e >> 6, cc = e & 63, j = ct0 + cc;
+            sR[k][cc] = (kc + k < nb && j < ng) ? R[(long)(kc + k) * ng + j] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
 #pragma unroll
-        for (int rb = 0; rb < 2; rb++) x[rb] = sP[wr + rb * 16 + li][k0 + lk];
+        for (int k0 = 0; k0 < KC; k0 += 4) {
+            double2 x[2], y[2];
 #pragma unroll
-        for (int cb = 0; cb < 2; cb++) y[cb] = sR[k0 + lk][wc + cb * 16 + li];
+            for (int rb = 0; rb < 2; rb++) x[rb] = sP[wr + rb * 16 + li][k0 + lk];
 #pragma unroll
-        for (int rb = 0; rb < 2; rb++)
+            for (int cb = 0; cb < 2; cb++) y[cb] = sR[k0 + lk][wc + cb * 16 + li];
 #pragma unroll
-            for (int cb = 0; cb < 2; cb++) {
-                accR[rb][cb] = mfma64(x[rb].x, y[cb].x, accR[rb][cb]);
-                accR[rb][cb] = mfma64(-x[rb].y, y[cb].y, accR[rb][cb]);
-                accI[rb][cb] = mfma64(x[rb].x, y[cb].y, accI[rb][cb]);
-                accI[rb][cb] = mfma64(x[rb].y, y[cb].x, accI[rb][cb]);
-            }
+            for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+                for (int cb = 0; cb < 2; cb++) {
+                    accR[rb][cb] = mfma64(x[rb].x, y[cb].x, accR[rb][cb]);
+                    accR[rb][cb] = mfma64(-x[rb].y, y[cb].y, accR[rb][cb]);
+                    accI[rb][cb] = mfma64(x[rb].x, y[cb].y, accI[rb][cb]);
+                    accI[rb][cb] = mfma64(x[rb].y, y[cb].x, accI[rb][cb]);
+                }
+        }
+        __syncthreads();
     }
 #pragma unroll
     for (int rb = 0; rb < 2; rb++)
