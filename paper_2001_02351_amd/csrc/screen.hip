@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(kGjPanelThreads)
 k_gj_panel(int ng, int c0, int nb, double2 *a, double2 *rk, int *piv, int *flag)
 {
     constexpr int NWV = kGjPanelThreads / 64;
-    __shared__ double2 fcol[kGjMaxNg];   // column c after the swap
+    __shared__ double2 fcol[kGjMaxNg];   // column c (after the swap)
     __shared__ double2 prow[kGjNb];      // scaled pivot row, panel columns
     __shared__ double bv[NWV];
     __shared__ int bi[NWV];
@@ -97,12 +97,18 @@ k_gj_panel(int ng, int c0, int nb, double2 *a, double2 *rk, int *piv, int *flag)
     const int jj = tid % kGjNb, rs = tid / kGjNb;   // panel column and row lane of the elimination
     constexpr int RSTEP = kGjPanelThreads / kGjNb;
     double2 *A = a + (long)f * ng * ng;
+    // column c0 once from memory; every later pivot column is kept in LDS by
+    // the elimination of the step before (the lanes of a wave share one row,
+    // so the lane writing column c+1 of row i does so after the wave has read
+    // column c of that row)
+    for (int i = tid; i < ng; i += kGjPanelThreads) fcol[i] = A[(long)i * ng + c0];
+    __syncthreads();
     for (int c = c0; c < c0 + nb; c++) {
         // pivot: largest |a_ic| over rows i >= c (wave shuffles, then across waves)
         double best = -1.0;
         int bidx = c;
         for (int i = c + tid; i < ng; i += kGjPanelThreads) {
-            const double2 v = A[(long)i * ng + c];
+            const double2 v = fcol[i];
             const double m = isfinite(v.x) && isfinite(v.y) ? hypot(v.x, v.y) : INFINITY;
             pivot_max(best, bidx, m, i);
         }
@@ -122,6 +128,11 @@ k_gj_panel(int ng, int c0, int nb, double2 *a, double2 *rk, int *piv, int *flag)
             piv[(long)f * ng + c] = r;
             if (!isfinite(best)) atomicOr(flag, kFlagNonFinite);
             else if (!(best > kPivotFloor)) atomicOr(flag, kFlagZeroPivot);
+            if (r != c) {
+                const double2 t = fcol[c];
+                fcol[c] = fcol[r];
+                fcol[r] = t;
+            }
         }
         if (r != c) {
             for (int j = tid; j < ng; j += kGjPanelThreads) {
@@ -131,10 +142,9 @@ k_gj_panel(int ng, int c0, int nb, double2 *a, double2 *rk, int *piv, int *flag)
             }
         }
         __syncthreads();
-        const double2 p = A[(long)c * ng + c];
+        const double2 p = fcol[c];
         const double den = p.x * p.x + p.y * p.y;
         const double2 ip = make_double2(p.x / den, -p.y / den);
-        for (int i = tid; i < ng; i += kGjPanelThreads) fcol[i] = A[(long)i * ng + c];
         if (tid < nb) {
             const int j = c0 + tid;
             prow[tid] = (j == c) ? ip : cmul(A[(long)c * ng + j], ip);
@@ -145,12 +155,12 @@ k_gj_panel(int ng, int c0, int nb, double2 *a, double2 *rk, int *piv, int *flag)
             const double2 pj = prow[jj];
             for (int i = rs; i < ng; i += RSTEP) {
                 double2 *x = A + (long)i * ng + j;
-                if (i == c) {
-                    *x = pj;
-                } else {
-                    const double2 fi = fcol[i];
-                    *x = (j == c) ? cmul(make_double2(-fi.x, -fi.y), ip) : csub(*x, cmul(fi, pj));
-                }
+                const double2 fi = fcol[i];
+                double2 v;
+                if (i == c) v = pj;
+                else v = (j == c) ? cmul(make_double2(-fi.x, -fi.y), ip) : csub(*x, cmul(fi, pj));
+                *x = v;
+                if (j == c + 1) fcol[i] = v;
             }
         }
         __syncthreads();
