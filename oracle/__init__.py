@@ -14,6 +14,8 @@ marshals numpy arrays and strings the steps together in the paper's order:
   a10 Wannier densities and W_ij                Eqs. matrix_U, rhoiqG
   q -> 0 head, wings and optics (oracle.head)  Eqs. eps00-cRPA, momentum, epsilonM,
                                                eels, optical-conductivity, reflectance
+  q-mesh sums of U, V, J, X (oracle.qsum)      Eqs. W, Wq, matrix_U, rhoiqG, matrix_V,
+                                               matrix_J, matrix_X
 
 Parity status of each function is listed in its docstring.
 """
