@@ -264,6 +264,62 @@ rp_status rp_wannier_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nw
                        double *Wij);
 
 /*
+ * One q-point's term of the q-mesh sums of the interaction parameters
+ * between orbital i in the home cell and orbital j in cell R (section
+ * "Interaction parameters", Eqs. W, Wq, matrix_U, rhoiqG, matrix_V, matrix_J,
+ * matrix_X).  Summed over every q of the mesh (accumulate = 0 for the first,
+ * 1 for the rest) it gives, in eV, with pre = HA 4 pi/(Omega N_q):
+ *   U_i0jR(w) = sum_q e^{-iq.R} pre [ sum_{G,G' in S_eps} rho_iq(G) eps^-1_GG'(q,w) conj(rho_jq(G'))
+ *                                     + sum_{G in tail} rho_iq(G) conj(rho_jq(G)) ]   screened direct
+ *   V_i0jR    = the same with eps^-1 = delta                                           bare direct
+ *   J_i0jR(w) = sum_q pre [ sum_{G,G'} rho_v(G) eps^-1_GG' conj(rho_v(G')) + tail ]      screened exchange
+ *   X_i0jR    = the same with eps^-1 = delta                                           bare exchange
+ * Direct densities rho_iq(G) = ntilde_i(q+G)/|q+G| as in rp_wannier_W.
+ * Exchange densities rho_v(G) = ntilde_v(q+G)/|q+G|, v = (R, i, j), with
+ * ntilde_v(Q) = (Omega/N_r) sum_p phi_i0(rt_p) phi_jR(rt_p) e^{iQ.rt_p}: rt_p
+ * the image of grid point p nearest the midpoint (c_i + c_j + R)/2,
+ * phi_i0(rt) = phi_i(p) where rt lies within half a cell of c_i (each
+ * fractional component of rt - c_i in [-1/2, 1/2)), else 0, and phi_jR(rt)
+ * = phi_j(p) where rt - R lies within half a cell of c_j, else 0.  X sums
+ * over S_eps and the tail like V.
+ * q = 0 (iq = 0): gsph[0] must be G = 0 (no other G = 0 in gsph or gtail)
+ * and eps_inv the inverse with head and wings (rp_screen_head).  The G = 0
+ * row and column then enter only through the head term
+ * A eps^-1_00 ntilde_a(0) conj(ntilde_b(0)) (eps^-1_00 -> 1 for V and X),
+ * A = rp_coulomb_cell_average(cell); the wings are dropped.  Elsewhere
+ * |q + G| = 0 is an error (RP_E_RANGE).
+ *
+ * phi (dev) double[nwan][N1][N2][N3], centre_frac (host) double[nwan][3]:
+ *   as rp_wannier_W.
+ * R (host) int[nR][3]: lattice vectors in units of a1, a2, a3.
+ * gsph (host) int[ng][3], gtail (host) int[ntail][3]: as rp_wannier_W.
+ * eps_inv (dev) c128[nfreq][ng][ng].
+ * U, J (dev) c128[nfreq][nR][nwan][nwan]; V, X (dev) c128[nR][nwan][nwan];
+ *   each may be NULL (not computed), not all four.  accumulate = 1 adds the
+ *   term to what they hold.
+ * Device workspace: about (nwan + C)(N_r + ng + ntail) + nfreq ng nwan complex
+ * values, C <= 512 exchange densities at a time (fewer on large grids).
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE, RP_E_UNSUPPORTED (nwan > 32,
+ * nR > 4096, an FFT length), RP_E_NOMEM, RP_E_DEVICE.
+ */
+rp_status rp_wannier_qterm(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nwan,
+                           const double *phi, const double *centre_frac, int nR, const int *R,
+                           int ng, const int *gsph, int ntail, const int *gtail, int nfreq,
+                           const double *eps_inv, int accumulate, double *U, double *J,
+                           double *V, double *X);
+
+/*
+ * A = (N_q Omega/(2 pi)^3) int_cell d^3q/|q|^2, the mean of 1/|q|^2 over the
+ * q-cell {sum_a x_a b_a/K_a : x in [-1/2, 1/2)^3} around Gamma, which replaces
+ * 1/|q|^2 in the q = 0 term of the mesh sums (the treatment of the Coulomb
+ * singularity the paper cites for Eq. rhoiqG).  Host computation only (no
+ * context, no device): six face pyramids, each h int_face dA/|p|^2 by
+ * composite Gauss-Legendre quadrature.
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE (degenerate lattice).
+ */
+rp_status rp_coulomb_cell_average(const rp_cell *cell, double *avg);
+
+/*
  * The q -> 0 head (section "Response function with random phase
  * approximation", Eqs. eps00-cRPA and momentum): for an empty band a and an
  * occupied band b at the same k, the G = 0 pair density tends to

@@ -32,6 +32,8 @@ from ._rp import (  # noqa: F401
     rp_tune_entry,
     rp_synchronize,
     rp_wannier_W,
+    rp_wannier_qterm,
+    rp_coulomb_cell_average,
     rp_weights,
 )
 from .build import build, library_path  # noqa: F401

@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_E_NULL", 2: "RP_E_SHAPE", 3: "RP_E_RANGE", 4:
 
 EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pair_density",
             "rp_weights", "rp_chi0_accumulate", "rp_chi0_batch", "rp_screen_W", "rp_wannier_W",
-            "rp_set_tuning", "rp_head_density", "rp_screen_head", "rp_profile", "rp_profile_read"]
+            "rp_set_tuning", "rp_head_density", "rp_screen_head", "rp_wannier_qterm",
+            "rp_coulomb_cell_average", "rp_profile", "rp_profile_read"]
 
 STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier", "batch"]
 
@@ -104,6 +105,8 @@ def load(path: Optional[str] = None):
         "rp_set_tuning": [P, I, ctypes.POINTER(rp_tune_entry)],
         "rp_head_density": [P, cellp, I, I, P, P, P, P, I, I, I, I, I, I, P, I, I, P],
         "rp_screen_head": [P, cellp, I, P, I, P, P, P, P],
+        "rp_wannier_qterm": [P, cellp, P, I, P, P, I, P, I, P, I, P, I, P, I, P, P, P, P],
+        "rp_coulomb_cell_average": [cellp, ctypes.POINTER(D)],
         "rp_profile": [P, I],
         "rp_profile_read": [P, P, P],
     }
@@ -308,6 +311,32 @@ def rp_wannier_W(ctx: Context, cell: rp_cell, iq, nwan, phi, centre_frac, ng, gs
                               int(ng), _hp(g_h), int(ntail), _hp(t_h), int(nfreq), _dp(eps_inv), _dp(Wij))
     ctx._leave()
     ctx._check(st, "rp_wannier_W")
+
+
+def rp_wannier_qterm(ctx: Context, cell: rp_cell, iq, nwan, phi, centre_frac, R, ng, gsph, ntail, gtail,
+                     nfreq, eps_inv, accumulate, U=None, J=None, V=None, X=None):
+    """One q-point's term of the q-sums of U, J (c128 [nfreq][nR][nwan][nwan]) and
+    V, X (c128 [nR][nwan][nwan]); any output may be None."""
+    iq_h, c_h = _host(iq, np.int32), _host(centre_frac, np.float64)
+    R_h = _host(R, np.int32).reshape(-1, 3)
+    g_h = _host(gsph, np.int32)
+    t_h = _host(gtail, np.int32) if ntail > 0 else None
+    ctx._enter()
+    st = ctx.lib.rp_wannier_qterm(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(nwan), _dp(phi), _hp(c_h),
+                                  int(R_h.shape[0]), _hp(R_h), int(ng), _hp(g_h), int(ntail), _hp(t_h),
+                                  int(nfreq), _dp(eps_inv), int(accumulate), _dp(U), _dp(J), _dp(V), _dp(X))
+    ctx._leave()
+    ctx._check(st, "rp_wannier_qterm")
+
+
+def rp_coulomb_cell_average(cell: rp_cell) -> float:
+    """Mean of 1/|q|^2 over the q-cell around Gamma (host computation; no
+    context or device needed)."""
+    out = ctypes.c_double(0.0)
+    st = load().rp_coulomb_cell_average(ctypes.byref(cell), ctypes.byref(out))
+    if st != 0:
+        raise RpError(st, "rp_coulomb_cell_average", "invalid cell")
+    return out.value
 
 
 def rp_set_tuning(ctx: Context, entries):

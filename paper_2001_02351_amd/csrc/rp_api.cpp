@@ -957,4 +957,175 @@ rp_status rp_wannier_W(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nw
     return check_launch(ctx, "wannier projection");
 }
 
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on the
+// Legendre recurrence, starting from the usual cosine estimates).
+static void gauss_legendre(int n, double *x, double *w)
+{
+    for (int i = 0; i < (n + 1) / 2; i++) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; k++) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Mean of 1/|q|^2 over the q-cell around Gamma: the cell (edges e_a = b_a /
+// K_a, x in [-1/2, 1/2)^3) is cut into six pyramids with apex at Gamma, one
+// per face; with q = t p (p on the face, t in [0, 1]) a pyramid over a face
+// at distance h contributes h int_face dA / |p|^2, integrated by composite
+// Gauss-Legendre quadrature (8 panels x 16 nodes per side).
+static double cell_average(const Geometry &g)
+{
+    constexpr int kNodes = 16, kPanels = 8;
+    double gx[kNodes], gw[kNodes];
+    gauss_legendre(kNodes, gx, gw);
+    double e[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) e[a][b] = g.rec[3 * a + b] / g.kmesh[a];
+    double total = 0.0;
+    for (int a = 0; a < 3; a++) {
+        const double *u = e[(a + 1) % 3], *v = e[(a + 2) % 3];
+        const double n[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+        const double area = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            const double c[3] = {0.5 * sgn * e[a][0], 0.5 * sgn * e[a][1], 0.5 * sgn * e[a][2]};
+            const double h = std::fabs(c[0] * n[0] + c[1] * n[1] + c[2] * n[2]) / area;
+            double face = 0.0;
+            for (int px = 0; px < kPanels; px++)
+                for (int ix = 0; ix < kNodes; ix++) {
+                    const double x = -0.5 + (px + 0.5 * (gx[ix] + 1.0)) / kPanels;
+                    for (int py = 0; py < kPanels; py++)
+                        for (int iy = 0; iy < kNodes; iy++) {
+                            const double y = -0.5 + (py + 0.5 * (gx[iy] + 1.0)) / kPanels;
+                            double p2 = 0.0;
+                            for (int d = 0; d < 3; d++) {
+                                const double pd = c[d] + x * u[d] + y * v[d];
+                                p2 += pd * pd;
+                            }
+                            face += gw[ix] * gw[iy] / p2;
+                        }
+                }
+            // each panel maps [-1, 1] onto a width of 1/kPanels: Jacobian (1/(2 kPanels))^2
+            total += h * area * face / (4.0 * kPanels * kPanels);
+        }
+    }
+    return (double)g.nk * g.volume / std::pow(2.0 * kPi, 3) * total;
+}
+
+rp_status rp_coulomb_cell_average(const rp_cell *cell, double *avg)
+{
+    if (!avg) return RP_E_NULL;
+    const int iq0[3] = {0, 0, 0};
+    Geometry g;
+    const rp_status st = geometry(nullptr, cell, iq0, &g);
+    if (st != RP_OK) return st;
+    *avg = cell_average(g);
+    return RP_OK;
+}
+
+rp_status rp_wannier_qterm(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nwan, const double *phi,
+                           const double *centre_frac, int nR, const int *R, int ng, const int *gsph, int ntail,
+                           const int *gtail, int nfreq, const double *eps_inv, int accumulate, double *U,
+                           double *J, double *V, double *X)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    Geometry g;
+    rp_status st = geometry(ctx, cell, iq, &g);
+    if (st != RP_OK) return st;
+    if (!phi || !centre_frac || !R || !eps_inv) return fail(ctx, RP_E_NULL, "NULL array argument");
+    if (!U && !J && !V && !X) return fail(ctx, RP_E_NULL, "no output requested");
+    if (nwan < 1 || nwan > 32) return fail(ctx, RP_E_UNSUPPORTED, "nwan = %d outside [1, 32]", nwan);
+    if (nR < 1 || nR > 4096) return fail(ctx, RP_E_UNSUPPORTED, "nR = %d outside [1, 4096]", nR);
+    if (ng < 1 || nfreq < 1 || ntail < 0) return fail(ctx, RP_E_SHAPE, "bad ng, ntail or nfreq");
+    if (accumulate != 0 && accumulate != 1) return fail(ctx, RP_E_RANGE, "accumulate must be 0 or 1");
+    const bool head = iq[0] == 0 && iq[1] == 0 && iq[2] == 0;
+    if (!gsph) return fail(ctx, RP_E_NULL, "gsph is NULL");
+    if (head) {
+        if (gsph[0] != 0 || gsph[1] != 0 || gsph[2] != 0)
+            return fail(ctx, RP_E_RANGE, "at q = 0 gsph[0] must be G = 0");
+        if ((st = check_gsph(ctx, g, ng - 1, gsph + 3, "gsph")) != RP_OK) return st;
+    } else if ((st = check_gsph(ctx, g, ng, gsph, "gsph")) != RP_OK) {
+        return st;
+    }
+    if ((st = check_gsph(ctx, g, ntail, gtail, "gtail")) != RP_OK) return st;
+    for (int i = 0; i < 3 * nwan; i++)
+        if (!std::isfinite(centre_frac[i])) return fail(ctx, RP_E_RANGE, "non-finite centre");
+    FftPlan plans[3];
+    if ((st = plans3(ctx, g, plans)) != RP_OK) return st;
+    const long nr = (long)g.fft[0] * g.fft[1] * g.fft[2];
+    const long ldp = (long)ng + ntail;
+    const long nvt = (long)nR * nwan * nwan;
+    // exchange densities per pass: grids of about 512 MB at most
+    const long nvc = std::max(1L, std::min({512L, nvt, (512L << 20) / (nr * (long)sizeof(double2))}));
+    const long nrt = wgemm_row_tiles(ng);
+    // workspace (double2 units):
+    //   grids [max(nvc, nwan)][nr] | PU [nwan][ldp] | PJ [nvc][ldp] | TU [nfreq][ng][nwan]
+    //   | part [nrt][nfreq][nvc] | bodyU [nfreq][nwan^2] | bareU, tailU [nwan^2] | bareJ, tailJ [nvc]
+    const size_t n2 = (size_t)nwan * nwan;
+    const size_t sz[] = {(size_t)std::max<long>(nvc, nwan) * nr, (size_t)nwan * ldp, (size_t)nvc * ldp,
+                         (size_t)nfreq * ng * nwan, (size_t)nrt * nfreq * nvc, (size_t)nfreq * n2, n2, n2,
+                         (size_t)nvc, (size_t)nvc};
+    size_t tot = 0;
+    for (size_t x : sz) tot += x;
+    if ((st = ensure(ctx, ctx->work, sizeof(double2) * tot)) != RP_OK) return st;
+    double2 *bufs[10];
+    bufs[0] = (double2 *)ctx->work.p;
+    for (int b = 1; b < 10; b++) bufs[b] = bufs[b - 1] + sz[b - 1];
+    double2 *grids = bufs[0], *PU = bufs[1], *PJ = bufs[2], *TU = bufs[3], *part = bufs[4], *bodyU = bufs[5];
+    double2 *bareU = bufs[6], *tailU = bufs[7], *bareJ = bufs[8], *tailJ = bufs[9];
+    // host lists: centres | gsph + gtail | R, packed into one upload
+    const size_t hc = sizeof(double) * 3 * nwan, hg = sizeof(int) * 3 * ldp, hr = sizeof(int) * 3 * nR;
+    std::vector<char> host(hc + hg + hr);
+    std::memcpy(host.data(), centre_frac, hc);
+    std::memcpy(host.data() + hc, gsph, sizeof(int) * 3 * ng);
+    if (ntail) std::memcpy(host.data() + hc + sizeof(int) * 3 * ng, gtail, sizeof(int) * 3 * ntail);
+    std::memcpy(host.data() + hc + hg, R, hr);
+    if ((st = upload(ctx, ctx->kinfo, host.data(), host.size())) != RP_OK) return st;
+    const double *dcen = (const double *)ctx->kinfo.p;
+    const int *dgl = (const int *)((const char *)ctx->kinfo.p + hc);
+    const int *dR = (const int *)((const char *)ctx->kinfo.p + hc + hg);
+    const double pre = kHartreeEv * 4.0 * kPi / (g.volume * g.nk);
+    const double avg = head ? cell_average(g) : 0.0;
+    const int klo = head ? 1 : 0;
+    const double2 *E = (const double2 *)eps_inv;
+    hipStream_t s = ctx->stream;
+    StageTimer t(ctx, RP_STAGE_WANNIER);
+    if (U || V) {
+        launch_wannier_density(s, g, plans, nwan, phi, dcen, grids);
+        launch_wannier_gather(s, g, nwan, (int)ldp, dgl, grids, PU, ctx->flag, head);
+        if (U) {
+            launch_wgemm(s, false, nfreq, ng, klo, nwan, PU, ldp, E, TU);
+            launch_wcross(s, nfreq, nwan, ng, klo, PU, ldp, TU, bodyU);
+        }
+        launch_wgram(s, (int)n2, nwan, false, ng, klo, ntail, PU, ldp, bareU, tailU);
+        launch_wsum_u(s, g, nfreq, nR, nwan, ng, dR, pre, head, avg, E, PU, ldp, bodyU, bareU, tailU, accumulate,
+                      (double2 *)U, (double2 *)V);
+    }
+    if (J || X) {
+        for (long v0 = 0; v0 < nvt; v0 += nvc) {
+            const int n = (int)std::min(nvc, nvt - v0);
+            launch_xdens(s, g, plans, nwan, phi, dcen, dR, v0, n, grids);
+            launch_wannier_gather(s, g, n, (int)ldp, dgl, grids, PJ, ctx->flag, head);
+            if (J) launch_wgemm(s, true, nfreq, ng, klo, n, PJ, ldp, E, part);
+            launch_wgram(s, n, 0, true, ng, klo, ntail, PJ, ldp, bareJ, tailJ);
+            launch_wsum_x(s, nfreq, nvt, v0, n, ng, pre, head, avg, E, PJ, ldp, part, bareJ, tailJ, accumulate,
+                          (double2 *)J, (double2 *)X);
+        }
+    }
+    return check_launch(ctx, "wannier q-term");
+}
+
 }  // extern "C"

@@ -180,10 +180,30 @@ void launch_optics(hipStream_t s, int nfreq, int ng, const double2 *einv, const 
 // wannier.hip
 void launch_wannier_density(hipStream_t s, const Geometry &g, const FftPlan plans[3], int nwan,
                             const double *phi, const double *centre_frac_dev, double2 *f);
+// zero_ok: where q + G = 0 store ntilde(0) instead of flagging the division
 void launch_wannier_gather(hipStream_t s, const Geometry &g, int nwan, int nlist,
-                           const int *glist, const double2 *fgrid, double2 *rho, int *flag);
+                           const int *glist, const double2 *fgrid, double2 *rho, int *flag,
+                           bool zero_ok = false);
 void launch_wannier_W(hipStream_t s, int nfreq, int nwan, int ng, const double2 *rho_eps,
                       int ntail, const double2 *rho_tail, const double2 *einv, double pre,
                       double2 *T, double2 *Wij);
+
+// qsum.hip: one q-point's term of the q-sums of U, V, J, X
+void launch_xdens(hipStream_t s, const Geometry &g, const FftPlan plans[3], int nwan, const double *phi,
+                  const double *centre_dev, const int *R_dev, long v0, int nvc, double2 *grids);
+int wgemm_row_tiles(int ng);
+void launch_wgemm(hipStream_t s, bool diag, int nfreq, int ng, int klo, int nv, const double2 *P, long ldp,
+                  const double2 *E, double2 *out);
+void launch_wcross(hipStream_t s, int nfreq, int nwan, int ng, int klo, const double2 *P, long ldp,
+                   const double2 *T, double2 *body);
+void launch_wgram(hipStream_t s, int nout, int nb, bool diag, int ng, int klo, int ntail, const double2 *P,
+                  long ldp, double2 *bare, double2 *tail);
+void launch_wsum_u(hipStream_t s, const Geometry &g, int nfreq, int nR, int nwan, int ng, const int *R_dev,
+                   double pre, bool head, double avg, const double2 *E, const double2 *P, long ldp,
+                   const double2 *body, const double2 *bare, const double2 *tail, int accumulate, double2 *U,
+                   double2 *V);
+void launch_wsum_x(hipStream_t s, int nfreq, long nvt, long v0, int nvc, int ng, double pre, bool head, double avg,
+                   const double2 *E, const double2 *P, long ldp, const double2 *part, const double2 *bare,
+                   const double2 *tail, int accumulate, double2 *J, double2 *X);
 
 }  // namespace rp

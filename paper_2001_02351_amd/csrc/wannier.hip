@@ -39,7 +39,7 @@ __global__ void k_wdens(int nwan, int N1, int N2, int N3, const double *phi, con
 __global__ void k_wgather(int nwan, int N1, int N2, int N3, int nlist, const int *g, double r0,
                           double r1, double r2, double r3, double r4, double r5, double r6, double r7,
                           double r8, double q1, double q2, double q3, double scale, const double2 *fg,
-                          double2 *rho, int *flag)
+                          double2 *rho, int *flag, int zero_ok)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long)nlist * nwan) return;
@@ -50,10 +50,16 @@ __global__ void k_wgather(int nwan, int N1, int N2, int N3, int nlist, const int
     const double y = f1 * r1 + f2 * r4 + f3 * r7;
     const double z = f1 * r2 + f2 * r5 + f3 * r8;
     const double qg = sqrt(x * x + y * y + z * z);
-    if (!(qg > 0.0)) atomicOr(flag, kFlagNonFinite);
     const long nr = (long)N1 * N2 * N3;
     const double2 v = fg[(long)i * nr + ((long)pmod(m1, N1) * N2 + pmod(m2, N2)) * N3 + pmod(m3, N3)];
-    rho[t] = cscale(v, scale / qg);
+    if (qg > 0.0) {
+        rho[t] = cscale(v, scale / qg);
+    } else if (zero_ok) {
+        rho[t] = cscale(v, scale);   // q + G = 0: ntilde(0) itself
+    } else {
+        atomicOr(flag, kFlagNonFinite);
+        rho[t] = cscale(v, scale / qg);
+    }
 }
 
 // T[f][G][j] = sum_G' eps^-1[f][G][G'] conj(rho_j(G')); one block per (G, f)
@@ -114,7 +120,7 @@ void launch_wannier_density(hipStream_t s, const Geometry &g, const FftPlan plan
 }
 
 void launch_wannier_gather(hipStream_t s, const Geometry &g, int nwan, int nlist, const int *glist,
-                           const double2 *fgrid, double2 *rho, int *flag)
+                           const double2 *fgrid, double2 *rho, int *flag, bool zero_ok)
 {
     const long tot = (long)nlist * nwan;
     if (tot == 0) return;
@@ -122,7 +128,8 @@ void launch_wannier_gather(hipStream_t s, const Geometry &g, int nwan, int nlist
     hipLaunchKernelGGL(k_wgather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nwan, g.fft[0],
                        g.fft[1], g.fft[2], nlist, glist, g.rec[0], g.rec[1], g.rec[2], g.rec[3], g.rec[4],
                        g.rec[5], g.rec[6], g.rec[7], g.rec[8], (double)g.iq[0] / g.kmesh[0],
-                       (double)g.iq[1] / g.kmesh[1], (double)g.iq[2] / g.kmesh[2], scale, fgrid, rho, flag);
+                       (double)g.iq[1] / g.kmesh[1], (double)g.iq[2] / g.kmesh[2], scale, fgrid, rho, flag,
+                       (int)zero_ok);
 }
 
 void launch_wannier_W(hipStream_t s, int nfreq, int nwan, int ng, const double2 *rho_eps, int ntail,

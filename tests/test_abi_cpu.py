@@ -110,3 +110,18 @@ def test_product_does_not_import_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "liboracle" not in txt, f
+
+
+def test_cell_average_host_routine_matches_the_oracle():
+    """rp_coulomb_cell_average is host code (no device): the library's
+    composite Gauss-Legendre value against the oracle's adaptive quadrature,
+    cubic and triclinic cells, and the error path for a degenerate cell."""
+    import paper_2001_02351_amd as rp
+    from oracle import qsum
+    for lat, kmesh in ((np.eye(3) * 7.26, (8, 8, 8)), (np.eye(3) * 5.0, (2, 3, 4)),
+                       (np.array([[6.0, 0.8, 0.0], [0.5, 7.0, 0.0], [0.3, -0.4, 6.5]]), (3, 2, 4))):
+        got = rp.rp_coulomb_cell_average(rp.make_cell(lat, (8, 8, 8), kmesh))
+        want = qsum.cell_average(lat, kmesh)
+        assert abs(got - want) < 1e-12 * want, (kmesh, got, want)
+    with pytest.raises(rp.RpError):
+        rp.rp_coulomb_cell_average(rp.make_cell(np.zeros((3, 3)), (8, 8, 8), (2, 2, 2)))
