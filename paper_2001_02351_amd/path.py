@@ -39,6 +39,16 @@ class DeviceInputs:
         self.nfreq = int(len(prob.freq_eV))
         self.device = dev
 
+    def at_q(self, prob_q) -> "DeviceInputs":
+        """A view for another q-point of the same system (prob_q: the same
+        band data with that q's iq and G lists); the device arrays are
+        shared, nothing is copied."""
+        import copy
+        v = copy.copy(self)
+        v.prob = prob_q
+        v.ng = int(prob_q.gsph.shape[0])
+        return v
+
 
 def weight_mode(prob) -> int:
     return _rp.RP_W_SAMPLING if int(np.prod(prob.kmesh)) == 1 else _rp.RP_W_TETRA
@@ -172,6 +182,46 @@ def wannier(ctx, d: DeviceInputs, eps_inv):
     _rp.rp_wannier_W(ctx, d.cell, p.iq, nwan, d.phi, p.centre_frac, d.ng, p.gsph, int(gt.shape[0]), gt,
                      d.nfreq, eps_inv, Wij)
     return Wij
+
+
+def qterm(ctx, d: DeviceInputs, eps_inv, glist, R, out: dict, accumulate: int):
+    """Adds this q-point's term of the q-sums of U, J, V, X into out
+    (device tensors, any subset of the keys); glist indexes eps_inv (G = 0
+    first at q = 0)."""
+    p = d.prob
+    gt = p.gtail if p.gtail is not None else np.zeros((0, 3), np.int32)
+    _rp.rp_wannier_qterm(ctx, d.cell, p.iq, int(p.phi.shape[0]), d.phi, p.centre_frac, R, int(len(glist)), glist,
+                         int(gt.shape[0]), gt, d.nfreq, eps_inv, accumulate, **out)
+
+
+def interaction(ctx, d: DeviceInputs, R, problem_at, prec: int = _rp.RP_FP64, kbatch: int = 1,
+                qhat=(1.0, 0.0, 0.0), want=("U", "J", "V", "X")):
+    """U, J (complex [nfreq][nR][nwan][nwan]) and V, X ([nR][nwan][nwan]) of
+    Eqs. matrix_U, matrix_J, matrix_V, matrix_X summed over the whole q mesh:
+    at every q chi0, eps^-1 and that q's term; at q = 0 through the head
+    path (G = 0 first, head density along qhat, eps^-1 with head and wings).
+    problem_at(iq) gives the system at q = iq/K (same band data, that q's G
+    lists; at q = 0 without G = 0).  Returns device tensors."""
+    import torch
+    p = d.prob
+    R = np.ascontiguousarray(np.asarray(R, np.int32).reshape(-1, 3))
+    nw = int(p.phi.shape[0])
+    shapes = dict(U=(d.nfreq, len(R), nw, nw, 2), J=(d.nfreq, len(R), nw, nw, 2), V=(len(R), nw, nw, 2),
+                  X=(len(R), nw, nw, 2))
+    out = {k: torch.empty(shapes[k], dtype=torch.float64, device=d.device) for k in want}
+    first = True
+    for iq in np.ndindex(*p.kmesh):
+        dq = d.at_q(problem_at(iq))
+        if iq == (0, 0, 0):
+            chi, glist = chi0_head(ctx, dq, qhat, prec=prec, kbatch=kbatch)
+            einv, _ = screen_head(ctx, dq, chi, glist)
+        else:
+            chi = chi0(ctx, dq, prec=prec, kbatch=kbatch)
+            einv, _ = screen(ctx, dq, chi, want_W=False)
+            glist = dq.prob.gsph
+        qterm(ctx, dq, einv, glist, R, out, 0 if first else 1)
+        first = False
+    return out
 
 
 def run_q(ctx, d: DeviceInputs, prec: int = _rp.RP_FP64, kbatch: int = 1):

@@ -12,7 +12,9 @@ from .gen import (  # noqa: F401
     BOHR_ANGSTROM,
     HARTREE_EV,
     Problem,
+    at_qpoint,
     make_problem,
+    qpoint_gvectors,
     mesh_fractions,
     batch_system,
     batch_system_qpoints,

@@ -25,7 +25,7 @@ from __future__ import annotations
 import math
 import os
 from concurrent.futures import ProcessPoolExecutor
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 from typing import Optional
 
 import numpy as np
@@ -203,6 +203,32 @@ def gaussian_orbitals(lat: np.ndarray, fft, centre_frac: np.ndarray,
     return out
 
 
+def qpoint_gvectors(lat, kmesh, iq, ng: int, gpsi: float):
+    """(gsph, gtail) for q = iq/K: S_eps the first ng Miller indices by |q+G|
+    (ties by (m1, m2, m3)), the tail those with |q+G| <= gpsi outside it.  At
+    q = 0 the G = 0 vector has no Coulomb factor and is left out of both
+    (S_eps then holds the ng shortest nonzero G)."""
+    recip = 2.0 * math.pi * np.linalg.inv(np.asarray(lat, np.float64)).T
+    qf = np.array(iq, dtype=np.float64) / np.array(kmesh, dtype=np.float64)
+    gsph = _sphere(recip, qf, None, count=ng)
+    full = _sphere(recip, qf, gpsi)
+    in_eps = {tuple(m) for m in gsph.tolist()}
+    gtail = np.array([m for m in full.tolist() if tuple(m) not in in_eps],
+                     dtype=np.int32).reshape(-1, 3)
+    if tuple(iq) == (0, 0, 0):
+        gsph = _sphere(recip, qf, None, count=ng + 1)[1:]
+        gtail = gtail[np.any(gtail != 0, axis=1)]
+    return gsph, np.ascontiguousarray(gtail)
+
+
+def at_qpoint(prob: "Problem", iq) -> "Problem":
+    """The same system at another q-point of its mesh: the band data are
+    shared, the G lists are those of q = iq/K (same N_G and wave-function
+    cutoff)."""
+    gsph, gtail = qpoint_gvectors(prob.lat, prob.kmesh, iq, int(prob.gsph.shape[0]), prob.gpsi)
+    return replace(prob, iq=tuple(int(x) for x in iq), gsph=gsph, gtail=gtail)
+
+
 def make_problem(*, name: str, a_bohr: float, fft, kmesh, iq, nocc: int, nemp: int,
                  gpsi: float, ng: int, freq_eV, delta_eV: float,
                  occ_window=(-8.0, -1.0), emp_window=(1.0, 20.0),
@@ -234,16 +260,7 @@ def make_problem(*, name: str, a_bohr: float, fft, kmesh, iq, nocc: int, nemp: i
         energy[i, :nocc] = np.sort(rng_e.uniform(*occ_window, nocc))
         energy[i, nocc:] = np.sort(rng_e.uniform(*emp_window, nemp))
 
-    qf = np.array(iq, dtype=np.float64) / np.array(kmesh, dtype=np.float64)
-    gsph = _sphere(recip, qf, None, count=ng)
-    full = _sphere(recip, qf, gpsi)
-    in_eps = {tuple(m) for m in gsph.tolist()}
-    gtail = np.array([m for m in full.tolist() if tuple(m) not in in_eps],
-                     dtype=np.int32).reshape(-1, 3)
-    if tuple(iq) == (0, 0, 0):
-        # |q+G| = 0 has no Coulomb factor; the G=0 row is dropped at q=0
-        gsph = _sphere(recip, qf, None, count=ng + 1)[1:]
-        gtail = gtail[np.any(gtail != 0, axis=1)]
+    gsph, gtail = qpoint_gvectors(lat, kmesh, iq, ng, gpsi)
 
     rng_w = np.random.default_rng(wan_ss)
     T = None

@@ -9,6 +9,7 @@ exchange densities in several passes and with accumulation over q."""
 import numpy as np
 import pytest
 
+import oracle
 from oracle import qsum
 from synth.gen import gaussian_orbitals
 
@@ -166,3 +167,50 @@ def test_qterm_rejects_bad_arguments(rp, ctx):
         rp.rp_wannier_qterm(ctx, cell, (0, 0, 0), nw, phi, c["cen"], c["R"], ng, gl[:ng], 0, None, nf, E, 2, U=U)
     assert e.value.status == 3
     rp.rp_synchronize(ctx)
+
+
+def test_full_qmesh_sum_matches_oracle(rp, ctx):
+    """U, J, V, X summed over a 2x2x2 q mesh through the whole FP64 path
+    (pair densities, weights, chi0, eps^-1 with the head at Gamma, the
+    q-terms) against the oracle's chain, to 1e-10."""
+    import copy
+
+    from oracle import head as ohead
+    from paper_2001_02351_amd import path
+    from synth import at_qpoint, make_problem
+    p = make_problem(name="qmesh", a_bohr=7.26, fft=(16, 16, 16), kmesh=(2, 2, 2), iq=(0, 0, 0), nocc=4,
+                     nemp=10, gpsi=2.4, ng=30, freq_eV=np.array([0.0, 6.0]), delta_eV=0.1, nwan=2,
+                     alpha_range=(0.8, 1.2), seed=41)
+    R = np.array([[0, 0, 0], [1, 0, 0], [0, -1, 0]], np.int32)
+    qhat = (1.0, 0.0, 0.0)
+    d = path.DeviceInputs(p)
+    got = path.interaction(ctx, d, R, lambda iq: at_qpoint(p, iq), prec=rp.RP_FP64, kbatch=4, qhat=qhat)
+    rp.rp_synchronize(ctx)
+    A = qsum.cell_average(p.lat, p.kmesh)
+    want = None
+    for iq in np.ndindex(*p.kmesh):
+        pq = at_qpoint(p, iq)
+        if iq == (0, 0, 0):
+            gl = np.concatenate([np.zeros((1, 3), np.int32), pq.gsph]).astype(np.int32)
+            q = copy.copy(pq)
+            q.gsph = gl
+            M = oracle.pair_densities(q, 0, p.nocc, p.nocc, p.nband, 0, p.nk)
+            M[:, 0] = ohead.head_density(pq, 0, p.nocc, p.nocc, p.nband, 0, p.nk, qhat)
+            w = oracle.prob_weights(pq, 0, p.nocc, p.nocc, p.nband, 0, p.nk)
+            _, einv = ohead.screen_head(p.lat, gl, oracle.chi0(M, w), oracle.invert)
+        else:
+            gl = pq.gsph
+            einv = oracle.run_path(pq)["eps_inv"]
+        allg = np.concatenate([gl, pq.gtail])
+        n_u = np.stack([qsum.exchange_ntilde(p.lat, p.fft, p.kmesh, iq, p.phi, p.centre_frac, [[0, 0, 0]],
+                                             allg)[0, i, i] for i in range(2)])
+        n_x = qsum.exchange_ntilde(p.lat, p.fft, p.kmesh, iq, p.phi, p.centre_frac, R, allg)
+        t = qsum.qterm(p.lat, p.kmesh, iq, n_u, n_x, len(gl), einv, R, allg,
+                       head_avg=A if iq == (0, 0, 0) else None)
+        want = t if want is None else {k: want[k] + t[k] for k in t}
+    _check(got, want, "2x2x2 q mesh")
+    # static screening lowers the on-site direct term below the bare one
+    U = _c(got["U"])
+    V = _c(got["V"])
+    for i in range(2):
+        assert U[0, 0, i, i].real < V[0, i, i].real
