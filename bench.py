@@ -504,6 +504,41 @@ def tune_leg(args):
     print(json.dumps({"tuning_table": args.tune, "entries": table["entries"]}), flush=True)
 
 
+def qterm_leg(rp, path, ctx, d, eps_inv, reps: int = 3):
+    """One q-point's term of the q-sums of U, J, V, X on the workload's
+    orbitals and its eps^-1 (split leg), for the 27 cells R in {-1, 0, 1}^3:
+    27 x nwan^2 exchange densities; the FP64 matrix-core quadratic forms take
+    8 N_G^2 (exchange densities + nwan) N_w flop."""
+    import itertools
+
+    import numpy as np
+    import torch
+    p = d.prob
+    nw = int(p.phi.shape[0])
+    R = np.array(list(itertools.product((-1, 0, 1), repeat=3)), np.int32)
+    out = dict(U=torch.empty((d.nfreq, len(R), nw, nw, 2), dtype=torch.float64, device=d.device),
+               J=torch.empty((d.nfreq, len(R), nw, nw, 2), dtype=torch.float64, device=d.device),
+               V=torch.empty((len(R), nw, nw, 2), dtype=torch.float64, device=d.device),
+               X=torch.empty((len(R), nw, nw, 2), dtype=torch.float64, device=d.device))
+    path.qterm(ctx, d, eps_inv, p.gsph, R, out, 0)
+    rp.rp_synchronize(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        path.qterm(ctx, d, eps_inv, p.gsph, R, out, 0)
+    rp.rp_synchronize(ctx)
+    t = (time.perf_counter() - t0) / reps
+    nv = len(R) * nw * nw
+    flops = 8.0 * d.ng ** 2 * (nv + nw) * d.nfreq
+    log(f"interaction q-term: {t * 1e3:.1f} ms per q-point ({nv} exchange densities)")
+    U = torch.view_as_complex(out["U"])
+    V = torch.view_as_complex(out["V"])
+    return {"nR": len(R), "nwan": nw, "exchange_densities": nv, "ng": d.ng, "ntail": int(p.gtail.shape[0]),
+            "nfreq": d.nfreq, "ms_per_qpoint": t * 1e3, "matrix_core_flop": flops,
+            "tflops_whole_call": flops / t / 1e12, "fp64_peak_tflops": PEAK_FP64_TFLOPS,
+            "U_00_w0_over_V_00": float((U[0, 13, 0, 0] / V[13, 0, 0]).real)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -515,6 +550,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-x6", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-qterm", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--profile-k", type=int, default=0)
     ap.add_argument("--batch", action="store_true")
@@ -605,6 +641,7 @@ def main():
             "eps_inv": rel(einv_s, einv_d),
             "W_ij_max_elementwise": float((torch.abs(torch.view_as_complex(wij_s) - wd) / torch.abs(wd)).max()),
         }
+    qterm = None if args.no_qterm else qterm_leg(rp, path, ctx, d, einv_s)
     ctx.close()
 
     npair_total = d.nk * prob.nocc * prob.nemp
@@ -667,6 +704,7 @@ def main():
             PEAK_BF16_TFLOPS,
         },
         "hbm_a2_a4": hbm,
+        "interaction_qterm": qterm,
         "cpu_baseline": None if baseline is None else {k: baseline[k] for k in
                                                         ("value", "unit", "cores", "cpu_model", "kind",
                                                          "sample")},
