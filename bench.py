@@ -504,7 +504,34 @@ def tune_leg(args):
     print(json.dumps({"tuning_table": args.tune, "entries": table["entries"]}), flush=True)
 
 
-def qterm_leg(rp, path, ctx, d, eps_inv, reps: int = 3):
+def qterm_cpu_baseline(prob, eps_inv_host) -> dict:
+    """The oracle's q-term (oracle/qsum.py, as it stands) on a bounded
+    sample of the same workload: the home cell R = 0 only (nwan^2 of the
+    27 nwan^2 exchange densities, plus the direct densities), all 20
+    frequencies; scaled to the 27 cells by the density count."""
+    import numpy as np
+
+    import oracle
+    from oracle import qsum
+    nw = int(prob.phi.shape[0])
+    allg = np.concatenate([prob.gsph, prob.gtail])
+    R0 = np.zeros((1, 3), np.int32)
+    t0 = time.perf_counter()
+    n_u = np.stack([qsum.exchange_ntilde(prob.lat, prob.fft, prob.kmesh, prob.iq, prob.phi, prob.centre_frac, R0,
+                                         allg)[0, i, i] for i in range(nw)])
+    t_u = time.perf_counter() - t0
+    n_x = qsum.exchange_ntilde(prob.lat, prob.fft, prob.kmesh, prob.iq, prob.phi, prob.centre_frac, R0, allg)
+    qsum.qterm(prob.lat, prob.kmesh, prob.iq, n_u, n_x, int(prob.gsph.shape[0]), eps_inv_host, R0, allg)
+    t = time.perf_counter() - t0
+    per_density = (t - t_u) / (nw * nw)
+    scaled = t_u + per_density * 27 * nw * nw
+    return {"value": scaled * 1e3, "unit": "ms per q-point term (27 cells, scaled)", "cores": oracle.threads_used(),
+            "cpu_model": _cpu_model(), "kind": "oracle",
+            "sample": f"R = 0 only: {nw} direct + {nw * nw} exchange densities, {len(prob.freq_eV)} frequencies, "
+                      f"{t:.1f} s; scaled by the exchange-density count to 27 cells"}
+
+
+def qterm_leg(rp, path, ctx, d, eps_inv, reps: int = 3, cpu: bool = False):
     """One q-point's term of the q-sums of U, J, V, X on the workload's
     orbitals and its eps^-1 (split leg), for the 27 cells R in {-1, 0, 1}^3:
     27 x nwan^2 exchange densities; the FP64 matrix-core quadratic forms take
@@ -533,10 +560,15 @@ def qterm_leg(rp, path, ctx, d, eps_inv, reps: int = 3):
     log(f"interaction q-term: {t * 1e3:.1f} ms per q-point ({nv} exchange densities)")
     U = torch.view_as_complex(out["U"])
     V = torch.view_as_complex(out["V"])
-    return {"nR": len(R), "nwan": nw, "exchange_densities": nv, "ng": d.ng, "ntail": int(p.gtail.shape[0]),
-            "nfreq": d.nfreq, "ms_per_qpoint": t * 1e3, "matrix_core_flop": flops,
-            "tflops_whole_call": flops / t / 1e12, "fp64_peak_tflops": PEAK_FP64_TFLOPS,
-            "U_00_w0_over_V_00": float((U[0, 13, 0, 0] / V[13, 0, 0]).real)}
+    res = {"nR": len(R), "nwan": nw, "exchange_densities": nv, "ng": d.ng, "ntail": int(p.gtail.shape[0]),
+           "nfreq": d.nfreq, "ms_per_qpoint": t * 1e3, "matrix_core_flop": flops,
+           "tflops_whole_call": flops / t / 1e12, "fp64_peak_tflops": PEAK_FP64_TFLOPS,
+           "U_00_w0_over_V_00": float((U[0, 13, 0, 0] / V[13, 0, 0]).real), "cpu_baseline": None}
+    if cpu:
+        log("timing the oracle's q-term on a bounded sample (host cores)")
+        res["cpu_baseline"] = qterm_cpu_baseline(p, path.to_complex(eps_inv))
+        log(f"oracle q-term sample: {res['cpu_baseline']['sample']}")
+    return res
 
 
 def main():
@@ -641,7 +673,8 @@ def main():
             "eps_inv": rel(einv_s, einv_d),
             "W_ij_max_elementwise": float((torch.abs(torch.view_as_complex(wij_s) - wd) / torch.abs(wd)).max()),
         }
-    qterm = None if args.no_qterm else qterm_leg(rp, path, ctx, d, einv_s)
+    qterm = None if args.no_qterm else qterm_leg(rp, path, ctx, d, einv_s,
+                                                 cpu=not args.no_cpu_baseline and not args.profile_k)
     ctx.close()
 
     npair_total = d.nk * prob.nocc * prob.nemp

@@ -172,7 +172,10 @@ def qterm(lat, kmesh, iq, n_u, n_x, ng, eps_inv, R, glist, head_avg=None) -> dic
     for f in range(nf):
         body_u = re @ E[f] @ re.conj().T
         sw_u = body_u + tail_u + E[f][0, 0] * hu
-        body_x = np.einsum("rijg,gh,rijh->rij", xe, E[f], xe.conj())
+        # sum_{G,G'} rho_v(G) eps^-1_GG' conj(rho_v(G')) for every v, as one
+        # matrix product over G' and a sum over G
+        xv = xe.reshape(-1, ng)
+        body_x = np.sum(xv.T * (E[f] @ xv.conj().T), axis=0).reshape(xe.shape[:3])
         sw_x = body_x + tail_x + E[f][0, 0] * hx
         for r in range(len(R)):
             U[f, r] = phase[r] * pre * sw_u
