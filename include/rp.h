@@ -320,6 +320,22 @@ rp_status rp_wannier_qterm(rp_ctx *ctx, const rp_cell *cell, const int iq[3], in
 rp_status rp_coulomb_cell_average(const rp_cell *cell, double *avg);
 
 /*
+ * The logarithmic frequency grid of the polarization function (section
+ * "Frequency grid", Eq. grid), host computation only (no context):
+ *   omega_i = (dw/(s-1)) (s^(i-1) - 1)                       i = 1 .. nmax
+ *   omega_i = emax 3^((i - nmax)/(nomega - nmax))             i = nmax+1 .. nomega
+ * with s fixed by omega_nmax = emax, i.e. s^(nmax-1) - (emax/dw)(s - 1) = 1
+ * (the sign the boundary condition requires), s != 1; so omega_1 = 0,
+ * omega_2 = dw, omega_nmax = emax and omega_nomega = 3 emax.  The paper's
+ * defaults: nomega = 70, nmax = 9 nomega/10 (pass nmax = 0), dw = 0.05 eV,
+ * emax = max E - min E over the bands.
+ * omega_eV (host) double[nomega] output.
+ * Errors: RP_E_NULL; RP_E_SHAPE (nomega < 3, nmax outside [2, nomega));
+ * RP_E_RANGE (dw <= 0, emax <= dw, non-finite).
+ */
+rp_status rp_frequency_grid(double emax_eV, double dw_eV, int nomega, int nmax, double *omega_eV);
+
+/*
  * The q -> 0 head (section "Response function with random phase
  * approximation", Eqs. eps00-cRPA and momentum): for an empty band a and an
  * occupied band b at the same k, the G = 0 pair density tends to

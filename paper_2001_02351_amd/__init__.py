@@ -34,6 +34,7 @@ from ._rp import (  # noqa: F401
     rp_wannier_W,
     rp_wannier_qterm,
     rp_coulomb_cell_average,
+    rp_frequency_grid,
     rp_weights,
 )
 from .build import build, library_path  # noqa: F401

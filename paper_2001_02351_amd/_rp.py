@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_E_NULL", 2: "RP_E_SHAPE", 3: "RP_E_RANGE", 4:
 EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pair_density",
             "rp_weights", "rp_chi0_accumulate", "rp_chi0_batch", "rp_screen_W", "rp_wannier_W",
             "rp_set_tuning", "rp_head_density", "rp_screen_head", "rp_wannier_qterm",
-            "rp_coulomb_cell_average", "rp_profile", "rp_profile_read"]
+            "rp_coulomb_cell_average", "rp_frequency_grid", "rp_profile", "rp_profile_read"]
 
 STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier", "batch"]
 
@@ -107,6 +107,7 @@ def load(path: Optional[str] = None):
         "rp_screen_head": [P, cellp, I, P, I, P, P, P, P],
         "rp_wannier_qterm": [P, cellp, P, I, P, P, I, P, I, P, I, P, I, P, I, P, P, P, P],
         "rp_coulomb_cell_average": [cellp, ctypes.POINTER(D)],
+        "rp_frequency_grid": [D, D, I, I, P],
         "rp_profile": [P, I],
         "rp_profile_read": [P, P, P],
     }
@@ -337,6 +338,16 @@ def rp_coulomb_cell_average(cell: rp_cell) -> float:
     if st != 0:
         raise RpError(st, "rp_coulomb_cell_average", "invalid cell")
     return out.value
+
+
+def rp_frequency_grid(emax_eV: float, dw_eV: float = 0.05, nomega: int = 70, nmax: int = 0) -> np.ndarray:
+    """The logarithmic frequency grid (eV), host computation; nmax = 0 takes
+    9 nomega / 10."""
+    out = np.zeros(max(0, int(nomega)), np.float64)
+    st = load().rp_frequency_grid(float(emax_eV), float(dw_eV), int(nomega), int(nmax), _hp(out) if out.size else None)
+    if st != 0:
+        raise RpError(st, "rp_frequency_grid", "invalid grid parameters")
+    return out
 
 
 def rp_set_tuning(ctx: Context, entries):

@@ -1024,6 +1024,47 @@ static double cell_average(const Geometry &g)
     return (double)g.nk * g.volume / std::pow(2.0 * kPi, 3) * total;
 }
 
+// Eq. grid.  The first branch is omega_i = dw (1 + s + ... + s^(i-2)); the
+// condition omega_{N_max} = E_max makes s the root of
+// g(s) = 1 + s + ... + s^(N_max-2) - E_max/dw, increasing on s > 0 with
+// g(0) = 1 - E_max/dw < 0, found by bisection.  The second branch is
+// E_max 3^((i - N_max)/(N_Omega - N_max)).
+rp_status rp_frequency_grid(double emax_eV, double dw_eV, int nomega, int nmax, double *omega_eV)
+{
+    if (!omega_eV) return RP_E_NULL;
+    if (nomega < 3) return RP_E_SHAPE;
+    if (nmax == 0) nmax = 9 * nomega / 10;
+    if (nmax < 2 || nmax >= nomega) return RP_E_SHAPE;
+    if (!(dw_eV > 0.0) || !(emax_eV > dw_eV) || !std::isfinite(emax_eV)) return RP_E_RANGE;
+    const double r = emax_eV / dw_eV;
+    auto g = [&](double x) {
+        double sum = 0.0, p = 1.0;
+        for (int j = 0; j <= nmax - 2; j++) {
+            sum += p;
+            p *= x;
+        }
+        return sum - r;
+    };
+    double lo = 0.0, hi = 2.0;
+    while (g(hi) <= 0.0) hi *= 2.0;
+    for (int it = 0; it < 200 && hi - lo > 0.0; it++) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        (g(mid) < 0.0 ? lo : hi) = mid;
+    }
+    const double sr = 0.5 * (lo + hi);
+    double sum = 0.0, p = 1.0;
+    omega_eV[0] = 0.0;
+    for (int i = 2; i <= nmax; i++) {
+        sum += p;
+        p *= sr;
+        omega_eV[i - 1] = dw_eV * sum;
+    }
+    for (int i = nmax + 1; i <= nomega; i++)
+        omega_eV[i - 1] = emax_eV * std::exp(std::log(3.0) * (double)(i - nmax) / (double)(nomega - nmax));
+    return RP_OK;
+}
+
 rp_status rp_coulomb_cell_average(const rp_cell *cell, double *avg)
 {
     if (!avg) return RP_E_NULL;
