@@ -16,6 +16,8 @@ marshals numpy arrays and strings the steps together in the paper's order:
                                                eels, optical-conductivity, reflectance
   q-mesh sums of U, V, J, X (oracle.qsum)      Eqs. W, Wq, matrix_U, rhoiqG, matrix_V,
                                                matrix_J, matrix_X
+  frequency grid (oracle.grid)                 Eq. grid
+  symmetry unfolding (oracle.symmetry)         Eqs. red-wavefunction, coef-G, symeps
 
 Parity status of each function is listed in its docstring.
 """

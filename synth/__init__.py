@@ -22,3 +22,5 @@ from .gen import (  # noqa: F401
     srvo3_workload,
     supercell_workload,
 )
+
+from .symmetric import screw_ops, star_table, symmetric_problem  # noqa: F401,E402
