@@ -336,6 +336,47 @@ rp_status rp_coulomb_cell_average(const rp_cell *cell, double *avg);
 rp_status rp_frequency_grid(double emax_eV, double dw_eV, int nomega, int nmax, double *omega_eV);
 
 /*
+ * Symmetry unfolding of plane-wave coefficients (section "Symmetry", Eqs.
+ * red-wavefunction, k-and-kirr, G-and-Girr, coef-G).  The operation maps
+ * fractional real-space coordinates x -> W x + t (W: integer, row-major,
+ * det +-1; t: fractional translation); on fractional reciprocal coordinates
+ * it acts as S = W^{-T}.  For k = S k* + Delta (k, k* given by mesh indices;
+ * Delta, the rewind vector, must come out integral):
+ *   C_G(k) = C_{S^{-1}(G + Delta)}(k*) e^{-i (G + Delta).T}
+ * i.e. for Miller indices m the source is W^T (m + Delta) and the phase
+ * e^{-2 pi i (m + Delta).t} (a global phase of the band is dropped, as in
+ * the paper).
+ * miller_irr (host) int[npw_irr][3], coef_irr (dev) c128[nband][ld_irr];
+ * miller (host) int[npw][3], the target list at k, each of whose source
+ * vectors must be in miller_irr; coef (dev) c128[nband][ld] output (columns
+ * npw .. ld-1 untouched).
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE (W not unimodular, k not an
+ * image of k*, a target without source, a mesh index outside the mesh),
+ * RP_E_NOMEM, RP_E_DEVICE.
+ */
+rp_status rp_unfold_coef(rp_ctx *ctx, const rp_cell *cell, const int W[9], const double t[3],
+                         const int ik_irr[3], int nband, int npw_irr, const int *miller_irr,
+                         const double *coef_irr, long ld_irr, const int ik[3], int npw,
+                         const int *miller, double *coef, long ld);
+
+/*
+ * Symmetry unfolding of a G-indexed matrix (Eq. symeps): eps^-1, or chi
+ * and W, which transform alike.  For q = S q* + Delta (as above):
+ *   X_{G,G'}(q, w) = X_{S^{-1}(G + Delta), S^{-1}(G' + Delta)}(q*, w) e^{+i (G - G').T}
+ * The phase sign is the one that Eq. chi's order M(G) conj(M(G')) and
+ * Eq. red-wavefunction's operator give (the paper prints e^{-i(G - G').T});
+ * it reproduces chi computed directly at q from the symmetric bands.
+ * gsph_irr (host) int[ng_irr][3], src (dev) c128[nfreq][ng_irr][ng_irr];
+ * gsph (host) int[ng][3], the list at q (usually S G* - Delta over gsph_irr),
+ * every source in gsph_irr; dst (dev) c128[nfreq][ng][ng], not src.
+ * Errors: RP_E_NULL, RP_E_SHAPE (ng > 6144), RP_E_RANGE, RP_E_ALIAS,
+ * RP_E_NOMEM, RP_E_DEVICE.
+ */
+rp_status rp_unfold_eps_inv(rp_ctx *ctx, const rp_cell *cell, const int W[9], const double t[3],
+                            const int iq_irr[3], int ng_irr, const int *gsph_irr, const int iq[3], int ng,
+                            const int *gsph, int nfreq, const double *src, double *dst);
+
+/*
  * The q -> 0 head (section "Response function with random phase
  * approximation", Eqs. eps00-cRPA and momentum): for an empty band a and an
  * occupied band b at the same k, the G = 0 pair density tends to
@@ -429,6 +470,7 @@ rp_status rp_set_tuning(rp_ctx *ctx, int n, const rp_tune_entry *table);
  *   RP_STAGE_WANNIER  Wannier densities and projection, a10
  *   RP_STAGE_BATCH    one rp_chi0_batch graph launch, a2-a6 of every problem
  *                     (the per-stage timers do not run inside the graph)
+ *   RP_STAGE_UNFOLD   symmetry unfolding of coefficients and eps^-1
  * rp_profile(ctx, 1) enables and resets; rp_profile(ctx, 0) disables.
  * rp_profile_read synchronizes the stream and returns, per stage, the summed
  * milliseconds and the number of timed launches (arrays of RP_NSTAGE).
@@ -442,7 +484,8 @@ enum {
     RP_STAGE_SCREEN = 5,
     RP_STAGE_WANNIER = 6,
     RP_STAGE_BATCH = 7,
-    RP_NSTAGE = 8
+    RP_STAGE_UNFOLD = 8,
+    RP_NSTAGE = 9
 };
 
 rp_status rp_profile(rp_ctx *ctx, int enable);

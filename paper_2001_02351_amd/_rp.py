@@ -29,9 +29,10 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_E_NULL", 2: "RP_E_SHAPE", 3: "RP_E_RANGE", 4:
 EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pair_density",
             "rp_weights", "rp_chi0_accumulate", "rp_chi0_batch", "rp_screen_W", "rp_wannier_W",
             "rp_set_tuning", "rp_head_density", "rp_screen_head", "rp_wannier_qterm",
-            "rp_coulomb_cell_average", "rp_frequency_grid", "rp_profile", "rp_profile_read"]
+            "rp_coulomb_cell_average", "rp_frequency_grid", "rp_unfold_coef", "rp_unfold_eps_inv",
+            "rp_profile", "rp_profile_read"]
 
-STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier", "batch"]
+STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier", "batch", "unfold"]
 
 
 class RpError(RuntimeError):
@@ -108,6 +109,8 @@ def load(path: Optional[str] = None):
         "rp_wannier_qterm": [P, cellp, P, I, P, P, I, P, I, P, I, P, I, P, I, P, P, P, P],
         "rp_coulomb_cell_average": [cellp, ctypes.POINTER(D)],
         "rp_frequency_grid": [D, D, I, I, P],
+        "rp_unfold_coef": [P, cellp, P, P, P, I, I, P, P, ctypes.c_long, P, I, P, P, ctypes.c_long],
+        "rp_unfold_eps_inv": [P, cellp, P, P, P, I, P, P, I, P, I, P, P],
         "rp_profile": [P, I],
         "rp_profile_read": [P, P, P],
     }
@@ -348,6 +351,41 @@ def rp_frequency_grid(emax_eV: float, dw_eV: float = 0.05, nomega: int = 70, nma
     if st != 0:
         raise RpError(st, "rp_frequency_grid", "invalid grid parameters")
     return out
+
+
+def _op(W, t):
+    return _host(W, np.int32).reshape(9), _host(t, np.float64).reshape(3)
+
+
+def _ld(t) -> int:
+    """Leading dimension (complex elements) of a [n][ld][2] or [n][2 ld] tensor."""
+    return int(t.shape[1]) if t.dim() == 3 else int(t.shape[1]) // 2
+
+
+def rp_unfold_coef(ctx: Context, cell: rp_cell, W, t, ik_irr, miller_irr, coef_irr, ik, miller, coef):
+    """coef_irr and coef: device tensors [nband][ld][2] or [nband][2 ld]
+    (interleaved complex); miller lists host int [n][3]."""
+    W_h, t_h = _op(W, t)
+    mi, mt = _host(miller_irr, np.int32).reshape(-1, 3), _host(miller, np.int32).reshape(-1, 3)
+    ki, kt = _host(ik_irr, np.int32), _host(ik, np.int32)
+    ctx._enter()
+    st = ctx.lib.rp_unfold_coef(ctx.handle, ctypes.byref(cell), _hp(W_h), _hp(t_h), _hp(ki), int(coef_irr.shape[0]),
+                                int(mi.shape[0]), _hp(mi), _dp(coef_irr), _ld(coef_irr), _hp(kt),
+                                int(mt.shape[0]), _hp(mt), _dp(coef), _ld(coef))
+    ctx._leave()
+    ctx._check(st, "rp_unfold_coef")
+
+
+def rp_unfold_eps_inv(ctx: Context, cell: rp_cell, W, t, iq_irr, gsph_irr, iq, gsph, src, dst):
+    """src [nfreq][ng_irr][ng_irr][2], dst [nfreq][ng][ng][2] device tensors."""
+    W_h, t_h = _op(W, t)
+    gi, gt = _host(gsph_irr, np.int32).reshape(-1, 3), _host(gsph, np.int32).reshape(-1, 3)
+    qi, qt = _host(iq_irr, np.int32), _host(iq, np.int32)
+    ctx._enter()
+    st = ctx.lib.rp_unfold_eps_inv(ctx.handle, ctypes.byref(cell), _hp(W_h), _hp(t_h), _hp(qi), int(gi.shape[0]),
+                                   _hp(gi), _hp(qt), int(gt.shape[0]), _hp(gt), int(src.shape[0]), _dp(src), _dp(dst))
+    ctx._leave()
+    ctx._check(st, "rp_unfold_eps_inv")
 
 
 def rp_set_tuning(ctx: Context, entries):

@@ -29,7 +29,7 @@ FLAGS = [
 ]
 
 SOURCES = ["rp_api.cpp", "fft.hip", "pair.hip", "tetra.hip", "chi_f64.hip", "chi_bf16.hip", "head.hip",
-           "screen.hip", "wannier.hip", "qsum.hip"]
+           "screen.hip", "wannier.hip", "qsum.hip", "symmetry.hip"]
 
 
 def library_path() -> str:

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <unordered_map>
 #include <vector>
 
 #include "rp_internal.h"
@@ -1063,6 +1064,137 @@ rp_status rp_frequency_grid(double emax_eV, double dw_eV, int nomega, int nmax, 
     for (int i = nmax + 1; i <= nomega; i++)
         omega_eV[i - 1] = emax_eV * std::exp(std::log(3.0) * (double)(i - nmax) / (double)(nomega - nmax));
     return RP_OK;
+}
+
+// ---- symmetry unfolding (Eqs. coef-G, symeps) ----
+
+// S = W^{-T} for an integer W with det W = +-1 (row-major); false otherwise
+static bool op_inverse_transpose(const int W[9], int S[9])
+{
+    const long det = (long)W[0] * (W[4] * W[8] - W[5] * W[7]) - (long)W[1] * (W[3] * W[8] - W[5] * W[6]) +
+                     (long)W[2] * (W[3] * W[7] - W[4] * W[6]);
+    if (det != 1 && det != -1) return false;
+    // W^{-1} = adj(W) / det, so S[i][j] = W^{-1}[j][i] = cof(W)[i][j] / det
+    const int c[9] = {W[4] * W[8] - W[5] * W[7], W[5] * W[6] - W[3] * W[8], W[3] * W[7] - W[4] * W[6],
+                      W[2] * W[7] - W[1] * W[8], W[0] * W[8] - W[2] * W[6], W[1] * W[6] - W[0] * W[7],
+                      W[1] * W[5] - W[2] * W[4], W[2] * W[3] - W[0] * W[5], W[0] * W[4] - W[1] * W[3]};
+    for (int i = 0; i < 9; i++) S[i] = (int)(c[i] / det);
+    return true;
+}
+
+// Delta = k - S k* for mesh indices n, n* (k = n / K), required integral
+static rp_status op_rewind(rp_ctx *ctx, const Geometry &g, const int S[9], const int nirr[3], const int n[3],
+                           int delta[3])
+{
+    for (int a = 0; a < 3; a++)
+        if (nirr[a] < 0 || nirr[a] >= g.kmesh[a] || n[a] < 0 || n[a] >= g.kmesh[a])
+            return fail(ctx, RP_E_RANGE, "mesh index outside the mesh");
+    for (int a = 0; a < 3; a++) {
+        double sk = 0.0;
+        for (int b = 0; b < 3; b++) sk += S[3 * a + b] * ((double)nirr[b] / g.kmesh[b]);
+        const double d = (double)n[a] / g.kmesh[a] - sk;
+        const double r = std::nearbyint(d);
+        if (std::fabs(d - r) > 1e-9) return fail(ctx, RP_E_RANGE, "the point is not the image of k* under the operation");
+        delta[a] = (int)r;
+    }
+    return RP_OK;
+}
+
+static inline long long miller_key(int a, int b, int c)
+{
+    return ((long long)(a + (1 << 20)) << 42) | ((long long)(b + (1 << 20)) << 21) | (long long)(c + (1 << 20));
+}
+
+// src_idx[g] = position in `from` of W^T (m_g + Delta) for each vector of `to`
+static rp_status op_source_index(rp_ctx *ctx, const int W[9], const int delta[3], int nfrom, const int *from, int nto,
+                                 const int *to, std::vector<int> &src_idx)
+{
+    std::unordered_map<long long, int> where;
+    where.reserve((size_t)nfrom * 2);
+    for (int i = 0; i < nfrom; i++) where.emplace(miller_key(from[3 * i], from[3 * i + 1], from[3 * i + 2]), i);
+    src_idx.resize(nto);
+    for (int g = 0; g < nto; g++) {
+        const int v[3] = {to[3 * g] + delta[0], to[3 * g + 1] + delta[1], to[3 * g + 2] + delta[2]};
+        int m[3];
+        for (int a = 0; a < 3; a++) m[a] = W[a] * v[0] + W[3 + a] * v[1] + W[6 + a] * v[2];   // (W^T v)_a
+        const auto it = where.find(miller_key(m[0], m[1], m[2]));
+        if (it == where.end())
+            return fail(ctx, RP_E_RANGE, "target vector %d (%d %d %d) has no source vector", g, to[3 * g],
+                        to[3 * g + 1], to[3 * g + 2]);
+        src_idx[g] = it->second;
+    }
+    return RP_OK;
+}
+
+static rp_status check_op(rp_ctx *ctx, const int W[9], const double t[3], int S[9])
+{
+    if (!W || !t) return fail(ctx, RP_E_NULL, "W or t is NULL");
+    if (!op_inverse_transpose(W, S)) return fail(ctx, RP_E_RANGE, "W is not an integer matrix of determinant +-1");
+    for (int a = 0; a < 3; a++)
+        if (!std::isfinite(t[a])) return fail(ctx, RP_E_RANGE, "non-finite translation");
+    return RP_OK;
+}
+
+rp_status rp_unfold_coef(rp_ctx *ctx, const rp_cell *cell, const int W[9], const double t[3], const int ik_irr[3],
+                         int nband, int npw_irr, const int *miller_irr, const double *coef_irr, long ld_irr,
+                         const int ik[3], int npw, const int *miller, double *coef, long ld)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    const int iq0[3] = {0, 0, 0};
+    Geometry g;
+    rp_status st = geometry(ctx, cell, iq0, &g);
+    if (st != RP_OK) return st;
+    int S[9], delta[3];
+    if ((st = check_op(ctx, W, t, S)) != RP_OK) return st;
+    if (!ik_irr || !ik) return fail(ctx, RP_E_NULL, "mesh index is NULL");
+    if ((st = op_rewind(ctx, g, S, ik_irr, ik, delta)) != RP_OK) return st;
+    if (nband < 1 || npw_irr < 1 || npw < 0 || ld_irr < npw_irr || ld < npw)
+        return fail(ctx, RP_E_SHAPE, "bad nband, plane-wave counts or leading dimensions");
+    if (!miller_irr || !coef_irr || (npw > 0 && (!miller || !coef))) return fail(ctx, RP_E_NULL, "NULL array argument");
+    std::vector<int> idx;
+    if ((st = op_source_index(ctx, W, delta, npw_irr, miller_irr, npw, miller, idx)) != RP_OK) return st;
+    if (npw == 0) return RP_OK;
+    std::vector<int> host((size_t)4 * npw);
+    std::memcpy(host.data(), idx.data(), sizeof(int) * npw);
+    std::memcpy(host.data() + npw, miller, sizeof(int) * 3 * npw);
+    if ((st = upload(ctx, ctx->kinfo, host.data(), sizeof(int) * host.size())) != RP_OK) return st;
+    const int *didx = (const int *)ctx->kinfo.p;
+    StageTimer tm(ctx, RP_STAGE_UNFOLD);
+    launch_unfold_coef(ctx->stream, nband, npw, didx, didx + npw, delta, t, (const double2 *)coef_irr, ld_irr,
+                       (double2 *)coef, ld);
+    return check_launch(ctx, "coefficient unfolding");
+}
+
+rp_status rp_unfold_eps_inv(rp_ctx *ctx, const rp_cell *cell, const int W[9], const double t[3], const int iq_irr[3],
+                            int ng_irr, const int *gsph_irr, const int iq[3], int ng, const int *gsph, int nfreq,
+                            const double *src, double *dst)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    const int iq0[3] = {0, 0, 0};
+    Geometry g;
+    rp_status st = geometry(ctx, cell, iq0, &g);
+    if (st != RP_OK) return st;
+    int S[9], delta[3];
+    if ((st = check_op(ctx, W, t, S)) != RP_OK) return st;
+    if (!iq_irr || !iq) return fail(ctx, RP_E_NULL, "mesh index is NULL");
+    if ((st = op_rewind(ctx, g, S, iq_irr, iq, delta)) != RP_OK) return st;
+    if (ng_irr < 1 || ng < 1 || ng > 6144 || nfreq < 1) return fail(ctx, RP_E_SHAPE, "bad ng, ng_irr or nfreq");
+    if (!gsph_irr || !gsph || !src || !dst) return fail(ctx, RP_E_NULL, "NULL array argument");
+    if (src == dst) return fail(ctx, RP_E_ALIAS, "source and destination must differ");
+    std::vector<int> idx;
+    if ((st = op_source_index(ctx, W, delta, ng_irr, gsph_irr, ng, gsph, idx)) != RP_OK) return st;
+    std::vector<int> host((size_t)4 * ng);
+    std::memcpy(host.data(), idx.data(), sizeof(int) * ng);
+    std::memcpy(host.data() + ng, gsph, sizeof(int) * 3 * ng);
+    if ((st = upload(ctx, ctx->kinfo, host.data(), sizeof(int) * host.size())) != RP_OK) return st;
+    if ((st = ensure(ctx, ctx->work, sizeof(double2) * (size_t)ng)) != RP_OK) return st;
+    const int *didx = (const int *)ctx->kinfo.p;
+    StageTimer tm(ctx, RP_STAGE_UNFOLD);
+    launch_unfold_matrix(ctx->stream, nfreq, ng, ng_irr, didx, didx + ng, t, (double2 *)ctx->work.p,
+                         (const double2 *)src, (double2 *)dst);
+    return check_launch(ctx, "eps^-1 unfolding");
 }
 
 rp_status rp_coulomb_cell_average(const rp_cell *cell, double *avg)

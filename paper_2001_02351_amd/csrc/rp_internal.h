@@ -188,6 +188,12 @@ void launch_wannier_W(hipStream_t s, int nfreq, int nwan, int ng, const double2 
                       int ntail, const double2 *rho_tail, const double2 *einv, double pre,
                       double2 *T, double2 *Wij);
 
+// symmetry.hip: unfolding of coefficients and of G-indexed matrices
+void launch_unfold_coef(hipStream_t s, int nband, int npw, const int *idx, const int *miller, const int delta[3],
+                        const double t[3], const double2 *src, long ld_src, double2 *dst, long ld_dst);
+void launch_unfold_matrix(hipStream_t s, int nfreq, int ng, int ng_src, const int *idx, const int *gsph,
+                          const double t[3], double2 *ph, const double2 *src, double2 *dst);
+
 // qsum.hip: one q-point's term of the q-sums of U, V, J, X
 void launch_xdens(hipStream_t s, const Geometry &g, const FftPlan plans[3], int nwan, const double *phi,
                   const double *centre_dev, const int *R_dev, long v0, int nvc, double2 *grids);
