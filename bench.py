@@ -504,6 +504,51 @@ def tune_leg(args):
     print(json.dumps({"tuning_table": args.tune, "entries": table["entries"]}), flush=True)
 
 
+def unfold_leg(rp, ctx, d, eps_inv, reps: int = 5) -> dict:
+    """The symmetry-unfolding gathers at the workload's shape: eps^-1 (N_G^2 x
+    N_w, Eq. symeps) and the coefficients of one k-point (all bands, Eq.
+    coef-G) moved by the operation x -> (y, z, x) + (1/2, 0, 0) of the cubic
+    cell (any operation of the lattice costs the same); algorithmic bytes = one
+    read and one write of every element."""
+    import numpy as np
+    import torch
+    p = d.prob
+    W = np.array([[0, 1, 0], [0, 0, 1], [1, 0, 0]], np.int32)
+    t = np.array([0.5, 0.0, 0.0])
+    S = np.rint(np.linalg.inv(W).T).astype(np.int64)
+    iq_s = np.array(p.iq)
+    iq_t = (S @ iq_s) % np.array(p.kmesh)
+    delta = ((iq_t / np.array(p.kmesh)) - S @ (iq_s / np.array(p.kmesh))).round().astype(np.int64)
+    gsph_t = np.ascontiguousarray((p.gsph @ S.T - delta).astype(np.int32))
+    dst = torch.empty_like(eps_inv)
+    rp.rp_unfold_eps_inv(ctx, d.cell, W, t, iq_s, p.gsph, iq_t, gsph_t, eps_inv, dst)
+    k0 = 1
+    n0 = int(p.npw[k0])
+    kf = np.array(np.unravel_index(k0, p.kmesh))
+    kt = (S @ kf) % np.array(p.kmesh)
+    dk = ((kt / np.array(p.kmesh)) - S @ (kf / np.array(p.kmesh))).round().astype(np.int64)
+    mt = np.ascontiguousarray((p.miller[k0, :n0] @ S.T - dk).astype(np.int32))
+    cdst = torch.empty_like(d.coef[k0])
+    rp.rp_unfold_coef(ctx, d.cell, W, t, kf, p.miller[k0, :n0], d.coef[k0], kt, mt, cdst)
+    rp.rp_synchronize(ctx)
+    rp.rp_profile(ctx, True)
+    for _ in range(reps):
+        rp.rp_unfold_eps_inv(ctx, d.cell, W, t, iq_s, p.gsph, iq_t, gsph_t, eps_inv, dst)
+    t_eps = rp.rp_profile_read(ctx)["unfold"][0] / reps
+    rp.rp_profile(ctx, True)
+    for _ in range(reps):
+        rp.rp_unfold_coef(ctx, d.cell, W, t, kf, p.miller[k0, :n0], d.coef[k0], kt, mt, cdst)
+    t_coef = rp.rp_profile_read(ctx)["unfold"][0] / reps
+    rp.rp_profile(ctx, False)
+    b_eps = 2.0 * d.nfreq * d.ng ** 2 * 16
+    b_coef = 2.0 * d.nband * n0 * 16
+    log(f"unfolding: eps^-1 {t_eps:.3f} ms ({b_eps / t_eps / 1e6:.0f} GB/s), coefficients of one k "
+        f"{t_coef:.3f} ms ({b_coef / t_coef / 1e6:.0f} GB/s)")
+    return {"eps_inv_ms": t_eps, "eps_inv_bytes": b_eps, "eps_inv_GB_s": b_eps / t_eps / 1e6,
+            "coef_ms_per_k": t_coef, "coef_bytes_per_k": b_coef, "coef_GB_s": b_coef / t_coef / 1e6,
+            "peak_GB_s": PEAK_HBM_GBS, "bound": "hbm"}
+
+
 def qterm_cpu_baseline(prob, eps_inv_host) -> dict:
     """The oracle's q-term (oracle/qsum.py, as it stands) on a bounded
     sample of the same workload: the home cell R = 0 only (nwan^2 of the
@@ -675,6 +720,7 @@ def main():
         }
     qterm = None if args.no_qterm else qterm_leg(rp, path, ctx, d, einv_s,
                                                  cpu=not args.no_cpu_baseline and not args.profile_k)
+    unfold = None if args.no_qterm else unfold_leg(rp, ctx, d, einv_s)
     ctx.close()
 
     npair_total = d.nk * prob.nocc * prob.nemp
@@ -738,6 +784,7 @@ def main():
         },
         "hbm_a2_a4": hbm,
         "interaction_qterm": qterm,
+        "symmetry_unfold": unfold,
         "cpu_baseline": None if baseline is None else {k: baseline[k] for k in
                                                         ("value", "unit", "cores", "cpu_model", "kind",
                                                          "sample")},
