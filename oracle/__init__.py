@@ -18,6 +18,7 @@ marshals numpy arrays and strings the steps together in the paper's order:
                                                matrix_J, matrix_X
   frequency grid (oracle.grid)                 Eq. grid
   symmetry unfolding (oracle.symmetry)         Eqs. red-wavefunction, coef-G, symeps
+  metallic tetrahedron weights (oracle.metal)  Eqs. Xakqbk, tetrahedron (Fermi-level cut)
 
 Parity status of each function is listed in its docstring.
 """
