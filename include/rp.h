@@ -74,7 +74,12 @@ typedef enum {
 
 typedef enum {
     RP_W_TETRA = 0,     /* generalized tetrahedron integration of X (Eq. tetrahedron) */
-    RP_W_SAMPLING = 1   /* X evaluated at the mesh point (Eq. Xakqbk as written) */
+    RP_W_SAMPLING = 1,  /* X evaluated at the mesh point (Eq. Xakqbk as written) */
+    RP_W_TETRA_METAL = 2 /* generalized tetrahedron restricted, within every
+                            tetrahedron, to the part where the linear
+                            interpolants satisfy E_b(k) < E_F < E_a(k+q)
+                            (E_F from rp_set_fermi_level); the occupied and
+                            empty band ranges may then overlap */
 } rp_weight_mode;
 
 typedef struct rp_ctx rp_ctx;
@@ -334,6 +339,19 @@ rp_status rp_coulomb_cell_average(const rp_cell *cell, double *avg);
  * RP_E_RANGE (dw <= 0, emax <= dw, non-finite).
  */
 rp_status rp_frequency_grid(double emax_eV, double dw_eV, int nomega, int nmax, double *omega_eV);
+
+/*
+ * The Fermi level E_F (eV, on the scale of energy_eV) that RP_W_TETRA_METAL
+ * weights cut the tetrahedra with; NaN clears it.  A call with
+ * RP_W_TETRA_METAL while none is set fails with RP_E_RANGE.  For a pair of a
+ * band a at k+q and a band b at k the tetrahedron integral of Eq.
+ * tetrahedron then runs over the part of each tetrahedron where
+ * E_b < E_F < E_a (b occupied, a empty); a tetrahedron where that holds at
+ * all four corners gives the insulating integral, one where E_b >= E_F or
+ * E_a <= E_F at all four gives nothing.
+ * Errors: RP_E_NULL.
+ */
+rp_status rp_set_fermi_level(rp_ctx *ctx, double ef_eV);
 
 /*
  * Symmetry unfolding of plane-wave coefficients (section "Symmetry", Eqs.

@@ -13,6 +13,7 @@ from ._rp import (  # noqa: F401
     RP_SPLIT_BF16_X6,
     RP_W_SAMPLING,
     RP_W_TETRA,
+    RP_W_TETRA_METAL,
     Context,
     RpError,
     load,
@@ -37,6 +38,7 @@ from ._rp import (  # noqa: F401
     rp_frequency_grid,
     rp_unfold_coef,
     rp_unfold_eps_inv,
+    rp_set_fermi_level,
     rp_weights,
 )
 from .build import build, library_path  # noqa: F401

@@ -22,6 +22,7 @@ RP_SPLIT_BF16 = 1
 RP_SPLIT_BF16_X6 = 2
 RP_W_TETRA = 0
 RP_W_SAMPLING = 1
+RP_W_TETRA_METAL = 2
 
 STATUS_NAMES = {0: "RP_OK", 1: "RP_E_NULL", 2: "RP_E_SHAPE", 3: "RP_E_RANGE", 4: "RP_E_ALIAS",
                 5: "RP_E_NOMEM", 6: "RP_E_DEVICE", 7: "RP_E_SINGULAR", 8: "RP_E_UNSUPPORTED"}
@@ -30,7 +31,7 @@ EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pa
             "rp_weights", "rp_chi0_accumulate", "rp_chi0_batch", "rp_screen_W", "rp_wannier_W",
             "rp_set_tuning", "rp_head_density", "rp_screen_head", "rp_wannier_qterm",
             "rp_coulomb_cell_average", "rp_frequency_grid", "rp_unfold_coef", "rp_unfold_eps_inv",
-            "rp_profile", "rp_profile_read"]
+            "rp_set_fermi_level", "rp_profile", "rp_profile_read"]
 
 STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier", "batch", "unfold"]
 
@@ -111,6 +112,7 @@ def load(path: Optional[str] = None):
         "rp_frequency_grid": [D, D, I, I, P],
         "rp_unfold_coef": [P, cellp, P, P, P, I, I, P, P, ctypes.c_long, P, I, P, P, ctypes.c_long],
         "rp_unfold_eps_inv": [P, cellp, P, P, P, I, P, P, I, P, I, P, P],
+        "rp_set_fermi_level": [P, D],
         "rp_profile": [P, I],
         "rp_profile_read": [P, P, P],
     }
@@ -386,6 +388,11 @@ def rp_unfold_eps_inv(ctx: Context, cell: rp_cell, W, t, iq_irr, gsph_irr, iq, g
                                    _hp(gi), _hp(qt), int(gt.shape[0]), _hp(gt), int(src.shape[0]), _dp(src), _dp(dst))
     ctx._leave()
     ctx._check(st, "rp_unfold_eps_inv")
+
+
+def rp_set_fermi_level(ctx: Context, ef_eV: float):
+    """Fermi level (eV) of the RP_W_TETRA_METAL weights; nan clears it."""
+    ctx._check(ctx.lib.rp_set_fermi_level(ctx.handle, float(ef_eV)), "rp_set_fermi_level")
 
 
 def rp_set_tuning(ctx: Context, entries):

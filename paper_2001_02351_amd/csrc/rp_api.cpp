@@ -343,6 +343,7 @@ struct ChiJob {
     int nfreq = 0;
     double delta = 0.0;
     rp_weight_mode wm = RP_W_TETRA;
+    double ef = 0.0;    // Fermi level (eV) of RP_W_TETRA_METAL
     rp_precision prec = RP_FP64;
     bool herm = false;  // real weights: chi Hermitian
     Tune tune;          // contraction launch shape
@@ -354,7 +355,10 @@ static rp_status weights_check(rp_ctx *ctx, const double *E, int nfreq, const do
     if (!E || !freq_eV) return fail(ctx, RP_E_NULL, "NULL energy or frequency array");
     if (nfreq < 1) return fail(ctx, RP_E_SHAPE, "nfreq must be >= 1");
     if (!(delta_eV >= 0.0) || !std::isfinite(delta_eV)) return fail(ctx, RP_E_RANGE, "delta must be >= 0");
-    if (wm != RP_W_TETRA && wm != RP_W_SAMPLING) return fail(ctx, RP_E_RANGE, "unknown weight mode");
+    if (wm != RP_W_TETRA && wm != RP_W_SAMPLING && wm != RP_W_TETRA_METAL)
+        return fail(ctx, RP_E_RANGE, "unknown weight mode");
+    if (wm == RP_W_TETRA_METAL && !std::isfinite(ctx->fermi_eV))
+        return fail(ctx, RP_E_RANGE, "metallic weights need a Fermi level (rp_set_fermi_level)");
     for (int f = 0; f < 2 * nfreq; f++)
         if (!std::isfinite(freq_eV[f])) return fail(ctx, RP_E_RANGE, "non-finite frequency");
     return RP_OK;
@@ -383,6 +387,7 @@ static rp_status chi_check(rp_ctx *ctx, const rp_cell *cell, const int iq[3], in
     c->nfreq = nfreq;
     c->delta = delta_eV;
     c->wm = wm;
+    c->ef = wm == RP_W_TETRA_METAL ? ctx->fermi_eV : 0.0;
     c->prec = prec;
     // on the imaginary axis (w = i nu) without broadening, z = i nu and
     // z' = -i nu = z* in Eqs. Xakqbk and tetrahedron, whose two terms are then
@@ -430,7 +435,7 @@ static rp_status chi_enqueue(rp_ctx *ctx, const ChiJob &c, int k0, int k1, const
         {
             StageTimer t(ctx, RP_STAGE_WEIGHTS);
             launch_weights(ctx->stream, c.g.kmesh, c.g.iq, c.nband, c.E, c.T, c.o0, c.o1, c.e0, c.e1, k0, k1,
-                           c.nfreq, dfreq, c.delta, (int)c.wm, bufs.w);
+                           c.nfreq, dfreq, c.delta, (int)c.wm, c.ef, bufs.w);
         }
         if ((st = check_launch(ctx, "weights")) != RP_OK) return st;
     }
@@ -607,7 +612,7 @@ rp_status rp_weights(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nban
     {
         StageTimer t(ctx, RP_STAGE_WEIGHTS);
         launch_weights(ctx->stream, g.kmesh, g.iq, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, nfreq,
-                       (const double2 *)ctx->freq.p, delta_eV, (int)wm, (double2 *)w);
+                       (const double2 *)ctx->freq.p, delta_eV, (int)wm, ctx->fermi_eV, (double2 *)w);
     }
     return check_launch(ctx, "weights");
 }
@@ -740,6 +745,7 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
         const void *ptrs[] = {p.miller, p.coef, p.energy_eV, p.T, p.chi};
         key_put(key, ptrs, sizeof ptrs);
         key_val(key, p.delta_eV);
+        key_val(key, cj[i].ef);
         const int tn[] = {cj[i].tune.chi_nw, cj[i].tune.chi_fill, cj[i].tune.chi_kernel, pj[i].fft_lines};
         key_put(key, tn, sizeof tn);
     }
@@ -1195,6 +1201,13 @@ rp_status rp_unfold_eps_inv(rp_ctx *ctx, const rp_cell *cell, const int W[9], co
     launch_unfold_matrix(ctx->stream, nfreq, ng, ng_irr, didx, didx + ng, t, (double2 *)ctx->work.p,
                          (const double2 *)src, (double2 *)dst);
     return check_launch(ctx, "eps^-1 unfolding");
+}
+
+rp_status rp_set_fermi_level(rp_ctx *ctx, double ef_eV)
+{
+    if (!ctx) return RP_E_NULL;
+    ctx->fermi_eV = ef_eV;
+    return RP_OK;
 }
 
 rp_status rp_coulomb_cell_average(const rp_cell *cell, double *avg)

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -74,6 +75,7 @@ struct rp_ctx {
     std::string batch_key;
     bool capturing = false;         // stage timers stay off while a graph is captured
     std::vector<rp_tune_entry> tuning;  // launch shapes per size class, matched in order
+    double fermi_eV = std::nan("");  // Fermi level of the metallic weights (RP_W_TETRA_METAL)
     // stage timers
     bool profiling = false;
     struct Mark {
@@ -140,7 +142,7 @@ void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], cons
 void launch_weights(hipStream_t s, const int kmesh[3], const int iq[3], int nband,
                     const double *E_eV, const double *T, int o0, int o1, int e0, int e1,
                     int k0, int k1, int nfreq, const double2 *freq_eV, double delta_eV,
-                    int mode, double2 *w);
+                    int mode, double ef_eV, double2 *w);
 
 // chi_f64.hip: chi += sum_p w_p M_p M_p^H on FP64 matrix cores.  herm: the
 // weights are real and only the upper tiles are formed (chi Hermitian).

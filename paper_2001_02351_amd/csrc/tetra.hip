@@ -227,6 +227,146 @@ __device__ double2 dd4_sorted(double2 z, const double *x, const double2 *lw)
 
 __device__ __forceinline__ int mesh_wrap(int n, int K) { return pmod(n, K); }
 
+// ---- metallic cut: the part of a tetrahedron where E_b < E_F < E_a ----
+//
+// Points are barycentric coordinates with respect to the tetrahedron T.  A
+// tetrahedron P is clipped to {phi < 0} for a linear phi given at its
+// corners: one corner inside leaves a corner tetrahedron; two or three leave
+// a triangular prism (bottom and top triangles joined by three lateral
+// edges), cut into three tetrahedra.
+
+__device__ __forceinline__ void lerp4(const double (&a)[4], const double (&b)[4], double s, double (&out)[4])
+{
+#pragma unroll
+    for (int d = 0; d < 4; d++) out[d] = a[d] + s * (b[d] - a[d]);
+}
+
+template <typename Emit>
+__device__ __forceinline__ void prism3(const double (&p0)[4], const double (&p1)[4], const double (&p2)[4],
+                                       const double (&q0)[4], const double (&q1)[4], const double (&q2)[4], Emit &emit)
+{
+    emit(p0, p1, p2, q0);
+    emit(p1, p2, q0, q1);
+    emit(p2, q0, q1, q2);
+}
+
+template <typename Emit>
+__device__ void clip_tet(const double (&P)[4][4], const double (&phi)[4], Emit &emit)
+{
+    int in[4], out[4], ni = 0, no = 0;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        if (phi[c] < 0.0) in[ni++] = c;
+        else out[no++] = c;
+    }
+    if (ni == 0) return;
+    if (ni == 4) {
+        emit(P[0], P[1], P[2], P[3]);
+        return;
+    }
+    // the point where phi = 0 on the edge from inside corner a to outside corner b
+    auto cut = [&](int a, int b, double (&q)[4]) { lerp4(P[a], P[b], phi[a] / (phi[a] - phi[b]), q); };
+    double x0[4], x1[4], x2[4];
+    if (ni == 1) {
+        cut(in[0], out[0], x0);
+        cut(in[0], out[1], x1);
+        cut(in[0], out[2], x2);
+        emit(P[in[0]], x0, x1, x2);
+    } else if (ni == 3) {
+        cut(in[0], out[0], x0);
+        cut(in[1], out[0], x1);
+        cut(in[2], out[0], x2);
+        prism3(P[in[0]], P[in[1]], P[in[2]], x0, x1, x2, emit);
+    } else {
+        double y1[4], y2[4];
+        cut(in[0], out[0], x1);
+        cut(in[0], out[1], x2);
+        cut(in[1], out[0], y1);
+        cut(in[1], out[1], y2);
+        prism3(P[in[0]], x1, x2, P[in[1]], y1, y2, emit);
+    }
+}
+
+__device__ __forceinline__ double det4(const double (&a)[4], const double (&b)[4], const double (&c)[4],
+                                       const double (&d)[4])
+{
+    // expansion along the first row
+    auto m3 = [](double a0, double a1, double a2, double b0, double b1, double b2, double c0, double c1, double c2) {
+        return a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
+    };
+    return a[0] * m3(b[1], b[2], b[3], c[1], c[2], c[3], d[1], d[2], d[3]) -
+           a[1] * m3(b[0], b[2], b[3], c[0], c[2], c[3], d[0], d[2], d[3]) +
+           a[2] * m3(b[0], b[1], b[3], c[0], c[1], c[3], d[0], d[1], d[3]) -
+           a[3] * m3(b[0], b[1], b[2], c[0], c[1], c[2], d[0], d[1], d[2]);
+}
+
+// sorting network on five keys, carrying the logarithms
+__device__ __forceinline__ void sort5(double (&xs)[5], double2 (&ls)[5])
+{
+#define RP_CSWAP(i, j)                                                                             \
+    {                                                                                              \
+        const bool sw_ = xs[j] < xs[i];                                                            \
+        const double xi_ = xs[i], xj_ = xs[j];                                                     \
+        const double2 li_ = ls[i], lj_ = ls[j];                                                    \
+        xs[i] = sw_ ? xj_ : xi_;                                                                   \
+        xs[j] = sw_ ? xi_ : xj_;                                                                   \
+        ls[i] = sw_ ? lj_ : li_;                                                                   \
+        ls[j] = sw_ ? li_ : lj_;                                                                   \
+    }
+    RP_CSWAP(0, 1) RP_CSWAP(3, 4) RP_CSWAP(2, 4) RP_CSWAP(2, 3) RP_CSWAP(0, 3)
+    RP_CSWAP(0, 2) RP_CSWAP(1, 4) RP_CSWAP(1, 3) RP_CSWAP(1, 2)
+#undef RP_CSWAP
+}
+
+// (1/|T|) int over {E_b < E_F < E_a} within T of lambda_v / (z - e): the
+// region is tiled by clipping T first to E_b < E_F, then each piece to
+// E_a > E_F; a piece S contributes (|S|/|T|) sum_j lambda_v(s_j) I_j^S(z),
+// I_j^S the vertex integral of S on the transition energies at its corners
+// (lambda_v is linear, so it is the barycentric combination of its corner
+// values).
+__device__ double2 clipped_vertex_integral(double2 zz, const double (&e)[4], const double (&eb)[4],
+                                           const double (&ea)[4], double ef, int v)
+{
+    const double T[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+    double phi1[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) phi1[c] = eb[c] - ef;
+    double2 acc = make_double2(0.0, 0.0);
+    auto inner = [&](const double (&r0)[4], const double (&r1)[4], const double (&r2)[4], const double (&r3)[4]) {
+        const double ratio = fabs(det4(r0, r1, r2, r3));
+        if (!(ratio > 0.0)) return;
+        const double *R[4] = {r0, r1, r2, r3};
+        double eS[4];
+        double2 lS[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            eS[j] = R[j][0] * e[0] + R[j][1] * e[1] + R[j][2] * e[2] + R[j][3] * e[3];
+            lS[j] = clog_d(make_double2(zz.x - eS[j], zz.y));
+        }
+        for (int j = 0; j < 4; j++) {
+            const double lam = R[j][v];
+            if (lam == 0.0) continue;
+            double xs[5] = {eS[0], eS[1], eS[2], eS[3], eS[j]};
+            double2 ls[5] = {lS[0], lS[1], lS[2], lS[3], lS[j]};
+            sort5(xs, ls);
+            const double2 d = dd4_sorted(zz, xs, ls);
+            acc.x += ratio * lam * d.x;
+            acc.y += ratio * lam * d.y;
+        }
+    };
+    auto outer = [&](const double (&q0)[4], const double (&q1)[4], const double (&q2)[4], const double (&q3)[4]) {
+        const double Q[4][4] = {{q0[0], q0[1], q0[2], q0[3]}, {q1[0], q1[1], q1[2], q1[3]},
+                                {q2[0], q2[1], q2[2], q2[3]}, {q3[0], q3[1], q3[2], q3[3]}};
+        double phi2[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            phi2[j] = ef - (Q[j][0] * ea[0] + Q[j][1] * ea[1] + Q[j][2] * ea[2] + Q[j][3] * ea[3]);
+        clip_tet(Q, phi2, inner);
+    };
+    clip_tet(T, phi1, outer);
+    return acc;
+}
+
 constexpr int kWThreads = 128;
 
 // One thread per (pair, frequency).  The corner energies e_j and log(z - e_j)
@@ -234,13 +374,22 @@ constexpr int kWThreads = 128;
 // tetrahedra sorts its five nodes (four corners, k's corner doubled) together
 // with their logarithms and evaluates I_v(z) and I_v(z') (only I_v(z) when
 // z' = z*).
+//
+// METAL: the Fermi level ef (hartree) cuts the tetrahedra.  With E_b < ef at
+// all four corners of a tetrahedron and E_a > ef at all four, the insulating
+// integral applies; with E_b >= ef or E_a <= ef at all four, the tetrahedron
+// contributes nothing; otherwise clipped_vertex_integral tiles the part where
+// E_b < ef < E_a (the corner energies of both bands are kept in LDS too).
+template <bool METAL>
 __global__ void __launch_bounds__(kWThreads)
 k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const double *E, const double *T,
           int o0, int nO, int e0, int nE, int k0, long npair, int nfreq, const double2 *freq,
-          double delta, int mode, double2 *w)
+          double delta, int mode, double ef, double2 *w)
 {
     __shared__ double sE[15][kWThreads];
     __shared__ double2 sL[15][kWThreads];
+    __shared__ double sB[METAL ? 15 : 1][kWThreads];
+    __shared__ double sA[METAL ? 15 : 1][kWThreads];
     const int tid = threadIdx.x;
     const long t = (long)blockIdx.x * blockDim.x + tid;
     if (t >= npair * nfreq) return;
@@ -267,7 +416,12 @@ k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const doubl
             const int m1 = n1 + code / 9 - 1, m2 = n2 + (code / 3) % 3 - 1, m3 = n3 + code % 3 - 1;
             const int kv = (mesh_wrap(m1, K1) * K2 + mesh_wrap(m2, K2)) * K3 + mesh_wrap(m3, K3);
             const int kvq = (mesh_wrap(m1 + q1, K1) * K2 + mesh_wrap(m2 + q2, K2)) * K3 + mesh_wrap(m3 + q3, K3);
+            const double eb = E[(long)kv * nband + b] * ha, ea = E[(long)kvq * nband + a] * ha;
             sE[j][tid] = (E[(long)kvq * nband + a] - E[(long)kv * nband + b]) * ha;
+            if constexpr (METAL) {
+                sB[j][tid] = eb;
+                sA[j][tid] = ea;
+            }
         }
         // on the imaginary axis without broadening z' = z*, and since the
         // corner energies are real I_v(z*) = conj(I_v(z)): x = 2 Re sum I_v(z)/6
@@ -278,6 +432,27 @@ k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const doubl
 #pragma unroll
             for (int j = 0; j < 15; j++) sL[j][tid] = clog_d(make_double2(zz.x - sE[j][tid], zz.y));
             for (int tt = 0; tt < 24; tt++) {
+                if constexpr (METAL) {
+                    double e4[4], b4[4], a4[4];
+                    bool all_in = true, none_b = true, none_a = true;
+                    int iv = 0;
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        const int sl = c_tetra.slot[tt][v];
+                        e4[v] = sE[sl][tid];
+                        b4[v] = sB[sl][tid];
+                        a4[v] = sA[sl][tid];
+                        if (sl == kTet.self) iv = v;
+                        all_in = all_in && b4[v] < ef && a4[v] > ef;
+                        none_b = none_b && !(b4[v] < ef);
+                        none_a = none_a && !(a4[v] > ef);
+                    }
+                    if (none_b || none_a) continue;
+                    if (!all_in) {
+                        x = cadd(x, clipped_vertex_integral(zz, e4, b4, a4, ef, iv));
+                        continue;
+                    }
+                }
                 double xs[5];
                 double2 ls[5];
 #pragma unroll
@@ -318,14 +493,20 @@ k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const doubl
 void launch_weights(hipStream_t s, const int kmesh[3], const int iq[3], int nband,
                     const double *E_eV, const double *T, int o0, int o1, int e0, int e1,
                     int k0, int k1, int nfreq, const double2 *freq_eV, double delta_eV,
-                    int mode, double2 *w)
+                    int mode, double ef_eV, double2 *w)
 {
     const long npair = (long)(k1 - k0) * (e1 - e0) * (o1 - o0);
     const long tot = npair * nfreq;
     if (tot == 0) return;
-    hipLaunchKernelGGL(k_weights, dim3((unsigned)((tot + kWThreads - 1) / kWThreads)), dim3(kWThreads), 0, s,
-                       kmesh[0], kmesh[1], kmesh[2], iq[0], iq[1], iq[2], nband, E_eV, T, o0, o1 - o0, e0,
-                       e1 - e0, k0, npair, nfreq, freq_eV, delta_eV, mode, w);
+    const dim3 grid((unsigned)((tot + kWThreads - 1) / kWThreads));
+    if (mode == RP_W_TETRA_METAL)
+        hipLaunchKernelGGL(k_weights<true>, grid, dim3(kWThreads), 0, s, kmesh[0], kmesh[1], kmesh[2], iq[0], iq[1],
+                           iq[2], nband, E_eV, T, o0, o1 - o0, e0, e1 - e0, k0, npair, nfreq, freq_eV, delta_eV,
+                           (int)RP_W_TETRA, ef_eV / kHartreeEv, w);
+    else
+        hipLaunchKernelGGL(k_weights<false>, grid, dim3(kWThreads), 0, s, kmesh[0], kmesh[1], kmesh[2], iq[0], iq[1],
+                           iq[2], nband, E_eV, T, o0, o1 - o0, e0, e1 - e0, k0, npair, nfreq, freq_eV, delta_eV,
+                           mode, 0.0, w);
 }
 
 }  // namespace rp
