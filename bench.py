@@ -504,6 +504,36 @@ def tune_leg(args):
     print(json.dumps({"tuning_table": args.tune, "entries": table["entries"]}), flush=True)
 
 
+def metal_weights_leg(rp, ctx, d, reps: int = 3) -> dict:
+    """The weights of one k batch (two k-points, 16 000 pairs, 20
+    frequencies) with the Fermi level cutting the tetrahedra: E_F is put
+    inside the occupied window of the workload's spectrum (-4 eV), so that the
+    occupied bands above it drop out and those crossing it are clipped;
+    beside it the insulating weights of the same batch."""
+    import torch
+    p = d.prob
+    npair = 2 * p.nocc * p.nemp
+    w = torch.empty((d.nfreq, npair, 2), dtype=torch.float64, device=d.device)
+    out = {}
+    rp.rp_set_fermi_level(ctx, -4.0)
+    for name, mode in (("insulating", rp.RP_W_TETRA), ("metal", rp.RP_W_TETRA_METAL)):
+        args = (ctx, d.cell, p.iq, d.nband, d.energy, d.T, 0, p.nocc, p.nocc, d.nband, 0, 2, d.nfreq, p.freq_eV,
+                p.delta_eV, mode, w)
+        rp.rp_weights(*args)
+        rp.rp_synchronize(ctx)
+        rp.rp_profile(ctx, True)
+        for _ in range(reps):
+            rp.rp_weights(*args)
+        out[name + "_ms_per_launch"] = rp.rp_profile_read(ctx)["weights"][0] / reps
+        rp.rp_profile(ctx, False)
+    rp.rp_set_fermi_level(ctx, float("nan"))
+    out["fermi_eV"] = -4.0
+    out["pairs_x_freq"] = npair * d.nfreq
+    log(f"weights of one k batch: insulating {out['insulating_ms_per_launch']:.2f} ms, "
+        f"metal cut {out['metal_ms_per_launch']:.2f} ms")
+    return out
+
+
 def unfold_leg(rp, ctx, d, eps_inv, reps: int = 5) -> dict:
     """The symmetry-unfolding gathers at the workload's shape: eps^-1 (N_G^2 x
     N_w, Eq. symeps) and the coefficients of one k-point (all bands, Eq.
@@ -721,6 +751,7 @@ def main():
     qterm = None if args.no_qterm else qterm_leg(rp, path, ctx, d, einv_s,
                                                  cpu=not args.no_cpu_baseline and not args.profile_k)
     unfold = None if args.no_qterm else unfold_leg(rp, ctx, d, einv_s)
+    metal_w = None if args.no_qterm else metal_weights_leg(rp, ctx, d)
     ctx.close()
 
     npair_total = d.nk * prob.nocc * prob.nemp
@@ -785,6 +816,7 @@ def main():
         "hbm_a2_a4": hbm,
         "interaction_qterm": qterm,
         "symmetry_unfold": unfold,
+        "metal_weights": metal_w,
         "cpu_baseline": None if baseline is None else {k: baseline[k] for k in
                                                         ("value", "unit", "cores", "cpu_model", "kind",
                                                          "sample")},
