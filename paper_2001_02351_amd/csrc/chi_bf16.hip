@@ -141,11 +141,18 @@ __device__ __forceinline__ void tile_of(int id, int t, int herm, int &rt, int &c
 // block adds its tile into chi (and, for an off-diagonal tile of a Hermitian
 // chi, the conjugate transpose into the mirrored tile); with several slices
 // it writes its FP32 partial tile to part[slice][f][NGP][NGP] for k_chi_reduce.
+//
+// Tail split (stail > 0): the grid is one-dimensional over the units (tile,
+// frequency group), unit = group * tiles + tile.  The first nfull units (whole
+// waves of the chip) run whole; each of the remaining units runs as stail
+// slices of sps pair steps, which write FP32 partial tiles
+// part[(unit - nfull) * stail + slice][NW][128][128] for k_chi_reduce_tail, so
+// that the last wave's work is spread over every compute unit.
 template <int NT, int NW>
 __global__ void __launch_bounds__(256)
 k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, const bf8 *__restrict__ Bp,
            int nfreq, const float2 *__restrict__ wq, int accumulate, double2 *__restrict__ chi, int herm,
-           int sps, float2 *__restrict__ part)
+           int sps, float2 *__restrict__ part, int nfull, int stail)
 {
     constexpr int NPL = 2 * NT;  // B planes
     // per stage: A [4 kg][8 row blocks][4 q][16][2] float2 (32 KB) and
@@ -156,14 +163,33 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
+    const int nt = NGP / kTile;
+    const int ntiles = herm ? nt * (nt + 1) / 2 : nt * nt;
+    int tile = blockIdx.x, group = blockIdx.z, step0 = blockIdx.y * sps, nstep;
+    float2 *tailp = nullptr;          // tail split: this slice's partial tile
+    if (stail > 0) {
+        const int b = blockIdx.x;
+        int unit = b;
+        step0 = 0;
+        nstep = npg / 4;
+        if (b >= nfull) {
+            const int t = b - nfull;
+            unit = nfull + t / stail;
+            step0 = (t % stail) * sps;
+            nstep = max(0, min(sps, npg / 4 - step0));
+            tailp = part + (long)t * NW * kTile * kTile;
+        }
+        tile = unit % ntiles;
+        group = unit / ntiles;
+    } else {
+        nstep = min(sps, npg / 4 - step0);
+    }
     int rt, ct;
-    tile_of(blockIdx.x, NGP / kTile, herm, rt, ct);
+    tile_of(tile, nt, herm, rt, ct);
     const int rt0 = rt * kTile, ct0 = ct * kTile;
     const int wr = wave >> 1, wc = wave & 1;
-    const int f0 = blockIdx.z * NW;
+    const int f0 = group * NW;
     const long plane = (long)npg * NGP;
-    const int step0 = blockIdx.y * sps;
-    const int nstep = min(sps, npg / 4 - step0);
 
     // DMA segments of 1 KB; wave w moves pair group kg = w: its 8 A row
     // blocks and its NPL x 2 B half-rows
@@ -309,7 +335,23 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     }
 
     // result register r of lane (li, lk) holds row 4 lk + r, column li of a 16x16 block
-    if (part) {
+    if (tailp) {
+#pragma unroll
+        for (int iw = 0; iw < NW; iw++)
+#pragma unroll
+            for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+                for (int cb = 0; cb < 4; cb++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int i = wr * 64 + rb * 16 + 4 * lk + r;
+                        const int j = wc * 64 + cb * 16 + li;
+                        tailp[((long)iw * kTile + i) * kTile + j] =
+                            make_float2(accR[iw][rb][cb][r], accI[iw][rb][cb][r]);
+                    }
+        return;
+    }
+    if (part && stail == 0) {
 #pragma unroll
         for (int iw = 0; iw < NW; iw++) {
             if (f0 + iw >= nfreq) continue;
@@ -580,6 +622,59 @@ k_chi_reduce(int nslice, int nfreq, int ng, int NGP, const float2 *__restrict__ 
     }
 }
 
+// chi (+)= sum over the stail slices of a tail unit's partial tiles (FP64
+// sum), with the mirrored conjugate transpose of an off-diagonal tile of a
+// Hermitian chi.  Block: 32 x 32 elements of one tail unit and one frequency
+// of its group (grid x = tail unit * 16 + chunk, z = frequency in the group).
+__global__ void __launch_bounds__(256)
+k_chi_reduce_tail(int nfull, int stail, int NGP, int nw, int nfreq, int ng, int herm, int accumulate,
+                  const float2 *__restrict__ part, double2 *__restrict__ chi)
+{
+    __shared__ double2 tr[32][33];
+    const int nt = NGP / kTile;
+    const int ntiles = herm ? nt * (nt + 1) / 2 : nt * nt;
+    const int u = blockIdx.x / 16, ch = blockIdx.x % 16;
+    const int unit = nfull + u;
+    const int tile = unit % ntiles, group = unit / ntiles;
+    const int iw = blockIdx.z, f = group * nw + iw;
+    if (f >= nfreq) return;
+    int rt, ct;
+    tile_of(tile, nt, herm, rt, ct);
+    const int ci = ch / 4, cj = ch % 4;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    double2 *C = chi + (long)f * ng * ng;
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        const int il = ci * 32 + ty + 8 * m, jl = cj * 32 + tx;
+        const float2 *src = part + (((long)u * stail) * nw + iw) * kTile * kTile + (long)il * kTile + jl;
+        double2 v = make_double2(0.0, 0.0);
+        for (int sl = 0; sl < stail; sl++) {
+            const float2 x = src[(long)sl * nw * kTile * kTile];
+            v.x += (double)x.x;
+            v.y += (double)x.y;
+        }
+        const int i = rt * kTile + il, j = ct * kTile + jl;
+        if (i < ng && j < ng) {
+            const long idx = (long)i * ng + j;
+            C[idx] = accumulate ? cadd(C[idx], v) : v;
+        }
+        tr[ty + 8 * m][tx] = v;
+    }
+    if (!(herm && rt != ct)) return;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        // element (row ct*128 + cj*32 + ty + 8m, column rt*128 + ci*32 + tx) of the mirrored tile
+        const int i = ct * kTile + cj * 32 + ty + 8 * m, j = rt * kTile + ci * 32 + tx;
+        const double2 a = tr[tx][ty + 8 * m];
+        const double2 v = make_double2(a.x, -a.y);
+        if (i < ng && j < ng) {
+            const long idx = (long)i * ng + j;
+            C[idx] = accumulate ? cadd(C[idx], v) : v;
+        }
+    }
+}
+
 long pad_pairs(long npair) { return (npair + kStep - 1) / kStep * kStep; }
 int pad_ng(int ng) { return (ng + kTile - 1) / kTile * kTile; }
 
@@ -625,11 +720,61 @@ static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fil
     *nslice = std::max(1, (nstep + per - 1) / per);
 }
 
+// Compute units of the current device (cached per device).
+static int cu_count()
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        hipDeviceProp_t prop;
+        cached[dev] = hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0
+                          ? prop.multiProcessorCount
+                          : 256;
+    }
+    return cached[dev];
+}
+
+// Tail split of the 128 x 128 form when the pair steps are not sliced: the
+// units (tile, frequency group) beyond the last whole wave of the chip run as
+// stail slices each, stail (2..16, each slice >= 8 steps) chosen to minimize
+// the time of the tail, ceil(R stail / CUs) / stail unit-times for R tail
+// units; *stail = 0 when no split helps (or slicing is off, fill = 0).
+static void tail_plan(long units, int nstep, int fill, int *nfull, int *stail)
+{
+    *nfull = (int)units;
+    *stail = 0;
+    const int cu = cu_count();
+    if (fill == 0 || units < cu) return;
+    const long R = units % cu;
+    if (R == 0) return;
+    double best = 1.0;
+    for (int sl = 2; sl <= 16 && nstep / sl >= 8; sl++) {
+        const double cost = (double)((R * sl + cu - 1) / cu) / sl;
+        if (cost < best - 1e-9) {
+            best = cost;
+            *stail = sl;
+        }
+    }
+    if (*stail) *nfull = (int)(units - R);
+}
+
 size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill, int kernel, int nterm)
 {
     int S, sps;
-    chi_slices(npair, ng, nfreq, herm, nw == 1 ? 1 : 2, fill, eff_kernel(kernel, ng, herm, nterm), &S, &sps);
-    if (S == 1) return 0;
+    const int form = eff_kernel(kernel, ng, herm, nterm);
+    nw = nw == 1 ? 1 : 2;
+    chi_slices(npair, ng, nfreq, herm, nw, fill, form, &S, &sps);
+    if (S == 1) {
+        if (form != 0) return 0;
+        const int t = pad_ng(ng) / kTile;
+        const long units = (herm ? (long)t * (t + 1) / 2 : (long)t * t) * ((nfreq + nw - 1) / nw);
+        int nfull, stail;
+        tail_plan(units, (int)(pad_pairs(npair) / kStep), fill, &nfull, &stail);
+        if (!stail) return 0;
+        return (size_t)(units - nfull) * stail * nw * kTile * kTile * sizeof(float2);
+    }
     return (size_t)S * nfreq * (size_t)pad_ng(ng) * pad_ng(ng) * sizeof(float2);
 }
 
@@ -688,10 +833,18 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
 #undef RP_CHIW
     } else {
         const unsigned tiles = herm ? (unsigned)(t * (t + 1) / 2) : (unsigned)(t * t);
-        const dim3 grid(tiles, (unsigned)S, nfg);
+        int nfull = 0, stail = 0;
+        if (S == 1) tail_plan((long)tiles * nfg, npg / 4, fill, &nfull, &stail);
+        const long ntail = stail ? (long)tiles * nfg - nfull : 0;
+        if (stail) {
+            sps = (npg / 4 + stail - 1) / stail;
+            P = (float2 *)part;
+        }
+        const dim3 grid = stail ? dim3((unsigned)(nfull + ntail * stail)) : dim3(tiles, (unsigned)S, nfg);
 #define RP_CHI(NT, NW)                                                                                         \
     hipLaunchKernelGGL((k_chi_bf16<NT, NW>), grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a, \
-                       (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P)
+                       (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P, \
+                       nfull, stail)
         if (nterm == 2) {
             if (nw == 1) RP_CHI(2, 1);
             else RP_CHI(2, 2);
@@ -700,6 +853,9 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
             else RP_CHI(3, 2);
         }
 #undef RP_CHI
+        if (stail)
+            hipLaunchKernelGGL(k_chi_reduce_tail, dim3((unsigned)(ntail * 16), 1, (unsigned)nw), dim3(256), 0, s,
+                               nfull, stail, NGP, nw, nfreq, ng, (int)herm, accumulate, (const float2 *)P, chi);
     }
     if (S > 1) {
         const int nc = NGP / 32;

@@ -130,3 +130,44 @@ def test_wide_contraction_form_matches(ctx, rp):
                   f"vs oracle {d_orc:.1e}", flush=True)
             assert d_ref < 1e-6 and d_orc < 1e-5
     rp.rp_set_tuning(ctx, [])
+
+
+@pytest.mark.parametrize("herm", [False, True])
+def test_tail_split_matches(ctx, rp, herm):
+    """The tail split (units beyond the last whole wave run as slices of the
+    pair steps, summed in FP64 by k_chi_reduce_tail): 360 units on complex
+    weights (N_G = 700, 20 real frequencies) and on the Hermitian half
+    (N_G = 1132, 16 imaginary frequencies), chi_fill = 400 so that the pair
+    steps are not sliced otherwise; against the unsplit run (fill 0) to 1e-6
+    and the oracle on sampled columns to 1e-5."""
+    from paper_2001_02351_amd import path
+    from synth import make_problem
+    if herm:
+        p = batch_system(21, 0)
+        o, e = (0, 8), (p.nocc, p.nocc + 16)
+    else:
+        p = make_problem(name="tail", a_bohr=7.26, fft=(24, 24, 24), kmesh=(2, 2, 2), iq=(1, 0, 0), nocc=8,
+                         nemp=24, gpsi=2.4, ng=700, freq_eV=np.linspace(0.0, 20.0, 20), delta_eV=0.1, seed=41)
+        o, e = (0, p.nocc), (p.nocc, p.nband)
+    d = path.DeviceInputs(p)
+
+    def chi_for(entries):
+        rp.rp_set_tuning(ctx, entries)
+        M = path.pair_density(ctx, d, 0, d.nk, o=o, e=e, prec=rp.RP_SPLIT_BF16)
+        chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device="cuda")
+        rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, d.T, *o, *e, 0, d.nk, d.ng, M, d.nfreq,
+                              p.freq_eV, p.delta_eV, path.weight_mode(p), rp.RP_SPLIT_BF16, 0, chi)
+        rp.rp_synchronize(ctx)
+        return path.to_complex(chi)
+
+    ref = chi_for([_entry(chi_fill=0)])
+    got = chi_for([_entry(chi_fill=400)])
+    M = oracle.pair_densities(p, *o, *e, 0, d.nk)
+    w = oracle.prob_weights(p, *o, *e, 0, d.nk)
+    cols = np.unique(np.concatenate([np.random.default_rng(8).choice(d.ng, 24, replace=False), [d.ng - 1]]))
+    want = oracle.chi0(M[:, cols], w)
+    d_ref = max(_rel(got[f], ref[f]) for f in range(d.nfreq))
+    d_orc = max(_rel(got[f][cols][:, cols], want[f]) for f in range(d.nfreq))
+    print(f"[tuning] tail split herm={herm}: vs unsplit {d_ref:.1e}, vs oracle {d_orc:.1e}", flush=True)
+    assert d_ref < 1e-6 and d_orc < 1e-5
+    rp.rp_set_tuning(ctx, [])
