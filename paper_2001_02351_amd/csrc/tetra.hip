@@ -163,8 +163,10 @@ __device__ __forceinline__ double2 dd_series(double2 z, const double *x, int a, 
         const double fh = c_series.f[m] * P[N];
         const double2 t = make_double2(wp.x * fh, wp.y * fh);
         sum = cadd(sum, t);
+        // stop after two consecutive terms below 1e-17 of the sum: the terms
+        // shrink at least fourfold, and FP64 resolves 1.1e-16 of the sum
         const double tm = fabs(t.x) + fabs(t.y), sm = fabs(sum.x) + fabs(sum.y);
-        if (tm <= 1e-18 * sm) {
+        if (tm <= 1e-17 * sm) {
             if (++quiet == 2) break;
         } else {
             quiet = 0;
