@@ -653,7 +653,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--fp64-warmup", type=int, default=0)
-    ap.add_argument("--kbatch", type=int, default=2)
+    ap.add_argument("--kbatch", type=int, default=16)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-x6", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -40,6 +40,11 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 128;
 constexpr int kStep = 32;  // pairs per matrix-core step
+// The FP32 accumulators of one block sum at most kFlush steps of 32 pairs
+// (16 384 pairs): a longer contraction is cut into slices of the pair steps
+// whose FP32 partial tiles are summed in FP64, so the accumulation error does
+// not grow with the pairs per launch.
+constexpr int kFlush = 512;
 
 __device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c)
 {
@@ -715,6 +720,10 @@ static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fil
         S = (int)std::min<long>((fill + blocks - 1) / blocks, nstep / 8);
         S = std::max(1, std::min(S, 64));
     }
+    // no slice longer than kFlush steps of the 128 x 128 form (the wide
+    // forms' steps hold 16 pairs)
+    const int lim = wide ? 2 * kFlush : kFlush;
+    S = std::max(S, (nstep + lim - 1) / lim);
     const int per = std::max(1, (nstep + S - 1) / S);
     *sps = per;
     *nslice = std::max(1, (nstep + per - 1) / per);
