@@ -141,8 +141,8 @@ __device__ __forceinline__ void tile_of(int id, int t, int herm, int &rt, int &c
     ct = rt + id;
 }
 
-// Grid: x = tile (all t x t tiles, or the upper triangle when herm), y = slice
-// of the pair steps (sps steps each), z = frequency group.  With one slice the
+// Grid: x = tile (all t x t tiles, or the upper triangle when herm), y =
+// frequency group, z = slice of the pair steps (sps steps each).  With one slice the
 // block adds its tile into chi (and, for an off-diagonal tile of a Hermitian
 // chi, the conjugate transpose into the mirrored tile); with several slices
 // it writes its FP32 partial tile to part[slice][f][NGP][NGP] for k_chi_reduce.
@@ -170,7 +170,9 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     const int li = lane & 15, lk = lane >> 4;
     const int nt = NGP / kTile;
     const int ntiles = herm ? nt * (nt + 1) / 2 : nt * nt;
-    int tile = blockIdx.x, group = blockIdx.z, step0 = blockIdx.y * sps, nstep;
+    // grid: x = tile, y = frequency group, z = slice of the pair steps (slowest,
+    // so that the blocks in flight share one slice's operands)
+    int tile = blockIdx.x, group = blockIdx.y, step0 = blockIdx.z * sps, nstep;
     float2 *tailp = nullptr;          // tail split: this slice's partial tile
     if (stail > 0) {
         const int b = blockIdx.x;
@@ -360,7 +362,7 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
 #pragma unroll
         for (int iw = 0; iw < NW; iw++) {
             if (f0 + iw >= nfreq) continue;
-            float2 *P = part + ((long)blockIdx.y * nfreq + f0 + iw) * NGP * NGP;
+            float2 *P = part + ((long)blockIdx.z * nfreq + f0 + iw) * NGP * NGP;
 #pragma unroll
             for (int rb = 0; rb < 4; rb++)
 #pragma unroll
@@ -849,7 +851,7 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
             sps = (npg / 4 + stail - 1) / stail;
             P = (float2 *)part;
         }
-        const dim3 grid = stail ? dim3((unsigned)(nfull + ntail * stail)) : dim3(tiles, (unsigned)S, nfg);
+        const dim3 grid = stail ? dim3((unsigned)(nfull + ntail * stail)) : dim3(tiles, nfg, (unsigned)S);
 #define RP_CHI(NT, NW)                                                                                         \
     hipLaunchKernelGGL((k_chi_bf16<NT, NW>), grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a, \
                        (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P, \
