@@ -505,20 +505,33 @@ def tune_leg(args):
 
 
 def metal_weights_leg(rp, ctx, d, reps: int = 3) -> dict:
-    """The weights of one k batch (two k-points, 16 000 pairs, 20
-    frequencies) with the Fermi level cutting the tetrahedra: E_F is put
-    inside the occupied window of the workload's spectrum (-4 eV), so that the
-    occupied bands above it drop out and those crossing it are clipped;
-    beside it the insulating weights of the same batch."""
+    """The weights of one k batch (two k-points, 20 frequencies) of a metal
+    shaped like the workload's: 40 + 200 bands on its 8^3 mesh with smooth
+    cosine dispersion (bandwidth 2 eV), the three bands 37..39 crossing
+    E_F = 0 (the t2g-like bands of the paper's metal), so they appear in both
+    band ranges (occupied 0..39, empty 37..239, 16 240 pairs per k-point); the
+    same batch with the insulating weights beside it.  Only the tetrahedra
+    near the Fermi surface of the crossing bands are cut."""
+    import math
+
+    import numpy as np
     import torch
     p = d.prob
-    npair = 2 * p.nocc * p.nemp
+    nb = d.nband
+    kf = np.stack(np.meshgrid(*[np.arange(K) / K for K in p.kmesh], indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(11)
+    centre = np.concatenate([np.linspace(-8.0, -1.5, 37), [-0.6, 0.0, 0.6], np.linspace(1.5, 20.0, nb - 40)])
+    phase = rng.uniform(0.0, 2.0 * math.pi, (nb, 3))
+    E = np.stack([centre[n] - (1.0 / 3.0) * np.sum(np.cos(2.0 * math.pi * kf + phase[n]), axis=1)
+                  for n in range(nb)], axis=1)
+    Ed = torch.from_numpy(np.ascontiguousarray(E)).to(d.device)
+    o, e = (0, p.nocc), (p.nocc - 3, nb)
+    npair = 2 * (o[1] - o[0]) * (e[1] - e[0])
     w = torch.empty((d.nfreq, npair, 2), dtype=torch.float64, device=d.device)
     out = {}
-    rp.rp_set_fermi_level(ctx, -4.0)
+    rp.rp_set_fermi_level(ctx, 0.0)
     for name, mode in (("insulating", rp.RP_W_TETRA), ("metal", rp.RP_W_TETRA_METAL)):
-        args = (ctx, d.cell, p.iq, d.nband, d.energy, d.T, 0, p.nocc, p.nocc, d.nband, 0, 2, d.nfreq, p.freq_eV,
-                p.delta_eV, mode, w)
+        args = (ctx, d.cell, p.iq, nb, Ed, None, *o, *e, 0, 2, d.nfreq, p.freq_eV, p.delta_eV, mode, w)
         rp.rp_weights(*args)
         rp.rp_synchronize(ctx)
         rp.rp_profile(ctx, True)
@@ -527,10 +540,9 @@ def metal_weights_leg(rp, ctx, d, reps: int = 3) -> dict:
         out[name + "_ms_per_launch"] = rp.rp_profile_read(ctx)["weights"][0] / reps
         rp.rp_profile(ctx, False)
     rp.rp_set_fermi_level(ctx, float("nan"))
-    out["fermi_eV"] = -4.0
-    out["pairs_x_freq"] = npair * d.nfreq
-    log(f"weights of one k batch: insulating {out['insulating_ms_per_launch']:.2f} ms, "
-        f"metal cut {out['metal_ms_per_launch']:.2f} ms")
+    out.update(fermi_eV=0.0, crossing_bands=3, pairs_x_freq=npair * d.nfreq)
+    log(f"weights of one k batch of the metal: insulating {out['insulating_ms_per_launch']:.2f} ms, "
+        f"Fermi-level cut {out['metal_ms_per_launch']:.2f} ms")
     return out
 
 
