@@ -458,6 +458,7 @@ def supercell_leg(args):
                         f"pair densities streamed in blocks of {eb} empty bands",
             "pairs_timed": pairs,
             "pairs_total": p.nocc * p.nemp,
+            "pair_grid": list(rp.rp_pair_grid(d.cell, p.iq, d.mmax, p.gsph, rp.RP_SPLIT_BF16)),
             "ng": d.ng,
             "nfreq": d.nfreq,
         },
@@ -767,6 +768,7 @@ def main():
     ctx.close()
 
     npair_total = d.nk * prob.nocc * prob.nemp
+    pair_grid = rp.rp_pair_grid(d.cell, prob.iq, d.mmax, prob.gsph, rp.RP_SPLIT_BF16)
     achieved = split["chi_kernel_flops_per_launch"] / (split["chi_kernel_ms_per_launch"] / 1e3) / 1e12
     rec = recorded_traffic()
     pc = recorded_pair_counters()
@@ -774,7 +776,7 @@ def main():
     if pc is not None:
         t_pair = split["stage_ms_per_step"]["pair"] / d.nk / 1e3      # s per k-point (one launch)
         t_ugrid = split["stage_ms_per_step"]["ugrid"] / d.nk / 1e3
-        alg = (prob.nocc + prob.nemp) * int(np.prod(prob.fft)) * 8 + prob.nocc * prob.nemp * d.ng * 16
+        alg = (prob.nocc + prob.nemp) * int(np.prod(pair_grid)) * 8 + prob.nocc * prob.nemp * d.ng * 16
         hbm = {
             "pair_kernel": {"bytes_per_launch": pc["pair_bytes_per_launch"], "ms_per_launch": t_pair * 1e3,
                             "achieved_GB_s": pc["pair_bytes_per_launch"] / t_pair / 1e9,
@@ -804,6 +806,7 @@ def main():
             "ng": d.ng,
             "nfreq": d.nfreq,
             "kbatch": args.kbatch,
+            "pair_grid": list(pair_grid),
             "precision": "split-BF16 chi0 (hi/mid BF16 terms, three-term compensated products, FP32 "
                          "accumulation, FP64 sum; FP32 pair-density grids), FP64 weights, eps^-1 and W_ij",
         },

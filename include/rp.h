@@ -118,7 +118,9 @@ const char *rp_last_error(const rp_ctx *ctx);
  *   u_{nk}(r_j) = sum_{G in S_psi(k)} C_{Gn}(k) e^{iG.r_j}                       (Eq. pak)
  *   M_p(G) = (1/N_r) sum_j conj(u_{a,k'}(r_j)) u_{b,k}(r_j) e^{i(G+G0).r_j}
  * where k+q = k' + G0 with k' on the mesh.  This equals the plane-wave
- * definition exactly when N_a > 2 mmax_a + max|m_a + G0_a| on each axis.
+ * definition exactly when N_a > 2 mmax_a + max|m_a + G0_a| on each axis, on
+ * cell->fft or on any smaller grid that satisfies it: the steps run on the
+ * grid rp_pair_grid reports.
  *
  * nband, npw_max     : bands and padded plane-wave count of coef/miller
  * npw      (host)    : int[Nk] plane waves per k
@@ -141,6 +143,22 @@ rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int
                           int npw_max, const int *npw, const int mmax[3], const int *miller,
                           const double *coef, int o0, int o1, int e0, int e1, int k0, int k1,
                           int ng, const int *gsph, rp_precision prec, double *M);
+
+/*
+ * The grid that rp_pair_density and the chi0 entry points that build pair
+ * densities run steps a2-a4 on, for these arguments; host computation only
+ * (no context).  Once N_a > 2 mmax_a + max|m_a + G0_a| on every axis, the
+ * FFT route gives the plane-wave definition of Eq. ism exactly, whatever the
+ * grid; the library then takes the smallest such grid that its lane kernels
+ * take (N2 = N3 from their line lengths, N1 any 2^a 3^b 5^c), never larger
+ * than cell->fft, and keeps cell->fft where none fits.  cell->fft itself
+ * must satisfy the condition (else RP_E_ALIAS, as in rp_pair_density).
+ * mmax (host) int[3], gsph (host) int[ng][3], prec: as rp_pair_density.
+ * grid (host) int[3] output.
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE, RP_E_ALIAS, RP_E_UNSUPPORTED.
+ */
+rp_status rp_pair_grid(const rp_cell *cell, const int iq[3], const int mmax[3], int ng,
+                       const int *gsph, rp_precision prec, int grid[3]);
 
 /*
  * Step a5: weights w_p(omega_f) = (2/Nk)(1 - T_{a,k+q} T_{b,k}) x_p(omega_f)

@@ -36,6 +36,7 @@ from ._rp import (  # noqa: F401
     rp_wannier_qterm,
     rp_coulomb_cell_average,
     rp_frequency_grid,
+    rp_pair_grid,
     rp_unfold_coef,
     rp_unfold_eps_inv,
     rp_set_fermi_level,

@@ -31,7 +31,7 @@ EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pa
             "rp_weights", "rp_chi0_accumulate", "rp_chi0_batch", "rp_screen_W", "rp_wannier_W",
             "rp_set_tuning", "rp_head_density", "rp_screen_head", "rp_wannier_qterm",
             "rp_coulomb_cell_average", "rp_frequency_grid", "rp_unfold_coef", "rp_unfold_eps_inv",
-            "rp_set_fermi_level", "rp_profile", "rp_profile_read"]
+            "rp_set_fermi_level", "rp_pair_grid", "rp_profile", "rp_profile_read"]
 
 STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier", "batch", "unfold"]
 
@@ -113,6 +113,7 @@ def load(path: Optional[str] = None):
         "rp_unfold_coef": [P, cellp, P, P, P, I, I, P, P, ctypes.c_long, P, I, P, P, ctypes.c_long],
         "rp_unfold_eps_inv": [P, cellp, P, P, P, I, P, P, I, P, I, P, P],
         "rp_set_fermi_level": [P, D],
+        "rp_pair_grid": [cellp, P, P, I, P, I, P],
         "rp_profile": [P, I],
         "rp_profile_read": [P, P, P],
     }
@@ -343,6 +344,18 @@ def rp_coulomb_cell_average(cell: rp_cell) -> float:
     if st != 0:
         raise RpError(st, "rp_coulomb_cell_average", "invalid cell")
     return out.value
+
+
+def rp_pair_grid(cell: rp_cell, iq, mmax, gsph, prec: int) -> tuple:
+    """The grid (N1, N2, N3) that the pair densities are built on for these
+    arguments (host computation; no context or device needed)."""
+    iq_h, mm_h, g_h = _host(iq, np.int32), _host(mmax, np.int32), _host(gsph, np.int32)
+    out = np.zeros(3, np.int32)
+    st = load().rp_pair_grid(ctypes.byref(cell), _hp(iq_h), _hp(mm_h), int(g_h.shape[0]), _hp(g_h), int(prec),
+                             _hp(out))
+    if st != 0:
+        raise RpError(st, "rp_pair_grid", STATUS_NAMES.get(st, str(st)))
+    return tuple(int(x) for x in out)
 
 
 def rp_frequency_grid(emax_eV: float, dw_eV: float = 0.05, nomega: int = 70, nmax: int = 0) -> np.ndarray:

@@ -419,6 +419,25 @@ static bool pair_lanes_f64(const int fft[3], int ng, int L3)
     }
 }
 
+int pair_lane_edge(int need, int limit, int ng, int L3, bool fp32)
+{
+    int best = 0;
+    auto take = [&](int n) {
+        const int f[3] = {1, n, n};
+        if (n < need || n > limit || (best && n >= best)) return;
+        if (fp32 ? pair_lanes_f32(f, ng, L3) : pair_lanes_f64(f, ng, L3)) best = n;
+    };
+#define RP_CASE(n) take(n);
+    if (fp32) {
+        RP_LANE_LENGTHS_F32(RP_CASE)
+        take(96);
+    } else {
+        RP_LANE_LENGTHS_F64(RP_CASE)
+    }
+#undef RP_CASE
+    return best;
+}
+
 bool pair_supported(const int fft[3], int ng, int L3, bool fp32)
 {
     if (fp32 ? pair_lanes_f32(fft, ng, L3) : pair_lanes_f64(fft, ng, L3)) return true;

@@ -220,6 +220,46 @@ static bool valid_prec(rp_precision prec)
     return prec == RP_FP64 || prec == RP_SPLIT_BF16 || prec == RP_SPLIT_BF16_X6;
 }
 
+// The Miller window [lo, hi] of the sphere per axis, and the grid that steps
+// a2-a4 run on.  The cell's grid must hold the sphere products alias-free:
+// N_a > 2 mmax_a + max |m_a + G0_a| (G0_a in {0, 1} when iq_a > 0).  The pair
+// densities at the sphere points (Eq. ism) are then the same on every such
+// grid, so the steps run on the smallest one the lane kernels take (N2 = N3
+// from their lengths, N1 any length with a plan), never larger than the
+// cell's; where no lane length fits, on the cell's grid.
+static rp_status pair_grid(rp_ctx *ctx, const Geometry &g, const int mmax[3], int ng, const int *gsph, bool fp32,
+                           int lo[3], int hi[3], int grid[3])
+{
+    int need[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = 1 << 30;
+        hi[a] = -(1 << 30);
+        for (int i = 0; i < ng; i++) {
+            lo[a] = std::min(lo[a], gsph[3 * i + a]);
+            hi[a] = std::max(hi[a], gsph[3 * i + a]);
+        }
+        const int up = hi[a] + (g.iq[a] > 0 ? 1 : 0);
+        const int gmax = std::max(std::abs(lo[a]), std::abs(up));
+        if (mmax[a] < 0) return fail(ctx, RP_E_SHAPE, "mmax[%d] < 0", a);
+        if (g.fft[a] <= 2 * mmax[a] + gmax)
+            return fail(ctx, RP_E_ALIAS, "axis %d: N=%d <= 2*mmax+|G|max = %d (pair products alias)", a,
+                        g.fft[a], 2 * mmax[a] + gmax);
+        need[a] = 2 * mmax[a] + gmax + 1;
+        grid[a] = g.fft[a];
+    }
+    if (g.fft[1] != g.fft[2]) return RP_OK;
+    const int n23 = pair_lane_edge(std::max(need[1], need[2]), g.fft[1], ng, hi[2] - lo[2] + 1, fp32);
+    if (!n23) return RP_OK;
+    FftPlan p;
+    for (int n = need[0]; n < g.fft[0]; n++)
+        if (make_plan(n, &p)) {
+            grid[0] = n;
+            break;
+        }
+    grid[1] = grid[2] = n23;
+    return RP_OK;
+}
+
 static rp_status pair_check(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband, int npw_max,
                             const int *npw, const int mmax[3], const int *miller, const double *coef, int o0,
                             int o1, int e0, int e1, int k0, int k1, int ng, const int *gsph, rp_precision prec,
@@ -240,23 +280,14 @@ static rp_status pair_check(rp_ctx *ctx, const rp_cell *cell, const int iq[3], i
     if ((st = plans3(ctx, g, j->plans)) != RP_OK) return st;
     for (int k = 0; k < g.nk; k++)
         if (npw[k] < 0 || npw[k] > npw_max) return fail(ctx, RP_E_SHAPE, "npw[%d] outside [0, npw_max]", k);
-    // alias-free condition per axis: N > 2 mmax + max |m + G0|, G0 in {0, 1} when iq > 0
+    int grid[3];
+    if ((st = pair_grid(ctx, g, mmax, ng, gsph, j->fp32, j->lo, j->hi, grid)) != RP_OK) return st;
+    j->fft_lines = tune_for(ctx, ng, g.fft).fft_lines;
     for (int a = 0; a < 3; a++) {
-        int lo = 1 << 30, hi = -(1 << 30);
-        for (int i = 0; i < ng; i++) {
-            lo = std::min(lo, gsph[3 * i + a]);
-            hi = std::max(hi, gsph[3 * i + a]);
-        }
-        j->lo[a] = lo;
-        j->hi[a] = hi;
-        const int up = hi + (iq[a] > 0 ? 1 : 0);
-        const int gmax = std::max(std::abs(lo), std::abs(up));
-        if (mmax[a] < 0) return fail(ctx, RP_E_SHAPE, "mmax[%d] < 0", a);
-        if (g.fft[a] <= 2 * mmax[a] + gmax)
-            return fail(ctx, RP_E_ALIAS, "axis %d: N=%d <= 2*mmax+|G|max = %d (pair products alias)", a,
-                        g.fft[a], 2 * mmax[a] + gmax);
         j->mmax[a] = mmax[a];
+        j->g.fft[a] = grid[a];
     }
+    if ((st = plans3(ctx, g, j->plans)) != RP_OK) return st;
     j->nband = nband;
     j->npw_max = npw_max;
     j->npw = npw;
@@ -267,7 +298,6 @@ static rp_status pair_check(rp_ctx *ctx, const rp_cell *cell, const int iq[3], i
     j->e0 = e0;
     j->e1 = e1;
     j->ng = ng;
-    j->fft_lines = tune_for(ctx, ng, g.fft).fft_lines;
     j->empty = (long)(o1 - o0) * (e1 - e0) * (k1 - k0) == 0;
     if (j->empty) return RP_OK;
     // the pair kernels' LDS plans (m3 window of the sphere, hi - lo + 1)
@@ -593,6 +623,21 @@ rp_status rp_pair_density(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int
     if ((st = ensure(ctx, grid, pair_grid_bytes(j))) != RP_OK) return st;
     if ((st = upload(ctx, ctx->glist, gsph, sizeof(int) * 3 * ng)) != RP_OK) return st;
     return pair_enqueue(ctx, j, k0, k1, (const int *)ctx->glist.p, grid.p, (double2 *)M);
+}
+
+rp_status rp_pair_grid(const rp_cell *cell, const int iq[3], const int mmax[3], int ng, const int *gsph,
+                       rp_precision prec, int grid[3])
+{
+    if (!mmax || !gsph || !grid) return RP_E_NULL;
+    Geometry g;
+    rp_status st = geometry(nullptr, cell, iq, &g);
+    if (st != RP_OK) return st;
+    if (ng < 1 || ng > 6144) return RP_E_UNSUPPORTED;
+    if (!valid_prec(prec)) return RP_E_RANGE;
+    FftPlan plans[3];
+    if ((st = plans3(nullptr, g, plans)) != RP_OK) return st;
+    int lo[3], hi[3];
+    return pair_grid(nullptr, g, mmax, ng, gsph, prec != RP_FP64, lo, hi, grid);
 }
 
 rp_status rp_weights(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband,

@@ -134,6 +134,9 @@ size_t pair_lds_bytes(const int fft[3], int L3, int rows, size_t csize, int npai
 int pair_rows(const int fft[3]);
 // whether a pair kernel can run this grid, sphere size and m3 window
 bool pair_supported(const int fft[3], int ng, int L3, bool fp32);
+// the smallest line length n of the lane kernels with need <= n <= limit that
+// takes this sphere and m3 window as N2 = N3 = n, or 0
+int pair_lane_edge(int need, int limit, int ng, int L3, bool fp32);
 void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], const void *u_occ,
                    const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3],
                    int lo3, int L3, bool fp32, double2 *M);

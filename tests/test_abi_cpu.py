@@ -125,3 +125,35 @@ def test_cell_average_host_routine_matches_the_oracle():
         assert abs(got - want) < 1e-12 * want, (kmesh, got, want)
     with pytest.raises(rp.RpError):
         rp.rp_coulomb_cell_average(rp.make_cell(np.zeros((3, 3)), (8, 8, 8), (2, 2, 2)))
+
+
+def test_pair_grid_is_the_smallest_alias_free_lane_grid():
+    """rp_pair_grid (host code): the grid that steps a2-a4 run on holds the
+    sphere products alias-free (N > 2 mmax + max |m + G0| per axis), takes
+    N2 = N3 from the lane kernels' lengths of the precision and N1 from
+    2^a 3^b 5^c, is never larger than the cell's grid, and is the cell's grid
+    where no lane length fits."""
+    import paper_2001_02351_amd as rp
+    from synth.gen import A_SRVO3_BOHR, qpoint_gvectors
+    lat = np.eye(3) * A_SRVO3_BOHR
+    g, _ = qpoint_gvectors(lat, (8, 8, 8), (1, 0, 0), 1500, 10.0)
+    cell = rp.make_cell(lat, (48, 48, 48), (8, 8, 8))
+    for prec in (rp.RP_FP64, rp.RP_SPLIT_BF16):
+        assert rp.rp_pair_grid(cell, (1, 0, 0), (12, 12, 12), g, prec) == (32, 32, 32)
+    # m in [-7, 6] on axis 1 and q's G0 = 1 there: 2*12 + 7 = 31 < 32 on every axis;
+    # one more unit of mmax on axis 1 needs N > 33 there: 36 for both of N2 = N3
+    assert rp.rp_pair_grid(cell, (1, 0, 0), (12, 13, 12), g, rp.RP_SPLIT_BF16) == (32, 36, 36)
+    assert rp.rp_pair_grid(cell, (1, 0, 0), (13, 12, 12), g, rp.RP_SPLIT_BF16) == (36, 32, 32)
+    # bound 2*11 + 3 = 25: FP32 lines of 27, FP64 lines of 32 (no 25, 27, 30 in FP64); N1 = 27
+    cube = np.array([(i, j, k) for i in range(-3, 4) for j in range(-3, 4) for k in range(-3, 4)], np.int32)
+    c0 = rp.make_cell(lat, (48, 48, 48), (2, 2, 2))
+    assert rp.rp_pair_grid(c0, (0, 0, 0), (11, 11, 11), cube, rp.RP_SPLIT_BF16) == (27, 27, 27)
+    assert rp.rp_pair_grid(c0, (0, 0, 0), (11, 11, 11), cube, rp.RP_FP64) == (27, 32, 32)
+    # never above the cell's grid; N2 != N3 keeps the cell's grid
+    for fft, want in (((30, 30, 30), (27, 27, 27)), ((27, 27, 27), (27, 27, 27)), ((32, 30, 30), (27, 27, 27)),
+                      ((48, 48, 40), (48, 48, 40))):
+        got = rp.rp_pair_grid(rp.make_cell(lat, fft, (2, 2, 2)), (0, 0, 0), (11, 11, 11), cube, rp.RP_SPLIT_BF16)
+        assert got == want, (fft, got)
+    with pytest.raises(rp.RpError) as e:
+        rp.rp_pair_grid(rp.make_cell(lat, (24, 24, 24), (2, 2, 2)), (0, 0, 0), (11, 11, 11), cube, rp.RP_FP64)
+    assert e.value.status == 4                      # RP_E_ALIAS: the cell's own grid folds

@@ -74,6 +74,31 @@ def test_pair_density_matches_oracle(ctx, c1, d1):
     assert _rel(M3, want) < 2e-6
 
 
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-6)])
+def test_pair_density_on_a_smaller_alias_free_grid(ctx, rp, prec, tol):
+    """A cell grid (40^3) far above what the sphere products need: steps
+    a2-a4 run on the smaller grid rp_pair_grid reports and still give the
+    oracle's densities on the cell's grid and the exact plane-wave form."""
+    from paper_2001_02351_amd import path
+    p = make_problem(name="oversampled", a_bohr=7.26, fft=(40, 40, 40), kmesh=(2, 2, 2), iq=(1, 0, 1), nocc=3,
+                     nemp=4, gpsi=2.6, ng=27, freq_eV=np.array([0.0]), delta_eV=0.1, seed=5)
+    d = path.DeviceInputs(p)
+    grid = rp.rp_pair_grid(d.cell, p.iq, d.mmax, p.gsph, prec)
+    print(f"[pair grid] prec={prec} cell 40^3 -> {grid}", flush=True)
+    assert np.prod(grid) * 8 < np.prod(p.fft)
+    M = path.to_complex(path.pair_density(ctx, d, 0, p.nk, prec=prec))
+    want = oracle.pair_densities(p, 0, p.nocc, p.nocc, p.nocc + p.nemp, 0, p.nk)
+    assert _rel(M, want) < tol
+    kp, g0 = oracle.kq(p.kmesh, p.iq)
+    for k in (0, 5):
+        n, kk = int(p.npw[k]), int(kp[k])
+        na = int(p.npw[kk])
+        row = (k * p.nemp + 2) * p.nocc + 1              # empty band nocc + 2 at k+q, occupied band 1 at k
+        exact = oracle.pair_conv(p.miller[kk, :na], p.coef[kk, p.nocc + 2, :na], p.miller[k, :n], p.coef[k, 1, :n],
+                                 g0[k], p.gsph)
+        assert np.max(np.abs(M[row] - exact)) < tol * np.abs(exact).max()
+
+
 def test_weights_match_oracle(ctx, rp, c1, d1):
     from paper_2001_02351_amd import path
     p, ref = c1
