@@ -19,6 +19,7 @@ marshals numpy arrays and strings the steps together in the paper's order:
   frequency grid (oracle.grid)                 Eq. grid
   symmetry unfolding (oracle.symmetry)         Eqs. red-wavefunction, coef-G, symeps
   metallic tetrahedron weights (oracle.metal)  Eqs. Xakqbk, tetrahedron (Fermi-level cut)
+  intraband (Drude) head term (oracle.drude)   Eqs. eps00, plasma, momentum
 
 Parity status of each function is listed in its docstring.
 """
