@@ -453,8 +453,13 @@ rp_status rp_head_density(rp_ctx *ctx, const rp_cell *cell, int nband, int npw_m
  *   optics[f] = {Re eps_M, Im eps_M, L, Re sigma, R}
  * with eps_M = 1/eps^-1_00, L = -Im eps^-1_00, Re sigma = (w/4 pi) Im eps_M
  * (w = Re freq in hartree, sigma in atomic units) and the reflectance
- * R = |(sqrt(eps_M) - 1)/(sqrt(eps_M) + 1)|^2.  No intraband (Drude) term:
- * the plasma-frequency term of Eq. eps00 is not included.
+ * R = |(sqrt(eps_M) - 1)/(sqrt(eps_M) + 1)|^2.  The intraband term of Eq.
+ * eps00 enters the head when rp_set_drude has set one: eps_00 -= wq /
+ * (w (w + i delta)) (w = freq_eV, complex).  Where w (w + i delta) = 0 that
+ * term is infinite: eps^-1 gets a zero head row and column and the inverse
+ * of eps's body (the limit), and that frequency's optics are
+ * {NaN, NaN, 0, NaN, 1} (L = 0 and R = 1 in the limit, eps_M and sigma
+ * undefined).
  *
  * gsph     (host) : int[ng][3], G = 0 first, no other zero vector
  * freq_eV  (host) : c128[nfreq]
@@ -466,6 +471,39 @@ rp_status rp_head_density(rp_ctx *ctx, const rp_cell *cell, int nband, int npw_m
 rp_status rp_screen_head(rp_ctx *ctx, const rp_cell *cell, int ng, const int *gsph, int nfreq,
                          const double *freq_eV, const double *chi, double *eps_inv,
                          double *optics);
+
+/*
+ * The plasma tensor of the intraband term (Eqs. eps00, plasma, momentum), in
+ * eV^2:
+ *   Omega^{mu nu} = (4 pi / Omega) (2 / N_k) sum_k sum_{a in [b0, b1)}
+ *                   (1 - T_ak^2) p^mu_a(k) p^nu_a(k) delta(E_ak - E_F)
+ * with the diagonal moments p_a(k) = <psi_a| -i grad |psi_a> = sum_G
+ * |C_Ga(k)|^2 (k + G) (Cartesian, the non-local term dropped as in the
+ * paper) and the Fermi-surface delta integrated on the linear tetrahedra of
+ * the weights (6 per mesh cell around its (0,0,0)-(1,1,1) diagonal).  The
+ * paper prints the Fermi-surface sum without the factor 4 pi / Omega and the
+ * spin sum 2; with them a free-electron gas gives 4 pi n.  The head term
+ * along qhat is wq = qhat . Omega . qhat (rp_set_drude).
+ *
+ * npw (host int[Nk]), miller (dev), coef (dev): as rp_pair_density;
+ * energy_eV (dev double[Nk][nband]); T (dev double[Nk][nband]) or NULL (no
+ * cRPA factor); bands [b0, b1) enter the sum (those that cross E_F matter).
+ * omega2_eV2 (host double[3][3]) output.  The call waits for the device.
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE, RP_E_NOMEM, RP_E_DEVICE.
+ */
+rp_status rp_plasma_frequency(rp_ctx *ctx, const rp_cell *cell, int nband, int npw_max,
+                              const int *npw, const int *miller, const double *coef,
+                              const double *energy_eV, const double *T, int b0, int b1,
+                              double ef_eV, double *omega2_eV2);
+
+/*
+ * The intraband term that rp_screen_head subtracts from eps_00 (Eq. eps00):
+ * wq = qhat . Omega . qhat (eV^2) and the broadening delta (eV) of
+ * -wq / (w (w + i delta)); wq = 0 removes it (the default, and Eq.
+ * eps00-cRPA).
+ * Errors: RP_E_NULL, RP_E_RANGE (non-finite, delta < 0).
+ */
+rp_status rp_set_drude(rp_ctx *ctx, double wq_eV2, double delta_eV);
 
 /*
  * Launch-shape tuning per size class (the autotuner in the Python package

@@ -37,6 +37,8 @@ from ._rp import (  # noqa: F401
     rp_coulomb_cell_average,
     rp_frequency_grid,
     rp_pair_grid,
+    rp_plasma_frequency,
+    rp_set_drude,
     rp_unfold_coef,
     rp_unfold_eps_inv,
     rp_set_fermi_level,

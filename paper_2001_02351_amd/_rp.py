@@ -31,7 +31,8 @@ EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pa
             "rp_weights", "rp_chi0_accumulate", "rp_chi0_batch", "rp_screen_W", "rp_wannier_W",
             "rp_set_tuning", "rp_head_density", "rp_screen_head", "rp_wannier_qterm",
             "rp_coulomb_cell_average", "rp_frequency_grid", "rp_unfold_coef", "rp_unfold_eps_inv",
-            "rp_set_fermi_level", "rp_pair_grid", "rp_profile", "rp_profile_read"]
+            "rp_set_fermi_level", "rp_pair_grid", "rp_plasma_frequency", "rp_set_drude", "rp_profile",
+            "rp_profile_read"]
 
 STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier", "batch", "unfold"]
 
@@ -114,6 +115,8 @@ def load(path: Optional[str] = None):
         "rp_unfold_eps_inv": [P, cellp, P, P, P, I, P, P, I, P, I, P, P],
         "rp_set_fermi_level": [P, D],
         "rp_pair_grid": [cellp, P, P, I, P, I, P],
+        "rp_plasma_frequency": [P, cellp, I, I, P, P, P, P, P, I, I, D, P],
+        "rp_set_drude": [P, D, D],
         "rp_profile": [P, I],
         "rp_profile_read": [P, P, P],
     }
@@ -344,6 +347,26 @@ def rp_coulomb_cell_average(cell: rp_cell) -> float:
     if st != 0:
         raise RpError(st, "rp_coulomb_cell_average", "invalid cell")
     return out.value
+
+
+def rp_plasma_frequency(ctx, cell: rp_cell, nband: int, npw_max: int, npw, miller, coef, energy_eV, T, b0: int,
+                        b1: int, ef_eV: float) -> np.ndarray:
+    """The intraband plasma tensor Omega^{mu nu} (eV^2, 3 x 3) of bands [b0, b1)."""
+    npw_h = _host(npw, np.int32)
+    out = np.zeros(9, np.float64)
+    ctx._enter()
+    st = ctx.lib.rp_plasma_frequency(ctx.handle, ctypes.byref(cell), int(nband), int(npw_max), _hp(npw_h),
+                                     _dp(miller), _dp(coef), _dp(energy_eV), _dp(T), int(b0), int(b1), float(ef_eV),
+                                     _hp(out))
+    ctx._leave()
+    ctx._check(st, "rp_plasma_frequency")
+    return out.reshape(3, 3)
+
+
+def rp_set_drude(ctx, wq_eV2: float, delta_eV: float) -> None:
+    """The intraband head term wq = qhat.Omega.qhat (eV^2) and its broadening
+    for rp_screen_head; wq = 0 removes it."""
+    ctx._check(ctx.lib.rp_set_drude(ctx.handle, float(wq_eV2), float(delta_eV)), "rp_set_drude")
 
 
 def rp_pair_grid(cell: rp_cell, iq, mmax, gsph, prec: int) -> tuple:

@@ -926,6 +926,52 @@ rp_status rp_head_density(rp_ctx *ctx, const rp_cell *cell, int nband, int npw_m
     return check_launch(ctx, "head density");
 }
 
+rp_status rp_plasma_frequency(rp_ctx *ctx, const rp_cell *cell, int nband, int npw_max, const int *npw,
+                              const int *miller, const double *coef, const double *energy_eV, const double *T, int b0,
+                              int b1, double ef_eV, double *omega2_eV2)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    Geometry g;
+    const int iq0[3] = {0, 0, 0};
+    rp_status st = geometry(ctx, cell, iq0, &g);
+    if (st != RP_OK) return st;
+    if (!npw || !miller || !coef || !energy_eV || !omega2_eV2) return fail(ctx, RP_E_NULL, "NULL array argument");
+    if (nband < 1 || b0 < 0 || b1 > nband || b0 > b1)
+        return fail(ctx, RP_E_RANGE, "band range [%d, %d) outside [0, nband = %d)", b0, b1, nband);
+    if (npw_max < 1) return fail(ctx, RP_E_SHAPE, "npw_max must be >= 1");
+    for (int k = 0; k < g.nk; k++)
+        if (npw[k] < 0 || npw[k] > npw_max) return fail(ctx, RP_E_SHAPE, "npw[%d] outside [0, npw_max]", k);
+    if (!std::isfinite(ef_eV)) return fail(ctx, RP_E_RANGE, "non-finite Fermi level");
+    const long n = (long)g.nk * (b1 - b0);
+    // workspace (doubles): p [n][3] | contributions [n][6] | sums [6]
+    if ((st = ensure(ctx, ctx->work, sizeof(double) * (9 * (size_t)n + 6))) != RP_OK) return st;
+    if ((st = upload(ctx, ctx->kinfo, npw, sizeof(int) * g.nk)) != RP_OK) return st;
+    double *p = (double *)ctx->work.p, *contrib = p + 3 * n, *sums = contrib + 6 * n;
+    launch_pdiag(ctx->stream, g, miller, (const double2 *)coef, (const int *)ctx->kinfo.p, nband, npw_max, b0, b1, p);
+    launch_fermi_plasma(ctx->stream, g.kmesh, nband, energy_eV, T, b0, b1, ef_eV, p, contrib, sums);
+    if ((st = check_launch(ctx, "plasma frequency")) != RP_OK) return st;
+    double h[6];
+    if (hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return fail(ctx, RP_E_DEVICE, "plasma frequency: copy to host failed");
+    // (4 pi / Omega) x 2 (spin) in hartree^2, then eV^2
+    const double s = 4.0 * kPi / g.volume * 2.0 * kHartreeEv * kHartreeEv;
+    const int ix[9] = {0, 3, 4, 3, 1, 5, 4, 5, 2};
+    for (int i = 0; i < 9; i++) omega2_eV2[i] = s * h[ix[i]];
+    return RP_OK;
+}
+
+rp_status rp_set_drude(rp_ctx *ctx, double wq_eV2, double delta_eV)
+{
+    if (!ctx) return RP_E_NULL;
+    if (!std::isfinite(wq_eV2) || !std::isfinite(delta_eV) || delta_eV < 0.0)
+        return fail(ctx, RP_E_RANGE, "the intraband term needs finite wq and delta >= 0");
+    ctx->drude_wq = wq_eV2;
+    ctx->drude_delta = delta_eV;
+    return RP_OK;
+}
+
 rp_status rp_screen_head(rp_ctx *ctx, const rp_cell *cell, int ng, const int *gsph, int nfreq,
                          const double *freq_eV, const double *chi, double *eps_inv, double *optics)
 {
@@ -957,8 +1003,12 @@ rp_status rp_screen_head(rp_ctx *ctx, const rp_cell *cell, int ng, const int *gs
     StageTimer t(ctx, RP_STAGE_SCREEN);
     launch_vsqrt(ctx->stream, g, ng, (const int *)ctx->glist.p, vs, ctx->flag, true);
     launch_eps(ctx->stream, nfreq, ng, vs, (const double2 *)chi, a, ctx->flag);
+    const double2 *fq = (const double2 *)ctx->freq.p;
+    const bool drude = ctx->drude_wq != 0.0;
+    if (drude) launch_drude_head(ctx->stream, nfreq, ng, fq, ctx->drude_wq, ctx->drude_delta, a);
     launch_invert(ctx->stream, nfreq, ng, a, (double2 *)ctx->rho.p, (int *)ctx->piv.p, ctx->flag);
-    if (optics) launch_optics(ctx->stream, nfreq, ng, a, (const double2 *)ctx->freq.p, optics);
+    if (drude) launch_drude_zero(ctx->stream, nfreq, ng, fq, ctx->drude_delta, a);
+    if (optics) launch_optics(ctx->stream, nfreq, ng, a, fq, optics);
     return check_launch(ctx, "screen head");
 }
 

@@ -76,6 +76,8 @@ struct rp_ctx {
     bool capturing = false;         // stage timers stay off while a graph is captured
     std::vector<rp_tune_entry> tuning;  // launch shapes per size class, matched in order
     double fermi_eV = std::nan("");  // Fermi level of the metallic weights (RP_W_TETRA_METAL)
+    double drude_wq = 0.0;           // intraband head term qhat.Omega.qhat (eV^2) of rp_screen_head
+    double drude_delta = 0.0;        // its broadening (eV)
     // stage timers
     bool profiling = false;
     struct Mark {
@@ -181,6 +183,17 @@ void launch_head(hipStream_t s, const Geometry &g, const int *miller, const doub
                  const int *npw_dev, int nband, int npw_max, int o0, int o1, int e0, int e1, int k0, int k1,
                  const double qhat[3], int ldm, int col, double2 *M, int *flag);
 void launch_optics(hipStream_t s, int nfreq, int ng, const double2 *einv, const double2 *freq, double *out);
+// head.hip: diagonal moments p[k][b1 - b0][3] (Cartesian) of bands [b0, b1)
+void launch_pdiag(hipStream_t s, const Geometry &g, const int *miller, const double2 *coef, const int *npw_dev,
+                  int nband, int npw_max, int b0, int b1, double *p);
+// head.hip: the intraband term of eps_00 (before the inversion) and the zero
+// head of eps^-1 where it is infinite (after it)
+void launch_drude_head(hipStream_t s, int nfreq, int ng, const double2 *freq, double wq, double delta, double2 *eps);
+void launch_drude_zero(hipStream_t s, int nfreq, int ng, const double2 *freq, double delta, double2 *einv);
+// tetra.hip: Fermi-surface weights times (1 - T^2) p p^T per (k, band), summed
+// into out[6] = {xx, yy, zz, xy, xz, yz} (contrib: [Nk][b1 - b0][6] workspace)
+void launch_fermi_plasma(hipStream_t s, const int kmesh[3], int nband, const double *E_eV, const double *T, int b0,
+                         int b1, double ef_eV, const double *p, double *contrib, double *out);
 
 // wannier.hip
 void launch_wannier_density(hipStream_t s, const Geometry &g, const FftPlan plans[3], int nwan,

@@ -490,6 +490,129 @@ k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const doubl
     w[t] = cscale(x, fac);
 }
 
+// ---- Fermi-surface weights of the intraband term (Eq. plasma) ----
+//
+// D_v = (1/|T|) int_T lambda_v delta(e - E) d^3k for the linear interpolant e
+// of the corner energies over T.  The section {e = E} is a triangle (one
+// corner on one side of E) or a quadrilateral (two on each side) with its
+// corners on the edges that E separates.  In the reference tetrahedron (corner
+// 0 at the origin, corner j at the j-th unit vector, volume 1/6) the delta
+// turns the volume integral into a section integral over |grad e|, and the
+// mean of the linear lambda_v over each triangle of the section is the mean of
+// its corner values.
+__device__ double fermi_corner(const double (&e)[4], int v, double E)
+{
+    int lo[4], hi[4], nl = 0, nh = 0;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        if (e[c] < E) lo[nl++] = c;
+        else hi[nh++] = c;
+    }
+    if (nl == 0 || nh == 0) return 0.0;
+    const double gx = e[1] - e[0], gy = e[2] - e[0], gz = e[3] - e[0];
+    const double gn = sqrt(gx * gx + gy * gy + gz * gz);
+    double P[4][3], L[4];
+    int np = 0;
+    // the point of edge (i, j) where e = E, and lambda_v there
+    auto edge = [&](int i, int j) {
+        const double t = (E - e[i]) / (e[j] - e[i]);
+#pragma unroll
+        for (int d = 0; d < 3; d++) P[np][d] = (i == d + 1 ? 1.0 - t : 0.0) + (j == d + 1 ? t : 0.0);
+        L[np] = (v == i ? 1.0 - t : 0.0) + (v == j ? t : 0.0);
+        np++;
+    };
+    if (nl == 1) {
+        edge(lo[0], hi[0]);
+        edge(lo[0], hi[1]);
+        edge(lo[0], hi[2]);
+    } else if (nh == 1) {
+        edge(lo[0], hi[0]);
+        edge(lo[1], hi[0]);
+        edge(lo[2], hi[0]);
+    } else {
+        // in cyclic order: consecutive corners share a face of T
+        edge(lo[0], hi[0]);
+        edge(lo[0], hi[1]);
+        edge(lo[1], hi[1]);
+        edge(lo[1], hi[0]);
+    }
+    auto area = [&](int a, int b, int c) {
+        const double u0 = P[b][0] - P[a][0], u1 = P[b][1] - P[a][1], u2 = P[b][2] - P[a][2];
+        const double w0 = P[c][0] - P[a][0], w1 = P[c][1] - P[a][1], w2 = P[c][2] - P[a][2];
+        const double x = u1 * w2 - u2 * w1, y = u2 * w0 - u0 * w2, z = u0 * w1 - u1 * w0;
+        return 0.5 * sqrt(x * x + y * y + z * z);
+    };
+    double sum = area(0, 1, 2) * (L[0] + L[1] + L[2]) / 3.0;
+    if (np == 4) sum += area(0, 2, 3) * (L[0] + L[2] + L[3]) / 3.0;
+    return 6.0 * sum / gn;
+}
+
+// One thread per (k, band a in [b0, b0 + nb)): the Fermi-surface weight
+// D(k) = (1/(6 N_k)) sum over the 24 tetrahedra around k of k's corner weight,
+// times (1 - T^2), times p p^T: contrib[t] = {xx, yy, zz, xy, xz, yz}.
+__global__ void __launch_bounds__(256)
+k_fermi_plasma(int K1, int K2, int K3, int nband, const double *__restrict__ E, const double *__restrict__ T,
+               int b0, int nb, double ef, const double *__restrict__ p, double *__restrict__ contrib)
+{
+    const int nk = K1 * K2 * K3;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nk * nb) return;
+    const int k = (int)(t / nb), a = b0 + (int)(t - (long)k * nb);
+    const int n1 = k / (K2 * K3), n2 = (k / K3) % K2, n3 = k % K3;
+    const double ha = 1.0 / kHartreeEv;
+    double e15[15];
+#pragma unroll
+    for (int j = 0; j < 15; j++) {
+        const int code = kTet.nbr[j];
+        const int kv = (mesh_wrap(n1 + code / 9 - 1, K1) * K2 + mesh_wrap(n2 + (code / 3) % 3 - 1, K2)) * K3 +
+                       mesh_wrap(n3 + code % 3 - 1, K3);
+        e15[j] = E[(long)kv * nband + a] * ha;
+    }
+    double D = 0.0;
+#pragma unroll
+    for (int tt = 0; tt < 24; tt++) {
+        double e[4];
+        int v = 0;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            e[c] = e15[kTet.slot[tt][c]];
+            if (kTet.slot[tt][c] == kTet.self) v = c;
+        }
+        D += fermi_corner(e, v, ef);
+    }
+    D /= 6.0 * nk;
+    if (T) D *= 1.0 - T[(long)k * nband + a] * T[(long)k * nband + a];
+    const double px = p[3 * t], py = p[3 * t + 1], pz = p[3 * t + 2];
+    double *o = contrib + 6 * t;
+    o[0] = D * px * px;
+    o[1] = D * py * py;
+    o[2] = D * pz * pz;
+    o[3] = D * px * py;
+    o[4] = D * px * pz;
+    o[5] = D * py * pz;
+}
+
+// out[q] = sum_t c[t][q], q < 6, in one block
+__global__ void __launch_bounds__(256) k_sum6(long n, const double *__restrict__ c, double *__restrict__ out)
+{
+    __shared__ double red[6][256];
+    const int tid = threadIdx.x;
+    double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (long i = tid; i < n; i += 256)
+#pragma unroll
+        for (int q = 0; q < 6; q++) s[q] += c[6 * i + q];
+#pragma unroll
+    for (int q = 0; q < 6; q++) red[q][tid] = s[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w)
+#pragma unroll
+            for (int q = 0; q < 6; q++) red[q][tid] += red[q][tid + w];
+        __syncthreads();
+    }
+    if (tid < 6) out[tid] = red[tid][0];
+}
+
 }  // namespace
 
 void launch_weights(hipStream_t s, const int kmesh[3], const int iq[3], int nband,
@@ -509,6 +632,16 @@ void launch_weights(hipStream_t s, const int kmesh[3], const int iq[3], int nban
         hipLaunchKernelGGL(k_weights<false>, grid, dim3(kWThreads), 0, s, kmesh[0], kmesh[1], kmesh[2], iq[0], iq[1],
                            iq[2], nband, E_eV, T, o0, o1 - o0, e0, e1 - e0, k0, npair, nfreq, freq_eV, delta_eV,
                            mode, 0.0, w);
+}
+
+void launch_fermi_plasma(hipStream_t s, const int kmesh[3], int nband, const double *E_eV, const double *T, int b0,
+                         int b1, double ef_eV, const double *p, double *contrib, double *out)
+{
+    const long n = (long)kmesh[0] * kmesh[1] * kmesh[2] * (b1 - b0);
+    if (n > 0)
+        hipLaunchKernelGGL(k_fermi_plasma, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, kmesh[0], kmesh[1],
+                           kmesh[2], nband, E_eV, T, b0, b1 - b0, ef_eV / kHartreeEv, p, contrib);
+    hipLaunchKernelGGL(k_sum6, dim3(1), dim3(256), 0, s, n, contrib, out);
 }
 
 }  // namespace rp

@@ -1,0 +1,131 @@
+"""GPU parity of the intraband (Drude) head term (Eqs. eps00, plasma,
+momentum) against the oracle (oracle/drude.py): the plasma tensor of a metal
+with and without the cRPA factor, and eps^-1 at q -> 0 with the term on the
+real and the imaginary axis, including the frequencies where it is
+infinite."""
+
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+from oracle import drude, head
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HA = drude.HARTREE_EV
+
+
+@pytest.fixture(scope="module")
+def rp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_02351_amd as rp
+    rp.load()
+    return rp
+
+
+@pytest.fixture(scope="module")
+def ctx(rp):
+    c = rp.Context(0)
+    yield c
+    c.close()
+
+
+def _metal():
+    from synth import make_problem
+    p = make_problem(name="drude", a_bohr=7.26, fft=(12, 12, 12), kmesh=(4, 3, 3), iq=(0, 0, 0), nocc=3, nemp=3,
+                     gpsi=2.4, ng=19, freq_eV=np.array([0.0]), delta_eV=0.1, seed=23)
+    kf = np.stack(np.meshgrid(*[np.arange(K) / K for K in p.kmesh], indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(5)
+    c = np.sort(rng.uniform(-3.0, 3.0, 6))
+    t = rng.uniform(0.5, 1.5, (6, 3))
+    E = np.stack([c[n] - np.sum(t[n] * np.cos(2 * math.pi * kf + n), axis=1) for n in range(6)], 1)
+    T = rng.uniform(0.0, 1.0, E.shape)
+    return dataclasses.replace(p, energy_eV=np.ascontiguousarray(E), T=np.ascontiguousarray(T))
+
+
+@pytest.mark.parametrize("crpa", [False, True])
+def test_plasma_tensor_matches_oracle(rp, ctx, crpa):
+    from paper_2001_02351_amd import path
+    p = _metal()
+    d = path.DeviceInputs(p)
+    ef, b0, b1 = 0.2, 1, 6
+    got = rp.rp_plasma_frequency(ctx, d.cell, d.nband, p.miller.shape[1], p.npw, d.miller, d.coef, d.energy,
+                                 d.T if crpa else None, b0, b1, ef)
+    want = drude.plasma_tensor(p, b0, b1, ef, T=p.T if crpa else None) * HA * HA
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"[drude] plasma tensor crpa={crpa}: diag {np.diag(got)} eV^2, rel {err:.1e}", flush=True)
+    assert np.abs(want).max() > 0.1
+    assert err < 1e-10
+    # E_F below every band: no Fermi surface
+    z = rp.rp_plasma_frequency(ctx, d.cell, d.nband, p.miller.shape[1], p.npw, d.miller, d.coef, d.energy, None, 0,
+                               6, -50.0)
+    assert np.all(z == 0.0)
+
+
+def _chi(ng, nfreq, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nfreq):
+        a = rng.normal(size=(ng, ng)) + 1j * rng.normal(size=(ng, ng))
+        h = -(a @ a.conj().T) * (0.02 / ng)
+        out.append(h + 0.002j * np.eye(ng))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("axis", ["real", "imaginary"])
+def test_drude_head_matches_oracle(rp, ctx, axis):
+    lat = np.eye(3) * 7.26
+    cell = rp.make_cell(lat, (12, 12, 12), (4, 4, 4))
+    gsph = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [-1, 0, 0], [0, -1, 0], [0, 0, -1], [1, 1, 0],
+                     [1, -1, 0], [0, 1, 1], [1, 0, 1]], np.int32)
+    ng = len(gsph)
+    if axis == "real":
+        freq, delta = np.array([0.0, 0.5, 2.0, 6.0, 15.0], np.complex128), 0.1
+    else:
+        freq, delta = 1j * np.array([0.0, 0.3, 2.0, 9.0]), 0.0
+    nf = len(freq)
+    chi = _chi(ng, nf, 7)
+    wq = 9.5                                    # eV^2
+    chi_d = torch.from_numpy(chi.view(np.float64).reshape(nf, ng, ng, 2).copy()).cuda()
+    einv = torch.empty_like(chi_d)
+    opt = torch.empty((nf, 5), dtype=torch.float64, device="cuda")
+    rp.rp_set_drude(ctx, wq, delta)
+    try:
+        rp.rp_screen_head(ctx, cell, ng, gsph, nf, freq, chi_d, einv, opt)
+        rp.rp_synchronize(ctx)
+    finally:
+        rp.rp_set_drude(ctx, 0.0, 0.0)
+    a = einv.cpu().numpy()
+    got = a[..., 0] + 1j * a[..., 1]
+    _, want = drude.drude_head(lat, gsph, chi, freq, delta, wq / HA ** 2, np.linalg.inv)
+    err = max(np.linalg.norm(got[f] - want[f]) / np.linalg.norm(want[f]) for f in range(nf))
+    print(f"[drude] head {axis}: eps^-1 rel {err:.1e}; eps^-1_00 {got[:, 0, 0]}", flush=True)
+    assert err < 1e-12
+    assert np.all(got[0, 0, :] == 0) and np.all(got[0, :, 0] == 0)      # w = 0: infinite head
+    o = opt.cpu().numpy()
+    assert o[0, 2] == 0.0 and o[0, 4] == 1.0 and np.all(np.isnan(o[0, [0, 1, 3]]))
+    ref = head.optics(want[1:, 0, 0], freq[1:])
+    for j, key in enumerate(("eps_M", None, "eels", "sigma", "refl")):
+        if key is None:
+            continue
+        w = ref[key].real if key == "eps_M" else ref[key]
+        assert np.allclose(o[1:, j], w, rtol=1e-10, atol=1e-13), key
+    assert np.allclose(o[1:, 1], ref["eps_M"].imag, rtol=1e-10, atol=1e-13)
+    # the term removed: the head oracle without it
+    rp.rp_screen_head(ctx, cell, ng, gsph, nf, freq, chi_d, einv, None)
+    rp.rp_synchronize(ctx)
+    a = einv.cpu().numpy()
+    _, plain = head.screen_head(lat, gsph, chi, np.linalg.inv)
+    assert np.max(np.abs(a[..., 0] + 1j * a[..., 1] - plain)) < 1e-12 * np.abs(plain).max()
+
+
+def test_drude_arguments(rp, ctx):
+    with pytest.raises(rp.RpError):
+        rp.rp_set_drude(ctx, float("nan"), 0.1)
+    with pytest.raises(rp.RpError):
+        rp.rp_set_drude(ctx, 1.0, -0.1)
+    rp.rp_set_drude(ctx, 0.0, 0.0)
