@@ -547,6 +547,34 @@ def metal_weights_leg(rp, ctx, d, reps: int = 3) -> dict:
     return out
 
 
+def drude_leg(rp, ctx, d, reps: int = 5) -> dict:
+    """The intraband plasma tensor (Eq. plasma) of the metal of
+    metal_weights_leg (the workload's coefficients on its 8^3 mesh, the cosine
+    spectrum with bands 37..39 crossing E_F = 0): diagonal moments of the three
+    bands and their Fermi-surface tetrahedron weights, one synchronous call."""
+    import math
+
+    import numpy as np
+    import torch
+    p = d.prob
+    nb = d.nband
+    kf = np.stack(np.meshgrid(*[np.arange(K) / K for K in p.kmesh], indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(11)
+    centre = np.concatenate([np.linspace(-8.0, -1.5, 37), [-0.6, 0.0, 0.6], np.linspace(1.5, 20.0, nb - 40)])
+    phase = rng.uniform(0.0, 2.0 * math.pi, (nb, 3))
+    E = np.stack([centre[n] - (1.0 / 3.0) * np.sum(np.cos(2.0 * math.pi * kf + phase[n]), axis=1)
+                  for n in range(nb)], axis=1)
+    Ed = torch.from_numpy(np.ascontiguousarray(E)).to(d.device)
+    args = (ctx, d.cell, nb, p.miller.shape[1], p.npw, d.miller, d.coef, Ed, None, 37, 40, 0.0)
+    om = rp.rp_plasma_frequency(*args)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        om = rp.rp_plasma_frequency(*args)
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    log(f"plasma tensor of the three bands at E_F: {ms:.3f} ms per call, diagonal {np.diag(om).round(3)} eV^2")
+    return {"ms_per_call": ms, "bands": [37, 40], "fermi_eV": 0.0, "omega2_eV2_diag": np.diag(om).tolist()}
+
+
 def unfold_leg(rp, ctx, d, eps_inv, reps: int = 5) -> dict:
     """The symmetry-unfolding gathers at the workload's shape: eps^-1 (N_G^2 x
     N_w, Eq. symeps) and the coefficients of one k-point (all bands, Eq.
@@ -765,6 +793,7 @@ def main():
                                                  cpu=not args.no_cpu_baseline and not args.profile_k)
     unfold = None if args.no_qterm else unfold_leg(rp, ctx, d, einv_s)
     metal_w = None if args.no_qterm else metal_weights_leg(rp, ctx, d)
+    drude_o = None if args.no_qterm else drude_leg(rp, ctx, d)
     ctx.close()
 
     npair_total = d.nk * prob.nocc * prob.nemp
@@ -832,6 +861,7 @@ def main():
         "interaction_qterm": qterm,
         "symmetry_unfold": unfold,
         "metal_weights": metal_w,
+        "drude_plasma": drude_o,
         "cpu_baseline": None if baseline is None else {k: baseline[k] for k in
                                                         ("value", "unit", "cores", "cpu_model", "kind",
                                                          "sample")},
