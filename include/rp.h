@@ -436,8 +436,11 @@ rp_status rp_unfold_eps_inv(rp_ctx *ctx, const rp_cell *cell, const int W[9], co
  * npw (host int[Nk]), miller (dev), coef (dev): as rp_pair_density;
  * energy_eV (dev double[Nk][nband]).
  * qhat (host double[3]): direction of q, Cartesian, normalized here.
- * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE, RP_E_NOMEM, RP_E_DEVICE; a pair
- * with E_a = E_b is flagged non-finite (rp_synchronize) and gets 0.
+ * Where the band ranges overlap (a metal) the intraband pairs a = b get 0:
+ * at q -> 0 they belong to the intraband term (rp_plasma_frequency,
+ * rp_set_drude).
+ * Errors: RP_E_NULL, RP_E_SHAPE, RP_E_RANGE, RP_E_NOMEM, RP_E_DEVICE; any
+ * other pair with E_a = E_b is flagged non-finite (rp_synchronize) and gets 0.
  */
 rp_status rp_head_density(rp_ctx *ctx, const rp_cell *cell, int nband, int npw_max, const int *npw,
                           const int *miller, const double *coef, const double *energy_eV, int o0,

@@ -52,7 +52,10 @@ def momentum_k(rec, kfrac, miller, coef_a, coef_b) -> np.ndarray:
 def head_density(prob, o0, o1, e0, e1, k0, k1, qhat) -> np.ndarray:
     """h[(k, a, b)] = qhat . p_ab(k) / (E_a(k) - E_b(k)) (energies in
     hartree) for occupied b in [o0, o1), empty a in [e0, e1), k in [k0, k1);
-    the pair layout of the pair densities (b fastest)."""
+    the pair layout of the pair densities (b fastest).  Where the band ranges
+    overlap (a metal), the intraband pairs a = b get h = 0: at q -> 0 they
+    belong to the intraband (Drude) term of Eq. eps00, not to the head
+    density."""
     rec = reciprocal(prob.lat)
     qhat = np.asarray(qhat, np.float64)
     qhat = qhat / np.linalg.norm(qhat)
@@ -65,7 +68,8 @@ def head_density(prob, o0, o1, e0, e1, k0, k1, qhat) -> np.ndarray:
         p = momentum_k(rec, kfrac, prob.miller[k, :n], prob.coef[k, e0:e1, :n], prob.coef[k, o0:o1, :n])
         pq = np.tensordot(qhat, p, axes=(0, 0))            # [a][b]
         de = (prob.energy_eV[k, e0:e1][:, None] - prob.energy_eV[k, o0:o1][None, :]) / HARTREE_EV
-        out[k - k0] = pq / de
+        same = (np.arange(e0, e1)[:, None] == np.arange(o0, o1)[None, :])
+        out[k - k0] = np.where(same, 0.0, pq / np.where(same, 1.0, de))
     return out.reshape(-1)
 
 

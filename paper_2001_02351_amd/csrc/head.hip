@@ -87,8 +87,11 @@ k_head(const int *__restrict__ miller, const double2 *__restrict__ coef, const d
     if (l4 == 0 && a < e0 + nE && b < o0 + nO) {
         const double de = (E[(long)k * nband + a] - E[(long)k * nband + b]) / kHartreeEv;
         const long p = ((long)(k - k0) * nE + (a - e0)) * nO + (b - o0);
+        // an intraband pair (a = b, overlapping band ranges of a metal) belongs
+        // to the intraband term of the head, not to the head density
         double2 h = make_double2(0.0, 0.0);
-        if (de != 0.0) h = make_double2(acc.x / de, acc.y / de);
+        if (a == b) h = make_double2(0.0, 0.0);
+        else if (de != 0.0) h = make_double2(acc.x / de, acc.y / de);
         else atomicOr(flag, kFlagNonFinite);
         M[p * ldm + col] = h;
     }

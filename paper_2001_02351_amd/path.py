@@ -153,15 +153,30 @@ def chi0_head(ctx, d: DeviceInputs, qhat, prec: int = _rp.RP_FP64, kbatch: int =
     return chi, gaug
 
 
-def screen_head(ctx, d: DeviceInputs, chi, gaug):
+def screen_head(ctx, d: DeviceInputs, chi, gaug, drude=None):
     """eps^-1 at q -> 0 with head and wings, and the optical quantities
-    {Re eps_M, Im eps_M, L, Re sigma, R} per frequency."""
+    {Re eps_M, Im eps_M, L, Re sigma, R} per frequency.  drude = (wq_eV2,
+    delta_eV) adds the intraband term -wq / (w (w + i delta)) to the head for
+    this call (wq = qhat . Omega . qhat from rp_plasma_frequency)."""
     import torch
     p = d.prob
     einv = torch.empty_like(chi)
     optics = torch.empty((d.nfreq, 5), dtype=torch.float64, device=d.device)
-    _rp.rp_screen_head(ctx, d.cell, int(gaug.shape[0]), gaug, d.nfreq, p.freq_eV, chi, einv, optics)
+    if drude is not None:
+        _rp.rp_set_drude(ctx, *drude)
+    try:
+        _rp.rp_screen_head(ctx, d.cell, int(gaug.shape[0]), gaug, d.nfreq, p.freq_eV, chi, einv, optics)
+    finally:
+        if drude is not None:
+            _rp.rp_set_drude(ctx, 0.0, 0.0)
     return einv, optics
+
+
+def plasma_tensor(ctx, d: DeviceInputs, b0: int, b1: int, ef_eV: float, crpa: bool = False):
+    """The intraband plasma tensor (eV^2, 3 x 3) of bands [b0, b1) at E_F."""
+    p = d.prob
+    return _rp.rp_plasma_frequency(ctx, d.cell, d.nband, p.miller.shape[1], p.npw, d.miller, d.coef, d.energy,
+                                   d.T if crpa else None, b0, b1, ef_eV)
 
 
 def screen(ctx, d: DeviceInputs, chi, want_eps_inv: bool = True, want_W: bool = True):

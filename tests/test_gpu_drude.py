@@ -129,3 +129,61 @@ def test_drude_arguments(rp, ctx):
     with pytest.raises(rp.RpError):
         rp.rp_set_drude(ctx, 1.0, -0.1)
     rp.rp_set_drude(ctx, 0.0, 0.0)
+
+
+def test_metal_head_chain_matches_oracle(rp, ctx):
+    """A metal at q -> 0 end to end in FP64: pair densities at iq = 0 with
+    G = 0 first, the head densities along qhat in that column (intraband
+    pairs zero), Fermi-cut weights over overlapping band ranges, the
+    contraction, the plasma tensor of the same bands, and eps^-1 with the
+    intraband term along qhat, against the oracle's chain."""
+    import oracle
+    from oracle import metal
+    from paper_2001_02351_amd import path
+    from synth import make_problem
+    p = make_problem(name="metal_head", a_bohr=7.26, fft=(12, 12, 12), kmesh=(2, 2, 2), iq=(0, 0, 0), nocc=3, nemp=3,
+                     gpsi=2.2, ng=26, freq_eV=np.array([0.0, 1.0, 4.0]), delta_eV=0.1, seed=29)
+    kf = np.stack(np.meshgrid(*[np.arange(K) / K for K in p.kmesh], indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(8)
+    c = np.sort(rng.uniform(-3.0, 3.0, 6))
+    t = rng.uniform(0.5, 1.5, (6, 3))
+    E = np.stack([c[n] - np.sum(t[n] * np.cos(2 * math.pi * kf + n), axis=1) for n in range(6)], 1)
+    p = dataclasses.replace(p, energy_eV=np.ascontiguousarray(E))
+    gaug = np.ascontiguousarray(np.concatenate([np.zeros((1, 3), np.int32), np.asarray(p.gsph, np.int32)]))
+    ng, nk, nf = len(gaug), p.nk, len(p.freq_eV)
+    ef, o, e = 0.2, (0, 4), (2, 6)
+    qhat = np.array([1.0, 0.5, 0.2]) / np.linalg.norm([1.0, 0.5, 0.2])
+    d = path.DeviceInputs(p)
+    npw_max = p.miller.shape[1]
+    M = torch.empty((nk * 4 * 4, ng, 2), dtype=torch.float64, device="cuda")
+    rp.rp_pair_density(ctx, d.cell, p.iq, d.nband, npw_max, p.npw, d.mmax, d.miller, d.coef, *o, *e, 0, nk, ng, gaug,
+                       rp.RP_FP64, M)
+    rp.rp_head_density(ctx, d.cell, d.nband, npw_max, p.npw, d.miller, d.coef, d.energy, *o, *e, 0, nk, qhat, ng, 0,
+                       M)
+    chi = torch.empty((nf, ng, ng, 2), dtype=torch.float64, device="cuda")
+    einv = torch.empty_like(chi)
+    rp.rp_set_fermi_level(ctx, ef)
+    try:
+        rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, None, *o, *e, 0, nk, ng, M, nf, p.freq_eV,
+                              p.delta_eV, rp.RP_W_TETRA_METAL, rp.RP_FP64, 0, chi)
+        Om = rp.rp_plasma_frequency(ctx, d.cell, d.nband, npw_max, p.npw, d.miller, d.coef, d.energy, None, 0, 6, ef)
+        wq = float(qhat @ Om @ qhat)
+        rp.rp_set_drude(ctx, wq, p.delta_eV)
+        rp.rp_screen_head(ctx, d.cell, ng, gaug, nf, p.freq_eV, chi, einv, None)
+        rp.rp_synchronize(ctx)
+    finally:
+        rp.rp_set_drude(ctx, 0.0, 0.0)
+        rp.rp_set_fermi_level(ctx, float("nan"))
+    got_chi, got = path.to_complex(chi), path.to_complex(einv)
+    Mo = oracle.pair_densities(dataclasses.replace(p, gsph=gaug), *o, *e, 0, nk)
+    Mo[:, 0] = head.head_density(p, *o, *e, 0, nk, qhat)
+    wo = metal.weights_metal(p.kmesh, p.iq, E, None, *o, *e, 0, nk, p.freq_eV, p.delta_eV, ef)
+    chi_o = oracle.chi0(Mo, wo)
+    wq_o = float(qhat @ drude.plasma_tensor(p, 0, 6, ef) @ qhat)
+    _, einv_o = drude.drude_head(p.lat, gaug, chi_o, p.freq_eV, p.delta_eV, wq_o, np.linalg.inv)
+    e_chi = max(np.linalg.norm(got_chi[f] - chi_o[f]) / np.linalg.norm(chi_o[f]) for f in range(nf))
+    e_inv = max(np.linalg.norm(got[f] - einv_o[f]) / np.linalg.norm(einv_o[f]) for f in range(nf))
+    print(f"[drude] metal head chain: wq {wq:.4f} eV^2, chi rel {e_chi:.1e}, eps^-1 rel {e_inv:.1e}", flush=True)
+    assert wq > 0 and abs(wq - wq_o * HA * HA) < 1e-10 * wq
+    assert e_chi < 1e-10 and e_inv < 1e-10
+    assert np.all(got[0, 0, :] == 0) and np.all(got[0, :, 0] == 0)     # w = 0 with delta > 0: infinite head
