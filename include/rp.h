@@ -14,8 +14,9 @@
  *   projection      W_ij(q,w) = (4 pi/(Omega Nq)) [ sum_GG' rho_i(G) eps^-1 rho_j(G')*
  *                                 + sum_{G in tail} rho_i(G) rho_j(G)* ]       Eqs. matrix_U, rhoiqG
  *
- * and around it: the q -> 0 head, wings and optical quantities (Eqs.
- * eps00-cRPA, momentum, epsilonM, eels, optical-conductivity, reflectance),
+ * and around it: the q -> 0 head, wings, intraband (Drude) term and optical
+ * quantities (Eqs. eps00, eps00-cRPA, plasma, momentum, epsilonM, eels,
+ * optical-conductivity, reflectance),
  * one q-point's term of the q-mesh sums of the screened and bare direct and
  * exchange integrals U, V, J, X (Eqs. matrix_U, matrix_V, matrix_J,
  * matrix_X), metallic tetrahedron weights (the Fermi level cutting the
