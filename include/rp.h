@@ -557,6 +557,8 @@ rp_status rp_set_tuning(rp_ctx *ctx, int n, const rp_tune_entry *table);
  *   RP_STAGE_BATCH    one rp_chi0_batch graph launch, a2-a6 of every problem
  *                     (the per-stage timers do not run inside the graph)
  *   RP_STAGE_UNFOLD   symmetry unfolding of coefficients and eps^-1
+ *   RP_STAGE_REDUCE   FP64 sums of the split-BF16 contraction's FP32 partial
+ *                     tiles into chi, a6 (sliced or tail-split launches)
  * rp_profile(ctx, 1) enables and resets; rp_profile(ctx, 0) disables.
  * rp_profile_read synchronizes the stream and returns, per stage, the summed
  * milliseconds and the number of timed launches (arrays of RP_NSTAGE).
@@ -571,7 +573,8 @@ enum {
     RP_STAGE_WANNIER = 6,
     RP_STAGE_BATCH = 7,
     RP_STAGE_UNFOLD = 8,
-    RP_NSTAGE = 9
+    RP_STAGE_REDUCE = 9,
+    RP_NSTAGE = 10
 };
 
 rp_status rp_profile(rp_ctx *ctx, int enable);

@@ -34,7 +34,7 @@ EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pa
             "rp_set_fermi_level", "rp_pair_grid", "rp_plasma_frequency", "rp_set_drude", "rp_profile",
             "rp_profile_read"]
 
-STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier", "batch", "unfold"]
+STAGES = ["ugrid", "pair", "weights", "prep", "chi", "screen", "wannier", "batch", "unfold", "reduce"]
 
 
 class RpError(RuntimeError):

@@ -811,7 +811,7 @@ void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, 
 
 void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, int accumulate, double2 *chi,
                      const void *split_a, const void *split_b, const void *split_w, bool herm, int nw, int fill,
-                     int kernel, void *part)
+                     int kernel, void *part, const std::function<void()> &before_reduce)
 {
     const long KP = pad_pairs(npair);
     const int NGP = pad_ng(ng);
@@ -864,11 +864,13 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
             else RP_CHI(3, 2);
         }
 #undef RP_CHI
+        if (stail && before_reduce) before_reduce();
         if (stail)
             hipLaunchKernelGGL(k_chi_reduce_tail, dim3((unsigned)(ntail * 16), 1, (unsigned)nw), dim3(256), 0, s,
                                nfull, stail, NGP, nw, nfreq, ng, (int)herm, accumulate, (const float2 *)P, chi);
     }
     if (S > 1) {
+        if (before_reduce) before_reduce();
         const int nc = NGP / 32;
         hipLaunchKernelGGL(k_chi_reduce, dim3((unsigned)(nc * nc), 1, (unsigned)nfreq), dim3(256), 0, s, S, nfreq, ng,
                            NGP, (const float2 *)P, accumulate, (int)herm, chi);

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <optional>
 #include <unordered_map>
 #include <vector>
 
@@ -479,9 +480,14 @@ static rp_status chi_enqueue(rp_ctx *ctx, const ChiJob &c, int k0, int k1, const
             launch_split_prep(ctx->stream, nterm, npair, c.ng, c.nfreq, M, bufs.w, c.herm, bufs.a, bufs.b,
                               bufs.sw);
         }
-        StageTimer t(ctx, RP_STAGE_CHI);
+        // the contraction and the FP64 sum of its partial tiles on separate timers
+        std::optional<StageTimer> tc, tr;
+        tc.emplace(ctx, RP_STAGE_CHI);
         launch_chi_bf16(ctx->stream, nterm, npair, c.ng, c.nfreq, accumulate, chi, bufs.a, bufs.b, bufs.sw, c.herm,
-                        c.tune.chi_nw, c.tune.chi_fill, c.tune.chi_kernel, bufs.part);
+                        c.tune.chi_nw, c.tune.chi_fill, c.tune.chi_kernel, bufs.part, [&] {
+                            tc.reset();
+                            tr.emplace(ctx, RP_STAGE_REDUCE);
+                        });
     }
     return check_launch(ctx, "chi0 contraction");
 }

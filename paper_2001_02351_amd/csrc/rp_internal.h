@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <cmath>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -162,9 +163,12 @@ size_t split_w_bytes(long npair, int nfreq);
 size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill, int kernel, int nterm);
 void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, const double2 *M,
                        const double2 *w, bool herm, void *split_a, void *split_b, void *split_w);
+// before_reduce (may be empty) is called on the host between the contraction
+// launch and the launch that sums its partial tiles, when there is one
 void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, int accumulate,
                      double2 *chi, const void *split_a, const void *split_b, const void *split_w,
-                     bool herm, int nw, int fill, int kernel, void *part);
+                     bool herm, int nw, int fill, int kernel, void *part,
+                     const std::function<void()> &before_reduce);
 
 // screen.hip
 void launch_vsqrt(hipStream_t s, const Geometry &g, int ng, const int *gsph, double *vs, int *flag,
