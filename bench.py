@@ -572,7 +572,20 @@ def drude_leg(rp, ctx, d, reps: int = 5) -> dict:
         om = rp.rp_plasma_frequency(*args)
     ms = (time.perf_counter() - t0) / reps * 1e3
     log(f"plasma tensor of the three bands at E_F: {ms:.3f} ms per call, diagonal {np.diag(om).round(3)} eV^2")
-    return {"ms_per_call": ms, "bands": [37, 40], "fermi_eV": 0.0, "omega2_eV2_diag": np.diag(om).tolist()}
+    # the q -> 0 head density (k.p transition moments) of two k-points, all 40 x 200 pairs, into column 0
+    M = torch.empty((2 * p.nocc * p.nemp, d.ng, 2), dtype=torch.float64, device=d.device)
+    hargs = (ctx, d.cell, nb, p.miller.shape[1], p.npw, d.miller, d.coef, d.energy, 0, p.nocc, p.nocc, nb, 0, 2,
+             np.array([1.0, 0.0, 0.0]), d.ng, 0, M)
+    rp.rp_head_density(*hargs)
+    rp.rp_synchronize(ctx)
+    rp.rp_profile(ctx, True)
+    for _ in range(reps):
+        rp.rp_head_density(*hargs)
+    hms = rp.rp_profile_read(ctx)["pair"][0] / reps / 2
+    rp.rp_profile(ctx, False)
+    log(f"q -> 0 head density: {hms:.3f} ms per k-point (8 000 pairs)")
+    return {"ms_per_call": ms, "bands": [37, 40], "fermi_eV": 0.0, "omega2_eV2_diag": np.diag(om).tolist(),
+            "head_density_ms_per_k": hms}
 
 
 def unfold_leg(rp, ctx, d, eps_inv, reps: int = 5) -> dict:
