@@ -1,13 +1,15 @@
 """Parity at the full SrVO3-shaped sizes (48^3 grid, 8^3 k, 40+200 bands,
 N_G = 1500, 20 real frequencies, 10 Wannier orbitals) in the launch
-configuration bench.py times (k batches of two k-points, all frequencies per
-launch), on outputs the oracle can compute one by one:
+configurations bench.py times (k batches of two and of sixteen k-points, all
+frequencies per launch), on outputs the oracle can compute one by one, and on
+properties that hold at any size:
 
 * pair densities and weights of sampled pairs of a full k batch,
 * chi over a k batch for a band subset, restricted to sampled rows/columns
   (the oracle's chi0 of the sampled columns of M is exactly that restriction),
 * eps^-1 / W and W_ij at N_G = 1500 for two frequencies of a synthetic chi,
-* batch linearity of chi at full size.
+* batch linearity of chi at full size; the 16-k-point sliced launch against
+  two-k-point launches and the FP64 contraction.
 """
 
 import numpy as np
@@ -134,6 +136,30 @@ def test_chi_batch_linearity_fullsize(ctx, rp, c2, d2):
     for f in (3, 17):
         B = (whole[f] - whole[f].conj().T) / 2j
         assert np.linalg.eigvalsh(B).max() < 1e-10 * np.abs(B).max()
+
+
+def test_chi_bench_launch_fullsize(ctx, rp, c2, d2):
+    """The contraction exactly as bench.py launches it: 16 k-points per launch
+    (128 000 pairs, all 40 x 200 bands, 20 real frequencies), split-BF16, the
+    4 000 pair steps cut into 8 FP32 slices summed in FP64.  Against the same
+    k-points in eight two-k-point launches (other slicing and FP32 groupings)
+    and both against the FP64 contraction of the same pair densities, to the
+    split form's 1e-5 (the FP64 path meets the oracle on the sampled blocks
+    above); the absorptive part stays negative semidefinite."""
+    from paper_2001_02351_amd import path
+    k0, k1 = 32, 48
+    one = path.to_complex(path.chi0(ctx, d2, prec=rp.RP_SPLIT_BF16, kbatch=16, k0=k0, k1=k1))
+    eight = path.to_complex(path.chi0(ctx, d2, prec=rp.RP_SPLIT_BF16, kbatch=2, k0=k0, k1=k1))
+    ref = path.to_complex(path.chi0(ctx, d2, prec=rp.RP_FP64, kbatch=16, k0=k0, k1=k1))
+    d_one = max(_rel(one[f], ref[f]) for f in range(d2.nfreq))
+    d_eight = max(_rel(eight[f], ref[f]) for f in range(d2.nfreq))
+    d_batch = max(_rel(one[f], eight[f]) for f in range(d2.nfreq))
+    print(f"[fullsize] vs FP64: 16-k launch {d_one:.1e}, 2-k launches {d_eight:.1e}; between them {d_batch:.1e}",
+          flush=True)
+    assert d_one < 1e-5 and d_eight < 1e-5 and d_batch < 1e-5
+    for f in (9, 19):
+        ev = np.linalg.eigvalsh((one[f] - one[f].conj().T) / 2j)
+        assert ev.max() < 1e-5 * abs(ev.min())
 
 
 @pytest.fixture(scope="module")
