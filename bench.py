@@ -139,37 +139,53 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(prob, nemp_sample: int = 100, nfreq_sample: int = 4):
-    """Time the FP64 oracle on a bounded sample: k = 0, all occupied bands x
-    the first `nemp_sample` empty bands, the first `nfreq_sample` frequencies
-    (pair densities, tetrahedron weights over the full mesh, chi0)."""
-    import copy
+def cpu_baseline(prob, ng_sample: int = 300):
+    """Time the FP64 oracle on a bounded sample of the q-point: k = 0 with all
+    occupied x empty bands and all frequencies, on the first `ng_sample`
+    vectors of the polarization sphere (pair densities on those vectors,
+    tetrahedron weights over the full mesh, chi0 of the sample).  value is the
+    sample's chi0 build rate 8 N_G'^2 P N_w / t.  The pair densities of a tenth
+    of the sample's pairs on the whole sphere are timed as well, and the
+    seconds per q-point are extrapolated from the sample (pair densities and
+    weights linearly in the k-points, chi0 also as N_G^2), labelled as an
+    extrapolation."""
+    from dataclasses import replace
 
     import numpy as np
 
     import oracle
-    p = copy.copy(prob)
-    p.freq_eV = np.ascontiguousarray(prob.freq_eV[:nfreq_sample])
-    o0, o1, e0, e1 = 0, p.nocc, p.nocc, p.nocc + nemp_sample
+    ngs = min(ng_sample, prob.ng)
+    sub = replace(prob, gsph=np.ascontiguousarray(prob.gsph[:ngs]))
+    o0, o1, e0, e1 = 0, prob.nocc, prob.nocc, prob.nocc + prob.nemp
     t0 = time.perf_counter()
-    M = oracle.pair_densities(p, o0, o1, e0, e1, 0, 1)
+    M = oracle.pair_densities(sub, o0, o1, e0, e1, 0, 1)
     t1 = time.perf_counter()
-    w = oracle.prob_weights(p, o0, o1, e0, e1, 0, 1)
+    w = oracle.prob_weights(prob, o0, o1, e0, e1, 0, 1)
     t2 = time.perf_counter()
     oracle.chi0(M, w)
     t3 = time.perf_counter()
     npair = M.shape[0]
-    flops = 8.0 * p.ng ** 2 * npair * nfreq_sample
+    e_tenth = e0 + max(1, (e1 - e0) // 10)
+    oracle.pair_densities(prob, o0, o1, e0, e_tenth, 0, 1)
+    t4 = time.perf_counter()
+    pair_full = (t4 - t3) * (e1 - e0) / (e_tenth - e0)
+    nfreq = len(prob.freq_eV)
+    flops = 8.0 * ngs ** 2 * npair * nfreq
+    per_q = prob.nk * (pair_full + (t2 - t1) + (t3 - t2) * (prob.ng / ngs) ** 2)
     return {
         "value": flops / (t3 - t0) / 1e12,
         "unit": "TFLOP/s",
         "cores": oracle.threads_used(),
         "cpu_model": _cpu_model(),
         "kind": "oracle",
-        "sample": (f"k=0 only, {p.nocc} occupied x {nemp_sample} empty bands ({npair} pairs), "
-                   f"{nfreq_sample} of {prob.nfreq} frequencies, N_G={p.ng}: pair densities "
-                   f"{t1 - t0:.1f} s, weights {t2 - t1:.1f} s, chi0 {t3 - t2:.1f} s"),
+        "sample": (f"k = 0 of {prob.nk}: all {prob.nocc} x {prob.nemp} bands ({npair} pairs), all {nfreq} "
+                   f"frequencies, the first {ngs} of the {prob.ng} sphere vectors: pair densities "
+                   f"{t1 - t0:.1f} s, weights {t2 - t1:.1f} s, chi0 {t3 - t2:.1f} s (measured, {t3 - t0:.1f} s); "
+                   f"pair densities on all {prob.ng} vectors for a tenth of the pairs {t4 - t3:.1f} s"),
         "seconds": t3 - t0,
+        "s_per_qpoint_extrapolated": per_q,
+        "extrapolation": (f"{prob.nk} k-points x (pair densities on all {prob.ng} vectors, scaled from a tenth "
+                          f"of the pairs; weights; chi0 scaled by ({prob.ng}/{ngs})^2)"),
     }
 
 
@@ -221,8 +237,36 @@ def run_leg(rp, path, ctx, d, prec, steps, warmup, kbatch):
     return res, chi, einv, Wij
 
 
-def batch_leg(args):
-    """The batched uneven workload through rp_chi0_batch (one JSON line)."""
+def _line(value, unit, steps, warmup, ms, config, extra):
+    """One JSON result line of the bench contract."""
+    out = {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic", "config": config}
+    out.update(extra)
+    return out
+
+
+def _chi_roofline(flops_per_launch, ms_per_launch):
+    """Roofline entry of the split-BF16 contraction kernel: algorithmic flops
+    per launch over its mean launch time, against the BF16 dense peak."""
+    if not ms_per_launch:
+        return None
+    a = flops_per_launch / (ms_per_launch / 1e3) / 1e12
+    return {"bound": "mfma", "achieved": a, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+            "frac": a / PEAK_BF16_TFLOPS, "kernel": "k_chi_bf16 (chi0 contraction, split-BF16)",
+            "flops_per_launch": flops_per_launch, "ms_per_launch": ms_per_launch}
+
+
+def batch_measure(args, embedded: bool = False) -> dict:
+    """The batched uneven workload (24 systems x 4 q-points, 16 imaginary
+    frequencies, split-BF16 chi0) through rp_chi0_batch: the graphs captured
+    on the first call, args.warmup untimed and args.steps timed batch calls
+    (median), then the same problems through per-problem calls with the stage
+    timers, whose contraction launches give the roofline (the algorithmic
+    Hermitian-half flops 4 N_G^2 P N_w of every problem over the summed
+    contraction time).  Standalone (--batch) the launch shapes are autotuned on
+    the workload first and the default shapes are timed beside; embedded in
+    the default run the package's tuning table is used."""
     import copy
 
     import torch
@@ -238,20 +282,21 @@ def batch_leg(args):
         probs += batch_system_qpoints(s)
     log(f"generated in {time.perf_counter() - t0:.1f} s")
     baseline = None
-    if not args.no_cpu_baseline and not args.batch_no_graph:
+    if not embedded and not args.no_cpu_baseline and not args.batch_no_graph:
         # the oracle on one problem of the batch (system 21, the fewest pairs
-        # per k-point): k = 0, all 29 occupied x 90 empty bands, 16 frequencies
+        # per k-point): k = 0, all bands, 16 frequencies, the first 300 sphere vectors
         small = [p for p in probs if p.name == "batch_system_21_q0"]
         if small:
             log("timing the FP64 oracle on a bounded sample of the batch (host cores)")
-            baseline = cpu_baseline(small[0], nemp_sample=90, nfreq_sample=16)
+            baseline = cpu_baseline(small[0])
             baseline["value"] /= 2.0     # Hermitian-half flops, as the batch rate counts them
             log(f"oracle sample: {baseline['sample']}")
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     rp.load()
-    ctx = rp.Context(0, tuning=None if args.batch_tuning in ("workload", "none") else args.batch_tuning)
+    mode = "default" if embedded else args.batch_tuning
+    ctx = rp.Context(0, tuning=None if mode in ("workload", "none") else mode)
     ds = []
     for i, p in enumerate(probs):
         if i % 4 == 0:
@@ -263,7 +308,7 @@ def batch_leg(args):
             ds.append(d)
     chis = [torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device=d.device) for d in ds]
     torch.cuda.synchronize()
-    log("inputs resident on the device")
+    log("batch inputs resident on the device")
     prec = rp.RP_SPLIT_BF16
     # k batches of about 40 000 pairs (at least one k-point)
     descs = []
@@ -274,7 +319,7 @@ def batch_leg(args):
     pairs = [d.nk * d.prob.nocc * d.prob.nemp for d in ds]
     f_herm = sum(4.0 * d.ng ** 2 * P * d.nfreq for d, P in zip(ds, pairs))
     table, t_tune = None, None
-    if args.batch_tuning == "workload":
+    if mode == "workload":
         # launch shapes tuned on the workload: one q-point of every system
         from paper_2001_02351_amd import autotune
         t = time.perf_counter()
@@ -298,16 +343,20 @@ def batch_leg(args):
             rp.rp_synchronize(ctx)
             log(f"per-problem calls {i}: {time.perf_counter() - t:.3f} s")
         ctx.close()
-        return
+        return {}
     t = time.perf_counter()
     rp.rp_chi0_batch(ctx, descs, prec)
     rp.rp_synchronize(ctx)
-    log(f"first batch call (capture + instantiate + run) {time.perf_counter() - t:.2f} s")
-    for i in range(args.warmup):
+    graphs, nodes = rp.rp_chi0_batch_graphs(ctx)
+    log(f"first batch call (capture of {graphs} graphs, {nodes} kernel nodes, + run) "
+        f"{time.perf_counter() - t:.2f} s")
+    warm = 1 if embedded else args.warmup
+    steps = 1 if embedded else args.steps
+    for i in range(warm):
         rp.rp_chi0_batch(ctx, descs, prec)
         rp.rp_synchronize(ctx)
     times = []
-    for i in range(args.steps):
+    for i in range(steps):
         torch.cuda.synchronize()
         t = time.perf_counter()
         rp.rp_chi0_batch(ctx, descs, prec)
@@ -317,7 +366,7 @@ def batch_leg(args):
     tb = sorted(times)[len(times) // 2]
     # the same batch with the library's default launch shapes (no table)
     untuned = None
-    if table is not None:
+    if table is not None and not embedded:
         rp.rp_set_tuning(ctx, [])
         rp.rp_chi0_batch(ctx, descs, prec)
         rp.rp_synchronize(ctx)
@@ -342,31 +391,31 @@ def batch_leg(args):
     rp.rp_profile(ctx, False)
     log(f"per-problem calls: {tu:.3f} s")
     ctx.close()
-    out = {
-        "metric": METRIC,
+    ms_chi, n_chi = stages["chi"]
+    roof = _chi_roofline(f_herm / max(1, n_chi), ms_chi / max(1, n_chi))
+    if roof:
+        roof["note"] = ("mean over the contraction launches of the per-problem calls; flops per launch = the "
+                        "batch's Hermitian-half flops / launches")
+    return {
         "value": f_herm / tb / 1e12,
         "unit": "TFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": tb * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "bf16",
-        "data": "synthetic",
+        "s_per_batch": tb,
+        "steps": steps,
+        "warmup": warm,
         "config": {
             "workload": f"batched uneven systems: {nsys} systems x 4 q-points, grids 24^3-40^3, k meshes "
                         "2^3-6^3, 16-64 + 48-256 bands, N_G 300-1200, 16 imaginary frequencies, delta=0, "
-                        "generalized tetrahedron, split-BF16 chi0, one rp_chi0_batch graph per step",
+                        "generalized tetrahedron, split-BF16 chi0, one rp_chi0_batch call (a sequence of "
+                        "captured graphs) per step",
             "problems": len(ds),
             "pairs": sum(pairs),
             "flops_hermitian_half": f_herm,
             "pairs_per_k_batch": args.batch_pairs,
+            "graphs": graphs,
+            "kernel_nodes": nodes,
         },
-        "s_per_batch": tb,
-        "tuning": None if table is None else {"mode": args.batch_tuning, "seconds": t_tune,
-                                              "entries": table["entries"]},
+        "roofline": roof,
+        "tuning": None if table is None else {"mode": mode, "seconds": t_tune, "entries": table["entries"]},
         "s_per_batch_default_shapes": untuned,
         "per_problem_calls_s": tu,
         "per_problem_stage_ms": {k: v[0] for k, v in stages.items()},
@@ -375,14 +424,24 @@ def batch_leg(args):
                                                         ("value", "unit", "cores", "cpu_model", "kind",
                                                          "sample")},
     }
-    print(json.dumps(out), flush=True)
 
 
-def supercell_leg(args):
+def batch_leg(args):
+    """--batch: the batched workload as its own JSON line."""
+    r = batch_measure(args)
+    if not r:
+        return
+    extra = {k: v for k, v in r.items() if k not in ("value", "unit", "steps", "warmup", "config")}
+    print(json.dumps(_line(r["value"], r["unit"], r["steps"], r["warmup"], r["s_per_batch"] * 1e3, r["config"],
+                           extra)), flush=True)
+
+
+def supercell_measure(args) -> dict:
     """The large-supercell shape (96^3, Gamma only, q = 0, 600 + 1200 bands,
     N_G = 6000, 16 real frequencies, 20 Wannier orbitals): split-BF16 chi0
-    streamed over blocks of empty bands, FP64 eps^-1 and W, W_ij (one JSON
-    line)."""
+    streamed over blocks of empty bands (one warm-up block, then the timed
+    q-point), FP64 eps^-1 and W, W_ij; the contraction launches give the
+    roofline."""
     import torch
 
     import paper_2001_02351_amd as rp
@@ -405,7 +464,7 @@ def supercell_leg(args):
     chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device=d.device)
     M = torch.empty((p.nocc * eb, d.ng, 2), dtype=torch.float64, device=d.device)
     torch.cuda.synchronize()
-    log("inputs resident on the device")
+    log("supercell inputs resident on the device")
 
     def block(i, acc):
         e0 = p.nocc + i * eb
@@ -424,7 +483,7 @@ def supercell_leg(args):
         block(i, 0 if i == 0 else 1)
     rp.rp_synchronize(ctx)
     t_chi = time.perf_counter() - t0
-    log(f"chi0 over {nrun} of {nblk} empty-band blocks: {t_chi:.2f} s")
+    log(f"supercell chi0 over {nrun} of {nblk} empty-band blocks: {t_chi:.2f} s")
     t0 = time.perf_counter()
     einv, W = path.screen(ctx, d, chi)
     rp.rp_synchronize(ctx)
@@ -439,19 +498,11 @@ def supercell_leg(args):
     pairs = p.nocc * min(p.nemp, nrun * eb)
     flops = 8.0 * d.ng ** 2 * pairs * d.nfreq
     scale = (p.nocc * p.nemp) / pairs
-    out = {
-        "metric": METRIC,
+    ms_chi, n_chi = stages["chi"]
+    return {
         "value": flops / t_chi / 1e12,
         "unit": "TFLOP/s",
-        "n_gpus": 1,
-        "steps": 1,
-        "warmup": 1,
-        "ms_per_step": (t_chi * scale + t_scr + t_wan) * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "bf16",
-        "data": "synthetic",
+        "s_per_qpoint": t_chi * scale + t_scr + t_wan,
         "config": {
             "workload": "supercell q-point: 96^3 grid, Gamma-only k, q = 0 (G = 0 dropped), 600 + 1200 bands, "
                         "N_G = 6000, 16 real frequencies, delta = 0.1 eV, sampling weights, 20 Wannier orbitals; "
@@ -462,13 +513,20 @@ def supercell_leg(args):
             "ng": d.ng,
             "nfreq": d.nfreq,
         },
+        "roofline": _chi_roofline(flops / max(1, n_chi), ms_chi / max(1, n_chi)),
         "t_chi0_s_timed": t_chi,
         "t_chi0_s_per_qpoint": t_chi * scale,
         "t_screen_s": t_scr,
         "t_wannier_s": t_wan,
         "stage_ms": {k: v[0] for k, v in stages.items()},
     }
-    print(json.dumps(out), flush=True)
+
+
+def supercell_leg(args):
+    """--supercell: the supercell shape as its own JSON line."""
+    r = supercell_measure(args)
+    extra = {k: v for k, v in r.items() if k not in ("value", "unit", "config")}
+    print(json.dumps(_line(r["value"], r["unit"], 1, 1, r["s_per_qpoint"] * 1e3, r["config"], extra)), flush=True)
 
 
 def tune_leg(args):
@@ -705,8 +763,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--fp64-warmup", type=int, default=0)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--fp64-warmup", type=int, default=1)
+    ap.add_argument("--x6-steps", type=int, default=3)
+    ap.add_argument("--x6-warmup", type=int, default=1)
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="skip the supercell and batched-workload legs of the default run")
     ap.add_argument("--kbatch", type=int, default=16)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-x6", action="store_true")
@@ -784,7 +846,7 @@ def main():
     wij_s = wij_s.clone()
     x6 = None
     if not args.no_x6:
-        x6, _, _, _ = run_leg(rp, path, ctx, d, rp.RP_SPLIT_BF16_X6, 1, 0, args.kbatch)
+        x6, _, _, _ = run_leg(rp, path, ctx, d, rp.RP_SPLIT_BF16_X6, args.x6_steps, args.x6_warmup, args.kbatch)
     fp64 = None
     agree = None
     if not args.no_fp64:
@@ -794,12 +856,19 @@ def main():
         def rel(a, b):
             a = torch.view_as_complex(a)
             b = torch.view_as_complex(b)
-            return max(float(torch.linalg.norm(a[f] - b[f]) / torch.linalg.norm(b[f])) for f in range(b.shape[0]))
+            fro = max(float(torch.linalg.norm(a[f] - b[f]) / torch.linalg.norm(b[f])) for f in range(b.shape[0]))
+            ew = max(float((a[f] - b[f]).abs().max() / b[f].abs().max()) for f in range(b.shape[0]))
+            return fro, ew
 
         wd = torch.view_as_complex(wij_d)
+        (c_f, c_e), (e_f, e_e) = rel(chi_s, chi_d), rel(einv_s, einv_d)
         agree = {
-            "chi": rel(chi_s, chi_d),
-            "eps_inv": rel(einv_s, einv_d),
+            "reference": "the GPU's FP64 path on the same q-point (its own parity with the oracle, and the "
+                         "split path's at this launch shape, are tested in tests/test_gpu_fullsize.py)",
+            "chi": c_f,
+            "chi_max_elementwise": c_e,
+            "eps_inv": e_f,
+            "eps_inv_max_elementwise": e_e,
             "W_ij_max_elementwise": float((torch.abs(torch.view_as_complex(wij_s) - wd) / torch.abs(wd)).max()),
         }
     qterm = None if args.no_qterm else qterm_leg(rp, path, ctx, d, einv_s,
@@ -808,6 +877,13 @@ def main():
     metal_w = None if args.no_qterm else metal_weights_leg(rp, ctx, d)
     drude_o = None if args.no_qterm else drude_leg(rp, ctx, d)
     ctx.close()
+    sc_leg = batch_o = None
+    if not args.no_extra_legs:
+        # (the 48^3 arrays stay resident: 288 GB of HBM hold all three workloads)
+        sc_leg = supercell_measure(args)
+        torch.cuda.empty_cache()
+        batch_o = batch_measure(args, embedded=True)
+        torch.cuda.empty_cache()
 
     npair_total = d.nk * prob.nocc * prob.nemp
     pair_grid = rp.rp_pair_grid(d.cell, prob.iq, d.mmax, prob.gsph, rp.RP_SPLIT_BF16)
@@ -856,7 +932,7 @@ def main():
         "split_bf16": split,
         "split_bf16_x6": x6,
         "fp64": fp64,
-        "split_vs_fp64_rel": agree,
+        "split_vs_gpu_fp64": agree,
         "roofline": {
             "bound": "mfma",
             "achieved": achieved,
@@ -875,9 +951,12 @@ def main():
         "symmetry_unfold": unfold,
         "metal_weights": metal_w,
         "drude_plasma": drude_o,
+        "supercell": sc_leg,
+        "batch": batch_o,
         "cpu_baseline": None if baseline is None else {k: baseline[k] for k in
                                                         ("value", "unit", "cores", "cpu_model", "kind",
-                                                         "sample")},
+                                                         "sample", "seconds", "s_per_qpoint_extrapolated",
+                                                         "extrapolation")},
     }
     if fp64 is not None:
         a64 = fp64["chi_kernel_flops_per_launch"] / (fp64["chi_kernel_ms_per_launch"] / 1e3) / 1e12

@@ -77,8 +77,11 @@ typedef enum {
                              densities computed on FP32 grids; weights,
                              eps^-1 and W_ij in FP64 */
     RP_SPLIT_BF16_X6 = 2  /* as RP_SPLIT_BF16 with x = x_hi + x_mid + x_lo and
-                             the six products of order <= 2 (about FP32
-                             accuracy, twice the matrix-core work) */
+                             the six products of order <= 2 (each product to
+                             about FP32 accuracy, twice the matrix-core work);
+                             chi's error is then set by the FP32 pair
+                             densities and the FP32 accumulation within a
+                             slice of pair steps, about 1e-6 relative */
 } rp_precision;
 
 typedef enum {
@@ -212,11 +215,12 @@ rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], 
  * Problems may differ in cell, grid, k mesh, bands, N_G and frequencies;
  * they run one after the other on the context's stream, sharing workspace.
  *
- * The first call captures every launch of the batch into a graph and
- * launches it.  A later call with the same problems (the same scalars and
- * pointers, and the same contents of the host arrays npw, gsph and freq_eV)
- * relaunches that graph without capturing again; any difference captures a
- * new graph.  The device arrays are read when the graph runs.
+ * The first call captures every launch of the batch into a sequence of
+ * graphs (rp_chi0_batch_graphs) and launches them.  A later call with the
+ * same problems (the same scalars and pointers, and the same contents of the
+ * host arrays npw, gsph and freq_eV) relaunches those graphs without
+ * capturing again; any difference captures anew.  The device arrays are read
+ * when the graphs run.
  *
  * Fields of rp_problem, as in rp_pair_density and rp_chi0_accumulate:
  *   npw (host int[Nk]), mmax, miller (dev), coef (dev), energy_eV (dev),
@@ -252,6 +256,16 @@ typedef struct rp_problem {
 } rp_problem;
 
 rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_precision prec);
+
+/*
+ * The graphs of the most recent rp_chi0_batch capture: a batch is captured
+ * as a sequence of graphs of at most about 2048 kernel nodes each (a graph
+ * closes after the k batch that reaches the bound), launched in order on the
+ * context's stream; graphs (host) gets their number and nodes (host) their
+ * kernel nodes in total (0 and 0 before the first batch).
+ * Errors: RP_E_NULL.
+ */
+rp_status rp_chi0_batch_graphs(rp_ctx *ctx, int *graphs, long *nodes);
 
 /*
  * Steps a7-a9: eps = I - v^1/2 chi v^1/2 with v^1/2_G = sqrt(4 pi/Omega)/|q+G|

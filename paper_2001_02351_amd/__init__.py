@@ -21,6 +21,7 @@ from ._rp import (  # noqa: F401
     make_cell,
     rp_chi0_accumulate,
     rp_chi0_batch,
+    rp_chi0_batch_graphs,
     rp_head_density,
     rp_problem,
     rp_last_error,

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_E_NULL", 2: "RP_E_SHAPE", 3: "RP_E_RANGE", 4:
                 5: "RP_E_NOMEM", 6: "RP_E_DEVICE", 7: "RP_E_SINGULAR", 8: "RP_E_UNSUPPORTED"}
 
 EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pair_density",
-            "rp_weights", "rp_chi0_accumulate", "rp_chi0_batch", "rp_screen_W", "rp_wannier_W",
+            "rp_weights", "rp_chi0_accumulate", "rp_chi0_batch", "rp_chi0_batch_graphs", "rp_screen_W", "rp_wannier_W",
             "rp_set_tuning", "rp_head_density", "rp_screen_head", "rp_wannier_qterm",
             "rp_coulomb_cell_average", "rp_frequency_grid", "rp_unfold_coef", "rp_unfold_eps_inv",
             "rp_set_fermi_level", "rp_pair_grid", "rp_plasma_frequency", "rp_set_drude", "rp_profile",
@@ -103,6 +103,7 @@ def load(path: Optional[str] = None):
         "rp_weights": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, D, I, P],
         "rp_chi0_accumulate": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, I, P, D, I, I, I, P],
         "rp_chi0_batch": [P, I, ctypes.POINTER(rp_problem), I],
+        "rp_chi0_batch_graphs": [P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_long)],
         "rp_screen_W": [P, cellp, P, I, P, I, P, P, P],
         "rp_wannier_W": [P, cellp, P, I, P, P, I, P, I, P, I, P, P],
         "rp_set_tuning": [P, I, ctypes.POINTER(rp_tune_entry)],
@@ -147,6 +148,39 @@ def _dp(t) -> Optional[int]:
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
     return t.data_ptr()
+
+
+def _need(t, name: str, kind: str, n: int, optional: bool = False):
+    """Checks that device tensor t holds at least n elements of kind "f64"
+    (float64; complex arrays as interleaved pairs) or "i32", so the library
+    never reads or writes past its end."""
+    import torch
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name} is required")
+    want = torch.float64 if kind == "f64" else torch.int32
+    if t.dtype != want:
+        raise ValueError(f"{name}: expected {want}, got {t.dtype}")
+    if t.numel() < n:
+        raise ValueError(f"{name}: {t.numel()} elements, the call needs {n}")
+
+
+def _nk(cell) -> int:
+    return int(cell.kmesh[0]) * int(cell.kmesh[1]) * int(cell.kmesh[2])
+
+
+def _nr(cell) -> int:
+    return int(cell.fft[0]) * int(cell.fft[1]) * int(cell.fft[2])
+
+
+def _pairs(o0, o1, e0, e1, k0, k1) -> int:
+    return max(0, k1 - k0) * max(0, e1 - e0) * max(0, o1 - o0)
+
+
+def _bands(cell, nband, npw_max, miller, coef):
+    _need(miller, "miller", "i32", _nk(cell) * int(npw_max) * 3)
+    _need(coef, "coef", "f64", _nk(cell) * int(nband) * int(npw_max) * 2)
 
 
 DEFAULT_TUNING = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json")
@@ -222,6 +256,8 @@ def rp_pair_density(ctx: Context, cell: rp_cell, iq, nband, npw_max, npw, mmax, 
                     o0, o1, e0, e1, k0, k1, ng, gsph, prec, M):
     iq_h, npw_h, mm_h = _host(iq, np.int32), _host(npw, np.int32), _host(mmax, np.int32)
     g_h = _host(gsph, np.int32)
+    _bands(cell, nband, npw_max, miller, coef)
+    _need(M, "M", "f64", _pairs(o0, o1, e0, e1, k0, k1) * int(ng) * 2)
     ctx._enter()
     st = ctx.lib.rp_pair_density(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(nband), int(npw_max),
                                  _hp(npw_h), _hp(mm_h), _dp(miller), _dp(coef), o0, o1, e0, e1, k0, k1,
@@ -233,6 +269,9 @@ def rp_pair_density(ctx: Context, cell: rp_cell, iq, nband, npw_max, npw, mmax, 
 def rp_weights(ctx: Context, cell: rp_cell, iq, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, nfreq,
                freq_eV, delta_eV, wm, w):
     iq_h, f_h = _host(iq, np.int32), _host(freq_eV, np.complex128)
+    _need(energy_eV, "energy_eV", "f64", _nk(cell) * int(nband))
+    _need(T, "T", "f64", _nk(cell) * int(nband), optional=True)
+    _need(w, "w", "f64", int(nfreq) * _pairs(o0, o1, e0, e1, k0, k1) * 2)
     ctx._enter()
     st = ctx.lib.rp_weights(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(nband), _dp(energy_eV),
                             _dp(T), o0, o1, e0, e1, k0, k1, int(nfreq), _hp(f_h), float(delta_eV),
@@ -241,9 +280,17 @@ def rp_weights(ctx: Context, cell: rp_cell, iq, nband, energy_eV, T, o0, o1, e0,
     ctx._check(st, "rp_weights")
 
 
+def _chi_args(cell, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, ng, M, nfreq, chi):
+    _need(energy_eV, "energy_eV", "f64", _nk(cell) * int(nband))
+    _need(T, "T", "f64", _nk(cell) * int(nband), optional=True)
+    _need(M, "M", "f64", _pairs(o0, o1, e0, e1, k0, k1) * int(ng) * 2)
+    _need(chi, "chi", "f64", int(nfreq) * int(ng) * int(ng) * 2)
+
+
 def rp_chi0_accumulate(ctx: Context, cell: rp_cell, iq, nband, energy_eV, T, o0, o1, e0, e1, k0, k1,
                        ng, M, nfreq, freq_eV, delta_eV, wm, prec, accumulate, chi):
     iq_h, f_h = _host(iq, np.int32), _host(freq_eV, np.complex128)
+    _chi_args(cell, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, ng, M, nfreq, chi)
     ctx._enter()
     st = ctx.lib.rp_chi0_accumulate(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(nband),
                                     _dp(energy_eV), _dp(T), o0, o1, e0, e1, k0, k1, int(ng), _dp(M),
@@ -270,6 +317,10 @@ def rp_chi0_batch(ctx: Context, problems, prec):
         for a in range(3):
             r.mmax[a] = int(mm_h[a])
         r.npw, r.gsph, r.freq_eV = _hp(npw_h), _hp(g_h), _hp(f_h)
+        _bands(q["cell"], q["nband"], q["npw_max"], q["miller"], q["coef"])
+        _need(q["energy_eV"], "energy_eV", "f64", _nk(q["cell"]) * int(q["nband"]))
+        _need(q.get("T"), "T", "f64", _nk(q["cell"]) * int(q["nband"]), optional=True)
+        _need(q["chi"], "chi", "f64", int(q["nfreq"]) * int(q["ng"]) ** 2 * 2)
         r.miller, r.coef = _dp(q["miller"]), _dp(q["coef"])
         r.energy_eV, r.T, r.chi = _dp(q["energy_eV"]), _dp(q.get("T")), _dp(q["chi"])
         for name in ("nband", "npw_max", "o0", "o1", "e0", "e1", "k0", "k1", "ng", "nfreq", "wm",
@@ -282,9 +333,19 @@ def rp_chi0_batch(ctx: Context, problems, prec):
     ctx._check(st, "rp_chi0_batch")
 
 
+def rp_chi0_batch_graphs(ctx: Context) -> tuple:
+    """(graphs, kernel nodes) of the most recent rp_chi0_batch capture."""
+    g, n = ctypes.c_int(0), ctypes.c_long(0)
+    ctx._check(ctx.lib.rp_chi0_batch_graphs(ctx.handle, ctypes.byref(g), ctypes.byref(n)), "rp_chi0_batch_graphs")
+    return g.value, n.value
+
+
 def rp_head_density(ctx: Context, cell: rp_cell, nband, npw_max, npw, miller, coef, energy_eV, o0, o1, e0, e1,
                     k0, k1, qhat, ng, col, M):
     npw_h, q_h = _host(npw, np.int32), _host(qhat, np.float64)
+    _bands(cell, nband, npw_max, miller, coef)
+    _need(energy_eV, "energy_eV", "f64", _nk(cell) * int(nband))
+    _need(M, "M", "f64", _pairs(o0, o1, e0, e1, k0, k1) * int(ng) * 2)
     ctx._enter()
     st = ctx.lib.rp_head_density(ctx.handle, ctypes.byref(cell), int(nband), int(npw_max), _hp(npw_h), _dp(miller),
                                  _dp(coef), _dp(energy_eV), o0, o1, e0, e1, k0, k1, _hp(q_h), int(ng), int(col),
@@ -295,6 +356,10 @@ def rp_head_density(ctx: Context, cell: rp_cell, nband, npw_max, npw, miller, co
 
 def rp_screen_head(ctx: Context, cell: rp_cell, ng, gsph, nfreq, freq_eV, chi, eps_inv, optics):
     g_h, f_h = _host(gsph, np.int32), _host(freq_eV, np.complex128)
+    n2 = int(nfreq) * int(ng) * int(ng) * 2
+    _need(chi, "chi", "f64", n2)
+    _need(eps_inv, "eps_inv", "f64", n2, optional=True)
+    _need(optics, "optics", "f64", int(nfreq) * 5, optional=True)
     ctx._enter()
     st = ctx.lib.rp_screen_head(ctx.handle, ctypes.byref(cell), int(ng), _hp(g_h), int(nfreq), _hp(f_h), _dp(chi),
                                 _dp(eps_inv), _dp(optics))
@@ -304,6 +369,10 @@ def rp_screen_head(ctx: Context, cell: rp_cell, ng, gsph, nfreq, freq_eV, chi, e
 
 def rp_screen_W(ctx: Context, cell: rp_cell, iq, ng, gsph, nfreq, chi, eps_inv, W):
     iq_h, g_h = _host(iq, np.int32), _host(gsph, np.int32)
+    n2 = int(nfreq) * int(ng) * int(ng) * 2
+    _need(chi, "chi", "f64", n2)
+    _need(eps_inv, "eps_inv", "f64", n2, optional=True)
+    _need(W, "W", "f64", n2, optional=True)
     ctx._enter()
     st = ctx.lib.rp_screen_W(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(ng), _hp(g_h), int(nfreq),
                              _dp(chi), _dp(eps_inv), _dp(W))
@@ -316,6 +385,9 @@ def rp_wannier_W(ctx: Context, cell: rp_cell, iq, nwan, phi, centre_frac, ng, gs
     iq_h, c_h = _host(iq, np.int32), _host(centre_frac, np.float64)
     g_h = _host(gsph, np.int32)
     t_h = _host(gtail, np.int32) if ntail > 0 else None
+    _need(phi, "phi", "f64", int(nwan) * _nr(cell))
+    _need(eps_inv, "eps_inv", "f64", int(nfreq) * int(ng) * int(ng) * 2)
+    _need(Wij, "Wij", "f64", int(nfreq) * int(nwan) * int(nwan) * 2)
     ctx._enter()
     st = ctx.lib.rp_wannier_W(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(nwan), _dp(phi), _hp(c_h),
                               int(ng), _hp(g_h), int(ntail), _hp(t_h), int(nfreq), _dp(eps_inv), _dp(Wij))
@@ -331,6 +403,11 @@ def rp_wannier_qterm(ctx: Context, cell: rp_cell, iq, nwan, phi, centre_frac, R,
     R_h = _host(R, np.int32).reshape(-1, 3)
     g_h = _host(gsph, np.int32)
     t_h = _host(gtail, np.int32) if ntail > 0 else None
+    nR = int(R_h.shape[0])
+    _need(phi, "phi", "f64", int(nwan) * _nr(cell))
+    _need(eps_inv, "eps_inv", "f64", int(nfreq) * int(ng) * int(ng) * 2)
+    for name, t, n in (("U", U, int(nfreq) * nR), ("J", J, int(nfreq) * nR), ("V", V, nR), ("X", X, nR)):
+        _need(t, name, "f64", n * int(nwan) * int(nwan) * 2, optional=True)
     ctx._enter()
     st = ctx.lib.rp_wannier_qterm(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(nwan), _dp(phi), _hp(c_h),
                                   int(R_h.shape[0]), _hp(R_h), int(ng), _hp(g_h), int(ntail), _hp(t_h),
@@ -354,6 +431,9 @@ def rp_plasma_frequency(ctx, cell: rp_cell, nband: int, npw_max: int, npw, mille
     """The intraband plasma tensor Omega^{mu nu} (eV^2, 3 x 3) of bands [b0, b1)."""
     npw_h = _host(npw, np.int32)
     out = np.zeros(9, np.float64)
+    _bands(cell, nband, npw_max, miller, coef)
+    _need(energy_eV, "energy_eV", "f64", _nk(cell) * int(nband))
+    _need(T, "T", "f64", _nk(cell) * int(nband), optional=True)
     ctx._enter()
     st = ctx.lib.rp_plasma_frequency(ctx.handle, ctypes.byref(cell), int(nband), int(npw_max), _hp(npw_h),
                                      _dp(miller), _dp(coef), _dp(energy_eV), _dp(T), int(b0), int(b1), float(ef_eV),
@@ -406,6 +486,8 @@ def rp_unfold_coef(ctx: Context, cell: rp_cell, W, t, ik_irr, miller_irr, coef_i
     W_h, t_h = _op(W, t)
     mi, mt = _host(miller_irr, np.int32).reshape(-1, 3), _host(miller, np.int32).reshape(-1, 3)
     ki, kt = _host(ik_irr, np.int32), _host(ik, np.int32)
+    _need(coef_irr, "coef_irr", "f64", int(coef_irr.shape[0]) * _ld(coef_irr) * 2)
+    _need(coef, "coef", "f64", int(coef_irr.shape[0]) * _ld(coef) * 2)
     ctx._enter()
     st = ctx.lib.rp_unfold_coef(ctx.handle, ctypes.byref(cell), _hp(W_h), _hp(t_h), _hp(ki), int(coef_irr.shape[0]),
                                 int(mi.shape[0]), _hp(mi), _dp(coef_irr), _ld(coef_irr), _hp(kt),
@@ -419,6 +501,9 @@ def rp_unfold_eps_inv(ctx: Context, cell: rp_cell, W, t, iq_irr, gsph_irr, iq, g
     W_h, t_h = _op(W, t)
     gi, gt = _host(gsph_irr, np.int32).reshape(-1, 3), _host(gsph, np.int32).reshape(-1, 3)
     qi, qt = _host(iq_irr, np.int32), _host(iq, np.int32)
+    nf = int(src.shape[0])
+    _need(src, "src", "f64", nf * int(gi.shape[0]) ** 2 * 2)
+    _need(dst, "dst", "f64", nf * int(gt.shape[0]) ** 2 * 2)
     ctx._enter()
     st = ctx.lib.rp_unfold_eps_inv(ctx.handle, ctypes.byref(cell), _hp(W_h), _hp(t_h), _hp(qi), int(gi.shape[0]),
                                    _hp(gi), _hp(qt), int(gt.shape[0]), _hp(gt), int(src.shape[0]), _dp(src), _dp(dst))

@@ -403,6 +403,253 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     }
 }
 
+// Row form of the 128 x 128 tile (the default for two frequencies per
+// block): wave w owns rows 64 (w / 2) .. 64 (w / 2) + 63 of the tile and all
+// 128 columns for frequency f0 + w % 2, so every (row, pair, frequency) of
+// the row operand is weighted and split by exactly one wave of the block,
+// and each split row block feeds 8 column blocks x 12 matrix-core ops.  The
+// split is done two values at a time (packed BF16 conversion, the hi terms
+// widened back to FP32 by shifts), so a 16-row x 32-pair block of the row
+// operand costs 88 vector instructions (2 NT = 4: weighting 32, split 48,
+// negation 8) for its 96 matrix-core ops.  Operand layouts, the two DMA
+// stages, the grid (tiles, frequency groups, slices, tail split) and the
+// outputs are those of k_chi_bf16 with NW = 2.  RW: real weights (their
+// imaginary parts are zero), weighting by two products instead of four.
+typedef float fl2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bh2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ unsigned pk_bf16(float a, float b)
+{
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){a, b}, bh2));
+}
+
+// two FP32 values -> NT packed words of BF16 terms (hi, mid[, lo]); every
+// remainder is exact in FP32
+template <int NT> __device__ __forceinline__ void split_pair(float x0, float x1, unsigned (&t)[NT])
+{
+#pragma unroll
+    for (int s = 0; s < NT; s++) {
+        t[s] = pk_bf16(x0, x1);
+        if (s + 1 < NT) {
+            x0 -= __uint_as_float(t[s] << 16);
+            x1 -= __uint_as_float(t[s] & 0xffff0000u);
+        }
+    }
+}
+
+template <int NT, bool RW>
+__global__ void __launch_bounds__(256)
+k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, const bf8 *__restrict__ Bp, int nfreq,
+           const float2 *__restrict__ wq, int accumulate, double2 *__restrict__ chi, int herm, int sps,
+           float2 *__restrict__ part, int nfull, int stail)
+{
+    constexpr int NW = 2;
+    constexpr int NPL = 2 * NT;
+    __shared__ float2 sA[2][4 * 8 * 128];
+    __shared__ bf8 sB[2][NPL * 4 * 128];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nt = NGP / kTile;
+    const int ntiles = herm ? nt * (nt + 1) / 2 : nt * nt;
+    int tile = blockIdx.x, group = blockIdx.y, step0 = blockIdx.z * sps, nstep;
+    float2 *tailp = nullptr;
+    if (stail > 0) {
+        const int b = blockIdx.x;
+        int unit = b;
+        step0 = 0;
+        nstep = npg / 4;
+        if (b >= nfull) {
+            const int t = b - nfull;
+            unit = nfull + t / stail;
+            step0 = (t % stail) * sps;
+            nstep = max(0, min(sps, npg / 4 - step0));
+            tailp = part + (long)t * NW * kTile * kTile;
+        }
+        tile = unit % ntiles;
+        group = unit / ntiles;
+    } else {
+        nstep = min(sps, npg / 4 - step0);
+    }
+    int rt, ct;
+    tile_of(tile, nt, herm, rt, ct);
+    const int rt0 = rt * kTile, ct0 = ct * kTile;
+    const int wr = wave >> 1, iw = wave & 1;
+    const int f0 = group * NW;
+    const int fw = min(f0 + iw, nfreq - 1);
+    const long plane = (long)npg * NGP;
+
+    // DMA as in k_chi_bf16: wave w moves pair group kg = w of the step
+    const float2 *srcA = Ap + ((long)wave * (NGP / 16) + rt0 / 16) * 128 + lane * 2;
+    const bf8 *srcB = Bp + (long)wave * NGP + ct0 + lane;
+    auto issue = [&](float2 *dA, bf8 *dB, int kg0) {
+        const float2 *a = srcA + (long)kg0 * (NGP / 16) * 128;
+        float2 *da = dA + wave * 8 * 128;
+#pragma unroll
+        for (int rb = 0; rb < 8; rb++) dma16(a + rb * 128, da + rb * 128);
+        const bf8 *b = srcB + (long)kg0 * NGP;
+#pragma unroll
+        for (int sp = 0; sp < NPL; sp++)
+#pragma unroll
+            for (int h = 0; h < 2; h++) dma16(b + sp * plane + 64 * h, dB + (sp * 4 + wave) * 128 + 64 * h);
+    };
+    // this lane's 8 pairs (8 lk .. 8 lk + 7 of the step) at frequency fw
+    const float4 *wsrc = (const float4 *)(wq + (long)fw * KP) + lk * 4;
+    auto wload = [&](int step, float4 (&dst)[4]) {
+#pragma unroll
+        for (int h = 0; h < 4; h++) dst[h] = wsrc[(long)step * 16 + h];
+    };
+
+    f4 accR[4][8], accI[4][8];
+#pragma unroll
+    for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 8; cb++) {
+            accR[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+            accI[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+
+    auto step = [&](float2 *__restrict__ nA, bf8 *__restrict__ nB, const float2 *__restrict__ cA,
+                    const bf8 *__restrict__ cB, int kgn, const float4 (&wc)[4]) {
+        if (kgn >= 0) issue(nA, nB, kgn);
+        // weighted, split row operand of the wave's 4 row blocks
+        bf8 ar[4][NT], ai[4][NT], an[4][NT];
+#pragma unroll
+        for (int rb = 0; rb < 4; rb++) {
+            const float2 *blk = cA + (lk * 8 + wr * 4 + rb) * 128 + li * 2;
+            u4 wr_[NT], wi_[NT];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const float4 v = *(const float4 *)(blk + q * 32);   // pairs 2q, 2q+1: (re, im, re, im)
+                const float4 w = wc[q];
+                float r0, i0, r1, i1;
+                if (RW) {
+                    r0 = v.x * w.x;
+                    i0 = v.y * w.x;
+                    r1 = v.z * w.z;
+                    i1 = v.w * w.z;
+                } else {
+                    r0 = v.x * w.x - v.y * w.y;
+                    i0 = v.x * w.y + v.y * w.x;
+                    r1 = v.z * w.z - v.w * w.w;
+                    i1 = v.z * w.w + v.w * w.z;
+                }
+                unsigned tr[NT], ti[NT];
+                split_pair<NT>(r0, r1, tr);
+                split_pair<NT>(i0, i1, ti);
+#pragma unroll
+                for (int s = 0; s < NT; s++) {
+                    wr_[s][q] = tr[s];
+                    wi_[s][q] = ti[s];
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < NT; s++) {
+                ar[rb][s] = __builtin_bit_cast(bf8, wr_[s]);
+                ai[rb][s] = __builtin_bit_cast(bf8, wi_[s]);
+                an[rb][s] = negate(ar[rb][s]);
+            }
+        }
+        // Re += Re a Re b + Im a Im b;  Im += Im a Re b - Re a Im b over the
+        // products s + u < NT; per column block 8 independent accumulators
+#pragma unroll
+        for (int cb = 0; cb < 8; cb++) {
+            bf8 B[NPL];
+#pragma unroll
+            for (int sp = 0; sp < NPL; sp++) B[sp] = cB[(sp * 4 + lk) * 128 + cb * 16 + li];
+#pragma unroll
+            for (int s = 0; s < NT; s++)
+#pragma unroll
+                for (int u = 0; u < NT; u++) {
+                    if (s + u >= NT) continue;
+#pragma unroll
+                    for (int rb = 0; rb < 4; rb++) {
+                        accR[rb][cb] = mfma_bf16(ar[rb][s], B[u], accR[rb][cb]);
+                        accI[rb][cb] = mfma_bf16(ai[rb][s], B[u], accI[rb][cb]);
+                    }
+#pragma unroll
+                    for (int rb = 0; rb < 4; rb++) {
+                        accR[rb][cb] = mfma_bf16(ai[rb][s], B[NT + u], accR[rb][cb]);
+                        accI[rb][cb] = mfma_bf16(an[rb][s], B[NT + u], accI[rb][cb]);
+                    }
+                }
+        }
+    };
+
+    float4 wcur[4], wnext[4];
+    if (nstep > 0) {
+        wload(step0, wnext);
+        issue(sA[0], sB[0], 4 * step0);
+    }
+    for (int t = 0; t < nstep; t++) {
+        const int stg = t & 1;
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 4; h++) wcur[h] = wnext[h];
+        const bool more = t + 1 < nstep;
+        if (more) wload(step0 + t + 1, wnext);
+        step(sA[stg ^ 1], sB[stg ^ 1], sA[stg], sB[stg], more ? 4 * (step0 + t + 1) : -1, wcur);
+    }
+
+    // result register r of lane (li, lk) holds row 4 lk + r, column li of a 16x16 block
+    if (tailp) {
+#pragma unroll
+        for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+            for (int cb = 0; cb < 8; cb++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int i = wr * 64 + rb * 16 + 4 * lk + r;
+                    const int j = cb * 16 + li;
+                    tailp[((long)iw * kTile + i) * kTile + j] = make_float2(accR[rb][cb][r], accI[rb][cb][r]);
+                }
+        return;
+    }
+    if (f0 + iw >= nfreq) return;
+    if (part && stail == 0) {
+        float2 *P = part + ((long)blockIdx.z * nfreq + f0 + iw) * NGP * NGP;
+#pragma unroll
+        for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+            for (int cb = 0; cb < 8; cb++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int i = rt0 + wr * 64 + rb * 16 + 4 * lk + r;
+                    const int j = ct0 + cb * 16 + li;
+                    P[(long)i * NGP + j] = make_float2(accR[rb][cb][r], accI[rb][cb][r]);
+                }
+        return;
+    }
+    const bool mirror = herm && rt != ct;
+    double2 *C = chi + (long)(f0 + iw) * ng * ng;
+#pragma unroll
+    for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 8; cb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int i = rt0 + wr * 64 + rb * 16 + 4 * lk + r;
+                const int j = ct0 + cb * 16 + li;
+                if (i < ng && j < ng) {
+                    const double2 a = make_double2((double)accR[rb][cb][r], (double)accI[rb][cb][r]);
+                    const long idx = (long)i * ng + j;
+                    C[idx] = accumulate ? cadd(C[idx], a) : a;
+                    if (mirror) {
+                        const long jdx = (long)j * ng + i;
+                        const double2 b = make_double2(a.x, -a.y);
+                        C[jdx] = accumulate ? cadd(C[jdx], b) : b;
+                    }
+                }
+            }
+}
+
+__device__ __forceinline__ f16v mfma32_bf16(bf8 a, bf8 b, f16v c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
 // Wide form: a 512-thread block owns a 256 x 32 CB tile of (G, G') for NW
 // frequencies (CB = 2: 256 x 64, NW = 1 or 2; CB = 4: 256 x 128, NW = 1); each
 // of its 8 waves (two per SIMD) owns 32 whole rows of the tile as CB 32 x 32
@@ -415,10 +662,6 @@ k_chi_bf16(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
 // contraction of one (a, b) pair is the same sum of split products as in
 // k_chi_bf16; only the tiling differs.  Not for a Hermitian chi.  Three LDS
 // stages (120 KB) let a step's DMA run two steps ahead of its use.
-__device__ __forceinline__ f16v mfma32_bf16(bf8 a, bf8 b, f16v c)
-{
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-}
 
 template <int NT, int NW, int CB>
 __global__ void __launch_bounds__(512)
@@ -856,13 +1099,21 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
     hipLaunchKernelGGL((k_chi_bf16<NT, NW>), grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a, \
                        (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P, \
                        nfull, stail)
-        if (nterm == 2) {
-            if (nw == 1) RP_CHI(2, 1);
-            else RP_CHI(2, 2);
+#define RP_ROWS(NT, RW)                                                                                       \
+    hipLaunchKernelGGL((k_chi_rows<NT, RW>), grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a,  \
+                       (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P, \
+                       nfull, stail)
+        if (nw == 1) {
+            if (nterm == 2) RP_CHI(2, 1);
+            else RP_CHI(3, 1);
+        } else if (nterm == 2) {
+            if (herm) RP_ROWS(2, true);
+            else RP_ROWS(2, false);
         } else {
-            if (nw == 1) RP_CHI(3, 1);
-            else RP_CHI(3, 2);
+            if (herm) RP_ROWS(3, true);
+            else RP_ROWS(3, false);
         }
+#undef RP_ROWS
 #undef RP_CHI
         if (stail && before_reduce) before_reduce();
         if (stail)

@@ -584,7 +584,7 @@ rp_status rp_destroy(rp_ctx *ctx)
     DevBuf *bufs[] = {&ctx->ugrid, &ctx->ugrid32, &ctx->weights, &ctx->glist, &ctx->freq,  &ctx->kinfo, &ctx->vsqrt,
                       &ctx->work,  &ctx->split_a, &ctx->split_b, &ctx->split_w, &ctx->rho, &ctx->piv,
                       &ctx->mbuf,  &ctx->bstage,  &ctx->chi_part};
-    if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
+    for (hipGraphExec_t e : ctx->batch_execs) (void)hipGraphExecDestroy(e);
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->flag) (void)hipFree(ctx->flag);
@@ -717,6 +717,10 @@ rp_status rp_set_tuning(rp_ctx *ctx, int n, const rp_tune_entry *table)
 
 // ---- batch of chi0 problems as one graph launch ----------------------------
 
+// bound on the kernel nodes of one captured graph of a batch
+constexpr long kGraphNodes = 2048;
+
+
 rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_precision prec)
 {
     if (!ctx) return RP_E_NULL;
@@ -805,23 +809,73 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
                         ctx->split_b.p, ctx->split_w.p, ctx->chi_part.p};
     key_put(key, ws, sizeof ws);
 
-    if (!ctx->batch_exec || key != ctx->batch_key) {
-        if (ctx->batch_exec) {
+    if (ctx->batch_execs.empty() || key != ctx->batch_key) {
+        if (!ctx->batch_execs.empty()) {
             if (hipStreamSynchronize(ctx->stream) != hipSuccess)
-                return fail(ctx, RP_E_DEVICE, "stream synchronize failed before replacing the batch graph");
-            (void)hipGraphExecDestroy(ctx->batch_exec);
-            ctx->batch_exec = nullptr;
+                return fail(ctx, RP_E_DEVICE, "stream synchronize failed before replacing the batch graphs");
+            for (hipGraphExec_t e : ctx->batch_execs) (void)hipGraphExecDestroy(e);
+            ctx->batch_execs.clear();
+            ctx->batch_nodes = 0;
             ctx->batch_key.clear();
         }
         if ((st = upload(ctx, ctx->bstage, stage.data(), stage.size())) != RP_OK) return st;
         const char *dstage = (const char *)ctx->bstage.p;
         const ChiBufs bufs{(double2 *)ctx->weights.p, ctx->split_a.p, ctx->split_b.p, ctx->split_w.p,
                            ctx->chi_part.p};
-        if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(ctx, RP_E_DEVICE, "stream capture could not begin");
-        }
-        ctx->capturing = true;
+        // The launches are captured as a sequence of graphs of at most about
+        // kGraphNodes kernel nodes each (a graph closes after the k batch that
+        // reaches the bound), launched in order on the stream: the same launches
+        // as one graph, without a serial chain of tens of thousands of nodes
+        // for the runtime (or a profiler) to walk.
+        std::vector<hipGraphExec_t> execs;
+        long nodes = 0, piece = 0;
+        bool in_capture = false;
+        auto drop = [&]() {
+            for (hipGraphExec_t e : execs) (void)hipGraphExecDestroy(e);
+        };
+        auto begin_piece = [&]() -> rp_status {
+            if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(ctx, RP_E_DEVICE, "stream capture could not begin");
+            }
+            ctx->capturing = true;
+            in_capture = true;
+            piece = 0;
+            return RP_OK;
+        };
+        auto end_piece = [&](rp_status prior) -> rp_status {
+            ctx->capturing = false;
+            in_capture = false;
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
+            if (prior != RP_OK || ec != hipSuccess || !graph) {
+                if (graph) (void)hipGraphDestroy(graph);
+                (void)hipGetLastError();
+                if (prior != RP_OK) {
+                    ctx->err = "batch capture: " + ctx->err;
+                    return prior;
+                }
+                return fail(ctx, RP_E_DEVICE, "stream capture failed: %s", hipGetErrorString(ec));
+            }
+            size_t n = 0;
+            (void)hipGraphGetNodes(graph, nullptr, &n);
+            hipGraphExec_t exec = nullptr;
+            const hipError_t ei = n ? hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) : hipSuccess;
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(ctx, RP_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+            }
+            if (exec) execs.push_back(exec);
+            nodes += (long)n;
+            return RP_OK;
+        };
+        // an upper bound on the kernels one k batch of kb k-points enqueues:
+        // per k the zero fill, two scatters, three transform passes and the pair
+        // kernel; per batch the weights, two preparation kernels, the
+        // contraction and the sum of its partial tiles
+        auto bound = [](int kb) { return 8L * kb + 6; };
+        st = begin_piece();
         for (int i = 0; i < nprob && st == RP_OK; i++) {
             const rp_problem &p = probs[i];
             const int *dg = (const int *)(dstage + goff[i]);
@@ -830,45 +884,47 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
             if (pj[i].empty) {
                 // no pairs: chi is overwritten with zero or left as it is
                 st = chi_enqueue(ctx, cj[i], p.k0, p.k0, nullptr, df, bufs, p.accumulate, chi);
+                piece += bound(0);
                 continue;
             }
             for (int ka = p.k0; ka < p.k1 && st == RP_OK; ka += p.kbatch) {
                 const int kb = std::min(p.k1, ka + p.kbatch);
+                if (piece > 0 && piece + bound(kb - ka) > kGraphNodes) {
+                    if ((st = end_piece(RP_OK)) != RP_OK || (st = begin_piece()) != RP_OK) break;
+                }
                 double2 *M = (double2 *)ctx->mbuf.p;
                 st = pair_enqueue(ctx, pj[i], ka, kb, dg, grid.p, M);
                 if (st == RP_OK)
                     st = chi_enqueue(ctx, cj[i], ka, kb, M, df, bufs, ka == p.k0 ? p.accumulate : 1, chi);
+                piece += bound(kb - ka);
             }
         }
-        ctx->capturing = false;
-        hipGraph_t graph = nullptr;
-        const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
-        if (st != RP_OK || ec != hipSuccess || !graph) {
-            if (graph) (void)hipGraphDestroy(graph);
-            (void)hipGetLastError();
-            if (st != RP_OK) {
-                ctx->err = "batch capture: " + ctx->err;
-                return st;
-            }
-            return fail(ctx, RP_E_DEVICE, "stream capture failed: %s", hipGetErrorString(ec));
+        if (in_capture) st = end_piece(st);
+        if (st != RP_OK) {
+            drop();
+            return st;
         }
-        hipGraphExec_t exec = nullptr;
-        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ei != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(ctx, RP_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
-        }
-        ctx->batch_exec = exec;
+        ctx->batch_execs = std::move(execs);
+        ctx->batch_nodes = nodes;
         ctx->batch_key = key;
     }
     {
         StageTimer t(ctx, RP_STAGE_BATCH);
-        if (hipGraphLaunch(ctx->batch_exec, ctx->stream) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(ctx, RP_E_DEVICE, "graph launch failed");
-        }
+        for (hipGraphExec_t e : ctx->batch_execs)
+            if (hipGraphLaunch(e, ctx->stream) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(ctx, RP_E_DEVICE, "graph launch failed");
+            }
     }
+    return RP_OK;
+}
+
+rp_status rp_chi0_batch_graphs(rp_ctx *ctx, int *graphs, long *nodes)
+{
+    if (!ctx) return RP_E_NULL;
+    if (!graphs || !nodes) return fail(ctx, RP_E_NULL, "NULL output");
+    *graphs = (int)ctx->batch_execs.size();
+    *nodes = ctx->batch_nodes;
     return RP_OK;
 }
 

@@ -71,8 +71,10 @@ struct rp_ctx {
     rp::DevBuf piv;                 // pivots
     rp::DevBuf mbuf;                // pair densities of one k batch (batch entry point)
     rp::DevBuf bstage;              // device copies of a batch's G and frequency lists
-    // the last batch's graph and the launch arguments it was captured with
-    hipGraphExec_t batch_exec = nullptr;
+    // the last batch's graphs (launched in order) and the launch arguments
+    // they were captured with; batch_nodes counts their kernel nodes
+    std::vector<hipGraphExec_t> batch_execs;
+    long batch_nodes = 0;
     std::string batch_key;
     bool capturing = false;         // stage timers stay off while a graph is captured
     std::vector<rp_tune_entry> tuning;  // launch shapes per size class, matched in order

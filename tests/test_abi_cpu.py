@@ -157,3 +157,24 @@ def test_pair_grid_is_the_smallest_alias_free_lane_grid():
     with pytest.raises(rp.RpError) as e:
         rp.rp_pair_grid(rp.make_cell(lat, (24, 24, 24), (2, 2, 2)), (0, 0, 0), (11, 11, 11), cube, rp.RP_FP64)
     assert e.value.status == 4                      # RP_E_ALIAS: the cell's own grid folds
+
+
+def test_binding_checks_tensor_dtype_and_size():
+    """The binding refuses a tensor of the wrong dtype or with fewer elements
+    than the call reads or writes, before anything reaches the library."""
+    torch = pytest.importorskip("torch")
+    from paper_2001_02351_amd import _rp
+    t = torch.zeros(10, dtype=torch.float64)
+    _rp._need(t, "x", "f64", 10)
+    _rp._need(None, "x", "f64", 10, optional=True)
+    with pytest.raises(ValueError, match="elements"):
+        _rp._need(t, "x", "f64", 11)
+    with pytest.raises(ValueError, match="expected"):
+        _rp._need(t.float(), "x", "f64", 4)
+    with pytest.raises(ValueError, match="expected"):
+        _rp._need(t, "x", "i32", 4)
+    with pytest.raises(ValueError, match="required"):
+        _rp._need(None, "x", "f64", 1)
+    cell = _rp.make_cell(np.eye(3), (4, 5, 6), (2, 3, 4))
+    assert _rp._nk(cell) == 24 and _rp._nr(cell) == 120
+    assert _rp._pairs(0, 3, 3, 7, 1, 4) == 36

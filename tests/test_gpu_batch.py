@@ -27,7 +27,10 @@ SYSTEMS = [21, 7, 6, 4, 18, 8]
 
 
 def _rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+    """The larger of the relative Frobenius norm of a - b and the largest
+    element-wise deviation over the largest |b|."""
+    d = np.abs(np.asarray(a) - np.asarray(b))
+    return max(np.linalg.norm(d) / np.linalg.norm(b), d.max() / np.abs(b).max())
 
 
 @pytest.fixture(scope="module")
@@ -173,3 +176,50 @@ def test_chi0_batch_rejects_bad_problems(ctx, rp):
         rp.rp_chi0_batch(ctx, [good], 7)
     assert e.value.status == 3
     rp.rp_chi0_batch(ctx, [], 0)   # an empty batch is a no-op
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_chi0_batch_across_graph_pieces(ctx, rp, prec):
+    """A batch whose launches exceed one graph's node bound (four q-points of
+    the 16^3 / 4^3 k parity system, one k-point per batch: 2 304 kernel nodes
+    in FP64, 2 816 in the split form) is captured as several graphs launched
+    in order; it equals the
+    per-problem calls, and problem 0 meets the oracle on sampled columns
+    (per frequency, relative Frobenius and element-wise)."""
+    from paper_2001_02351_amd import path
+    from synth import at_qpoint, parity_workload
+    base = parity_workload()
+    ds = [path.DeviceInputs(at_qpoint(base, iq)) for iq in ((1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1))]
+    kbatch = 1
+    chis = [torch.full((d.nfreq, d.ng, d.ng, 2), float("nan"), dtype=torch.float64, device="cuda") for d in ds]
+    probs = [path.batch_problem(d, c, kbatch) for d, c in zip(ds, chis)]
+    rp.rp_chi0_batch(ctx, probs, prec)
+    rp.rp_synchronize(ctx)
+    graphs, nodes = rp.rp_chi0_batch_graphs(ctx)
+    print(f"[batch pieces] prec={prec}: {graphs} graphs, {nodes} kernel nodes", flush=True)
+    assert graphs >= 2 and nodes > 2048
+    assert nodes <= graphs * (2048 + 14)
+    for i, d in enumerate(ds):
+        ref = _per_problem(ctx, rp, d, (0, d.prob.nocc), (d.prob.nocc, d.prob.nband), prec, kbatch)
+        err = float(torch.linalg.norm(chis[i] - ref) / torch.linalg.norm(ref))
+        print(f"[batch pieces] problem {i}: rel diff {err:.1e}", flush=True)
+        assert err <= 1e-14
+    # relaunch of the unchanged batch: the same graphs, the same result
+    before = [c.clone() for c in chis]
+    rp.rp_chi0_batch(ctx, probs, prec)
+    rp.rp_synchronize(ctx)
+    assert rp.rp_chi0_batch_graphs(ctx) == (graphs, nodes)
+    for c, b in zip(chis, before):
+        assert torch.equal(c, b)
+    d = ds[0]
+    p = d.prob
+    M = oracle.pair_densities(p, 0, p.nocc, p.nocc, p.nband, 0, d.nk)
+    w = oracle.prob_weights(p, 0, p.nocc, p.nocc, p.nband, 0, d.nk)
+    cols = np.unique(np.concatenate([np.random.default_rng(3).choice(d.ng, 30, replace=False), [0, d.ng - 1]]))
+    want = oracle.chi0(M[:, cols], w)
+    got = path.to_complex(chis[0])[:, cols][:, :, cols]
+    tol = 1e-10 if prec == 0 else 1e-5
+    fro = max(_rel(got[f], want[f]) for f in range(d.nfreq))
+    ew = max(np.abs(got[f] - want[f]).max() / np.abs(want[f]).max() for f in range(d.nfreq))
+    print(f"[batch pieces] problem 0 vs oracle: {fro:.1e} (Frobenius), {ew:.1e} (element-wise)", flush=True)
+    assert fro < tol and ew < tol

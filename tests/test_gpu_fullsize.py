@@ -9,7 +9,9 @@ properties that hold at any size:
   (the oracle's chi0 of the sampled columns of M is exactly that restriction),
 * eps^-1 / W and W_ij at N_G = 1500 for two frequencies of a synthetic chi,
 * batch linearity of chi at full size; the 16-k-point sliced launch against
-  two-k-point launches and the FP64 contraction.
+  two-k-point launches and the FP64 contraction,
+* that launch (split-BF16 and FP64) against the oracle's Eq. chi of all its
+  128 000 pairs on 48 sampled rows and columns.
 """
 
 import numpy as np
@@ -26,7 +28,10 @@ KB = (36, 38)          # one k batch of the bench's size (kbatch = 2)
 
 
 def _rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+    """The larger of the relative Frobenius norm of a - b and the largest
+    element-wise deviation over the largest |b|."""
+    d = np.abs(np.asarray(a) - np.asarray(b))
+    return max(np.linalg.norm(d) / np.linalg.norm(b), d.max() / np.abs(b).max())
 
 
 @pytest.fixture(scope="module")
@@ -108,6 +113,11 @@ def chi_subset(c2):
     return o, e, M, w, cols
 
 
+# The six-product form's bound: its products are FP32-accurate, so chi's error
+# comes from the FP32 pair densities (about 1e-7) and from FP32 accumulation
+# within one slice of at most 512 matrix-core steps, whose rounding grows like
+# 2^-24 sqrt(512) = 1.3e-6 of the partial sums; 5e-6 leaves a factor of about
+# four over that estimate (measured 9.4e-7 at this size).
 @pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-5), (2, 5e-6)])
 def test_chi_sampled_block(ctx, rp, c2, d2, chi_subset, prec, tol):
     from paper_2001_02351_amd import path
@@ -138,19 +148,60 @@ def test_chi_batch_linearity_fullsize(ctx, rp, c2, d2):
         assert np.linalg.eigvalsh(B).max() < 1e-10 * np.abs(B).max()
 
 
-def test_chi_bench_launch_fullsize(ctx, rp, c2, d2):
-    """The contraction exactly as bench.py launches it: 16 k-points per launch
-    (128 000 pairs, all 40 x 200 bands, 20 real frequencies), split-BF16, the
-    4 000 pair steps cut into 8 FP32 slices summed in FP64.  Against the same
-    k-points in eight two-k-point launches (other slicing and FP32 groupings)
-    and both against the FP64 contraction of the same pair densities, to the
-    split form's 1e-5 (the FP64 path meets the oracle on the sampled blocks
-    above); the absorptive part stays negative semidefinite."""
+BENCH_K = (32, 48)     # one contraction launch of the bench: 16 k-points, all 40 x 200 bands
+
+
+@pytest.fixture(scope="module")
+def bench_launch(ctx, rp, d2):
+    """chi over the bench's 16-k-point launch (128 000 pairs, 20 real
+    frequencies): split-BF16 as one launch (4 000 pair steps cut into 8 FP32
+    slices summed in FP64) and as eight two-k-point launches, and FP64 as one
+    launch."""
     from paper_2001_02351_amd import path
-    k0, k1 = 32, 48
+    k0, k1 = BENCH_K
+    print("[fullsize] bench launch: split 16-k, split 8 x 2-k, FP64 16-k", flush=True)
     one = path.to_complex(path.chi0(ctx, d2, prec=rp.RP_SPLIT_BF16, kbatch=16, k0=k0, k1=k1))
     eight = path.to_complex(path.chi0(ctx, d2, prec=rp.RP_SPLIT_BF16, kbatch=2, k0=k0, k1=k1))
     ref = path.to_complex(path.chi0(ctx, d2, prec=rp.RP_FP64, kbatch=16, k0=k0, k1=k1))
+    return one, eight, ref
+
+
+@pytest.fixture(scope="module")
+def bench_launch_oracle(c2):
+    """The oracle's chi of the same 128 000 pairs on sampled G columns: 48
+    columns from the slab |m3| <= 1 of the sphere (which keeps the oracle's
+    separable transform to a three-plane window), spread so that every
+    128-row tile of the padded N_G holds some, and the oracle's weights."""
+    p = c2
+    rng = np.random.default_rng(21)
+    slab = np.where(np.abs(p.gsph[:, 2]) <= 1)[0]
+    cols = []
+    for t in range(0, p.ng, 128):
+        cand = slab[(slab >= t) & (slab < t + 128)]
+        if len(cand):
+            cols.append(int(rng.choice(cand)))
+    rest = np.setdiff1d(slab, cols)
+    cols = np.unique(np.concatenate([cols, rng.choice(rest, 48 - len(cols), replace=False)]))
+    print(f"[fullsize] oracle pair densities of the bench launch on {len(cols)} columns (128 000 pairs)",
+          flush=True)
+    sub = _with_gsph(p, p.gsph[cols])
+    M = oracle.pair_densities(sub, 0, p.nocc, p.nocc, p.nband, *BENCH_K)
+    w = oracle.prob_weights(p, 0, p.nocc, p.nocc, p.nband, *BENCH_K)
+    print("[fullsize] oracle chi of the bench launch on the sampled columns", flush=True)
+    return cols, oracle.chi0(M, w)
+
+
+def _with_gsph(p, gsph):
+    from dataclasses import replace
+    return replace(p, gsph=np.ascontiguousarray(gsph, dtype=np.int32))
+
+
+def test_chi_bench_launch_fullsize(bench_launch, d2):
+    """The split launch against eight two-k-point launches (other slicing and
+    FP32 groupings) and both against the FP64 contraction of the same pair
+    densities, to the split form's 1e-5; the absorptive part stays negative
+    semidefinite."""
+    one, eight, ref = bench_launch
     d_one = max(_rel(one[f], ref[f]) for f in range(d2.nfreq))
     d_eight = max(_rel(eight[f], ref[f]) for f in range(d2.nfreq))
     d_batch = max(_rel(one[f], eight[f]) for f in range(d2.nfreq))
@@ -160,6 +211,20 @@ def test_chi_bench_launch_fullsize(ctx, rp, c2, d2):
     for f in (9, 19):
         ev = np.linalg.eigvalsh((one[f] - one[f].conj().T) / 2j)
         assert ev.max() < 1e-5 * abs(ev.min())
+
+
+def test_chi_bench_launch_against_the_oracle(bench_launch, bench_launch_oracle, d2):
+    """The bench's launch (split-BF16 as one sliced launch, and FP64) against
+    the oracle's Eq. chi of all 128 000 pairs on the sampled rows and columns,
+    per frequency: relative Frobenius norm and largest element-wise deviation
+    over the largest |chi|, FP64 1e-10 and split-BF16 1e-5."""
+    one, _, ref = bench_launch
+    cols, want = bench_launch_oracle
+    for name, got, tol in (("FP64", ref, 1e-10), ("split-BF16", one, 1e-5)):
+        blk = got[:, cols][:, :, cols]
+        err = max(_rel(blk[f], want[f]) for f in range(d2.nfreq))
+        print(f"[fullsize] bench launch {name} vs oracle on {len(cols)} columns: {err:.2e}", flush=True)
+        assert err < tol
 
 
 @pytest.fixture(scope="module")

@@ -20,7 +20,10 @@ torch = pytest.importorskip("torch")
 
 
 def _rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+    """The larger of the relative Frobenius norm of a - b and the largest
+    element-wise deviation over the largest |b|."""
+    d = np.abs(np.asarray(a) - np.asarray(b))
+    return max(np.linalg.norm(d) / np.linalg.norm(b), d.max() / np.abs(b).max())
 
 
 def _rel_per_freq(a, b):

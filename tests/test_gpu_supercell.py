@@ -5,6 +5,8 @@ any size where it cannot:
 
 * pair densities of 8 x 16 bands (FP64 and FP32 grids) against the oracle,
 * chi of those pairs at N_G = 6000 (two frequencies) on a sampled block,
+* chi of 16 800 pairs (two FP32 slices of the split contraction) at N_G = 6000
+  on sampled rows and columns against the oracle,
 * eps^-1 at N_G = 6000 of a synthetic chi: the residual eps eps^-1 - I, and W
   against its definition v^1/2 eps^-1 v^1/2 (v^1/2 computed here),
 * W_ij of the 20 orbitals (first 600 G of the sphere, empty tail) against the
@@ -27,7 +29,10 @@ HARTREE_EV = 27.211386245988
 
 
 def _rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+    """The larger of the relative Frobenius norm of a - b and the largest
+    element-wise deviation over the largest |b|."""
+    d = np.abs(np.asarray(a) - np.asarray(b))
+    return max(np.linalg.norm(d) / np.linalg.norm(b), d.max() / np.abs(b).max())
 
 
 @pytest.fixture(scope="module")
@@ -93,6 +98,46 @@ def test_supercell_chi_block(ctx, rp, sc, dsc, oracle_pairs, prec, tol):
     want = oracle.chi0(M[:, cols], w[:nf])
     err = max(_rel(got[f], want[f]) for f in range(nf))
     print(f"[supercell] chi block prec={prec}: rel err {err:.2e}", flush=True)
+    assert err < tol
+
+
+SLICED = (0, 600), (600, 628)   # 16 800 pairs: 525 pair steps, two FP32 slices of the split contraction
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-5)])
+def test_supercell_sliced_chi_block(ctx, rp, sc, dsc, prec, tol):
+    """A block of 600 x 28 bands (16 800 pairs, more than one 512-step FP32
+    slice of the split contraction, so it is cut into two slices summed in
+    FP64) at N_G = 6000 and two frequencies, against the oracle's Eq. chi of
+    the same pairs on sampled rows and columns (slab |m3| <= 1 of the sphere,
+    spread over the row tiles), per frequency: relative Frobenius norm and
+    largest element-wise deviation over the largest |chi|."""
+    from paper_2001_02351_amd import path
+    from dataclasses import replace
+    O2, E2 = SLICED
+    nf = 2
+    rng = np.random.default_rng(17)
+    slab = np.where(np.abs(sc.gsph[:, 2]) <= 1)[0]
+    cols = []
+    for t in range(0, sc.ng, 512):
+        cand = slab[(slab >= t) & (slab < t + 512)]
+        if len(cand):
+            cols.append(int(rng.choice(cand)))
+    cols = np.unique(np.concatenate([cols, rng.choice(np.setdiff1d(slab, cols), 40 - len(cols), replace=False)]))
+    print(f"[supercell] oracle pair densities of 16 800 pairs on {len(cols)} columns", flush=True)
+    M = oracle.pair_densities(replace(sc, gsph=np.ascontiguousarray(sc.gsph[cols])), *O2, *E2, 0, 1)
+    w = oracle.prob_weights(sc, *O2, *E2, 0, 1)[:nf]
+    want = oracle.chi0(M, w)
+    npair = (O2[1] - O2[0]) * (E2[1] - E2[0])
+    Md = torch.empty((npair, dsc.ng, 2), dtype=torch.float64, device="cuda")
+    path.pair_density(ctx, dsc, 0, 1, o=O2, e=E2, out=Md, prec=prec)
+    chi = torch.empty((nf, dsc.ng, dsc.ng, 2), dtype=torch.float64, device="cuda")
+    rp.rp_chi0_accumulate(ctx, dsc.cell, sc.iq, dsc.nband, dsc.energy, dsc.T, *O2, *E2, 0, 1, dsc.ng, Md,
+                          nf, sc.freq_eV[:nf], sc.delta_eV, path.weight_mode(sc), prec, 0, chi)
+    idx = torch.from_numpy(cols).cuda()
+    got = path.to_complex(chi.index_select(1, idx).index_select(2, idx))
+    err = max(_rel(got[f], want[f]) for f in range(nf))
+    print(f"[supercell] sliced chi block prec={prec}: rel err {err:.2e}", flush=True)
     assert err < tol
 
 

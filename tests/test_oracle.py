@@ -135,6 +135,49 @@ def test_pair_grid_route_equals_plane_wave_convolution():
             assert np.max(np.abs(Mc)) > 1e-3
 
 
+def test_pair_densities_path_assembly_matches_plane_wave_form():
+    """oracle.pair_densities (the layout the library writes: pairs (k, a, b)
+    with b fastest, a empty at k' = k + q on the mesh, b occupied at k, the
+    umklapp G0 shifting the gather) against the plane-wave convolution of Eq.
+    ism, with k' and G0 worked out here from the mesh arithmetic, for pairs
+    at k-points with and without umklapp.  A k <-> k' swap, a conj on the
+    wrong side, a wrong G0 or a wrong pair index fails it."""
+    kmesh, iq = (3, 2, 2), (2, 1, 0)
+    p = make_problem(name="t", a_bohr=7.26, fft=(16, 16, 16), kmesh=kmesh, iq=iq,
+                     nocc=3, nemp=3, gpsi=3.0, ng=27, freq_eV=[0.0], delta_eV=0.1, seed=9)
+    assert np.abs(p.miller).max() * 2 + np.abs(p.gsph).max() + 2 < 16
+    o0, o1, e0, e1, k0, k1 = 1, 3, 3, 6, 2, 8
+    M = oracle.pair_densities(p, o0, o1, e0, e1, k0, k1)
+    assert M.shape == ((k1 - k0) * (e1 - e0) * (o1 - o0), p.ng)
+    K = np.array(kmesh)
+    umklapp = 0
+    checked = 0
+    for k in range(k0, k1):
+        n = np.array(np.unravel_index(k, kmesh))
+        s = n + np.array(iq)
+        kk = int(np.ravel_multi_index(tuple(s % K), kmesh))
+        g0 = s // K
+        umklapp += int(np.any(g0 != 0))
+        for a, b in ((e0, o0), (e1 - 1, o1 - 1), (e0 + 1, o0 + 1)):
+            row = ((k - k0) * (e1 - e0) + (a - e0)) * (o1 - o0) + (b - o0)
+            na, nb = p.npw[kk], p.npw[k]
+            want = oracle.pair_conv(p.miller[kk, :na], p.coef[kk, a, :na],
+                                    p.miller[k, :nb], p.coef[k, b, :nb], g0, p.gsph)
+            assert np.max(np.abs(M[row] - want)) < 1e-13, (k, a, b)
+            assert np.max(np.abs(want)) > 1e-3
+            checked += 1
+    assert umklapp >= 2 and checked >= 9
+    # the swapped assignment (empty band at k, occupied at k') is a different
+    # array: the check above would see it
+    k = k0
+    n = np.array(np.unravel_index(k, kmesh))
+    kk = int(np.ravel_multi_index(tuple((n + np.array(iq)) % K), kmesh))
+    wrong = oracle.pair_conv(p.miller[k, :p.npw[k]], p.coef[k, e0, :p.npw[k]],
+                             p.miller[kk, :p.npw[kk]], p.coef[kk, o0, :p.npw[kk]],
+                             (n + np.array(iq)) // K, p.gsph)
+    assert np.max(np.abs(M[0] - wrong)) > 1e-3
+
+
 def test_pair_density_matches_numpy_fft():
     fft = (8, 6, 10)
     ua, ub = _rand_c(fft), _rand_c(fft)
