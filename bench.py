@@ -139,7 +139,7 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(prob, ng_sample: int = 300):
+def cpu_baseline(prob, ng_sample: int = 500):
     """Time the FP64 oracle on a bounded sample of the q-point: k = 0 with all
     occupied x empty bands and all frequencies, on the first `ng_sample`
     vectors of the polarization sphere (pair densities on those vectors,
@@ -284,7 +284,7 @@ def batch_measure(args, embedded: bool = False) -> dict:
     baseline = None
     if not embedded and not args.no_cpu_baseline and not args.batch_no_graph:
         # the oracle on one problem of the batch (system 21, the fewest pairs
-        # per k-point): k = 0, all bands, 16 frequencies, the first 300 sphere vectors
+        # per k-point): k = 0, all bands, 16 frequencies, the first 500 sphere vectors
         small = [p for p in probs if p.name == "batch_system_21_q0"]
         if small:
             log("timing the FP64 oracle on a bounded sample of the batch (host cores)")

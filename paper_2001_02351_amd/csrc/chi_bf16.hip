@@ -510,52 +510,88 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
             accI[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
         }
 
+    // the weighted, split row operand of row block rb of the wave
+    auto split_rows = [&](const float2 *__restrict__ cA, int rb, const float4 (&wc)[4], bf8 (&ar)[NT],
+                          bf8 (&ai)[NT], bf8 (&an)[NT]) {
+        const float2 *blk = cA + (lk * 8 + wr * 4 + rb) * 128 + li * 2;
+        u4 wr_[NT], wi_[NT];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const float4 v = *(const float4 *)(blk + q * 32);   // pairs 2q, 2q+1: (re, im, re, im)
+            const float4 w = wc[q];
+            float r0, i0, r1, i1;
+            if (RW) {
+                r0 = v.x * w.x;
+                i0 = v.y * w.x;
+                r1 = v.z * w.z;
+                i1 = v.w * w.z;
+            } else {
+                r0 = v.x * w.x - v.y * w.y;
+                i0 = v.x * w.y + v.y * w.x;
+                r1 = v.z * w.z - v.w * w.w;
+                i1 = v.z * w.w + v.w * w.z;
+            }
+            unsigned tr[NT], ti[NT];
+            split_pair<NT>(r0, r1, tr);
+            split_pair<NT>(i0, i1, ti);
+#pragma unroll
+            for (int s = 0; s < NT; s++) {
+                wr_[s][q] = tr[s];
+                wi_[s][q] = ti[s];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NT; s++) {
+            ar[s] = __builtin_bit_cast(bf8, wr_[s]);
+            ai[s] = __builtin_bit_cast(bf8, wi_[s]);
+            an[s] = negate(ar[s]);
+        }
+    };
+    // Re += Re a Re b + Im a Im b;  Im += Im a Re b - Re a Im b over the
+    // products s + u < NT, for row block rb and column block cb
+    auto products = [&](int rb, int cb, const bf8 (&ar)[NT], const bf8 (&ai)[NT], const bf8 (&an)[NT],
+                        const bf8 (&B)[NPL]) {
+#pragma unroll
+        for (int s = 0; s < NT; s++)
+#pragma unroll
+            for (int u = 0; u < NT; u++) {
+                if (s + u >= NT) continue;
+                accR[rb][cb] = mfma_bf16(ar[s], B[u], accR[rb][cb]);
+                accI[rb][cb] = mfma_bf16(ai[s], B[u], accI[rb][cb]);
+                accR[rb][cb] = mfma_bf16(ai[s], B[NT + u], accR[rb][cb]);
+                accI[rb][cb] = mfma_bf16(an[s], B[NT + u], accI[rb][cb]);
+            }
+    };
+    constexpr int NPROD = 4 * NT * (NT + 1) / 2;   // matrix-core ops per (row block, column block)
+
     auto step = [&](float2 *__restrict__ nA, bf8 *__restrict__ nB, const float2 *__restrict__ cA,
                     const bf8 *__restrict__ cB, int kgn, const float4 (&wc)[4]) {
         if (kgn >= 0) issue(nA, nB, kgn);
-        // weighted, split row operand of the wave's 4 row blocks
         bf8 ar[4][NT], ai[4][NT], an[4][NT];
+        bf8 B[NPL];
+#pragma unroll
+        for (int sp = 0; sp < NPL; sp++) B[sp] = cB[(sp * 4 + lk) * 128 + li];
+        split_rows(cA, 0, wc, ar[0], ai[0], an[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        // column block 0, one row block after the other: the split of row
+        // block rb + 1 is issued among the matrix-core ops of row block rb
 #pragma unroll
         for (int rb = 0; rb < 4; rb++) {
-            const float2 *blk = cA + (lk * 8 + wr * 4 + rb) * 128 + li * 2;
-            u4 wr_[NT], wi_[NT];
+            products(rb, 0, ar[rb], ai[rb], an[rb], B);
+            if (rb + 1 < 4) {
+                split_rows(cA, rb + 1, wc, ar[rb + 1], ai[rb + 1], an[rb + 1]);
+                __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);       // the row block's LDS reads
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const float4 v = *(const float4 *)(blk + q * 32);   // pairs 2q, 2q+1: (re, im, re, im)
-                const float4 w = wc[q];
-                float r0, i0, r1, i1;
-                if (RW) {
-                    r0 = v.x * w.x;
-                    i0 = v.y * w.x;
-                    r1 = v.z * w.z;
-                    i1 = v.w * w.z;
-                } else {
-                    r0 = v.x * w.x - v.y * w.y;
-                    i0 = v.x * w.y + v.y * w.x;
-                    r1 = v.z * w.z - v.w * w.w;
-                    i1 = v.z * w.w + v.w * w.z;
-                }
-                unsigned tr[NT], ti[NT];
-                split_pair<NT>(r0, r1, tr);
-                split_pair<NT>(i0, i1, ti);
-#pragma unroll
-                for (int s = 0; s < NT; s++) {
-                    wr_[s][q] = tr[s];
-                    wi_[s][q] = ti[s];
+                for (int i = 0; i < NPROD; i++) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one matrix-core op
+                    __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);   // then vector instructions
                 }
             }
-#pragma unroll
-            for (int s = 0; s < NT; s++) {
-                ar[rb][s] = __builtin_bit_cast(bf8, wr_[s]);
-                ai[rb][s] = __builtin_bit_cast(bf8, wi_[s]);
-                an[rb][s] = negate(ar[rb][s]);
-            }
+            __builtin_amdgcn_sched_barrier(0);
         }
-        // Re += Re a Re b + Im a Im b;  Im += Im a Re b - Re a Im b over the
-        // products s + u < NT; per column block 8 independent accumulators
+        // the other column blocks: 8 independent accumulators per product
 #pragma unroll
-        for (int cb = 0; cb < 8; cb++) {
-            bf8 B[NPL];
+        for (int cb = 1; cb < 8; cb++) {
 #pragma unroll
             for (int sp = 0; sp < NPL; sp++) B[sp] = cB[(sp * 4 + lk) * 128 + cb * 16 + li];
 #pragma unroll

@@ -189,7 +189,9 @@ def test_abi_errors(ctx, rp, c1, d1):
     from paper_2001_02351_amd import path
     p, _ = c1
     d = d1
-    M = torch.empty((p.nocc * p.nemp, p.ng, 2), dtype=torch.float64, device="cuda")
+    # large enough for every call below (the binding refuses a tensor smaller
+    # than the pair ranges ask for before the library checks the ranges)
+    M = torch.empty(((p.nocc + 2) * (p.nemp + 2), p.ng, 2), dtype=torch.float64, device="cuda")
     small = rp.make_cell(p.lat, (10, 10, 10), p.kmesh)
     with pytest.raises(rp.RpError) as e:
         rp.rp_pair_density(ctx, small, p.iq, d.nband, p.miller.shape[1], p.npw, d.mmax, d.miller,
@@ -209,9 +211,14 @@ def test_abi_errors(ctx, rp, c1, d1):
     with pytest.raises(rp.RpError) as e:
         rp.rp_screen_W(ctx, d.cell, (0, 0, 0), 4, g_with_zero, 1, chi, None, None)
     assert e.value.status == 3            # RP_E_RANGE: |q+G| = 0
+    big = torch.empty((1, 6145, 6145, 2), dtype=torch.float64, device="cuda")
     with pytest.raises(rp.RpError) as e:
-        rp.rp_screen_W(ctx, d.cell, p.iq, 6145, np.ones((6145, 3), np.int32), 1, chi, None, None)
+        rp.rp_screen_W(ctx, d.cell, p.iq, 6145, np.ones((6145, 3), np.int32), 1, big, None, None)
     assert e.value.status == 8            # RP_E_UNSUPPORTED: N_G above the inversion's LDS plan
+    del big
+    # the binding refuses an undersized tensor before the library sees it
+    with pytest.raises(ValueError, match="elements"):
+        rp.rp_screen_W(ctx, d.cell, p.iq, 6145, np.ones((6145, 3), np.int32), 1, chi, None, None)
     with pytest.raises(rp.RpError) as e:
         rp.rp_weights(ctx, d.cell, p.iq, d.nband, d.energy, None, 0, 1, 1, 2, 0, 1, 1, [0.0],
                       -0.1, 0, torch.empty((1, 1, 2), dtype=torch.float64, device="cuda"))

@@ -90,7 +90,9 @@ def test_tunings_compute_the_same_chi(ctx, rp):
             d_ref = max(_rel(got[f], ref[f]) for f in range(d.nfreq))
             d_orc = max(_rel(got[f][cols][:, cols], want[f]) for f in range(d.nfreq))
             print(f"[tuning] nw={nw} fill={fill}: vs default {d_ref:.1e}, vs oracle {d_orc:.1e}", flush=True)
-            assert d_ref < 1e-6 and d_orc < 1e-5
+            # two split-BF16 results (other FP32 groupings of the same sums) each lie
+            # about 1e-6 from the exact chi element-wise, so they differ by up to 2e-6
+            assert d_ref < 2e-6 and d_orc < 1e-5
     rp.rp_set_tuning(ctx, [])
 
 
@@ -131,7 +133,8 @@ def test_wide_contraction_form_matches(ctx, rp):
             d_orc = max(_rel(got[f], want[f]) for f in range(d.nfreq))
             print(f"[tuning] wide form {kern} nw={nw} fill={fill}: vs default {d_ref:.1e}, "
                   f"vs oracle {d_orc:.1e}", flush=True)
-            assert d_ref < 1e-6 and d_orc < 1e-5
+            # two split-BF16 results, each about 1e-6 from the exact chi element-wise
+            assert d_ref < 2e-6 and d_orc < 1e-5
     rp.rp_set_tuning(ctx, [])
 
 
@@ -141,7 +144,7 @@ def test_tail_split_matches(ctx, rp, herm):
     pair steps, summed in FP64 by k_chi_reduce_tail): 360 units on complex
     weights (N_G = 700, 20 real frequencies) and on the Hermitian half
     (N_G = 1132, 16 imaginary frequencies), chi_fill = 400 so that the pair
-    steps are not sliced otherwise; against the unsplit run (fill 0) to 1e-6
+    steps are not sliced otherwise; against the unsplit run (fill 0) to 2e-6
     and the oracle on sampled columns to 1e-5."""
     from paper_2001_02351_amd import path
     from synth import make_problem
@@ -172,5 +175,6 @@ def test_tail_split_matches(ctx, rp, herm):
     d_ref = max(_rel(got[f], ref[f]) for f in range(d.nfreq))
     d_orc = max(_rel(got[f][cols][:, cols], want[f]) for f in range(d.nfreq))
     print(f"[tuning] tail split herm={herm}: vs unsplit {d_ref:.1e}, vs oracle {d_orc:.1e}", flush=True)
-    assert d_ref < 1e-6 and d_orc < 1e-5
+    # two split-BF16 results, each about 1e-6 from the exact chi element-wise
+    assert d_ref < 2e-6 and d_orc < 1e-5
     rp.rp_set_tuning(ctx, [])
