@@ -204,6 +204,29 @@ rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], 
                              rp_precision prec, int accumulate, double *chi);
 
 /*
+ * rp_chi0_accumulate without allocating, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as
+ * rp_chi0_accumulate; its workspace (frequencies, weights, split operands,
+ * partial tiles) is carved from a fixed device array of 128 MiB that the
+ * library holds on each GPU it runs on until the process ends, instead of
+ * the context's growable buffers, and nothing is allocated or freed.  A call
+ * whose workspace would exceed 128 MiB fails with RP_E_SHAPE before anything
+ * is enqueued (fewer pairs per call fit: e.g. 12 288 pairs at N_G = 89 and
+ * 10 frequencies take about 98 MiB in the split form).  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (contexts on different
+ * streams) race and must be ordered by the caller; each call writes every
+ * workspace byte it reads.
+ * Errors: as rp_chi0_accumulate; RP_E_SHAPE beyond the fixed workspace;
+ * RP_E_DEVICE when the array has no device address on this GPU.
+ */
+rp_status rp_chi0_accumulate_noalloc(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband,
+                                     const double *energy_eV, const double *T, int o0, int o1, int e0,
+                                     int e1, int k0, int k1, int ng, const double *M, int nfreq,
+                                     const double *freq_eV, double delta_eV, rp_weight_mode wm,
+                                     rp_precision prec, int accumulate, double *chi);
+
+/*
  * Steps a2-a6 for a batch of independent chi0 problems (section "Parallel
  * calculation": q-points are independent, and chi of one q is a sum of
  * band-pair blocks), enqueued as one HIP graph launch.  Each problem carries

@@ -20,6 +20,7 @@ from ._rp import (  # noqa: F401
     load_tuning,
     make_cell,
     rp_chi0_accumulate,
+    rp_chi0_accumulate_noalloc,
     rp_chi0_batch,
     rp_chi0_batch_graphs,
     rp_head_density,

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_E_NULL", 2: "RP_E_SHAPE", 3: "RP_E_RANGE", 4:
                 5: "RP_E_NOMEM", 6: "RP_E_DEVICE", 7: "RP_E_SINGULAR", 8: "RP_E_UNSUPPORTED"}
 
 EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pair_density",
-            "rp_weights", "rp_chi0_accumulate", "rp_chi0_batch", "rp_chi0_batch_graphs", "rp_screen_W", "rp_wannier_W",
+            "rp_weights", "rp_chi0_accumulate", "rp_chi0_accumulate_noalloc", "rp_chi0_batch", "rp_chi0_batch_graphs", "rp_screen_W", "rp_wannier_W",
             "rp_set_tuning", "rp_head_density", "rp_screen_head", "rp_wannier_qterm",
             "rp_coulomb_cell_average", "rp_frequency_grid", "rp_unfold_coef", "rp_unfold_eps_inv",
             "rp_set_fermi_level", "rp_pair_grid", "rp_plasma_frequency", "rp_set_drude", "rp_profile",
@@ -102,6 +102,7 @@ def load(path: Optional[str] = None):
         "rp_pair_density": [P, cellp, P, I, I, P, P, P, P, I, I, I, I, I, I, I, P, I, P],
         "rp_weights": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, D, I, P],
         "rp_chi0_accumulate": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, I, P, D, I, I, I, P],
+        "rp_chi0_accumulate_noalloc": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, I, P, D, I, I, I, P],
         "rp_chi0_batch": [P, I, ctypes.POINTER(rp_problem), I],
         "rp_chi0_batch_graphs": [P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_long)],
         "rp_screen_W": [P, cellp, P, I, P, I, P, P, P],
@@ -298,6 +299,19 @@ def rp_chi0_accumulate(ctx: Context, cell: rp_cell, iq, nband, energy_eV, T, o0,
                                     int(accumulate), _dp(chi))
     ctx._leave()
     ctx._check(st, "rp_chi0_accumulate")
+
+
+def rp_chi0_accumulate_noalloc(ctx: Context, cell: rp_cell, iq, nband, energy_eV, T, o0, o1, e0, e1, k0, k1,
+                               ng, M, nfreq, freq_eV, delta_eV, wm, prec, accumulate, chi):
+    iq_h, f_h = _host(iq, np.int32), _host(freq_eV, np.complex128)
+    _chi_args(cell, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, ng, M, nfreq, chi)
+    ctx._enter()
+    st = ctx.lib.rp_chi0_accumulate_noalloc(ctx.handle, ctypes.byref(cell), _hp(iq_h), int(nband),
+                                            _dp(energy_eV), _dp(T), o0, o1, e0, e1, k0, k1, int(ng), _dp(M),
+                                            int(nfreq), _hp(f_h), float(delta_eV), int(wm), int(prec),
+                                            int(accumulate), _dp(chi))
+    ctx._leave()
+    ctx._check(st, "rp_chi0_accumulate_noalloc")
 
 
 def rp_chi0_batch(ctx: Context, problems, prec):

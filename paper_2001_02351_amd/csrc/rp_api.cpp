@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <optional>
 #include <unordered_map>
 #include <vector>
@@ -497,6 +498,37 @@ static void key_put(std::string &key, const void *p, size_t n) { key.append((con
 
 template <typename T> static void key_val(std::string &key, const T &v) { key_put(key, &v, sizeof v); }
 
+// Fixed workspace of rp_chi0_accumulate_noalloc: a device array in the
+// library's code object, so each GPU that loads the library holds one copy of
+// kScratchBytes until the process ends.  Host code never uses the name
+// `scratch` as an address: the device address comes from hipGetSymbolAddress,
+// once per device with that device current, and is kept per device.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64];
+static bool g_scratch_done[64];
+
+// The address of this device's scratch array (the device must be current),
+// or nullptr when the runtime cannot resolve it.
+static void *scratch_address(int device)
+{
+    if (device < 0 || device >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ptr = nullptr;
+        }
+        g_scratch_ptr[device] = ptr;
+        g_scratch_done[device] = true;
+    }
+    return g_scratch_ptr[device];
+}
+
 }  // namespace rp
 
 using namespace rp;
@@ -531,6 +563,7 @@ rp_status rp_create(rp_ctx **out, int device, void *hip_stream)
         delete ctx;
         return RP_E_DEVICE;
     }
+    ctx->scratch = scratch_address(device);
     *out = ctx;
     return RP_OK;
 }
@@ -694,6 +727,43 @@ rp_status rp_chi0_accumulate(rp_ctx *ctx, const rp_cell *cell, const int iq[3], 
     const ChiBufs bufs{(double2 *)ctx->weights.p, ctx->split_a.p, ctx->split_b.p, ctx->split_w.p,
                        ctx->chi_part.p};
     return chi_enqueue(ctx, c, k0, k1, (const double2 *)M, (const double2 *)ctx->freq.p, bufs, accumulate,
+                       (double2 *)chi);
+}
+
+rp_status rp_chi0_accumulate_noalloc(rp_ctx *ctx, const rp_cell *cell, const int iq[3], int nband,
+                                     const double *energy_eV, const double *T, int o0, int o1, int e0, int e1,
+                                     int k0, int k1, int ng, const double *M, int nfreq, const double *freq_eV,
+                                     double delta_eV, rp_weight_mode wm, rp_precision prec, int accumulate,
+                                     double *chi)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    ChiJob c;
+    rp_status st = chi_check(ctx, cell, iq, nband, energy_eV, T, o0, o1, e0, e1, k0, k1, ng, nfreq, freq_eV,
+                             delta_eV, wm, prec, accumulate, &c);
+    if (st != RP_OK) return st;
+    if (!M || !chi) return fail(ctx, RP_E_NULL, "NULL M or chi");
+    if (!ctx->scratch) return fail(ctx, RP_E_DEVICE, "the fixed workspace has no device address on this GPU");
+    // the workspace of rp_chi0_accumulate, carved from the fixed array in
+    // 256-byte aligned pieces: frequencies, weights, split operands, partial tiles
+    const long npair = (long)(k1 - k0) * (e1 - e0) * (o1 - o0);
+    const ChiBytes nb = chi_bytes(c, npair);
+    auto up = [](size_t n) { return (n + 255) / 256 * 256; };
+    const size_t off_f = 0, off_w = up(sizeof(double2) * nfreq);
+    const size_t off_a = off_w + up(nb.w), off_b = off_a + up(nb.a), off_sw = off_b + up(nb.b);
+    const size_t off_part = off_sw + up(nb.sw), need = off_part + up(nb.part);
+    if (need > kScratchBytes)
+        return fail(ctx, RP_E_SHAPE,
+                    "this call needs %zu bytes of workspace, more than the fixed %zu (fewer pairs per call)", need,
+                    kScratchBytes);
+    char *base = (char *)ctx->scratch;
+    if (hipMemcpyAsync(base + off_f, freq_eV, sizeof(double2) * nfreq, hipMemcpyHostToDevice, ctx->stream) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, RP_E_DEVICE, "host-to-device copy of the frequencies failed");
+    }
+    const ChiBufs bufs{(double2 *)(base + off_w), base + off_a, base + off_b, base + off_sw, base + off_part};
+    return chi_enqueue(ctx, c, k0, k1, (const double2 *)M, (const double2 *)(base + off_f), bufs, accumulate,
                        (double2 *)chi);
 }
 

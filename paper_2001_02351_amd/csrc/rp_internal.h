@@ -55,6 +55,7 @@ struct rp_ctx {
     bool own_stream = false;
     std::string err;
     int *flag = nullptr;            // device int[4] fault flags
+    void *scratch = nullptr;        // this device's fixed workspace (rp_chi0_accumulate_noalloc)
     rp::DevBuf ugrid;               // u-grids of one k: [nO + nE][N1][N2][N3] c128
     rp::DevBuf ugrid32;             // the same grids in FP32 (split-precision path)
     rp::DevBuf weights;             // w[nfreq][npair] c128
