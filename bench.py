@@ -193,11 +193,10 @@ def run_leg(rp, path, ctx, d, prec, steps, warmup, kbatch):
     import torch
     npair_total = d.nk * d.prob.nocc * d.prob.nemp
     flops = 8.0 * d.ng ** 2 * npair_total * d.nfreq
-    Mbuf = torch.empty((kbatch * d.prob.nocc * d.prob.nemp, d.ng, 2), dtype=torch.float64, device=d.device)
     chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device=d.device)
     for i in range(warmup):
         log(f"prec={prec} warmup step {i}")
-        c = path.chi0(ctx, d, prec=prec, kbatch=kbatch, chi=chi, Mbuf=Mbuf)
+        c = path.chi0(ctx, d, prec=prec, kbatch=kbatch, chi=chi)
         einv, W = path.screen(ctx, d, c)
         path.wannier(ctx, d, einv)
         rp.rp_synchronize(ctx)
@@ -206,7 +205,7 @@ def run_leg(rp, path, ctx, d, prec, steps, warmup, kbatch):
     for i in range(steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        c = path.chi0(ctx, d, prec=prec, kbatch=kbatch, chi=chi, Mbuf=Mbuf)
+        c = path.chi0(ctx, d, prec=prec, kbatch=kbatch, chi=chi)
         rp.rp_synchronize(ctx)
         t1 = time.perf_counter()
         einv, W = path.screen(ctx, d, c)
@@ -462,17 +461,15 @@ def supercell_measure(args) -> dict:
     nrun = nblk if args.sc_blocks <= 0 else min(nblk, args.sc_blocks)
     prec = rp.RP_SPLIT_BF16
     chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device=d.device)
-    M = torch.empty((p.nocc * eb, d.ng, 2), dtype=torch.float64, device=d.device)
     torch.cuda.synchronize()
     log("supercell inputs resident on the device")
 
     def block(i, acc):
+        # one empty-band block: its pair kernels write the contraction's operands
         e0 = p.nocc + i * eb
         e1 = min(p.nocc + p.nemp, e0 + eb)
-        Mk = M[: p.nocc * (e1 - e0)]
-        path.pair_density(ctx, d, 0, 1, o=(0, p.nocc), e=(e0, e1), out=Mk, prec=prec)
-        rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, d.T, 0, p.nocc, e0, e1, 0, 1, d.ng, Mk,
-                              d.nfreq, p.freq_eV, p.delta_eV, path.weight_mode(p), prec, acc, chi)
+        rp.rp_chi0_run(ctx, path.batch_problem(d, chi, 1, o=(0, p.nocc), e=(e0, e1), k=(0, 1), accumulate=acc),
+                       prec)
 
     block(0, 0)                                      # warm-up (kernel loading)
     rp.rp_synchronize(ctx)

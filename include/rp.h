@@ -232,9 +232,14 @@ rp_status rp_chi0_accumulate_noalloc(rp_ctx *ctx, const rp_cell *cell, const int
  * band-pair blocks), enqueued as one HIP graph launch.  Each problem carries
  * the arguments of rp_pair_density and rp_chi0_accumulate; its k range
  * [k0, k1) is processed kbatch k-points at a time: the pair densities of a
- * batch go to a context-owned buffer, then their weights and contraction are
+ * batch go to context-owned buffers, then their weights and contraction are
  * added into the problem's chi (the first batch overwrites chi when
- * accumulate = 0).  A problem with no pairs only clears chi (accumulate = 0).
+ * accumulate = 0).  In FP64 the buffer holds M as rp_pair_density writes it;
+ * in the split forms the pair kernels write the contraction's operands
+ * directly (each M value rounded to FP32, and its BF16 terms), the same
+ * operands rp_chi0_accumulate prepares from M, so chi is the same as from
+ * rp_pair_density and rp_chi0_accumulate per batch, bit for bit.  A problem
+ * with no pairs only clears chi (accumulate = 0).
  * Problems may differ in cell, grid, k mesh, bands, N_G and frequencies;
  * they run one after the other on the context's stream, sharing workspace.
  *
@@ -249,8 +254,9 @@ rp_status rp_chi0_accumulate_noalloc(rp_ctx *ctx, const rp_cell *cell, const int
  *   npw (host int[Nk]), mmax, miller (dev), coef (dev), energy_eV (dev),
  *   T (dev or NULL), gsph (host int[ng][3]), freq_eV (host c128[nfreq]),
  *   chi (dev c128[nfreq][ng][ng] output, hartree^-1).
- * kbatch >= 1 sets the pair-density buffer: 16*kbatch*(o1-o0)*(e1-e0)*ng
- * bytes for the largest problem.
+ * kbatch >= 1 sets the pair-density buffers for the largest problem, with
+ * P = kbatch*(o1-o0)*(e1-e0): FP64 16*P*ng bytes; split forms 20*KP*NGP bytes
+ * (KP = P rounded up to 32, NGP = ng rounded up to 128).
  * prec applies to every problem.
  * Errors: those of rp_pair_density and rp_chi0_accumulate, with "problem i:"
  * in the message; RP_E_SHAPE for kbatch < 1 or nprob < 0.  On a non-OK
@@ -289,6 +295,21 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
  * Errors: RP_E_NULL.
  */
 rp_status rp_chi0_batch_graphs(rp_ctx *ctx, int *graphs, long *nodes);
+
+/*
+ * Steps a2-a6 of one chi0 problem (Eqs. ism and chi), enqueued directly on
+ * the context's stream (no graph): the k range [k0, k1) of *p is processed
+ * kbatch k-points at a time exactly as one problem of rp_chi0_batch, with
+ * the same buffers (in the split forms the pair kernels write the
+ * contraction's operands, and no FP64 M exists), so chi equals that of
+ * rp_chi0_batch, and of rp_pair_density and rp_chi0_accumulate per k batch,
+ * bit for bit.  Fields of *p as in rp_chi0_batch; p is read during the call
+ * only.
+ * Errors: those of rp_pair_density and rp_chi0_accumulate; RP_E_NULL for a
+ * NULL p or chi; RP_E_SHAPE for kbatch < 1.  On a non-OK status nothing has
+ * been launched.
+ */
+rp_status rp_chi0_run(rp_ctx *ctx, const rp_problem *p, rp_precision prec);
 
 /*
  * Steps a7-a9: eps = I - v^1/2 chi v^1/2 with v^1/2_G = sqrt(4 pi/Omega)/|q+G|

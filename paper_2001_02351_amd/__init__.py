@@ -23,6 +23,7 @@ from ._rp import (  # noqa: F401
     rp_chi0_accumulate_noalloc,
     rp_chi0_batch,
     rp_chi0_batch_graphs,
+    rp_chi0_run,
     rp_head_density,
     rp_problem,
     rp_last_error,

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_E_NULL", 2: "RP_E_SHAPE", 3: "RP_E_RANGE", 4:
                 5: "RP_E_NOMEM", 6: "RP_E_DEVICE", 7: "RP_E_SINGULAR", 8: "RP_E_UNSUPPORTED"}
 
 EXPORTED = ["rp_create", "rp_destroy", "rp_synchronize", "rp_last_error", "rp_pair_density",
-            "rp_weights", "rp_chi0_accumulate", "rp_chi0_accumulate_noalloc", "rp_chi0_batch", "rp_chi0_batch_graphs", "rp_screen_W", "rp_wannier_W",
+            "rp_weights", "rp_chi0_accumulate", "rp_chi0_accumulate_noalloc", "rp_chi0_batch", "rp_chi0_batch_graphs", "rp_chi0_run", "rp_screen_W", "rp_wannier_W",
             "rp_set_tuning", "rp_head_density", "rp_screen_head", "rp_wannier_qterm",
             "rp_coulomb_cell_average", "rp_frequency_grid", "rp_unfold_coef", "rp_unfold_eps_inv",
             "rp_set_fermi_level", "rp_pair_grid", "rp_plasma_frequency", "rp_set_drude", "rp_profile",
@@ -105,6 +105,7 @@ def load(path: Optional[str] = None):
         "rp_chi0_accumulate_noalloc": [P, cellp, P, I, P, P, I, I, I, I, I, I, I, P, I, P, D, I, I, I, P],
         "rp_chi0_batch": [P, I, ctypes.POINTER(rp_problem), I],
         "rp_chi0_batch_graphs": [P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_long)],
+        "rp_chi0_run": [P, ctypes.POINTER(rp_problem), I],
         "rp_screen_W": [P, cellp, P, I, P, I, P, P, P],
         "rp_wannier_W": [P, cellp, P, I, P, P, I, P, I, P, I, P, P],
         "rp_set_tuning": [P, I, ctypes.POINTER(rp_tune_entry)],
@@ -314,6 +315,29 @@ def rp_chi0_accumulate_noalloc(ctx: Context, cell: rp_cell, iq, nband, energy_eV
     ctx._check(st, "rp_chi0_accumulate_noalloc")
 
 
+def _fill_problem(r, q, keep):
+    """Fills the rp_problem r from the dict q (host copies appended to keep)."""
+    r.cell = q["cell"]
+    for a in range(3):
+        r.iq[a] = int(q["iq"][a])
+    npw_h, mm_h = _host(q["npw"], np.int32), _host(q["mmax"], np.int32)
+    g_h, f_h = _host(q["gsph"], np.int32), _host(q["freq_eV"], np.complex128)
+    keep += [npw_h, g_h, f_h]
+    for a in range(3):
+        r.mmax[a] = int(mm_h[a])
+    r.npw, r.gsph, r.freq_eV = _hp(npw_h), _hp(g_h), _hp(f_h)
+    _bands(q["cell"], q["nband"], q["npw_max"], q["miller"], q["coef"])
+    _need(q["energy_eV"], "energy_eV", "f64", _nk(q["cell"]) * int(q["nband"]))
+    _need(q.get("T"), "T", "f64", _nk(q["cell"]) * int(q["nband"]), optional=True)
+    _need(q["chi"], "chi", "f64", int(q["nfreq"]) * int(q["ng"]) ** 2 * 2)
+    r.miller, r.coef = _dp(q["miller"]), _dp(q["coef"])
+    r.energy_eV, r.T, r.chi = _dp(q["energy_eV"]), _dp(q.get("T")), _dp(q["chi"])
+    for name in ("nband", "npw_max", "o0", "o1", "e0", "e1", "k0", "k1", "ng", "nfreq", "wm",
+                 "kbatch", "accumulate"):
+        setattr(r, name, int(q[name]))
+    r.delta_eV = float(q["delta_eV"])
+
+
 def rp_chi0_batch(ctx: Context, problems, prec):
     """problems: a sequence of dicts with the rp_problem fields; "cell" is an
     rp_cell, host arrays (npw, mmax, gsph, freq_eV) are numpy-convertible,
@@ -321,30 +345,22 @@ def rp_chi0_batch(ctx: Context, problems, prec):
     keep = []
     arr = (rp_problem * max(1, len(problems)))()
     for i, q in enumerate(problems):
-        r = arr[i]
-        r.cell = q["cell"]
-        for a in range(3):
-            r.iq[a] = int(q["iq"][a])
-        npw_h, mm_h = _host(q["npw"], np.int32), _host(q["mmax"], np.int32)
-        g_h, f_h = _host(q["gsph"], np.int32), _host(q["freq_eV"], np.complex128)
-        keep += [npw_h, g_h, f_h]
-        for a in range(3):
-            r.mmax[a] = int(mm_h[a])
-        r.npw, r.gsph, r.freq_eV = _hp(npw_h), _hp(g_h), _hp(f_h)
-        _bands(q["cell"], q["nband"], q["npw_max"], q["miller"], q["coef"])
-        _need(q["energy_eV"], "energy_eV", "f64", _nk(q["cell"]) * int(q["nband"]))
-        _need(q.get("T"), "T", "f64", _nk(q["cell"]) * int(q["nband"]), optional=True)
-        _need(q["chi"], "chi", "f64", int(q["nfreq"]) * int(q["ng"]) ** 2 * 2)
-        r.miller, r.coef = _dp(q["miller"]), _dp(q["coef"])
-        r.energy_eV, r.T, r.chi = _dp(q["energy_eV"]), _dp(q.get("T")), _dp(q["chi"])
-        for name in ("nband", "npw_max", "o0", "o1", "e0", "e1", "k0", "k1", "ng", "nfreq", "wm",
-                     "kbatch", "accumulate"):
-            setattr(r, name, int(q[name]))
-        r.delta_eV = float(q["delta_eV"])
+        _fill_problem(arr[i], q, keep)
     ctx._enter()
     st = ctx.lib.rp_chi0_batch(ctx.handle, len(problems), arr, int(prec))
     ctx._leave()
     ctx._check(st, "rp_chi0_batch")
+
+
+def rp_chi0_run(ctx: Context, problem, prec):
+    """One problem (a dict as for rp_chi0_batch), enqueued without a graph."""
+    keep = []
+    r = rp_problem()
+    _fill_problem(r, problem, keep)
+    ctx._enter()
+    st = ctx.lib.rp_chi0_run(ctx.handle, ctypes.byref(r), int(prec))
+    ctx._leave()
+    ctx._check(st, "rp_chi0_run")
 
 
 def rp_chi0_batch_graphs(ctx: Context) -> tuple:

@@ -28,6 +28,7 @@
 #include <algorithm>
 
 #include "fft_lds.h"
+#include "split_ops.h"
 
 namespace rp {
 
@@ -49,16 +50,6 @@ constexpr int kFlush = 512;
 __device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-template <int NT> __device__ __forceinline__ void split(float x, __bf16 (&t)[NT])
-{
-    float r = x;
-#pragma unroll
-    for (int s = 0; s < NT; s++) {
-        t[s] = (__bf16)r;
-        if (s + 1 < NT) r = r - (float)t[s];
-    }
 }
 
 __device__ __forceinline__ bf8 negate(bf8 v)
@@ -108,6 +99,28 @@ __global__ void k_split_prep(long npair, int ng, int npg, int NGP, const double2
     const long plane = (long)npg * NGP;
 #pragma unroll
     for (int s = 0; s < 2 * NT; s++) Bp[s * plane + t] = pl[s];
+}
+
+// zeros into the padding slots of the operands: the first nrow threads take
+// (pair group, padding row), the rest (pair group holding padding pairs, row)
+__global__ void k_ops_pad(SplitOps o, long npair, int ng, long nrow, long ntot)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntot) return;
+    long pg;
+    int g, j0;
+    if (t < nrow) {
+        const int pad = o.NGP - ng;
+        pg = t / pad;
+        g = ng + (int)(t - pg * pad);
+        j0 = 0;
+    } else {
+        const long u = t - nrow;
+        pg = npair / 8 + u / ng;
+        g = (int)(u - (u / ng) * ng);
+        j0 = (int)max(0L, npair - pg * 8);
+    }
+    for (int j = j0; j < 8; j++) ops_store(o, pg * 8 + j, g, 0.f, 0.f);
 }
 
 // real_w: the weights are real (imaginary frequencies, no broadening) and
@@ -1068,8 +1081,20 @@ size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill
     return (size_t)S * nfreq * (size_t)pad_ng(ng) * pad_ng(ng) * sizeof(float2);
 }
 
-void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, const double2 *M,
-                       const double2 *w, bool herm, void *split_a, void *split_b, void *split_w)
+SplitOps split_ops(void *split_a, void *split_b, long npair, int ng, int nterm)
+{
+    SplitOps o;
+    o.A = split_a;
+    o.B = split_b;
+    o.p0 = 0;
+    o.NGP = pad_ng(ng);
+    o.npg = (int)(pad_pairs(npair) / 8);
+    o.nterm = nterm;
+    return o;
+}
+
+void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, const double2 *M, void *split_a,
+                       void *split_b)
 {
     const long KP = pad_pairs(npair);
     const int NGP = pad_ng(ng);
@@ -1083,7 +1108,23 @@ void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, 
     else
         hipLaunchKernelGGL(k_split_prep<3>, grid, dim3(256), 0, s, npair, ng, npg, NGP, M, (float2 *)split_a,
                            (bf8 *)split_b);
+}
+
+void launch_ops_pad(hipStream_t s, const SplitOps &ops, long npair, int ng)
+{
+    if (npair <= 0) return;
+    const long nrow = (long)ops.npg * (ops.NGP - ng);
+    const long ntot = nrow + (ops.npg - npair / 8) * (long)ng;
+    if (ntot == 0) return;
+    hipLaunchKernelGGL(k_ops_pad, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, ops, npair, ng, nrow,
+                       ntot);
+}
+
+void launch_weight_prep(hipStream_t s, long npair, int nfreq, const double2 *w, bool herm, void *split_w)
+{
+    const long KP = pad_pairs(npair);
     const long nw = KP * nfreq;
+    if (nw == 0) return;
     hipLaunchKernelGGL(k_weight_prep, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, npair, KP, nfreq, w,
                        (int)herm, (float2 *)split_w);
 }

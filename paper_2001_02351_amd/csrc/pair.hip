@@ -10,18 +10,71 @@
 // registers, so no full-size intermediate ever leaves LDS.  The grids and
 // transforms run in FP64 (double2) or FP32 (float2); M is written in FP64.
 #include <algorithm>
+#include <type_traits>
 
 #include "fft_lds.h"
+#include "split_ops.h"
 
 namespace rp {
 
 namespace {
 
+// The block's pair densities as split operands: pair (a, b) of this k is
+// pair p0 + a nO + b of the contraction call.  The value is the FP64 M of the
+// plain output, (double) acc / N_r, rounded to FP32, so the operands equal
+// those the split preparation makes from M.  Two pairs b, b + 1 that share a
+// group of 8 at an even position go out in one store.
+template <int I, int N, typename F> __device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+template <typename C, int NA, int NB, int MAXG>
+__device__ __forceinline__ void pair_ops_out(const C (&acc)[NA * NB][MAXG], int a0, int b0, int nO, int nE,
+                                             int ng, int tid, double inv, const SplitOps &ops)
+{
+    auto val = [&](int q, int t) {
+        return make_float2((float)((double)acc[q][t].x * inv), (float)((double)acc[q][t].y * inv));
+    };
+    // compile-time band indices, so that acc stays in registers
+    static_for<0, NA>([&](auto IA) {
+        constexpr int ia = decltype(IA)::value;
+        const int a = a0 + ia;
+        if (a >= nE) return;
+        const long P0 = ops.p0 + (long)a * nO + b0;
+        if constexpr (NB == 2) {
+            if (b0 + 1 < nO && (P0 & 1) == 0) {
+#pragma unroll
+                for (int t = 0; t < MAXG; t++) {
+                    const int g = tid + t * 256;
+                    if (g < ng) ops_store2(ops, P0, g, val(ia * NB, t), val(ia * NB + 1, t));
+                }
+                return;
+            }
+        }
+        static_for<0, NB>([&](auto IB) {
+            constexpr int ib = decltype(IB)::value;
+            if (b0 + ib >= nO) return;
+#pragma unroll
+            for (int t = 0; t < MAXG; t++) {
+                const int g = tid + t * 256;
+                if (g < ng) {
+                    const float2 v = val(ia * NB + ib, t);
+                    ops_store(ops, P0 + ib, g, v.x, v.y);
+                }
+            }
+        });
+    });
+}
+
 template <typename C, int NA, int NB, int MAXG>
 __global__ void __launch_bounds__(256)
 k_pair(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int nE, int N1, int N2, int N3,
        FftPlan p2, FftPlan p3, int ng, const int *__restrict__ gsph, int g01, int g02, int g03, int lo3,
-       int L3, int rows, double2 *__restrict__ M)
+       int L3, int rows, double2 *__restrict__ M, SplitOps ops)
 {
     typedef typename CxT<C>::T T;
     constexpr int NP = NA * NB;
@@ -118,6 +171,10 @@ k_pair(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int nE,
         }
     }
     const double inv = 1.0 / (double)nr;
+    if (ops.A) {
+        pair_ops_out<C, NA, NB, MAXG>(acc, a0, b0, nO, nE, ng, tid, inv, ops);
+        return;
+    }
 #pragma unroll
     for (int ia = 0; ia < NA; ia++)
 #pragma unroll
@@ -177,7 +234,8 @@ template <typename C, int N, int NP> constexpr int lanes_l3max()
 template <typename C, int N, int NA, int NB, int MAXG>
 __global__ void __launch_bounds__(256, 2)
 k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int nE, int N1, int ng,
-             const int *__restrict__ gsph, int g01, int g02, int g03, int lo3, int L3, double2 *__restrict__ M)
+             const int *__restrict__ gsph, int g01, int g02, int g03, int lo3, int L3, double2 *__restrict__ M,
+             SplitOps ops)
 {
     constexpr int G = pair_group<N>(), Q = N / G, NP = NA * NB;
     constexpr int NGRP = 256 / G;             // lane groups per workgroup
@@ -321,6 +379,10 @@ k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, i
         }
     }
     const double inv = 1.0 / (double)nr;
+    if (ops.A) {
+        pair_ops_out<C, NA, NB, MAXG>(acc, a0, b0, nO, nE, ng, tid, inv, ops);
+        return;
+    }
 #pragma unroll
     for (int qq = 0; qq < NP; qq++) {
         const int a = a0 + qq / NB, b = b0 + qq % NB;
@@ -336,12 +398,12 @@ k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, i
 
 template <typename C, int N, int NA, int NB>
 void launch_pair_lanes(hipStream_t s, int N1, const C *u_occ, const C *u_emp, int nO, int nE, int ng,
-                       const int *gsph, const int g0[3], int lo3, int L3, double2 *M)
+                       const int *gsph, const int g0[3], int lo3, int L3, double2 *M, const SplitOps &ops)
 {
     const unsigned nblk = (unsigned)(((nE + NA - 1) / NA) * ((nO + NB - 1) / NB));
 #define RP_PAIRL(G)                                                                                          \
     hipLaunchKernelGGL((k_pair_lanes<C, N, NA, NB, G>), dim3(nblk), dim3(256), 0, s, u_occ, u_emp, nO, nE,   \
-                       N1, ng, gsph, g0[0], g0[1], g0[2], lo3, L3, M)
+                       N1, ng, gsph, g0[0], g0[1], g0[2], lo3, L3, M, ops)
     if constexpr (N >= 96) {
         // large grids come with large spheres: 2048, 4096 or 6144 points
         if (ng <= 2048) RP_PAIRL(8);
@@ -358,14 +420,16 @@ void launch_pair_lanes(hipStream_t s, int N1, const C *u_occ, const C *u_emp, in
 
 template <typename C, int NA, int NB>
 void launch_pair_t(hipStream_t s, const FftPlan plans[3], const int fft[3], const C *u_occ, const C *u_emp,
-                   int nO, int nE, int ng, const int *gsph, const int g0[3], int lo3, int L3, double2 *M)
+                   int nO, int nE, int ng, const int *gsph, const int g0[3], int lo3, int L3, double2 *M,
+                   const SplitOps &ops)
 {
     const int rows = pair_rows(fft);
     const size_t shm = pair_lds_bytes(fft, L3, rows, sizeof(C), NA * NB);
     const unsigned nblk = (unsigned)(((nE + NA - 1) / NA) * ((nO + NB - 1) / NB));
 #define RP_PAIR(G)                                                                                          \
     hipLaunchKernelGGL((k_pair<C, NA, NB, G>), dim3(nblk), dim3(256), shm, s, u_occ, u_emp, nO, nE, fft[0], \
-                       fft[1], fft[2], plans[1], plans[2], ng, gsph, g0[0], g0[1], g0[2], lo3, L3, rows, M)
+                       fft[1], fft[2], plans[1], plans[2], ng, gsph, g0[0], g0[1], g0[2], lo3, L3, rows, M, \
+                       ops)
     if (ng <= 512) RP_PAIR(2);
     else if (ng <= 1024) RP_PAIR(4);
     else if (ng <= 2048) RP_PAIR(8);
@@ -445,26 +509,32 @@ bool pair_supported(const int fft[3], int ng, int L3, bool fp32)
     return pair_lds_bytes(fft, L3, pair_rows(fft), fp32 ? 8 : 16, fp32 ? 4 : 1) <= 160 * 1024;
 }
 
-void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], const void *u_occ,
-                   const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3], int lo3,
-                   int L3, bool fp32, double2 *M)
+// the FP32 or FP64 pair kernel for this grid: the lane-group form when it
+// takes the grid, sphere and window, else the generic LDS form
+static void launch_pair_any(hipStream_t s, const FftPlan plans[3], const int fft[3], const void *u_occ,
+                            const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3], int lo3,
+                            int L3, bool fp32, double2 *M, const SplitOps &ops)
 {
     if (fp32 && pair_lanes_f32(fft, ng, L3)) {
         const float2 *uo = (const float2 *)u_occ, *ue = (const float2 *)u_emp;
         switch (fft[1]) {
-#define RP_CASE(n) \
-        case n: launch_pair_lanes<float2, n, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+#define RP_CASE(n)                                                                                          \
+        case n:                                                                                             \
+            launch_pair_lanes<float2, n, 2, 2>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M, ops);   \
+            return;
             RP_LANE_LENGTHS_F32(RP_CASE)
 #undef RP_CASE
-        case 96: launch_pair_lanes<float2, 96, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+        case 96: launch_pair_lanes<float2, 96, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M, ops); return;
         default: break;
         }
     }
     if (!fp32 && pair_lanes_f64(fft, ng, L3)) {
         const double2 *uo = (const double2 *)u_occ, *ue = (const double2 *)u_emp;
         switch (fft[1]) {
-#define RP_CASE(n) \
-        case n: launch_pair_lanes<double2, n, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M); return;
+#define RP_CASE(n)                                                                                          \
+        case n:                                                                                             \
+            launch_pair_lanes<double2, n, 2, 1>(s, fft[0], uo, ue, nO, nE, ng, gsph, g0, lo3, L3, M, ops);  \
+            return;
             RP_LANE_LENGTHS_F64(RP_CASE)
 #undef RP_CASE
         default: break;
@@ -472,10 +542,24 @@ void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], cons
     }
     if (fp32)
         launch_pair_t<float2, 2, 2>(s, plans, fft, (const float2 *)u_occ, (const float2 *)u_emp, nO, nE, ng,
-                                    gsph, g0, lo3, L3, M);
+                                    gsph, g0, lo3, L3, M, ops);
     else
         launch_pair_t<double2, 1, 1>(s, plans, fft, (const double2 *)u_occ, (const double2 *)u_emp, nO, nE,
-                                     ng, gsph, g0, lo3, L3, M);
+                                     ng, gsph, g0, lo3, L3, M, ops);
+}
+
+void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], const void *u_occ,
+                   const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3], int lo3,
+                   int L3, bool fp32, double2 *M)
+{
+    launch_pair_any(s, plans, fft, u_occ, u_emp, nO, nE, ng, gsph, g0, lo3, L3, fp32, M, SplitOps{});
+}
+
+void launch_pair_ops(hipStream_t s, const FftPlan plans[3], const int fft[3], const void *u_occ,
+                     const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3], int lo3, int L3,
+                     const SplitOps &ops)
+{
+    launch_pair_any(s, plans, fft, u_occ, u_emp, nO, nE, ng, gsph, g0, lo3, L3, true, nullptr, ops);
 }
 
 }  // namespace rp

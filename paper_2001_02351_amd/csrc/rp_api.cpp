@@ -318,10 +318,11 @@ static size_t pair_grid_bytes(const PairJob &j)
 
 // Enqueues steps a2-a4 for k in [k0, k1): per k, the u-grids of the occupied
 // bands at k and of the empty bands at k+q (into `grid`), then the pair
-// kernel into M[k - k0].  dg is the device copy of the G list.  No
-// allocation, copy or synchronization.
+// kernel into M[k - k0], or, when ops is given (FP32 grids), into the split
+// operands of one contraction over the pairs of [k0, k1) in M's order.  dg is
+// the device copy of the G list.  No allocation, copy or synchronization.
 static rp_status pair_enqueue(rp_ctx *ctx, const PairJob &j, int k0, int k1, const int *dg, void *grid,
-                              double2 *M)
+                              double2 *M, const SplitOps *ops = nullptr)
 {
     const Geometry &g = j.g;
     const int nO = j.o1 - j.o0, nE = j.e1 - j.e0;
@@ -346,13 +347,19 @@ static rp_status pair_enqueue(rp_ctx *ctx, const PairJob &j, int k0, int k1, con
                           j.npw_max, grid, j.fp32, j.fft_lines);
         }
         const int lo3 = j.lo[2] + g0[2];
-        double2 *Mk = M + (long)(k - k0) * nE * nO * j.ng;
         {
             StageTimer t(ctx, RP_STAGE_PAIR);
-            if (j.fp32) {
+            if (ops) {
+                SplitOps o = *ops;
+                o.p0 = (long)(k - k0) * nE * nO;
+                const float2 *v = (const float2 *)grid;
+                launch_pair_ops(ctx->stream, j.plans, g.fft, v, v + nr * nO, nO, nE, j.ng, dg, g0, lo3, L3, o);
+            } else if (j.fp32) {
+                double2 *Mk = M + (long)(k - k0) * nE * nO * j.ng;
                 const float2 *v = (const float2 *)grid;
                 launch_pair_k(ctx->stream, j.plans, g.fft, v, v + nr * nO, nO, nE, j.ng, dg, g0, lo3, L3, true, Mk);
             } else {
+                double2 *Mk = M + (long)(k - k0) * nE * nO * j.ng;
                 const double2 *u = (const double2 *)grid;
                 launch_pair_k(ctx->stream, j.plans, g.fft, u, u + nr * nO, nO, nE, j.ng, dg, g0, lo3, L3, false,
                               Mk);
@@ -456,10 +463,13 @@ struct ChiBufs {
 };
 
 // Enqueues the weights of the pairs of k in [k0, k1) into bufs.w (dfreq is the
-// device copy of the frequencies) and the contraction of M into chi.  No
-// allocation, copy or synchronization.
+// device copy of the frequencies) and the contraction of M into chi.  With
+// ops_ready (split forms) the pair kernels have already written the pairs'
+// operands into bufs.a / bufs.b and M is not read: only their padding is
+// cleared.  No allocation, copy or synchronization.
 static rp_status chi_enqueue(rp_ctx *ctx, const ChiJob &c, int k0, int k1, const double2 *M,
-                             const double2 *dfreq, const ChiBufs &bufs, int accumulate, double2 *chi)
+                             const double2 *dfreq, const ChiBufs &bufs, int accumulate, double2 *chi,
+                             bool ops_ready = false)
 {
     const long npair = (long)(k1 - k0) * (c.e1 - c.e0) * (c.o1 - c.o0);
     rp_status st;
@@ -478,8 +488,11 @@ static rp_status chi_enqueue(rp_ctx *ctx, const ChiJob &c, int k0, int k1, const
         const int nterm = c.prec == RP_SPLIT_BF16 ? 2 : 3;
         {
             StageTimer t(ctx, RP_STAGE_PREP);
-            launch_split_prep(ctx->stream, nterm, npair, c.ng, c.nfreq, M, bufs.w, c.herm, bufs.a, bufs.b,
-                              bufs.sw);
+            if (ops_ready)
+                launch_ops_pad(ctx->stream, split_ops(bufs.a, bufs.b, npair, c.ng, nterm), npair, c.ng);
+            else
+                launch_split_prep(ctx->stream, nterm, npair, c.ng, M, bufs.a, bufs.b);
+            launch_weight_prep(ctx->stream, npair, c.nfreq, bufs.w, c.herm, bufs.sw);
         }
         // the contraction and the FP64 sum of its partial tiles on separate timers
         std::optional<StageTimer> tc, tr;
@@ -785,6 +798,75 @@ rp_status rp_set_tuning(rp_ctx *ctx, int n, const rp_tune_entry *table)
     return RP_OK;
 }
 
+// Enqueues steps a2-a6 for the k batch [ka, kb) of one problem: in FP64 the
+// pair densities into ctx->mbuf and the contraction of them; in the split
+// forms the pair kernels write the contraction's operands into bufs.a /
+// bufs.b directly (no FP64 M), then the contraction.  dg and df are the
+// device copies of the problem's G and frequency lists.
+static rp_status kbatch_enqueue(rp_ctx *ctx, const PairJob &pj, const ChiJob &cj, int ka, int kb, const int *dg,
+                                const double2 *df, void *grid, const ChiBufs &bufs, int accumulate, double2 *chi)
+{
+    rp_status st;
+    if (cj.prec == RP_FP64) {
+        double2 *M = (double2 *)ctx->mbuf.p;
+        if ((st = pair_enqueue(ctx, pj, ka, kb, dg, grid, M)) != RP_OK) return st;
+        return chi_enqueue(ctx, cj, ka, kb, M, df, bufs, accumulate, chi);
+    }
+    const long npair = (long)(kb - ka) * (pj.e1 - pj.e0) * (pj.o1 - pj.o0);
+    const SplitOps ops = split_ops(bufs.a, bufs.b, npair, pj.ng, cj.prec == RP_SPLIT_BF16 ? 2 : 3);
+    if ((st = pair_enqueue(ctx, pj, ka, kb, dg, grid, nullptr, &ops)) != RP_OK) return st;
+    return chi_enqueue(ctx, cj, ka, kb, nullptr, df, bufs, accumulate, chi, true);
+}
+
+rp_status rp_chi0_run(rp_ctx *ctx, const rp_problem *p, rp_precision prec)
+{
+    if (!ctx) return RP_E_NULL;
+    (void)hipSetDevice(ctx->device);
+    if (!p) return fail(ctx, RP_E_NULL, "problem is NULL");
+    if (!valid_prec(prec)) return fail(ctx, RP_E_RANGE, "unknown precision");
+    PairJob pj;
+    ChiJob cj;
+    rp_status st = pair_check(ctx, &p->cell, p->iq, p->nband, p->npw_max, p->npw, p->mmax, p->miller, p->coef,
+                              p->o0, p->o1, p->e0, p->e1, p->k0, p->k1, p->ng, p->gsph, prec, &pj);
+    if (st != RP_OK) return st;
+    if ((st = chi_check(ctx, &p->cell, p->iq, p->nband, p->energy_eV, p->T, p->o0, p->o1, p->e0, p->e1, p->k0,
+                        p->k1, p->ng, p->nfreq, p->freq_eV, p->delta_eV, p->wm, prec, p->accumulate, &cj)) != RP_OK)
+        return st;
+    if (p->kbatch < 1) return fail(ctx, RP_E_SHAPE, "kbatch must be >= 1");
+    if (!p->chi) return fail(ctx, RP_E_NULL, "chi is NULL");
+    const long npk = (long)(p->o1 - p->o0) * (p->e1 - p->e0);
+    const long npair = npk * std::min(p->kbatch, std::max(1, p->k1 - p->k0));
+    const ChiBytes nb = chi_bytes(cj, pj.empty ? 0 : npair);
+    DevBuf &grid = pj.fp32 ? ctx->ugrid32 : ctx->ugrid;
+    if (!pj.empty) {
+        if ((st = ensure(ctx, grid, pair_grid_bytes(pj))) != RP_OK) return st;
+        if (prec == RP_FP64 && (st = ensure(ctx, ctx->mbuf, sizeof(double2) * (size_t)npair * p->ng)) != RP_OK)
+            return st;
+    }
+    if ((st = ensure(ctx, ctx->weights, nb.w)) != RP_OK) return st;
+    if (prec != RP_FP64) {
+        if ((st = ensure(ctx, ctx->split_a, nb.a)) != RP_OK) return st;
+        if ((st = ensure(ctx, ctx->split_b, nb.b)) != RP_OK) return st;
+        if ((st = ensure(ctx, ctx->split_w, nb.sw)) != RP_OK) return st;
+        if ((st = ensure(ctx, ctx->chi_part, nb.part)) != RP_OK) return st;
+    }
+    if ((st = upload(ctx, ctx->glist, p->gsph, sizeof(int) * 3 * p->ng)) != RP_OK) return st;
+    if ((st = upload(ctx, ctx->freq, p->freq_eV, sizeof(double2) * p->nfreq)) != RP_OK) return st;
+    const int *dg = (const int *)ctx->glist.p;
+    const double2 *df = (const double2 *)ctx->freq.p;
+    const ChiBufs bufs{(double2 *)ctx->weights.p, ctx->split_a.p, ctx->split_b.p, ctx->split_w.p,
+                       ctx->chi_part.p};
+    double2 *chi = (double2 *)p->chi;
+    if (pj.empty) return chi_enqueue(ctx, cj, p->k0, p->k0, nullptr, df, bufs, p->accumulate, chi);
+    for (int ka = p->k0; ka < p->k1; ka += p->kbatch) {
+        const int kb = std::min(p->k1, ka + p->kbatch);
+        if ((st = kbatch_enqueue(ctx, pj, cj, ka, kb, dg, df, grid.p, bufs, ka == p->k0 ? p->accumulate : 1,
+                                 chi)) != RP_OK)
+            return st;
+    }
+    return RP_OK;
+}
+
 // ---- batch of chi0 problems as one graph launch ----------------------------
 
 // bound on the kernel nodes of one captured graph of a batch
@@ -822,7 +904,7 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
         const long npair = npk * std::min(p.kbatch, std::max(1, p.k1 - p.k0));
         if (!pj[i].empty) {
             grid_b = std::max(grid_b, pair_grid_bytes(pj[i]));
-            m_b = std::max(m_b, sizeof(double2) * (size_t)npair * p.ng);
+            if (prec == RP_FP64) m_b = std::max(m_b, sizeof(double2) * (size_t)npair * p.ng);
         }
         const ChiBytes b = chi_bytes(cj[i], pj[i].empty ? 0 : npair);
         cb.w = std::max(cb.w, b.w);
@@ -942,8 +1024,9 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
         };
         // an upper bound on the kernels one k batch of kb k-points enqueues:
         // per k the zero fill, two scatters, three transform passes and the pair
-        // kernel; per batch the weights, two preparation kernels, the
-        // contraction and the sum of its partial tiles
+        // kernel; per batch the weights, two preparation kernels (operands or
+        // their padding, and the weights), the contraction and the sum of its
+        // partial tiles
         auto bound = [](int kb) { return 8L * kb + 6; };
         st = begin_piece();
         for (int i = 0; i < nprob && st == RP_OK; i++) {
@@ -962,10 +1045,8 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
                 if (piece > 0 && piece + bound(kb - ka) > kGraphNodes) {
                     if ((st = end_piece(RP_OK)) != RP_OK || (st = begin_piece()) != RP_OK) break;
                 }
-                double2 *M = (double2 *)ctx->mbuf.p;
-                st = pair_enqueue(ctx, pj[i], ka, kb, dg, grid.p, M);
-                if (st == RP_OK)
-                    st = chi_enqueue(ctx, cj[i], ka, kb, M, df, bufs, ka == p.k0 ? p.accumulate : 1, chi);
+                st = kbatch_enqueue(ctx, pj[i], cj[i], ka, kb, dg, df, grid.p, bufs, ka == p.k0 ? p.accumulate : 1,
+                                    chi);
                 piece += bound(kb - ka);
             }
         }

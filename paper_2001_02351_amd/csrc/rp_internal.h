@@ -135,6 +135,16 @@ void launch_ugrid2(hipStream_t s, const FftPlan plans[3], const int fft[3], cons
 void launch_fft3d(hipStream_t s, const FftPlan plans[3], const int fft[3], int ngrids,
                   double2 *data);
 
+// Split-BF16 operands of one contraction call (layout in split_ops.h): the
+// FP32 row blocks A, the BF16 planes B, the padded sizes, and p0, the index
+// within the call's pairs of the first pair a pair-kernel launch writes.
+struct SplitOps {
+    void *A = nullptr;
+    void *B = nullptr;
+    long p0 = 0;
+    int NGP = 0, npg = 0, nterm = 0;
+};
+
 // pair.hip: pair densities of one k (grids in FP64, or FP32 when fp32).
 size_t pair_lds_bytes(const int fft[3], int L3, int rows, size_t csize, int npairs);
 int pair_rows(const int fft[3]);
@@ -146,6 +156,11 @@ int pair_lane_edge(int need, int limit, int ng, int L3, bool fp32);
 void launch_pair_k(hipStream_t s, const FftPlan plans[3], const int fft[3], const void *u_occ,
                    const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3],
                    int lo3, int L3, bool fp32, double2 *M);
+// the same pair densities written as split operands (FP32 grids only): pair
+// (a, b) of this k goes to pair p0 + a nO + b of ops
+void launch_pair_ops(hipStream_t s, const FftPlan plans[3], const int fft[3], const void *u_occ,
+                     const void *u_emp, int nO, int nE, int ng, const int *gsph, const int g0[3], int lo3, int L3,
+                     const SplitOps &ops);
 
 // tetra.hip: weights of a pair range.
 void launch_weights(hipStream_t s, const int kmesh[3], const int iq[3], int nband,
@@ -164,8 +179,17 @@ size_t split_a_bytes(long npair, int ng);
 size_t split_b_bytes(long npair, int ng);
 size_t split_w_bytes(long npair, int nfreq);
 size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill, int kernel, int nterm);
-void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, int nfreq, const double2 *M,
-                       const double2 *w, bool herm, void *split_a, void *split_b, void *split_w);
+// the operand layout of npair pairs at ng rows in split_a / split_b (p0 = 0)
+SplitOps split_ops(void *split_a, void *split_b, long npair, int ng, int nterm);
+// the operands of M (FP64, npair x ng) into split_a / split_b
+void launch_split_prep(hipStream_t s, int nterm, long npair, int ng, const double2 *M, void *split_a,
+                       void *split_b);
+// zeros into the padding slots of the operands of npair pairs (rows ng..NGP-1
+// of every pair, pairs npair..KP-1 of every row), for operands whose pairs
+// the pair kernels write
+void launch_ops_pad(hipStream_t s, const SplitOps &ops, long npair, int ng);
+// the FP32 weights [nfreq][KP] of the contraction
+void launch_weight_prep(hipStream_t s, long npair, int nfreq, const double2 *w, bool herm, void *split_w);
 // before_reduce (may be empty) is called on the host between the contraction
 // launch and the launch that sums its partial tiles, when there is one
 void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, int accumulate,

@@ -81,27 +81,15 @@ def weights(ctx, d: DeviceInputs, k0, k1, o=None, e=None, mode: Optional[int] = 
 
 
 def chi0(ctx, d: DeviceInputs, prec: int = _rp.RP_FP64, kbatch: int = 1, k0: int = 0,
-         k1: Optional[int] = None, chi=None, Mbuf=None):
-    """chi0 over k in [k0, k1) (all bands), pair densities streamed per k batch."""
+         k1: Optional[int] = None, chi=None):
+    """chi0 over k in [k0, k1) (all bands): one rp_chi0_run call, the pair
+    densities of kbatch k-points at a time feeding the contraction (in the
+    split forms as the contraction's operands, with no FP64 M)."""
     import torch
-    p = d.prob
     k1 = d.nk if k1 is None else k1
     if chi is None:
         chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device=d.device)
-    npk = p.nocc * p.nemp
-    if Mbuf is None:
-        Mbuf = torch.empty((kbatch * npk, d.ng, 2), dtype=torch.float64, device=d.device)
-    first = True
-    for ka in range(k0, k1, kbatch):
-        kb = min(k1, ka + kbatch)
-        M = Mbuf[: (kb - ka) * npk]
-        pair_density(ctx, d, ka, kb, out=M, prec=prec)
-        _rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, d.T, 0, p.nocc, p.nocc,
-                               p.nocc + p.nemp, ka, kb, d.ng, M, d.nfreq, p.freq_eV, p.delta_eV,
-                               weight_mode(p), prec, 0 if first else 1, chi)
-        first = False
-    if first:
-        chi.zero_()
+    _rp.rp_chi0_run(ctx, batch_problem(d, chi, kbatch, k=(k0, k1)), prec)
     return chi
 
 

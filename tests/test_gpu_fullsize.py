@@ -213,6 +213,25 @@ def test_chi_bench_launch_fullsize(bench_launch, d2):
         assert ev.max() < 1e-5 * abs(ev.min())
 
 
+def test_chi_bench_launch_fused_equals_two_calls(ctx, rp, bench_launch, d2):
+    """The bench's launch through rp_chi0_run (the pair kernels write the
+    contraction's split operands) equals rp_pair_density + rp_chi0_accumulate
+    (the operands prepared from FP64 M) bit for bit."""
+    from paper_2001_02351_amd import path
+    one, _, _ = bench_launch
+    p = d2.prob
+    k0, k1 = BENCH_K
+    M = path.pair_density(ctx, d2, k0, k1, prec=rp.RP_SPLIT_BF16)
+    chi = torch.empty((d2.nfreq, d2.ng, d2.ng, 2), dtype=torch.float64, device="cuda")
+    rp.rp_chi0_accumulate(ctx, d2.cell, p.iq, d2.nband, d2.energy, d2.T, 0, p.nocc, p.nocc, p.nband, k0, k1, d2.ng,
+                          M, d2.nfreq, p.freq_eV, p.delta_eV, path.weight_mode(p), rp.RP_SPLIT_BF16, 0, chi)
+    rp.rp_synchronize(ctx)
+    del M
+    two = path.to_complex(chi)
+    print(f"[fullsize] fused vs two calls: max |diff| {np.abs(one - two).max():.1e}", flush=True)
+    assert np.array_equal(one, two)
+
+
 def test_chi_bench_launch_against_the_oracle(bench_launch, bench_launch_oracle, d2):
     """The bench's launch (split-BF16 as one sliced launch, and FP64) against
     the oracle's Eq. chi of all 128 000 pairs on the sampled rows and columns,

@@ -1,0 +1,144 @@
+"""rp_chi0_run: chi0 of one problem with the pair densities of each k batch
+feeding the contraction directly (in the split forms the pair kernels write
+the contraction's FP32 row blocks and BF16 planes, with no FP64 M).
+
+Against rp_pair_density + rp_chi0_accumulate per k batch (the split operands
+prepared from FP64 M), bit for bit, in FP64, split-BF16 and split-BF16 x6, on:
+* the 25^3 batch system (one lane per FFT line in FP32, the generic pair
+  kernel in FP64), 7 x 13 bands (odd occupied count: every pair stored
+  alone), 3 k-points per batch over 8 (a ragged last batch), 273 pairs per
+  full batch (not a multiple of 8 or 32), N_G not a multiple of 16;
+* the 24^3 batch system (four lanes per line), 8 x 16 bands (pairs stored two
+  at a time), 16 imaginary frequencies (Hermitian chi);
+* a 16^3 system with 20 real frequencies and delta > 0 (complex weights),
+  N_G = 200, 5 x 19 bands;
+* a 20^3 system whose pair grid (20^3) no lane length takes: the generic
+  FP32 pair kernel, 5 x 11 bands, N_G = 300, 6 real frequencies.
+And the oracle on sampled columns for the first case, and the errors.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import batch_system, make_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _rel(a, b):
+    """The larger of the relative Frobenius norm of a - b and the largest
+    element-wise deviation over the largest |b|."""
+    d = np.abs(np.asarray(a) - np.asarray(b))
+    return max(np.linalg.norm(d) / np.linalg.norm(b), d.max() / np.abs(b).max())
+
+
+@pytest.fixture(scope="module")
+def rp():
+    import paper_2001_02351_amd as rp
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rp.load()
+    return rp
+
+
+@pytest.fixture(scope="module")
+def ctx(rp):
+    c = rp.Context(0, tuning=None)
+    yield c
+    c.close()
+
+
+def _case(name):
+    if name == "25cube_odd":
+        p = batch_system(7, 0)
+        return p, (0, 7), (p.nocc, p.nocc + 13), 3
+    if name == "24cube_herm":
+        p = batch_system(21, 0)
+        return p, (0, 8), (p.nocc, p.nocc + 16), 3
+    if name == "20cube_generic":
+        p = make_problem(name="run20", a_bohr=7.26, fft=(20, 20, 20), kmesh=(2, 2, 2), iq=(1, 0, 0), nocc=8,
+                         nemp=24, gpsi=6.0, ng=300, freq_eV=np.linspace(0.0, 20.0, 6), delta_eV=0.1, seed=29)
+        return p, (0, 5), (8, 19), 3
+    p = make_problem(name="run", a_bohr=7.26, fft=(16, 16, 16), kmesh=(2, 2, 2), iq=(1, 0, 0), nocc=8, nemp=24,
+                     gpsi=2.4, ng=200, freq_eV=np.linspace(0.0, 20.0, 20), delta_eV=0.1, seed=29)
+    return p, (0, 5), (8, 27), 3
+
+
+def _two_calls(ctx, rp, d, o, e, prec, kbatch):
+    from paper_2001_02351_amd import path
+    p = d.prob
+    npk = (o[1] - o[0]) * (e[1] - e[0])
+    chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device="cuda")
+    M = torch.empty((kbatch * npk, d.ng, 2), dtype=torch.float64, device="cuda")
+    for ka in range(0, d.nk, kbatch):
+        kb = min(d.nk, ka + kbatch)
+        Mk = M[: (kb - ka) * npk]
+        path.pair_density(ctx, d, ka, kb, o=o, e=e, out=Mk, prec=prec)
+        rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, d.T, *o, *e, ka, kb, d.ng, Mk, d.nfreq,
+                              p.freq_eV, p.delta_eV, path.weight_mode(p), prec, 0 if ka == 0 else 1, chi)
+    return chi
+
+
+@pytest.mark.parametrize("name", ["25cube_odd", "24cube_herm", "16cube_real", "20cube_generic"])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_run_equals_two_calls(ctx, rp, name, prec):
+    from paper_2001_02351_amd import path
+    p, o, e, kbatch = _case(name)
+    d = path.DeviceInputs(p)
+    grid = rp.rp_pair_grid(d.cell, p.iq, d.mmax, p.gsph, prec)
+    print(f"[run] {name} prec={prec}: pair grid {grid}, bands {o} x {e}, N_G {d.ng}, kbatch {kbatch} of {d.nk}",
+          flush=True)
+    if name == "20cube_generic":
+        assert grid == (20, 20, 20)
+    chi = torch.full((d.nfreq, d.ng, d.ng, 2), float("nan"), dtype=torch.float64, device="cuda")
+    rp.rp_chi0_run(ctx, path.batch_problem(d, chi, kbatch, o=o, e=e), prec)
+    ref = _two_calls(ctx, rp, d, o, e, prec, kbatch)
+    rp.rp_synchronize(ctx)
+    diff = float((chi - ref).abs().max())
+    print(f"[run] {name} prec={prec}: max |diff| {diff:.1e}", flush=True)
+    assert torch.equal(chi, ref)
+    if name == "25cube_odd":
+        M = oracle.pair_densities(p, *o, *e, 0, d.nk)
+        w = oracle.prob_weights(p, *o, *e, 0, d.nk)
+        cols = np.unique(np.concatenate([np.random.default_rng(4).choice(d.ng, 30, replace=False), [d.ng - 1]]))
+        want = oracle.chi0(M[:, cols], w)
+        got = path.to_complex(chi)[:, cols][:, :, cols]
+        err = max(_rel(got[f], want[f]) for f in range(d.nfreq))
+        print(f"[run] {name} prec={prec}: vs oracle {err:.1e}", flush=True)
+        assert err < (1e-10 if prec == 0 else 1e-5)
+
+
+def test_run_accumulates_and_clears(ctx, rp):
+    """accumulate = 1 adds into chi; an empty k range with accumulate = 0
+    clears chi."""
+    from paper_2001_02351_amd import path
+    p, o, e, kbatch = _case("24cube_herm")
+    d = path.DeviceInputs(p)
+    chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device="cuda")
+    prob = path.batch_problem(d, chi, kbatch, o=o, e=e)
+    rp.rp_chi0_run(ctx, prob, rp.RP_SPLIT_BF16)
+    once = chi.clone()
+    rp.rp_chi0_run(ctx, dict(prob, accumulate=1), rp.RP_SPLIT_BF16)
+    rp.rp_synchronize(ctx)
+    assert float(torch.linalg.norm(chi - 2 * once) / torch.linalg.norm(once)) <= 1e-14
+    rp.rp_chi0_run(ctx, path.batch_problem(d, chi, kbatch, o=o, e=e, k=(2, 2)), rp.RP_SPLIT_BF16)
+    rp.rp_synchronize(ctx)
+    assert float(chi.abs().max()) == 0.0
+
+
+def test_run_errors(ctx, rp):
+    from paper_2001_02351_amd import path
+    p, o, e, kbatch = _case("24cube_herm")
+    d = path.DeviceInputs(p)
+    chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device="cuda")
+    good = path.batch_problem(d, chi, kbatch, o=o, e=e)
+    for bad, status in ((dict(good, kbatch=0), 2), (dict(good, k1=d.nk + 1), 2), (dict(good, e1=d.nband + 1), 2)):
+        with pytest.raises(rp.RpError) as err:
+            rp.rp_chi0_run(ctx, bad, rp.RP_SPLIT_BF16)
+        assert err.value.status == status
+    with pytest.raises(rp.RpError) as err:
+        rp.rp_chi0_run(ctx, good, 7)
+    assert err.value.status == 3
