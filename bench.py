@@ -18,13 +18,14 @@ Inputs are resident in HBM before the timed region.
                 library's stream) against the BF16 dense peak; traffic is the
                 HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE
                 counters, scaled by what they read for a plain copy, as
-                recorded in profiles/k_chi_bf16_traffic.md (reported only
+                recorded in profiles/k_chi_rows_traffic.md (reported only
                 while the kernel source matches the recorded hash), and
                 mfma_counter_frac the executed MFMA flops from the BF16
                 MOPS counter recorded there
   hbm_a2_a4     HBM bytes of the pair kernel and the u-grid kernels from
                 profiles/pair_stage_hbm_counters.md over their stage times,
-                with the algorithmic bytes (u-grids once + M) beside them
+                with the algorithmic bytes (u-grids once + the
+                contraction operands it writes) beside them
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload
 
 Counter runs use two extra modes: --copy-calibration (a plain 1 GiB device
@@ -62,7 +63,7 @@ METRIC = "χ0 build TFLOP/s + s/q-point, split-BF16 vs FP64, at rel err ≤1e-5 
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_chi_bf16_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_chi_rows_traffic.md")
 CHI_SOURCE = os.path.join(ROOT, "paper_2001_02351_amd", "csrc", "chi_bf16.hip")
 
 
@@ -90,7 +91,7 @@ def _recorded(path, keys):
 
 
 def recorded_traffic():
-    """HBM bytes and BF16 MFMA ops per k_chi_bf16 launch from the committed
+    """HBM bytes and BF16 MFMA ops per contraction launch from the committed
     counter summary, or None when there is none or the kernel source changed
     since it was taken."""
     vals = _recorded(TRAFFIC_FILE, ("traffic_bytes_per_launch", "mfma_mops_per_launch",
@@ -252,7 +253,7 @@ def _chi_roofline(flops_per_launch, ms_per_launch):
         return None
     a = flops_per_launch / (ms_per_launch / 1e3) / 1e12
     return {"bound": "mfma", "achieved": a, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-            "frac": a / PEAK_BF16_TFLOPS, "kernel": "k_chi_bf16 (chi0 contraction, split-BF16)",
+            "frac": a / PEAK_BF16_TFLOPS, "kernel": "k_chi_rows (chi0 contraction, split-BF16)",
             "flops_per_launch": flops_per_launch, "ms_per_launch": ms_per_launch}
 
 
@@ -937,7 +938,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_BF16_TFLOPS,
             "traffic": None if rec is None else rec["traffic_bytes_per_launch"],
-            "kernel": "k_chi_bf16 (chi0 contraction, split-BF16)",
+            "kernel": "k_chi_rows (chi0 contraction, split-BF16)",
             "mfma_executed_frac": 3.0 * achieved / PEAK_BF16_TFLOPS,
             "mfma_counter_frac": None if rec is None or "mfma_mops_per_launch" not in rec else
             rec["mfma_mops_per_launch"] * 512.0 / (split["chi_kernel_ms_per_launch"] / 1e3) / 1e12 /

@@ -12,18 +12,20 @@
 // The products run on v_mfma_f32_16x16x32_bf16 with FP32 accumulators; each
 // call's partial sums are added into chi in FP64.
 //
-// A prep pass converts the FP64 pair densities once per call into
-//   Ap: FP32 complex, 1 KB blocks [KP/8][NGP/16][4][16][2]: for a group of 8
-//       pairs and 16 rows, pair quarter q holds rows 0..15 x pairs 2q, 2q+1
-//       (row side, scaled by w and split in registers)
-//   Bp: 2 NT BF16 planes [2 NT][KP/8][NGP][8] (column side; re terms, im terms)
-//   Wq: FP32 weights [nfreq][KP]
-// with KP = pairs padded to 32 and NGP = ng padded to 128 (zeros).
+// The operands (layout in split_ops.h) are the FP32 row blocks Ap (scaled by
+// w and split in registers), the 2 NT BF16 column planes Bp and the FP32
+// weights Wq [nfreq][KP], with KP = pairs padded to 32 and NGP = ng padded to
+// 128 (zeros).  The FP32 pair kernels write Ap and Bp directly; k_split_prep
+// makes them from FP64 M for callers that hold M.
 //
-// Tiling: a 256-thread block owns a 128x128 tile of (G, G') for NW = 1 or 2
-// frequencies (a tuning choice); each wave a 64x64 sub-tile (4x4 blocks of 16x16).  Steps of 32
-// pairs stream through two LDS buffers (32 KB of A and 16 NT KB of B each)
-// by global_load_lds DMA, so the next step's operands arrive while the matrix
+// Tiling (row form, k_chi_rows, the default for two frequencies per block): a
+// 256-thread block owns a 128x128 tile of (G, G') for 2 frequencies; wave w
+// holds rows 64 (w / 2) .. + 63 and all 128 columns for frequency w % 2 (4 x 8
+// blocks of 16x16), so each weighted row operand is split by one wave only.
+// k_chi_bf16 (one frequency per block, four 64x64 sub-tiles) and the
+// eight-wave 256-row forms are the tuning alternatives.  Steps of 32 pairs
+// stream through two LDS buffers (32 KB of A and 16 NT KB of B each) by
+// global_load_lds DMA, so the next step's operands arrive while the matrix
 // cores work on the current one.
 #include <algorithm>
 

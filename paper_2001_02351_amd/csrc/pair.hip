@@ -24,6 +24,17 @@ namespace {
 // plain output, (double) acc / N_r, rounded to FP32, so the operands equal
 // those the split preparation makes from M.  Two pairs b, b + 1 that share a
 // group of 8 at an even position go out in one store.
+// The band block of this workgroup.  Workgroup i is dispatched to XCD i mod 8;
+// the blocks are renumbered so that each XCD takes a contiguous run of them:
+// the blocks of one empty band (which read the same u-grid rows) and the
+// blocks whose pairs share a group of 8 in the split operands (whose partial
+// lines then merge in one L2) run on the same XCD.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_block()
+{
+    const int n = gridDim.x, x = blockIdx.x & 7;
+    return x * (n >> 3) + min(x, n & 7) + (blockIdx.x >> 3);
+}
+
 template <int I, int N, typename F> __device__ __forceinline__ void static_for(F &&f)
 {
     if constexpr (I < N) {
@@ -82,7 +93,8 @@ k_pair(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int nE,
     C *smem = (C *)smem_d;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int nbB = (nO + NB - 1) / NB;
-    const int a0 = (blockIdx.x / nbB) * NA, b0 = (blockIdx.x % nbB) * NB;
+    const int bid = xcd_block();
+    const int a0 = (bid / nbB) * NA, b0 = (bid % nbB) * NB;
     const long nr = (long)N1 * N2 * N3;
     const C *ua[NA];
     const C *ub[NB];
@@ -248,7 +260,8 @@ k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, i
     const int tid = threadIdx.x;
     const int s = tid & (G - 1), grp = tid / G, r = group_row<G>(s);
     const int nbB = (nO + NB - 1) / NB;
-    const int a0 = (blockIdx.x / nbB) * NA, b0 = (blockIdx.x % nbB) * NB;
+    const int bid = xcd_block();
+    const int a0 = (bid / nbB) * NA, b0 = (bid % nbB) * NB;
     const long nr = (long)N1 * N * N;
     fill_twiddles(tw1, N1, tid, 256);
     fill_twiddles(twN, N, tid, 256);
