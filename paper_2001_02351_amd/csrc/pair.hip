@@ -223,7 +223,8 @@ template <int N> constexpr int pair_group()
 }
 
 // widest m3 window the lane-group form holds in LDS: two windows of
-// [NP][N][L3M] under 72 KB (FP32) or 48 KB (FP64), so two workgroups share a CU
+// [NP][N][L3M] under 72 KB (FP32) or 48 KB (FP64), so that at least two
+// workgroups share a CU (the windows are allocated at the call's own width)
 template <typename C, int N, int NP> constexpr int lanes_l3max()
 {
     constexpr int budget = sizeof(C) == 8 ? 73728 : 49152;
@@ -240,9 +241,10 @@ template <typename C, int N, int NP> constexpr int lanes_l3max()
 // phases A and B evenly, and a lane holds N/G points of a line, which leaves
 // room for the sphere accumulators.  The two m3-window buffers alternate
 // between planes, so phase A of plane j1+1 may start while other waves still
-// read plane j1's window in phase C: two barriers per plane.  LDS stays under
-// half a CU's, so two workgroups share a CU and cover each other's load and
-// barrier waits.
+// read plane j1's window in phase C: two barriers per plane.  The windows take
+// dynamic LDS of the call's window width: at least two workgroups share a CU
+// (three for the 15-wide window of a 32-point grid, where the registers then
+// limit it) and cover each other's load and barrier waits.
 template <typename C, int N, int NA, int NB, int MAXG>
 __global__ void __launch_bounds__(256, 2)
 k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int nE, int N1, int ng,
@@ -251,9 +253,9 @@ k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, i
 {
     constexpr int G = pair_group<N>(), Q = N / G, NP = NA * NB;
     constexpr int NGRP = 256 / G;             // lane groups per workgroup
-    constexpr int L3M = lanes_l3max<C, N, NP>();
     constexpr int TA = (NP * N + NGRP - 1) / NGRP;    // phase-A lines per group
-    __shared__ C win[2][NP * N * L3M];        // two windows [NP][N][L3]
+    extern __shared__ float4 pair_lanes_dyn[];
+    C *win[2] = {(C *)pair_lanes_dyn, (C *)pair_lanes_dyn + (size_t)NP * N * L3};   // two windows [NP][N][L3]
     __shared__ C tw1[256];
     __shared__ C twN[N];
     __shared__ C twQ[Q];
@@ -269,7 +271,7 @@ k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, i
 
     C acc[NP][MAXG];
     // per sphere point, packed into one register: bits 0-13 the window index
-    // (m2 mod N) L3 + m3 - lo3 (< N L3M <= 2304), bits 14-21 the j1 phase step
+    // (m2 mod N) L3 + m3 - lo3 (< N times the widest window <= 2304), bits 14-21 the j1 phase step
     // m1 mod N1, bits 22-29 the running phase index (N1 <= 256)
     unsigned pk[MAXG];
 #pragma unroll
@@ -414,9 +416,17 @@ void launch_pair_lanes(hipStream_t s, int N1, const C *u_occ, const C *u_emp, in
                        const int *gsph, const int g0[3], int lo3, int L3, double2 *M, const SplitOps &ops)
 {
     const unsigned nblk = (unsigned)(((nE + NA - 1) / NA) * ((nO + NB - 1) / NB));
+    // the two m3 windows, sized by this window (not its largest allowed width):
+    // narrow windows leave room for a third workgroup per CU
+    const size_t shm = 2 * sizeof(C) * (size_t)(NA * NB) * N * L3;
 #define RP_PAIRL(G)                                                                                          \
-    hipLaunchKernelGGL((k_pair_lanes<C, N, NA, NB, G>), dim3(nblk), dim3(256), 0, s, u_occ, u_emp, nO, nE,   \
-                       N1, ng, gsph, g0[0], g0[1], g0[2], lo3, L3, M, ops)
+    do {                                                                                                     \
+        if (shm > 65536)                                                                                     \
+            (void)hipFuncSetAttribute((const void *)&k_pair_lanes<C, N, NA, NB, G>,                          \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                 \
+        hipLaunchKernelGGL((k_pair_lanes<C, N, NA, NB, G>), dim3(nblk), dim3(256), shm, s, u_occ, u_emp, nO, \
+                           nE, N1, ng, gsph, g0[0], g0[1], g0[2], lo3, L3, M, ops);                          \
+    } while (0)
     if constexpr (N >= 96) {
         // large grids come with large spheres: 2048, 4096 or 6144 points
         if (ng <= 2048) RP_PAIRL(8);

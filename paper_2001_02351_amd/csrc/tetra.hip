@@ -371,11 +371,13 @@ __device__ double2 clipped_vertex_integral(double2 zz, const double (&e)[4], con
 
 constexpr int kWThreads = 128;
 
-// One thread per (pair, frequency).  The corner energies e_j and log(z - e_j)
-// of the 15 distinct corners live in LDS ([slot][thread]); each of the 24
-// tetrahedra sorts its five nodes (four corners, k's corner doubled) together
-// with their logarithms and evaluates I_v(z) and I_v(z') (only I_v(z) when
-// z' = z*).
+// One thread per (pair, frequency).  The corner energies e_j of the 15
+// distinct corners live in registers (the tetrahedron table indexes them with
+// the same slot in every lane, which the compiler turns into register-relative
+// moves) and the logarithms log(z - e_j) in LDS ([slot][thread]), so five
+// 128-thread blocks share a CU; each of the 24 tetrahedra sorts its five nodes
+// (four corners, k's corner doubled) together with their logarithms and
+// evaluates I_v(z) and I_v(z') (only I_v(z) when z' = z*).
 //
 // METAL: the Fermi level ef (hartree) cuts the tetrahedra.  With E_b < ef at
 // all four corners of a tetrahedron and E_a > ef at all four, the insulating
@@ -388,7 +390,7 @@ k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const doubl
           int o0, int nO, int e0, int nE, int k0, long npair, int nfreq, const double2 *freq,
           double delta, int mode, double ef, double2 *w)
 {
-    __shared__ double sE[15][kWThreads];
+    double eR[15];
     __shared__ double2 sL[15][kWThreads];
     __shared__ double sB[METAL ? 15 : 1][kWThreads];
     __shared__ double sA[METAL ? 15 : 1][kWThreads];
@@ -419,7 +421,7 @@ k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const doubl
             const int kv = (mesh_wrap(m1, K1) * K2 + mesh_wrap(m2, K2)) * K3 + mesh_wrap(m3, K3);
             const int kvq = (mesh_wrap(m1 + q1, K1) * K2 + mesh_wrap(m2 + q2, K2)) * K3 + mesh_wrap(m3 + q3, K3);
             const double eb = E[(long)kv * nband + b] * ha, ea = E[(long)kvq * nband + a] * ha;
-            sE[j][tid] = (E[(long)kvq * nband + a] - E[(long)kv * nband + b]) * ha;
+            eR[j] = (E[(long)kvq * nband + a] - E[(long)kv * nband + b]) * ha;
             if constexpr (METAL) {
                 sB[j][tid] = eb;
                 sA[j][tid] = ea;
@@ -432,7 +434,7 @@ k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const doubl
         for (int zi = 0; zi < (conj_pair ? 1 : 2); zi++) {
             const double2 zz = zi ? zp : z;
 #pragma unroll
-            for (int j = 0; j < 15; j++) sL[j][tid] = clog_d(make_double2(zz.x - sE[j][tid], zz.y));
+            for (int j = 0; j < 15; j++) sL[j][tid] = clog_d(make_double2(zz.x - eR[j], zz.y));
             for (int tt = 0; tt < 24; tt++) {
                 if constexpr (METAL) {
                     double e4[4], b4[4], a4[4];
@@ -441,7 +443,7 @@ k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const doubl
 #pragma unroll
                     for (int v = 0; v < 4; v++) {
                         const int sl = c_tetra.slot[tt][v];
-                        e4[v] = sE[sl][tid];
+                        e4[v] = eR[sl];
                         b4[v] = sB[sl][tid];
                         a4[v] = sA[sl][tid];
                         if (sl == kTet.self) iv = v;
@@ -460,10 +462,10 @@ k_weights(int K1, int K2, int K3, int q1, int q2, int q3, int nband, const doubl
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
                     const int sl = c_tetra.slot[tt][v];
-                    xs[v] = sE[sl][tid];
+                    xs[v] = eR[sl];
                     ls[v] = sL[sl][tid];
                 }
-                xs[4] = sE[kTet.self][tid];
+                xs[4] = eR[kTet.self];
                 ls[4] = sL[kTet.self][tid];
                 // sorting network on five keys, carrying the logarithms
 #define RP_CSWAP(i, j)                                                                             \
