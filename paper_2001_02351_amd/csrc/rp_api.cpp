@@ -312,8 +312,7 @@ static rp_status pair_check(rp_ctx *ctx, const rp_cell *cell, const int iq[3], i
 // u-grid workspace of one k: the occupied and the empty bands' grids.
 static size_t pair_grid_bytes(const PairJob &j)
 {
-    const long nr = (long)j.g.fft[0] * j.g.fft[1] * j.g.fft[2];
-    return (size_t)nr * (size_t)((j.o1 - j.o0) + (j.e1 - j.e0)) * (j.fp32 ? sizeof(float2) : sizeof(double2));
+    return ugrid_bytes(j.g.fft, (j.o1 - j.o0) + (j.e1 - j.e0), j.npw_max, j.fp32);
 }
 
 // Enqueues steps a2-a4 for k in [k0, k1): per k, the u-grids of the occupied
@@ -1023,10 +1022,11 @@ rp_status rp_chi0_batch(rp_ctx *ctx, int nprob, const rp_problem *probs, rp_prec
             return RP_OK;
         };
         // an upper bound on the kernels one k batch of kb k-points enqueues:
-        // per k the zero fill, two scatters, three transform passes and the pair
-        // kernel; per batch the weights, two preparation kernels (operands or
-        // their padding, and the weights), the contraction and the sum of its
-        // partial tiles
+        // per k the u-grids (a plane sort, the planar transforms and the axis-1
+        // pass; or, for grids too large for that, a zero fill, two scatters and
+        // three passes) and the pair kernel; per batch the weights, two
+        // preparation kernels (operands or their padding, and the weights), the
+        // contraction and the sum of its partial tiles
         auto bound = [](int kb) { return 8L * kb + 6; };
         st = begin_piece();
         for (int i = 0; i < nprob && st == RP_OK; i++) {

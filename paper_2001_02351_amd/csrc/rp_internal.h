@@ -126,7 +126,9 @@ class StageTimer {
 
 // fft.hip: u-grids (scatter + pruned 3-D transform) of two band sets stored
 // one after the other in u (nA grids from millerA/coefA, then nB from
-// millerB/coefB), FP32 or FP64.
+// millerB/coefB), FP32 or FP64; u holds ugrid_bytes (the grids, then a small
+// sort workspace; band_stride is the npw_max of the coefficient rows).
+size_t ugrid_bytes(const int fft[3], int nbands, int npw_max, bool fp32);
 void launch_ugrid2(hipStream_t s, const FftPlan plans[3], const int fft[3], const int mmax[3], int nA, int npwA,
                    const int *millerA, const double2 *coefA, int nB, int npwB, const int *millerB,
                    const double2 *coefB, int band_stride, void *u, bool fp32, int lines);

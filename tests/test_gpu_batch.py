@@ -180,16 +180,17 @@ def test_chi0_batch_rejects_bad_problems(ctx, rp):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_chi0_batch_across_graph_pieces(ctx, rp, prec):
-    """A batch whose launches exceed one graph's node bound (four q-points of
+    """A batch whose launches exceed one graph's node bound (six q-points of
     the 16^3 / 4^3 k parity system, one k-point per batch: 2 304 kernel nodes
-    in FP64, 2 816 in the split form) is captured as several graphs launched
+    in FP64, 3 072 in the split form) is captured as several graphs launched
     in order; it equals the
     per-problem calls, and problem 0 meets the oracle on sampled columns
     (per frequency, relative Frobenius and element-wise)."""
     from paper_2001_02351_amd import path
     from synth import at_qpoint, parity_workload
     base = parity_workload()
-    ds = [path.DeviceInputs(at_qpoint(base, iq)) for iq in ((1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1))]
+    qs = ((1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1), (1, 0, 1), (0, 1, 1))
+    ds = [path.DeviceInputs(at_qpoint(base, iq)) for iq in qs]
     kbatch = 1
     chis = [torch.full((d.nfreq, d.ng, d.ng, 2), float("nan"), dtype=torch.float64, device="cuda") for d in ds]
     probs = [path.batch_problem(d, c, kbatch) for d, c in zip(ds, chis)]
