@@ -128,8 +128,7 @@ k_plane_sort(const int *millerA, int npwA, const int *millerB, int npwB, int N1,
         of[N1] = sum;
     }
     __syncthreads();
-    for (int g = tid; g < npw; g += 256) perm[(long)set * npw_max + atomicAdd(&cnt[pmod(mil[3 * g], N1)], 1)] = g;
-    (void)pm;
+    for (int g = tid; g < npw; g += 256) pm[atomicAdd(&cnt[pmod(mil[3 * g], N1)], 1)] = g;
 }
 
 // Axes 3 and 2 of the u-grids plane by plane in LDS: block (j1, band)
