@@ -70,104 +70,112 @@ __global__ void k_eps(int nfreq, int ng, const double *vs, const double2 *chi, d
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGjNb = 64;       // panel width
-constexpr int kGjPanelThreads = 1024;
-constexpr int kGjMaxNg = 6144;  // largest N_G the panel kernel's LDS holds
+constexpr int kGjNb = 64;            // panel width
+constexpr int kGjPivotThreads = 1024;
+constexpr int kGjElimRows = 16;      // rows per elimination workgroup (4 per thread)
 
-// The steps of panel [c0, c0 + nb) on the panel's columns; one block per
-// matrix.  Per step: pivot search over rows >= c of column c, swap of the
-// full rows, scaling of the pivot row's panel entries, elimination of the
-// other rows' panel entries.  At the end the panel's pivot rows (all
-// columns) are saved to rk [nb][ng] for the update of the other columns.
 // (|v|, row) of the larger pivot candidate; ties go to the lower row
 __device__ __forceinline__ void pivot_max(double &m, int &r, double om, int orow)
 {
     if (om > m || (om == m && orow < r)) { m = om; r = orow; }
 }
 
-__global__ void __launch_bounds__(kGjPanelThreads)
-k_gj_panel(int ng, int c0, int nb, double2 *a, double2 *rk, int *piv, int *flag)
+// Step c of panel [c0, c0 + nb), first half, one block per matrix: pivot
+// search over rows >= c of column c, swap of the full rows r and c, and the
+// scaled pivot row's panel entries into prow[f][0 .. nb) (1/a_cc in column
+// c itself).
+__global__ void __launch_bounds__(kGjPivotThreads)
+k_gj_pivot(int ng, int c0, int nb, int c, double2 *a, double2 *prow, int *piv, int *flag)
 {
-    constexpr int NWV = kGjPanelThreads / 64;
-    __shared__ double2 fcol[kGjMaxNg];   // column c (after the swap)
-    __shared__ double2 prow[kGjNb];      // scaled pivot row, panel columns
+    constexpr int NWV = kGjPivotThreads / 64;
     __shared__ double bv[NWV];
     __shared__ int bi[NWV];
     const int f = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int jj = tid % kGjNb, rs = tid / kGjNb;   // panel column and row lane of the elimination
-    constexpr int RSTEP = kGjPanelThreads / kGjNb;
     double2 *A = a + (long)f * ng * ng;
-    // column c0 once from memory; every later pivot column is kept in LDS by
-    // the elimination of the step before (the lanes of a wave share one row,
-    // so the lane writing column c+1 of row i does so after the wave has read
-    // column c of that row)
-    for (int i = tid; i < ng; i += kGjPanelThreads) fcol[i] = A[(long)i * ng + c0];
-    __syncthreads();
-    for (int c = c0; c < c0 + nb; c++) {
-        // pivot: largest |a_ic| over rows i >= c (wave shuffles, then across waves)
-        double best = -1.0;
-        int bidx = c;
-        for (int i = c + tid; i < ng; i += kGjPanelThreads) {
-            const double2 v = fcol[i];
-            const double m = isfinite(v.x) && isfinite(v.y) ? hypot(v.x, v.y) : INFINITY;
-            pivot_max(best, bidx, m, i);
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) pivot_max(best, bidx, __shfl_xor(best, o), __shfl_xor(bidx, o));
-        if (lane == 0) {
-            bv[wave] = best;
-            bi[wave] = bidx;
-        }
-        __syncthreads();
-        best = bv[0];
-        bidx = bi[0];
-#pragma unroll
-        for (int w = 1; w < NWV; w++) pivot_max(best, bidx, bv[w], bi[w]);
-        const int r = bidx;
-        if (tid == 0) {
-            piv[(long)f * ng + c] = r;
-            if (!isfinite(best)) atomicOr(flag, kFlagNonFinite);
-            else if (!(best > kPivotFloor)) atomicOr(flag, kFlagZeroPivot);
-            if (r != c) {
-                const double2 t = fcol[c];
-                fcol[c] = fcol[r];
-                fcol[r] = t;
-            }
-        }
-        if (r != c) {
-            for (int j = tid; j < ng; j += kGjPanelThreads) {
-                const double2 t = A[(long)c * ng + j];
-                A[(long)c * ng + j] = A[(long)r * ng + j];
-                A[(long)r * ng + j] = t;
-            }
-        }
-        __syncthreads();
-        const double2 p = fcol[c];
-        const double den = p.x * p.x + p.y * p.y;
-        const double2 ip = make_double2(p.x / den, -p.y / den);
-        if (tid < nb) {
-            const int j = c0 + tid;
-            prow[tid] = (j == c) ? ip : cmul(A[(long)c * ng + j], ip);
-        }
-        __syncthreads();
-        if (jj < nb) {
-            const int j = c0 + jj;
-            const double2 pj = prow[jj];
-            for (int i = rs; i < ng; i += RSTEP) {
-                double2 *x = A + (long)i * ng + j;
-                const double2 fi = fcol[i];
-                double2 v;
-                if (i == c) v = pj;
-                else v = (j == c) ? cmul(make_double2(-fi.x, -fi.y), ip) : csub(*x, cmul(fi, pj));
-                *x = v;
-                if (j == c + 1) fcol[i] = v;
-            }
-        }
-        __syncthreads();
+    double best = -1.0;
+    int bidx = c;
+    for (int i = c + tid; i < ng; i += kGjPivotThreads) {
+        const double2 v = A[(long)i * ng + c];
+        const double m = isfinite(v.x) && isfinite(v.y) ? hypot(v.x, v.y) : INFINITY;
+        pivot_max(best, bidx, m, i);
     }
-    double2 *R = rk + (long)f * kGjNb * ng;
-    for (int kk = 0; kk < nb; kk++)
-        for (int j = tid; j < ng; j += kGjPanelThreads) R[(long)kk * ng + j] = A[(long)(c0 + kk) * ng + j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) pivot_max(best, bidx, __shfl_xor(best, o), __shfl_xor(bidx, o));
+    if (lane == 0) {
+        bv[wave] = best;
+        bi[wave] = bidx;
+    }
+    __syncthreads();
+    best = bv[0];
+    bidx = bi[0];
+#pragma unroll
+    for (int w = 1; w < NWV; w++) pivot_max(best, bidx, bv[w], bi[w]);
+    const int r = bidx;
+    if (tid == 0) {
+        piv[(long)f * ng + c] = r;
+        if (!isfinite(best)) atomicOr(flag, kFlagNonFinite);
+        else if (!(best > kPivotFloor)) atomicOr(flag, kFlagZeroPivot);
+    }
+    if (r != c) {
+        for (int j = tid; j < ng; j += kGjPivotThreads) {
+            const double2 t = A[(long)c * ng + j];
+            A[(long)c * ng + j] = A[(long)r * ng + j];
+            A[(long)r * ng + j] = t;
+        }
+    }
+    __syncthreads();
+    const double2 p = A[(long)c * ng + c];
+    const double den = p.x * p.x + p.y * p.y;
+    const double2 ip = make_double2(p.x / den, -p.y / den);
+    if (tid < nb) {
+        const int j = c0 + tid;
+        prow[(long)f * kGjNb + tid] = (j == c) ? ip : cmul(A[(long)c * ng + j], ip);
+    }
+}
+
+// Step c, second half: the panel columns of every row, grid (row blocks of
+// kGjElimRows, matrices).  Row c takes the scaled pivot row; column c of the
+// other rows takes -a_ic/a_cc; the other entries a_ij - a_ic prow_j.  Each
+// thread reads the a_ic of its rows before any thread of the block (which
+// owns those rows whole) writes column c.
+__global__ void __launch_bounds__(256)
+k_gj_elim(int ng, int c0, int nb, int c, double2 *a, const double2 *prow)
+{
+    const int f = blockIdx.y, tid = threadIdx.x, jj = tid & 63, rr = tid >> 6;
+    double2 *A = a + (long)f * ng * ng;
+    const double2 *pr = prow + (long)f * kGjNb;
+    const int i0 = blockIdx.x * kGjElimRows + rr;
+    double2 fi[kGjElimRows / 4];
+#pragma unroll
+    for (int q = 0; q < kGjElimRows / 4; q++) {
+        const int i = i0 + 4 * q;
+        fi[q] = i < ng ? A[(long)i * ng + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    if (jj >= nb) return;
+    const int j = c0 + jj;
+    const double2 pj = pr[jj], ip = pr[c - c0];
+#pragma unroll
+    for (int q = 0; q < kGjElimRows / 4; q++) {
+        const int i = i0 + 4 * q;
+        if (i >= ng) continue;
+        double2 *x = A + (long)i * ng + j;
+        double2 v;
+        if (i == c) v = pj;
+        else v = (j == c) ? cmul(make_double2(-fi[q].x, -fi[q].y), ip) : csub(*x, cmul(fi[q], pj));
+        *x = v;
+    }
+}
+
+// After the panel: its pivot rows (all columns) into rk [f][nb][ng] for the
+// update of the other columns.
+__global__ void k_gj_saverows(int ng, int c0, int nb, const double2 *a, double2 *rk)
+{
+    const int f = blockIdx.y;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nb * ng) return;
+    const int kk = (int)(t / ng), j = (int)(t - (long)kk * ng);
+    rk[((long)f * kGjNb + kk) * ng + j] = a[(long)f * ng * ng + (long)(c0 + kk) * ng + j];
 }
 
 __device__ __forceinline__ d4 mfma64(double x, double y, d4 c)
@@ -295,15 +303,24 @@ void launch_eps(hipStream_t s, int nfreq, int ng, const double *vs, const double
                        eps, flag);
 }
 
-size_t invert_scratch_bytes(int ng, int nfreq) { return sizeof(double2) * (size_t)kGjNb * ng * nfreq; }
+// the pivot rows of a panel [nfreq][kGjNb][ng], then the scaled pivot rows [nfreq][kGjNb]
+size_t invert_scratch_bytes(int ng, int nfreq) { return sizeof(double2) * (size_t)kGjNb * (ng + 1) * nfreq; }
 
 void launch_invert(hipStream_t s, int nfreq, int ng, double2 *a, double2 *scratch, int *piv, int *flag)
 {
     const unsigned t = (unsigned)((ng + 63) / 64);
+    double2 *prow = scratch + (size_t)kGjNb * ng * nfreq;
+    const dim3 eg((unsigned)((ng + kGjElimRows - 1) / kGjElimRows), (unsigned)nfreq);
     for (int c0 = 0; c0 < ng; c0 += kGjNb) {
         const int nb = std::min(kGjNb, ng - c0);
-        hipLaunchKernelGGL(k_gj_panel, dim3(nfreq), dim3(kGjPanelThreads), 0, s, ng, c0, nb, a, scratch, piv,
-                           flag);
+        for (int c = c0; c < c0 + nb; c++) {
+            hipLaunchKernelGGL(k_gj_pivot, dim3(nfreq), dim3(kGjPivotThreads), 0, s, ng, c0, nb, c, a, prow, piv,
+                               flag);
+            hipLaunchKernelGGL(k_gj_elim, eg, dim3(256), 0, s, ng, c0, nb, c, a, prow);
+        }
+        const long nrow = (long)nb * ng;
+        hipLaunchKernelGGL(k_gj_saverows, dim3((unsigned)((nrow + 255) / 256), (unsigned)nfreq), dim3(256), 0, s,
+                           ng, c0, nb, a, scratch);
         hipLaunchKernelGGL(k_gj_update, dim3(t, t, nfreq), dim3(256), 0, s, ng, c0, nb, a, scratch);
     }
     const long rows = (long)nfreq * ng;
