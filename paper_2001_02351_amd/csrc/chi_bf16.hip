@@ -583,13 +583,14 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
                     const bf8 *__restrict__ cB, int kgn, const float4 (&wc)[4]) {
         if (kgn >= 0) issue(nA, nB, kgn);
         bf8 ar[4][NT], ai[4][NT], an[4][NT];
-        bf8 B[NPL];
+        bf8 B[NPL], Bn[NPL];   // this column block's fragments and the next one's
 #pragma unroll
         for (int sp = 0; sp < NPL; sp++) B[sp] = cB[(sp * 4 + lk) * 128 + li];
         split_rows(cA, 0, wc, ar[0], ai[0], an[0]);
         __builtin_amdgcn_sched_barrier(0);
         // column block 0, one row block after the other: the split of row
-        // block rb + 1 is issued among the matrix-core ops of row block rb
+        // block rb + 1 is issued among the matrix-core ops of row block rb,
+        // and column block 1's fragments are read during row block 3's
 #pragma unroll
         for (int rb = 0; rb < 4; rb++) {
             products(rb, 0, ar[rb], ai[rb], an[rb], B);
@@ -601,14 +602,28 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one matrix-core op
                     __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);   // then vector instructions
                 }
+            } else {
+#pragma unroll
+                for (int sp = 0; sp < NPL; sp++) Bn[sp] = cB[(sp * 4 + lk) * 128 + 16 + li];
+                // one matrix-core op (after the wait for this block's data),
+                // then the next fragments' reads, then the other ops
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, NPL, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NPROD - 1, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        // the other column blocks: 8 independent accumulators per product
+        // the other column blocks: 8 independent accumulators per product;
+        // the next column block's fragments are read ahead of each block's
+        // matrix-core ops, so their LDS latency is covered by those ops
 #pragma unroll
         for (int cb = 1; cb < 8; cb++) {
 #pragma unroll
-            for (int sp = 0; sp < NPL; sp++) B[sp] = cB[(sp * 4 + lk) * 128 + cb * 16 + li];
+            for (int sp = 0; sp < NPL; sp++) B[sp] = Bn[sp];
+            if (cb + 1 < 8) {
+#pragma unroll
+                for (int sp = 0; sp < NPL; sp++) Bn[sp] = cB[(sp * 4 + lk) * 128 + (cb + 1) * 16 + li];
+            }
 #pragma unroll
             for (int s = 0; s < NT; s++)
 #pragma unroll
@@ -625,6 +640,12 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
                         accI[rb][cb] = mfma_bf16(an[rb][s], B[NT + u], accI[rb][cb]);
                     }
                 }
+            if (cb + 1 < 8) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, NPL, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 4 * NPROD - 1, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
     };
 
