@@ -306,8 +306,9 @@ rp_status rp_chi0_batch_graphs(rp_ctx *ctx, int *graphs, long *nodes);
  * bit for bit.  Fields of *p as in rp_chi0_batch; p is read during the call
  * only.
  * Errors: those of rp_pair_density and rp_chi0_accumulate; RP_E_NULL for a
- * NULL p or chi; RP_E_SHAPE for kbatch < 1.  On a non-OK status nothing has
- * been launched.
+ * NULL p or chi; RP_E_SHAPE for kbatch < 1.  Argument errors are found before
+ * anything is enqueued; a failed launch (RP_E_DEVICE) can leave chi holding
+ * the k batches enqueued before it.
  */
 rp_status rp_chi0_run(rp_ctx *ctx, const rp_problem *p, rp_precision prec);
 
