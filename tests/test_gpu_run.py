@@ -15,6 +15,10 @@ prepared from FP64 M), bit for bit, in FP64, split-BF16 and split-BF16 x6, on:
 * a 20^3 system whose pair grid (20^3) no lane length takes: the generic
   FP32 pair kernel, 5 x 11 bands, N_G = 300, 6 real frequencies.
 And the oracle on sampled columns for the first case, and the errors.
+The sampling and the metallic tetrahedron weights, each with the cRPA
+transition probabilities T (bands 6..9 of a 16^3 problem, the band ranges
+cutting through them; for the metal, overlapping band ranges), against the
+two calls bit for bit and the oracle.
 """
 
 import numpy as np
@@ -67,9 +71,10 @@ def _case(name):
     return p, (0, 5), (8, 27), 3
 
 
-def _two_calls(ctx, rp, d, o, e, prec, kbatch):
+def _two_calls(ctx, rp, d, o, e, prec, kbatch, wm=None):
     from paper_2001_02351_amd import path
     p = d.prob
+    wm = path.weight_mode(p) if wm is None else wm
     npk = (o[1] - o[0]) * (e[1] - e[0])
     chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device="cuda")
     M = torch.empty((kbatch * npk, d.ng, 2), dtype=torch.float64, device="cuda")
@@ -78,7 +83,7 @@ def _two_calls(ctx, rp, d, o, e, prec, kbatch):
         Mk = M[: (kb - ka) * npk]
         path.pair_density(ctx, d, ka, kb, o=o, e=e, out=Mk, prec=prec)
         rp.rp_chi0_accumulate(ctx, d.cell, p.iq, d.nband, d.energy, d.T, *o, *e, ka, kb, d.ng, Mk, d.nfreq,
-                              p.freq_eV, p.delta_eV, path.weight_mode(p), prec, 0 if ka == 0 else 1, chi)
+                              p.freq_eV, p.delta_eV, wm, prec, 0 if ka == 0 else 1, chi)
     return chi
 
 
@@ -109,6 +114,58 @@ def test_run_equals_two_calls(ctx, rp, name, prec):
         err = max(_rel(got[f], want[f]) for f in range(d.nfreq))
         print(f"[run] {name} prec={prec}: vs oracle {err:.1e}", flush=True)
         assert err < (1e-10 if prec == 0 else 1e-5)
+
+
+def _weights_case(mode):
+    """16^3 problem with the cRPA T on bands 6..9; the metal's band windows
+    overlap around E_F = 0 and so do its band ranges (bands 7 and 8 in both)."""
+    win = dict(occ_window=(-6.0, 0.5), emp_window=(-0.5, 12.0)) if mode == "metal" else {}
+    p = make_problem(name="runT", a_bohr=7.26, fft=(16, 16, 16), kmesh=(2, 2, 2), iq=(1, 1, 0), nocc=8, nemp=16,
+                     gpsi=2.4, ng=180, freq_eV=np.array([0.0, 2.0, 7.5, 15.0]), delta_eV=0.2, crpa=True, seed=31,
+                     **win)
+    o, e = ((4, 9), (7, 13)) if mode == "metal" else ((3, 8), (8, 20))
+    return p, o, e, 3, 0.0
+
+
+_ORACLE_CHI = {}
+
+
+def _oracle_chi(mode):
+    """The oracle's chi0 of _weights_case(mode) (computed once per mode)."""
+    if mode not in _ORACLE_CHI:
+        from oracle import metal
+        p, o, e, _, ef = _weights_case(mode)
+        M = oracle.pair_densities(p, *o, *e, 0, p.nk)
+        if mode == "sampling":
+            w = oracle.prob_weights(p, *o, *e, 0, p.nk, mode=1)
+        else:
+            w = metal.weights_metal(p.kmesh, p.iq, p.energy_eV, p.T, *o, *e, 0, p.nk, p.freq_eV, p.delta_eV, ef)
+        _ORACLE_CHI[mode] = oracle.chi0(M, w)
+    return _ORACLE_CHI[mode]
+
+
+@pytest.mark.parametrize("mode", ["sampling", "metal"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_run_weight_modes_with_T(ctx, rp, mode, prec):
+    from paper_2001_02351_amd import path
+    p, o, e, kbatch, ef = _weights_case(mode)
+    d = path.DeviceInputs(p)
+    assert d.T is not None
+    wm = rp.RP_W_SAMPLING if mode == "sampling" else rp.RP_W_TETRA_METAL
+    if mode == "metal":
+        rp.rp_set_fermi_level(ctx, ef)
+    print(f"[run] weights {mode} prec={prec}: bands {o} x {e}, N_G {d.ng}, kbatch {kbatch} of {d.nk}", flush=True)
+    chi = torch.full((d.nfreq, d.ng, d.ng, 2), float("nan"), dtype=torch.float64, device="cuda")
+    rp.rp_chi0_run(ctx, dict(path.batch_problem(d, chi, kbatch, o=o, e=e), wm=wm), prec)
+    ref = _two_calls(ctx, rp, d, o, e, prec, kbatch, wm)
+    rp.rp_synchronize(ctx)
+    print(f"[run] weights {mode} prec={prec}: max |diff| {float((chi - ref).abs().max()):.1e}", flush=True)
+    assert torch.equal(chi, ref)
+    want = _oracle_chi(mode)
+    got = path.to_complex(chi)
+    err = max(_rel(got[f], want[f]) for f in range(d.nfreq))
+    print(f"[run] weights {mode} prec={prec}: vs oracle {err:.1e}", flush=True)
+    assert err < (1e-10 if prec == 0 else 1e-5)
 
 
 def test_run_accumulates_and_clears(ctx, rp):
