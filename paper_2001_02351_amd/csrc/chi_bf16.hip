@@ -22,8 +22,11 @@
 // 256-thread block owns a 128x128 tile of (G, G') for 2 frequencies; wave w
 // holds rows 64 (w / 2) .. + 63 and all 128 columns for frequency w % 2 (4 x 8
 // blocks of 16x16), so each weighted row operand is split by one wave only.
-// k_chi_bf16 (one frequency per block, four 64x64 sub-tiles) and the
-// eight-wave 256-row forms are the tuning alternatives.  Steps of 32 pairs
+// A Hermitian chi (real weights) with a multiple of four frequencies runs in
+// the same form as 64-row strips x 128 columns for 4 frequencies, each strip's
+// column tiles starting at its own diagonal.  k_chi_bf16 (one frequency per
+// block, four 64x64 sub-tiles) and the eight-wave 256-row forms are the tuning
+// alternatives.  Steps of 32 pairs
 // stream through two LDS buffers (32 KB of A and 16 NT KB of B each) by
 // global_load_lds DMA, so the next step's operands arrive while the matrix
 // cores work on the current one.
@@ -154,6 +157,35 @@ __device__ __forceinline__ void tile_of(int id, int t, int herm, int &rt, int &c
         rt++;
     }
     ct = rt + id;
+}
+
+// Strip tiling of a Hermitian chi (the upper triangle G <= G'): 64-row
+// strips r = 0 .. ceil(ng / 64) - 1, whose 128-column tiles start at the
+// strip's own first row, columns 64 r + 128 j, j < ceil((ng - 64 r) / 128).
+// Only the lower half of each strip's leading 64 x 64 block and the columns
+// past ng are formed without being needed, where 128 x 128 tiles of the
+// upper triangle also form the lower half of every diagonal tile and the
+// padding up to the next multiple of 128.
+constexpr int kStrip = 64;
+
+__host__ __device__ __forceinline__ int strip_tiles(int ng, int r) { return (ng - kStrip * r + kTile - 1) / kTile; }
+
+__host__ __device__ inline long strip_tiles_total(int ng)
+{
+    long n = 0;
+    for (int r = 0; r * kStrip < ng; r++) n += strip_tiles(ng, r);
+    return n;
+}
+
+// strip r and column tile j of block index id
+__device__ __forceinline__ void strip_tile_of(int id, int ng, int &r, int &j)
+{
+    r = 0;
+    for (int m = strip_tiles(ng, 0); id >= m; m = strip_tiles(ng, r)) {
+        id -= m;
+        r++;
+    }
+    j = id;
 }
 
 // Grid: x = tile (all t x t tiles, or the upper triangle when herm), y =
@@ -452,13 +484,17 @@ template <int NT> __device__ __forceinline__ void split_pair(float x0, float x1,
     }
 }
 
-template <int NT, bool RW>
+// ST: the strip tiling of a Hermitian chi (herm = 1, stail = 0): a block
+// owns a 64-row strip x 128 columns for 4 frequencies, wave w the strip for
+// frequency f0 + w, so every wave does the same work as in the 128 x 128 form.
+template <int NT, bool RW, bool ST>
 __global__ void __launch_bounds__(256)
 k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, const bf8 *__restrict__ Bp, int nfreq,
            const float2 *__restrict__ wq, int accumulate, double2 *__restrict__ chi, int herm, int sps,
            float2 *__restrict__ part, int nfull, int stail)
 {
-    constexpr int NW = 2;
+    constexpr int NW = ST ? 4 : 2;
+    constexpr int NRB = ST ? 4 : 8;   // 16-row blocks of the block's rows
     constexpr int NPL = 2 * NT;
     __shared__ float2 sA[2][4 * 8 * 128];
     __shared__ bf8 sB[2][NPL * 4 * 128];
@@ -487,27 +523,38 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     } else {
         nstep = min(sps, npg / 4 - step0);
     }
-    int rt, ct;
-    tile_of(tile, nt, herm, rt, ct);
-    const int rt0 = rt * kTile, ct0 = ct * kTile;
-    const int wr = wave >> 1, iw = wave & 1;
+    int rt, ct, rt0, ct0;
+    if constexpr (ST) {
+        strip_tile_of(tile, ng, rt, ct);
+        rt0 = rt * kStrip;
+        ct0 = rt0 + ct * kTile;
+    } else {
+        tile_of(tile, nt, herm, rt, ct);
+        rt0 = rt * kTile;
+        ct0 = ct * kTile;
+    }
+    const int wr = ST ? 0 : wave >> 1, iw = ST ? wave : wave & 1;
     const int f0 = group * NW;
     const int fw = min(f0 + iw, nfreq - 1);
     const long plane = (long)npg * NGP;
 
-    // DMA as in k_chi_bf16: wave w moves pair group kg = w of the step
+    // DMA as in k_chi_bf16: wave w moves pair group kg = w of the step.  A
+    // strip tile's columns can run past NGP: those lanes read column NGP - 1
+    // (their results are never stored).
     const float2 *srcA = Ap + ((long)wave * (NGP / 16) + rt0 / 16) * 128 + lane * 2;
-    const bf8 *srcB = Bp + (long)wave * NGP + ct0 + lane;
+    const bf8 *srcB = Bp + (long)wave * NGP + (ST ? min(ct0 + lane, NGP - 1) : ct0 + lane);
+    const bf8 *srcB1 = ST ? Bp + (long)wave * NGP + min(ct0 + 64 + lane, NGP - 1) : srcB + 64;
     auto issue = [&](float2 *dA, bf8 *dB, int kg0) {
         const float2 *a = srcA + (long)kg0 * (NGP / 16) * 128;
         float2 *da = dA + wave * 8 * 128;
 #pragma unroll
-        for (int rb = 0; rb < 8; rb++) dma16(a + rb * 128, da + rb * 128);
-        const bf8 *b = srcB + (long)kg0 * NGP;
+        for (int rb = 0; rb < NRB; rb++) dma16(a + rb * 128, da + rb * 128);
+        const bf8 *b0 = srcB + (long)kg0 * NGP, *b1 = srcB1 + (long)kg0 * NGP;
 #pragma unroll
-        for (int sp = 0; sp < NPL; sp++)
-#pragma unroll
-            for (int h = 0; h < 2; h++) dma16(b + sp * plane + 64 * h, dB + (sp * 4 + wave) * 128 + 64 * h);
+        for (int sp = 0; sp < NPL; sp++) {
+            dma16(b0 + sp * plane, dB + (sp * 4 + wave) * 128);
+            dma16(b1 + sp * plane, dB + (sp * 4 + wave) * 128 + 64);
+        }
     };
     // this lane's 8 pairs (8 lk .. 8 lk + 7 of the step) at frequency fw
     const float4 *wsrc = (const float4 *)(wq + (long)fw * KP) + lk * 4;
@@ -690,11 +737,14 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
                 for (int r = 0; r < 4; r++) {
                     const int i = rt0 + wr * 64 + rb * 16 + 4 * lk + r;
                     const int j = ct0 + cb * 16 + li;
-                    P[(long)i * NGP + j] = make_float2(accR[rb][cb][r], accI[rb][cb][r]);
+                    if (!ST || j < NGP) P[(long)i * NGP + j] = make_float2(accR[rb][cb][r], accI[rb][cb][r]);
                 }
         return;
     }
-    const bool mirror = herm && rt != ct;
+    // Hermitian: the conjugate of an element outside the block's diagonal
+    // tile (128 x 128 form) or outside its strip's leading 64 columns (strip
+    // form) also goes to the mirrored position, formed by no other block
+    const bool mirror_tile = herm && rt != ct;
     double2 *C = chi + (long)(f0 + iw) * ng * ng;
 #pragma unroll
     for (int rb = 0; rb < 4; rb++)
@@ -704,6 +754,7 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
             for (int r = 0; r < 4; r++) {
                 const int i = rt0 + wr * 64 + rb * 16 + 4 * lk + r;
                 const int j = ct0 + cb * 16 + li;
+                const bool mirror = ST ? j >= rt0 + kStrip : mirror_tile;
                 if (i < ng && j < ng) {
                     const double2 a = make_double2((double)accR[rb][cb][r], (double)accI[rb][cb][r]);
                     const long idx = (long)i * ng + j;
@@ -897,18 +948,23 @@ k_chi_bf16_wide(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap
 }
 
 // chi (+)= sum over slices of the partial tiles, in FP64, for the computed
-// tiles; for an off-diagonal tile of a Hermitian chi the conjugate transpose
-// goes to the mirrored tile through LDS.  Block: 32 x 32 elements of one
+// tiles; for a Hermitian chi formed by row strips of hs rows (128 x 128 tiles
+// of the upper triangle: hs = 128; the strip tiling: hs = 64) the conjugate
+// transpose of a chunk past its strip's leading hs columns goes to the
+// mirrored chunk through LDS.  Block: 32 x 32 elements of one
 // frequency (grid x over the NGP/32 x NGP/32 chunks, z over frequencies).
 __global__ void __launch_bounds__(256)
 k_chi_reduce(int nslice, int nfreq, int ng, int NGP, const float2 *__restrict__ part, int accumulate, int herm,
-             double2 *__restrict__ chi)
+             int hs, double2 *__restrict__ chi)
 {
     __shared__ double2 tr[32][33];
     const int nc = NGP / 32;
     const int ci = blockIdx.x / nc, cj = blockIdx.x - ci * nc;
-    const int rt = ci / (kTile / 32), ct = cj / (kTile / 32);
-    if (herm && rt > ct) return;
+    // Hermitian: the chunk's rows lie in strip rs of hs rows, whose blocks
+    // formed the columns from the strip's first row on; the columns past the
+    // strip's own hs also go to the mirrored chunk
+    const int rs = ci * 32 / hs;
+    if (herm && cj * 32 < rs * hs) return;
     const int f = blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const long plane = (long)NGP * NGP;
@@ -929,7 +985,7 @@ k_chi_reduce(int nslice, int nfreq, int ng, int NGP, const float2 *__restrict__ 
         }
         tr[ty + 8 * m][tx] = v;
     }
-    if (!(herm && rt < ct)) return;
+    if (!(herm && cj * 32 >= (rs + 1) * hs)) return;
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < 4; m++) {
@@ -1019,11 +1075,22 @@ static int eff_kernel(int kernel, int ng, bool herm, int nterm)
 // Slices of the pair steps for one contraction: with fill > 0, enough slices
 // that the grid holds about `fill` blocks (one block per CU fits), each slice
 // at least 8 steps; fill = 0 never slices.
+// The strip tiling runs for a Hermitian chi in the row form (two-frequency
+// groups requested) when the frequencies come in groups of four.
+static bool use_strips(bool herm, int nw, int nfreq, int wide)
+{
+    return herm && nw == 2 && !wide && nfreq % 4 == 0;
+}
+
 static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fill, int wide, int *nslice,
                        int *sps)
 {
     const int t = pad_ng(ng) / kTile;
     long tiles = herm ? (long)t * (t + 1) / 2 : (long)t * t;
+    if (use_strips(herm, nw, nfreq, wide)) {
+        tiles = strip_tiles_total(ng);
+        nw = 4;
+    }
     int nstep = (int)(pad_pairs(npair) / kStep);
     if (wide) {
         const int tn = wide == 2 ? 128 : 64;
@@ -1093,7 +1160,7 @@ size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill
     nw = nw == 1 ? 1 : 2;
     chi_slices(npair, ng, nfreq, herm, nw, fill, form, &S, &sps);
     if (S == 1) {
-        if (form != 0) return 0;
+        if (form != 0 || use_strips(herm, nw, nfreq, form)) return 0;
         const int t = pad_ng(ng) / kTile;
         const long units = (herm ? (long)t * (t + 1) / 2 : (long)t * t) * ((nfreq + nw - 1) / nw);
         int nfull, stail;
@@ -1185,6 +1252,15 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
             else RP_CHIW(3, 2, 2);
         }
 #undef RP_CHIW
+    } else if (use_strips(herm, nw, nfreq, wide)) {
+        const dim3 grid((unsigned)strip_tiles_total(ng), (unsigned)(nfreq / 4), (unsigned)S);
+#define RP_STRIPS(NT)                                                                                         \
+    hipLaunchKernelGGL((k_chi_rows<NT, true, true>), grid, dim3(256), 0, s, npg, NGP, KP, ng,                 \
+                       (const float2 *)split_a, (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, \
+                       chi, 1, sps, P, 0, 0)
+        if (nterm == 2) RP_STRIPS(2);
+        else RP_STRIPS(3);
+#undef RP_STRIPS
     } else {
         const unsigned tiles = herm ? (unsigned)(t * (t + 1) / 2) : (unsigned)(t * t);
         int nfull = 0, stail = 0;
@@ -1200,7 +1276,7 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
                        (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P, \
                        nfull, stail)
 #define RP_ROWS(NT, RW)                                                                                       \
-    hipLaunchKernelGGL((k_chi_rows<NT, RW>), grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a,  \
+    hipLaunchKernelGGL((k_chi_rows<NT, RW, false>), grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a,  \
                        (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P, \
                        nfull, stail)
         if (nw == 1) {
@@ -1223,8 +1299,9 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
     if (S > 1) {
         if (before_reduce) before_reduce();
         const int nc = NGP / 32;
+        const int hs = use_strips(herm, nw, nfreq, wide) ? kStrip : kTile;
         hipLaunchKernelGGL(k_chi_reduce, dim3((unsigned)(nc * nc), 1, (unsigned)nfreq), dim3(256), 0, s, S, nfreq, ng,
-                           NGP, (const float2 *)P, accumulate, (int)herm, chi);
+                           NGP, (const float2 *)P, accumulate, (int)herm, hs, chi);
     }
 }
 

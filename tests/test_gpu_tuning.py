@@ -142,14 +142,18 @@ def test_wide_contraction_form_matches(ctx, rp):
 def test_tail_split_matches(ctx, rp, herm):
     """The tail split (units beyond the last whole wave run as slices of the
     pair steps, summed in FP64 by k_chi_reduce_tail): 360 units on complex
-    weights (N_G = 700, 20 real frequencies) and on the Hermitian half
-    (N_G = 1132, 16 imaginary frequencies), chi_fill = 400 so that the pair
+    weights (N_G = 700, 20 real frequencies) and 315 on the Hermitian half
+    (N_G = 1132, the first 14 of 16 imaginary frequencies: a frequency count
+    that is not a multiple of four keeps the 128 x 128 tiles, which split
+    their tail; the strip tiling does not), chi_fill = 400 so that the pair
     steps are not sliced otherwise; against the unsplit run (fill 0) to 2e-6
     and the oracle on sampled columns to 1e-5."""
     from paper_2001_02351_amd import path
     from synth import make_problem
     if herm:
+        import dataclasses
         p = batch_system(21, 0)
+        p = dataclasses.replace(p, freq_eV=p.freq_eV[:14])
         o, e = (0, 8), (p.nocc, p.nocc + 16)
     else:
         p = make_problem(name="tail", a_bohr=7.26, fft=(24, 24, 24), kmesh=(2, 2, 2), iq=(1, 0, 0), nocc=8,
@@ -177,4 +181,45 @@ def test_tail_split_matches(ctx, rp, herm):
     print(f"[tuning] tail split herm={herm}: vs unsplit {d_ref:.1e}, vs oracle {d_orc:.1e}", flush=True)
     # two split-BF16 results, each about 1e-6 from the exact chi element-wise
     assert d_ref < 2e-6 and d_orc < 1e-5
+    rp.rp_set_tuning(ctx, [])
+
+
+@pytest.mark.parametrize("ng", [89, 200, 300, 351])
+def test_strip_tiling_hermitian(ctx, rp, ng):
+    """Hermitian chi (imaginary frequencies, delta = 0) in the two-frequency
+    row form runs as 64-row strips whose column tiles start at the strip's
+    diagonal (four frequencies per workgroup).  On a 16^3 problem with 8
+    frequencies and N_G from under one tile (89) to ragged multiples (200,
+    300, 351), unsliced and sliced, two- and three-term splits: the whole
+    chi against the oracle element-wise (1e-5; the FP32 pair densities bound
+    both split forms at about 2e-6) and against the 128 x 128 one-frequency
+    form (2e-6)."""
+    from paper_2001_02351_amd import path
+    from synth import make_problem
+    p = make_problem(name="strips", a_bohr=7.26, fft=(16, 16, 16), kmesh=(2, 2, 2), iq=(1, 0, 0), nocc=8,
+                     nemp=24, gpsi=2.4, ng=ng, freq_eV=1j * np.array([0.0, 0.3, 1.0, 2.5, 6.0, 15.0, 40.0, 100.0]),
+                     delta_eV=0.0, seed=41)
+    d = path.DeviceInputs(p)
+    assert d.ng == ng and d.nfreq == 8
+    M = oracle.pair_densities(p, 0, p.nocc, p.nocc, p.nband, 0, d.nk)
+    w = oracle.prob_weights(p, 0, p.nocc, p.nocc, p.nband, 0, d.nk)
+    want = oracle.chi0(M, w)
+
+    def chi_for(prec, entries):
+        rp.rp_set_tuning(ctx, entries)
+        chi = torch.full((d.nfreq, d.ng, d.ng, 2), float("nan"), dtype=torch.float64, device="cuda")
+        path.chi0(ctx, d, prec=prec, kbatch=d.nk, chi=chi)
+        rp.rp_synchronize(ctx)
+        return path.to_complex(chi)
+
+    for prec in (rp.RP_SPLIT_BF16, rp.RP_SPLIT_BF16_X6):
+        one = chi_for(prec, [_entry(chi_nw=1, chi_fill=0)])
+        for fill in (0, 4096):
+            got = chi_for(prec, [_entry(chi_nw=2, chi_fill=fill)])
+            assert np.isfinite(got).all()
+            d_orc = max(_rel(got[f], want[f]) for f in range(d.nfreq))
+            d_one = max(_rel(got[f], one[f]) for f in range(d.nfreq))
+            print(f"[strips] ng={ng} prec={prec} fill={fill}: vs oracle {d_orc:.1e}, vs one-frequency form "
+                  f"{d_one:.1e}", flush=True)
+            assert d_orc < 1e-5 and d_one < 2e-6
     rp.rp_set_tuning(ctx, [])
