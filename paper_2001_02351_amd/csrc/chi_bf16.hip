@@ -22,9 +22,10 @@
 // 256-thread block owns a 128x128 tile of (G, G') for 2 frequencies; wave w
 // holds rows 64 (w / 2) .. + 63 and all 128 columns for frequency w % 2 (4 x 8
 // blocks of 16x16), so each weighted row operand is split by one wave only.
-// A Hermitian chi (real weights) with a multiple of four frequencies runs in
-// the same form as 64-row strips x 128 columns for 4 frequencies, each strip's
-// column tiles starting at its own diagonal.  k_chi_bf16 (one frequency per
+// With a multiple of four frequencies the same form runs as 64-row strips x
+// 128 columns for 4 frequencies (the same work per wave, half the row operand
+// per workgroup and the column operand shared by four frequencies); for a
+// Hermitian chi each strip's column tiles start at its own diagonal.  k_chi_bf16 (one frequency per
 // block, four 64x64 sub-tiles) and the eight-wave 256-row forms are the tuning
 // alternatives.  Steps of 32 pairs
 // stream through two LDS buffers (32 KB of A and 16 NT KB of B each) by
@@ -484,9 +485,10 @@ template <int NT> __device__ __forceinline__ void split_pair(float x0, float x1,
     }
 }
 
-// ST: the strip tiling of a Hermitian chi (herm = 1, stail = 0): a block
-// owns a 64-row strip x 128 columns for 4 frequencies, wave w the strip for
-// frequency f0 + w, so every wave does the same work as in the 128 x 128 form.
+// ST: the strip tiling (stail = 0): a block owns a 64-row strip x 128 columns
+// for 4 frequencies, wave w the strip for frequency f0 + w, so every wave does
+// the same work as in the 128 x 128 form; grid x runs over the strip tiles of
+// the upper triangle (herm) or over all 2 t x t strip tiles (row-major).
 template <int NT, bool RW, bool ST>
 __global__ void __launch_bounds__(256)
 k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, const bf8 *__restrict__ Bp, int nfreq,
@@ -525,9 +527,16 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     }
     int rt, ct, rt0, ct0;
     if constexpr (ST) {
-        strip_tile_of(tile, ng, rt, ct);
-        rt0 = rt * kStrip;
-        ct0 = rt0 + ct * kTile;
+        if (herm) {
+            strip_tile_of(tile, ng, rt, ct);
+            rt0 = rt * kStrip;
+            ct0 = rt0 + ct * kTile;
+        } else {
+            rt = tile / nt;
+            ct = tile - rt * nt;
+            rt0 = rt * kStrip;
+            ct0 = ct * kTile;
+        }
     } else {
         tile_of(tile, nt, herm, rt, ct);
         rt0 = rt * kTile;
@@ -754,7 +763,7 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
             for (int r = 0; r < 4; r++) {
                 const int i = rt0 + wr * 64 + rb * 16 + 4 * lk + r;
                 const int j = ct0 + cb * 16 + li;
-                const bool mirror = ST ? j >= rt0 + kStrip : mirror_tile;
+                const bool mirror = ST ? herm && j >= rt0 + kStrip : mirror_tile;
                 if (i < ng && j < ng) {
                     const double2 a = make_double2((double)accR[rb][cb][r], (double)accI[rb][cb][r]);
                     const long idx = (long)i * ng + j;
@@ -1075,11 +1084,35 @@ static int eff_kernel(int kernel, int ng, bool herm, int nterm)
 // Slices of the pair steps for one contraction: with fill > 0, enough slices
 // that the grid holds about `fill` blocks (one block per CU fits), each slice
 // at least 8 steps; fill = 0 never slices.
-// The strip tiling runs for a Hermitian chi in the row form (two-frequency
-// groups requested) when the frequencies come in groups of four.
-static bool use_strips(bool herm, int nw, int nfreq, int wide)
+// The strip tiling takes the row form's place (two-frequency groups
+// requested) when the frequencies come in groups of four: always for a
+// Hermitian chi; for complex weights (strips over all rows, the same
+// workgroups and the same arithmetic per element as the 128 x 128 tiles) when
+// the pair steps are sliced or the 128 x 128 form's tail split would not
+// apply, as the strips do not split their tail.
+static bool strips_allowed(bool herm, int nw, int nfreq, int wide)
 {
-    return herm && nw == 2 && !wide && nfreq % 4 == 0;
+    (void)herm;
+    return nw == 2 && !wide && nfreq % 4 == 0;
+}
+
+static void tail_plan(long units, int nstep, int fill, int *nfull, int *stail);
+
+static bool use_strips(bool herm, int nw, int nfreq, int wide, long npair, int ng, int fill, int S)
+{
+    if (!strips_allowed(herm, nw, nfreq, wide)) return false;
+    if (herm || S > 1) return true;
+    const long t = pad_ng(ng) / kTile;
+    int nfull, stail;
+    tail_plan(t * t * (nfreq / 2), (int)(pad_pairs(npair) / kStep), fill, &nfull, &stail);
+    return stail == 0;
+}
+
+// workgroups per frequency group and slice of the strip tiling
+static long strip_blocks(int ng, bool herm)
+{
+    const long t = pad_ng(ng) / kTile;
+    return herm ? strip_tiles_total(ng) : 2 * t * t;
 }
 
 static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fill, int wide, int *nslice,
@@ -1087,8 +1120,9 @@ static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fil
 {
     const int t = pad_ng(ng) / kTile;
     long tiles = herm ? (long)t * (t + 1) / 2 : (long)t * t;
-    if (use_strips(herm, nw, nfreq, wide)) {
-        tiles = strip_tiles_total(ng);
+    if (herm && strips_allowed(herm, nw, nfreq, wide)) {
+        // (for complex weights the strips hold as many workgroups as the tiles)
+        tiles = strip_blocks(ng, herm);
         nw = 4;
     }
     int nstep = (int)(pad_pairs(npair) / kStep);
@@ -1160,7 +1194,7 @@ size_t chi_part_bytes(long npair, int ng, int nfreq, bool herm, int nw, int fill
     nw = nw == 1 ? 1 : 2;
     chi_slices(npair, ng, nfreq, herm, nw, fill, form, &S, &sps);
     if (S == 1) {
-        if (form != 0 || use_strips(herm, nw, nfreq, form)) return 0;
+        if (form != 0 || use_strips(herm, nw, nfreq, form, npair, ng, fill, S)) return 0;
         const int t = pad_ng(ng) / kTile;
         const long units = (herm ? (long)t * (t + 1) / 2 : (long)t * t) * ((nfreq + nw - 1) / nw);
         int nfull, stail;
@@ -1252,14 +1286,19 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
             else RP_CHIW(3, 2, 2);
         }
 #undef RP_CHIW
-    } else if (use_strips(herm, nw, nfreq, wide)) {
-        const dim3 grid((unsigned)strip_tiles_total(ng), (unsigned)(nfreq / 4), (unsigned)S);
-#define RP_STRIPS(NT)                                                                                         \
-    hipLaunchKernelGGL((k_chi_rows<NT, true, true>), grid, dim3(256), 0, s, npg, NGP, KP, ng,                 \
+    } else if (use_strips(herm, nw, nfreq, wide, npair, ng, fill, S)) {
+        const dim3 grid((unsigned)strip_blocks(ng, herm), (unsigned)(nfreq / 4), (unsigned)S);
+#define RP_STRIPS(NT, RW)                                                                                     \
+    hipLaunchKernelGGL((k_chi_rows<NT, RW, true>), grid, dim3(256), 0, s, npg, NGP, KP, ng,                   \
                        (const float2 *)split_a, (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, \
-                       chi, 1, sps, P, 0, 0)
-        if (nterm == 2) RP_STRIPS(2);
-        else RP_STRIPS(3);
+                       chi, (int)herm, sps, P, 0, 0)
+        if (herm) {
+            if (nterm == 2) RP_STRIPS(2, true);
+            else RP_STRIPS(3, true);
+        } else {
+            if (nterm == 2) RP_STRIPS(2, false);
+            else RP_STRIPS(3, false);
+        }
 #undef RP_STRIPS
     } else {
         const unsigned tiles = herm ? (unsigned)(t * (t + 1) / 2) : (unsigned)(t * t);
@@ -1299,7 +1338,7 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
     if (S > 1) {
         if (before_reduce) before_reduce();
         const int nc = NGP / 32;
-        const int hs = use_strips(herm, nw, nfreq, wide) ? kStrip : kTile;
+        const int hs = herm && strips_allowed(herm, nw, nfreq, wide) ? kStrip : kTile;
         hipLaunchKernelGGL(k_chi_reduce, dim3((unsigned)(nc * nc), 1, (unsigned)nfreq), dim3(256), 0, s, S, nfreq, ng,
                            NGP, (const float2 *)P, accumulate, (int)herm, hs, chi);
     }

@@ -184,11 +184,14 @@ def test_tail_split_matches(ctx, rp, herm):
     rp.rp_set_tuning(ctx, [])
 
 
+@pytest.mark.parametrize("axis", ["imaginary", "real"])
 @pytest.mark.parametrize("ng", [89, 200, 300, 351])
-def test_strip_tiling_hermitian(ctx, rp, ng):
-    """Hermitian chi (imaginary frequencies, delta = 0) in the two-frequency
-    row form runs as 64-row strips whose column tiles start at the strip's
-    diagonal (four frequencies per workgroup).  On a 16^3 problem with 8
+def test_strip_tiling(ctx, rp, ng, axis):
+    """With a multiple of four frequencies the two-frequency row form runs as
+    64-row strips x 128 columns for four frequencies: over the upper triangle
+    with each strip's column tiles starting at its diagonal for a Hermitian
+    chi (imaginary frequencies, delta = 0), over the whole matrix for complex
+    weights (real frequencies, delta > 0).  On a 16^3 problem with 8
     frequencies and N_G from under one tile (89) to ragged multiples (200,
     300, 351), unsliced and sliced, two- and three-term splits: the whole
     chi against the oracle element-wise (1e-5; the FP32 pair densities bound
@@ -196,9 +199,12 @@ def test_strip_tiling_hermitian(ctx, rp, ng):
     form (2e-6)."""
     from paper_2001_02351_amd import path
     from synth import make_problem
+    if axis == "imaginary":
+        freq, delta = 1j * np.array([0.0, 0.3, 1.0, 2.5, 6.0, 15.0, 40.0, 100.0]), 0.0
+    else:
+        freq, delta = np.array([0.0, 1.0, 2.5, 5.0, 8.0, 12.0, 16.0, 20.0]), 0.1
     p = make_problem(name="strips", a_bohr=7.26, fft=(16, 16, 16), kmesh=(2, 2, 2), iq=(1, 0, 0), nocc=8,
-                     nemp=24, gpsi=2.4, ng=ng, freq_eV=1j * np.array([0.0, 0.3, 1.0, 2.5, 6.0, 15.0, 40.0, 100.0]),
-                     delta_eV=0.0, seed=41)
+                     nemp=24, gpsi=2.4, ng=ng, freq_eV=freq, delta_eV=delta, seed=41)
     d = path.DeviceInputs(p)
     assert d.ng == ng and d.nfreq == 8
     M = oracle.pair_densities(p, 0, p.nocc, p.nocc, p.nband, 0, d.nk)
@@ -219,7 +225,7 @@ def test_strip_tiling_hermitian(ctx, rp, ng):
             assert np.isfinite(got).all()
             d_orc = max(_rel(got[f], want[f]) for f in range(d.nfreq))
             d_one = max(_rel(got[f], one[f]) for f in range(d.nfreq))
-            print(f"[strips] ng={ng} prec={prec} fill={fill}: vs oracle {d_orc:.1e}, vs one-frequency form "
+            print(f"[strips] {axis} ng={ng} prec={prec} fill={fill}: vs oracle {d_orc:.1e}, vs one-frequency form "
                   f"{d_one:.1e}", flush=True)
             assert d_orc < 1e-5 and d_one < 2e-6
     rp.rp_set_tuning(ctx, [])
