@@ -27,6 +27,8 @@ Inputs are resident in HBM before the timed region.
                 with the algorithmic bytes (u-grids once + the
                 contraction operands it writes) beside them
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload
+  vs_oracle_sample  the GPU's chi0 of that sample (split, x6 and FP64)
+                against the oracle's result there, element-wise and in norm
 
 Counter runs use two extra modes: --copy-calibration (a plain 1 GiB device
 copy, three times) and --profile-k N (the split chi0 build over the first N
@@ -163,7 +165,7 @@ def cpu_baseline(prob, ng_sample: int = 500):
     t1 = time.perf_counter()
     w = oracle.prob_weights(prob, o0, o1, e0, e1, 0, 1)
     t2 = time.perf_counter()
-    oracle.chi0(M, w)
+    chi_sample = oracle.chi0(M, w)
     t3 = time.perf_counter()
     npair = M.shape[0]
     e_tenth = e0 + max(1, (e1 - e0) // 10)
@@ -187,7 +189,31 @@ def cpu_baseline(prob, ng_sample: int = 500):
         "s_per_qpoint_extrapolated": per_q,
         "extrapolation": (f"{prob.nk} k-points x (pair densities on all {prob.ng} vectors, scaled from a tenth "
                           f"of the pairs; weights; chi0 scaled by ({prob.ng}/{ngs})^2)"),
+        "chi_sample": chi_sample,   # the sample's chi0, [nfreq][ngs][ngs] (not part of the JSON line)
     }
+
+
+def oracle_sample_errors(rp, path, ctx, d, baseline) -> dict:
+    """The GPU path's chi0 over the cpu_baseline sample (k = 0, all bands and
+    frequencies) against the oracle's, on the sample's leading ngs x ngs block
+    of the sphere: per frequency the relative Frobenius norm of the difference
+    and max |diff| / max |chi|, the largest over the frequencies."""
+    import numpy as np
+    import torch
+    want = baseline["chi_sample"]
+    ngs = want.shape[1]
+    chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device=d.device)
+    out = {"sample": f"chi0 of k = 0 (all bands, all {d.nfreq} frequencies) on the first {ngs} x {ngs} of the "
+                     f"{d.ng} x {d.ng} sphere block, against the cpu_baseline leg's oracle result"}
+    for name, prec in (("split_bf16", rp.RP_SPLIT_BF16), ("split_bf16_x6", rp.RP_SPLIT_BF16_X6),
+                       ("fp64", rp.RP_FP64)):
+        path.chi0(ctx, d, prec=prec, kbatch=1, k0=0, k1=1, chi=chi)
+        rp.rp_synchronize(ctx)
+        got = path.to_complex(chi[:, :ngs, :ngs].contiguous())
+        fro = max(float(np.linalg.norm(got[f] - want[f]) / np.linalg.norm(want[f])) for f in range(d.nfreq))
+        ew = max(float(np.abs(got[f] - want[f]).max() / np.abs(want[f]).max()) for f in range(d.nfreq))
+        out[name] = {"chi": fro, "chi_max_elementwise": ew}
+    return out
 
 
 def run_leg(rp, path, ctx, d, prec, steps, warmup, kbatch):
@@ -869,6 +895,7 @@ def main():
             "eps_inv_max_elementwise": e_e,
             "W_ij_max_elementwise": float((torch.abs(torch.view_as_complex(wij_s) - wd) / torch.abs(wd)).max()),
         }
+    vs_oracle = None if baseline is None else oracle_sample_errors(rp, path, ctx, d, baseline)
     qterm = None if args.no_qterm else qterm_leg(rp, path, ctx, d, einv_s,
                                                  cpu=not args.no_cpu_baseline and not args.profile_k)
     unfold = None if args.no_qterm else unfold_leg(rp, ctx, d, einv_s)
@@ -931,6 +958,7 @@ def main():
         "split_bf16_x6": x6,
         "fp64": fp64,
         "split_vs_gpu_fp64": agree,
+        "vs_oracle_sample": vs_oracle,
         "roofline": {
             "bound": "mfma",
             "achieved": achieved,
