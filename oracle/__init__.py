@@ -40,9 +40,12 @@ _lib = None
 
 
 def lib():
+    """The oracle's C library (liboracle.so, built on first use); the
+    environment variable RP_ORACLE_LIB names another build of oracle.c to load
+    instead (the sanitized build of build.build_sanitized)."""
     global _lib
     if _lib is None:
-        path = library_path()
+        path = os.environ.get("RP_ORACLE_LIB") or library_path()
         if not os.path.exists(path):
             _build()
         _lib = ctypes.CDLL(path)

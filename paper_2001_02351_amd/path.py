@@ -237,6 +237,102 @@ def run_q(ctx, d: DeviceInputs, prec: int = _rp.RP_FP64, kbatch: int = 1):
     return out
 
 
+def _save_atomic(path: str, obj) -> None:
+    """Writes a numpy array (.npy format) or a JSON-ready dict to path + ".tmp"
+    and renames it over path, so that an interrupted save never leaves a
+    partial file under the final name."""
+    import json
+    import os
+    tmp = path + ".tmp"
+    if isinstance(obj, np.ndarray):
+        with open(tmp, "wb") as f:
+            np.save(f, obj)
+    else:
+        with open(tmp, "w") as f:
+            json.dump(obj, f)
+    os.replace(tmp, path)
+
+
+def run_q_checkpointed(ctx, d: DeviceInputs, out_dir: str, prec: int = _rp.RP_FP64, kbatch: int = 1,
+                       every: int = 1, stop_after: Optional[int] = None):
+    """run_q with its results kept in out_dir (the per-q result directories
+    of the paper's chi calculation): chi.npy, eps_inv.npy, W.npy and, with
+    Wannier orbitals, Wij.npy (complex128), then done.json.
+
+    The chi0 accumulation is checkpointed every `every` k batches
+    (chi_partial.npy and progress.json with the next k-point); a later call
+    with the same out_dir and the same parameters resumes after the last
+    checkpoint (rp_chi0_run with accumulate = 1 on the restored chi, the
+    same sums in the same order, so the results are those of an
+    uninterrupted run), and a finished q-point is read back, not recomputed.
+    stop_after (a count of k batches) returns None once that many batches
+    have been checkpointed in this call, as an interrupted run would leave
+    out_dir.  Returns a dict of host arrays and "source": "computed",
+    "resumed" or "files"."""
+    import json
+    import os
+
+    import torch
+    os.makedirs(out_dir, exist_ok=True)
+    p = d.prob
+    keys = ["chi", "eps_inv", "W"] + (["Wij"] if d.phi is not None else [])
+    meta = dict(prec=int(prec), kbatch=int(kbatch), nk=d.nk, ng=d.ng, nfreq=d.nfreq,
+                iq=[int(x) for x in p.iq], nocc=int(p.nocc), nemp=int(p.nemp))
+    done = os.path.join(out_dir, "done.json")
+    if os.path.exists(done):
+        with open(done) as f:
+            if json.load(f) != meta:
+                raise ValueError(f"{out_dir} holds a q-point computed with other parameters")
+        out = {k: np.load(os.path.join(out_dir, k + ".npy")) for k in keys}
+        out["source"] = "files"
+        return out
+    prog = os.path.join(out_dir, "progress.json")
+    part = os.path.join(out_dir, "chi_partial.npy")
+    chi = torch.empty((d.nfreq, d.ng, d.ng, 2), dtype=torch.float64, device=d.device)
+    k = 0
+    source = "computed"
+    if os.path.exists(prog):
+        with open(prog) as f:
+            saved = json.load(f)
+        if {x: saved.get(x) for x in meta} != meta:
+            raise ValueError(f"{out_dir} holds a partial chi0 computed with other parameters")
+        k = int(saved["k_next"])
+        host = np.load(part)
+        chi.copy_(torch.from_numpy(np.ascontiguousarray(host).view(np.float64).reshape(chi.shape)))
+        source = "resumed"
+    step = max(1, every) * kbatch
+    batches = 0
+    while k < d.nk:
+        k1 = min(d.nk, k + step)
+        _rp.rp_chi0_run(ctx, batch_problem(d, chi, kbatch, k=(k, k1), accumulate=0 if k == 0 else 1), prec)
+        _save_atomic(part, to_complex(chi))
+        _save_atomic(prog, dict(meta, k_next=k1))
+        k = k1
+        batches += 1
+        if stop_after is not None and batches >= stop_after and k < d.nk:
+            return None
+    einv, W = screen(ctx, d, chi)
+    res = dict(chi=to_complex(chi), eps_inv=to_complex(einv), W=to_complex(W))
+    if d.phi is not None:
+        res["Wij"] = to_complex(wannier(ctx, d, einv))
+    for key in keys:
+        _save_atomic(os.path.join(out_dir, key + ".npy"), res[key])
+    _save_atomic(done, meta)
+    for f in (part, prog):
+        os.remove(f)
+    res["source"] = source
+    return res
+
+
+def run_qpoints(ctx, ds, root: str, prec: int = _rp.RP_FP64, kbatch: int = 1, every: int = 1):
+    """run_q_checkpointed for several q-points (DeviceInputs), in
+    root/q001, root/q002, ...; q-points already finished are read back and
+    an interrupted one resumes.  Returns the list of result dicts."""
+    import os
+    return [run_q_checkpointed(ctx, d, os.path.join(root, f"q{i + 1:03d}"), prec=prec, kbatch=kbatch, every=every)
+            for i, d in enumerate(ds)]
+
+
 def to_complex(t) -> np.ndarray:
     """Device [..., 2] float64 tensor -> host complex128 array."""
     a = t.detach().cpu().numpy()
