@@ -23,9 +23,11 @@
 // holds rows 64 (w / 2) .. + 63 and all 128 columns for frequency w % 2 (4 x 8
 // blocks of 16x16), so each weighted row operand is split by one wave only.
 // With a multiple of four frequencies the same form runs as 64-row strips x
-// 128 columns for 4 frequencies (the same work per wave, half the row operand
-// per workgroup and the column operand shared by four frequencies); for a
-// Hermitian chi each strip's column tiles start at its own diagonal.  k_chi_bf16 (one frequency per
+// 128 columns for 4 frequencies (a Hermitian chi with a multiple of eight: as
+// 32-row strips x 128 columns for 8): the same work per wave, a half or a
+// quarter of the row operand per workgroup and the column operand shared by
+// four or eight frequencies; for a Hermitian chi each strip's column tiles
+// start at its own diagonal.  k_chi_bf16 (one frequency per
 // block, four 64x64 sub-tiles) and the eight-wave 256-row forms are the tuning
 // alternatives.  Steps of 32 pairs
 // stream through two LDS buffers (32 KB of A and 16 NT KB of B each) by
@@ -160,29 +162,27 @@ __device__ __forceinline__ void tile_of(int id, int t, int herm, int &rt, int &c
     ct = rt + id;
 }
 
-// Strip tiling of a Hermitian chi (the upper triangle G <= G'): 64-row
-// strips r = 0 .. ceil(ng / 64) - 1, whose 128-column tiles start at the
-// strip's own first row, columns 64 r + 128 j, j < ceil((ng - 64 r) / 128).
-// Only the lower half of each strip's leading 64 x 64 block and the columns
-// past ng are formed without being needed, where 128 x 128 tiles of the
-// upper triangle also form the lower half of every diagonal tile and the
+// Strip tiling of a Hermitian chi (the upper triangle G <= G'): strips of h
+// rows (h = 64 or 32), r = 0 .. ceil(ng / h) - 1, whose 128-column tiles start
+// at the strip's own first row, columns h r + 128 j, j < ceil((ng - h r) /
+// 128).  Only the lower half of each strip's leading h x h block and the
+// columns past ng are formed without being needed, where 128 x 128 tiles of
+// the upper triangle also form the lower half of every diagonal tile and the
 // padding up to the next multiple of 128.
-constexpr int kStrip = 64;
+__host__ __device__ __forceinline__ int strip_tiles(int ng, int h, int r) { return (ng - h * r + kTile - 1) / kTile; }
 
-__host__ __device__ __forceinline__ int strip_tiles(int ng, int r) { return (ng - kStrip * r + kTile - 1) / kTile; }
-
-__host__ __device__ inline long strip_tiles_total(int ng)
+__host__ __device__ inline long strip_tiles_total(int ng, int h)
 {
     long n = 0;
-    for (int r = 0; r * kStrip < ng; r++) n += strip_tiles(ng, r);
+    for (int r = 0; r * h < ng; r++) n += strip_tiles(ng, h, r);
     return n;
 }
 
 // strip r and column tile j of block index id
-__device__ __forceinline__ void strip_tile_of(int id, int ng, int &r, int &j)
+__device__ __forceinline__ void strip_tile_of(int id, int ng, int h, int &r, int &j)
 {
     r = 0;
-    for (int m = strip_tiles(ng, 0); id >= m; m = strip_tiles(ng, r)) {
+    for (int m = strip_tiles(ng, h, 0); id >= m; m = strip_tiles(ng, h, r)) {
         id -= m;
         r++;
     }
@@ -485,18 +485,27 @@ template <int NT> __device__ __forceinline__ void split_pair(float x0, float x1,
     }
 }
 
-// ST: the strip tiling (stail = 0): a block owns a 64-row strip x 128 columns
-// for 4 frequencies, wave w the strip for frequency f0 + w, so every wave does
-// the same work as in the 128 x 128 form; grid x runs over the strip tiles of
-// the upper triangle (herm) or over all 2 t x t strip tiles (row-major).
-template <int NT, bool RW, bool ST>
+// SM, the strip tiling (stail = 0): SM = 4, a block owns a 64-row strip x 128
+// columns for 4 frequencies, wave w the strip for frequency f0 + w; SM = 8, a
+// 32-row strip x 128 columns for 8 frequencies, wave w the strip for
+// frequencies f0 + 2 w and f0 + 2 w + 1.  Either way every wave forms four
+// (16-row block, frequency) combinations x 128 columns, the same work as in
+// the 128 x 128 form (SM = 0); grid x runs over the strip tiles of the upper
+// triangle (herm) or over all NGP / h x t strip tiles (row-major).
+template <int NT, bool RW, int SM>
 __global__ void __launch_bounds__(256)
 k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, const bf8 *__restrict__ Bp, int nfreq,
            const float2 *__restrict__ wq, int accumulate, double2 *__restrict__ chi, int herm, int sps,
            float2 *__restrict__ part, int nfull, int stail)
 {
-    constexpr int NW = ST ? 4 : 2;
-    constexpr int NRB = ST ? 4 : 8;   // 16-row blocks of the block's rows
+    constexpr bool ST = SM != 0;
+    constexpr int NW = ST ? SM : 2;           // frequencies per block
+    constexpr int WW = SM == 8 ? 2 : 1;       // frequencies per wave
+    constexpr int SH = SM == 8 ? 32 : 64;     // strip height
+    constexpr int NRB = ST ? SH / 16 : 8;     // 16-row blocks of the block's rows
+    // combination c of a wave: 16-row block crb(c) of its rows, its frequency cw(c)
+    auto crb = [](int c) { return WW == 2 ? (c & 1) : c; };
+    auto cw = [](int c) { return WW == 2 ? (c >> 1) : 0; };
     constexpr int NPL = 2 * NT;
     __shared__ float2 sA[2][4 * 8 * 128];
     __shared__ bf8 sB[2][NPL * 4 * 128];
@@ -528,13 +537,13 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     int rt, ct, rt0, ct0;
     if constexpr (ST) {
         if (herm) {
-            strip_tile_of(tile, ng, rt, ct);
-            rt0 = rt * kStrip;
+            strip_tile_of(tile, ng, SH, rt, ct);
+            rt0 = rt * SH;
             ct0 = rt0 + ct * kTile;
         } else {
             rt = tile / nt;
             ct = tile - rt * nt;
-            rt0 = rt * kStrip;
+            rt0 = rt * SH;
             ct0 = ct * kTile;
         }
     } else {
@@ -544,7 +553,7 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     }
     const int wr = ST ? 0 : wave >> 1, iw = ST ? wave : wave & 1;
     const int f0 = group * NW;
-    const int fw = min(f0 + iw, nfreq - 1);
+    const int fv = f0 + WW * iw;              // the wave's first frequency
     const long plane = (long)npg * NGP;
 
     // DMA as in k_chi_bf16: wave w moves pair group kg = w of the step.  A
@@ -565,11 +574,15 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
             dma16(b1 + sp * plane, dB + (sp * 4 + wave) * 128 + 64);
         }
     };
-    // this lane's 8 pairs (8 lk .. 8 lk + 7 of the step) at frequency fw
-    const float4 *wsrc = (const float4 *)(wq + (long)fw * KP) + lk * 4;
-    auto wload = [&](int step, float4 (&dst)[4]) {
+    // this lane's 8 pairs (8 lk .. 8 lk + 7 of the step) at the wave's frequencies
+    const float4 *wsrc[WW];
 #pragma unroll
-        for (int h = 0; h < 4; h++) dst[h] = wsrc[(long)step * 16 + h];
+    for (int v = 0; v < WW; v++) wsrc[v] = (const float4 *)(wq + (long)min(fv + v, nfreq - 1) * KP) + lk * 4;
+    auto wload = [&](int step, float4 (&dst)[WW][4]) {
+#pragma unroll
+        for (int v = 0; v < WW; v++)
+#pragma unroll
+            for (int h = 0; h < 4; h++) dst[v][h] = wsrc[v][(long)step * 16 + h];
     };
 
     f4 accR[4][8], accI[4][8];
@@ -636,13 +649,13 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
     constexpr int NPROD = 4 * NT * (NT + 1) / 2;   // matrix-core ops per (row block, column block)
 
     auto step = [&](float2 *__restrict__ nA, bf8 *__restrict__ nB, const float2 *__restrict__ cA,
-                    const bf8 *__restrict__ cB, int kgn, const float4 (&wc)[4]) {
+                    const bf8 *__restrict__ cB, int kgn, const float4 (&wc)[WW][4]) {
         if (kgn >= 0) issue(nA, nB, kgn);
         bf8 ar[4][NT], ai[4][NT], an[4][NT];
         bf8 B[NPL], Bn[NPL];   // this column block's fragments and the next one's
 #pragma unroll
         for (int sp = 0; sp < NPL; sp++) B[sp] = cB[(sp * 4 + lk) * 128 + li];
-        split_rows(cA, 0, wc, ar[0], ai[0], an[0]);
+        split_rows(cA, crb(0), wc[cw(0)], ar[0], ai[0], an[0]);
         __builtin_amdgcn_sched_barrier(0);
         // column block 0, one row block after the other: the split of row
         // block rb + 1 is issued among the matrix-core ops of row block rb,
@@ -651,7 +664,7 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
         for (int rb = 0; rb < 4; rb++) {
             products(rb, 0, ar[rb], ai[rb], an[rb], B);
             if (rb + 1 < 4) {
-                split_rows(cA, rb + 1, wc, ar[rb + 1], ai[rb + 1], an[rb + 1]);
+                split_rows(cA, crb(rb + 1), wc[cw(rb + 1)], ar[rb + 1], ai[rb + 1], an[rb + 1]);
                 __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);       // the row block's LDS reads
 #pragma unroll
                 for (int i = 0; i < NPROD; i++) {
@@ -705,7 +718,7 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
         }
     };
 
-    float4 wcur[4], wnext[4];
+    float4 wcur[WW][4], wnext[WW][4];
     if (nstep > 0) {
         wload(step0, wnext);
         issue(sA[0], sB[0], 4 * step0);
@@ -715,7 +728,9 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
 #pragma unroll
-        for (int h = 0; h < 4; h++) wcur[h] = wnext[h];
+        for (int v = 0; v < WW; v++)
+#pragma unroll
+            for (int h = 0; h < 4; h++) wcur[v][h] = wnext[v][h];
         const bool more = t + 1 < nstep;
         if (more) wload(step0 + t + 1, wnext);
         step(sA[stg ^ 1], sB[stg ^ 1], sA[stg], sB[stg], more ? 4 * (step0 + t + 1) : -1, wcur);
@@ -735,37 +750,40 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
                 }
         return;
     }
-    if (f0 + iw >= nfreq) return;
+    // combination c: rows rt0 + wr 64 + 16 crb(c) .., frequency fv + cw(c)
     if (part && stail == 0) {
-        float2 *P = part + ((long)blockIdx.z * nfreq + f0 + iw) * NGP * NGP;
 #pragma unroll
-        for (int rb = 0; rb < 4; rb++)
+        for (int c = 0; c < 4; c++) {
+            if (fv + cw(c) >= nfreq) continue;
+            float2 *P = part + ((long)blockIdx.z * nfreq + fv + cw(c)) * NGP * NGP;
 #pragma unroll
             for (int cb = 0; cb < 8; cb++)
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const int i = rt0 + wr * 64 + rb * 16 + 4 * lk + r;
+                    const int i = rt0 + wr * 64 + crb(c) * 16 + 4 * lk + r;
                     const int j = ct0 + cb * 16 + li;
-                    if (!ST || j < NGP) P[(long)i * NGP + j] = make_float2(accR[rb][cb][r], accI[rb][cb][r]);
+                    if (!ST || j < NGP) P[(long)i * NGP + j] = make_float2(accR[c][cb][r], accI[c][cb][r]);
                 }
+        }
         return;
     }
     // Hermitian: the conjugate of an element outside the block's diagonal
-    // tile (128 x 128 form) or outside its strip's leading 64 columns (strip
+    // tile (128 x 128 form) or outside its strip's leading SH columns (strip
     // form) also goes to the mirrored position, formed by no other block
     const bool mirror_tile = herm && rt != ct;
-    double2 *C = chi + (long)(f0 + iw) * ng * ng;
 #pragma unroll
-    for (int rb = 0; rb < 4; rb++)
+    for (int c = 0; c < 4; c++) {
+        if (fv + cw(c) >= nfreq) continue;
+        double2 *C = chi + (long)(fv + cw(c)) * ng * ng;
 #pragma unroll
         for (int cb = 0; cb < 8; cb++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int i = rt0 + wr * 64 + rb * 16 + 4 * lk + r;
+                const int i = rt0 + wr * 64 + crb(c) * 16 + 4 * lk + r;
                 const int j = ct0 + cb * 16 + li;
-                const bool mirror = ST ? herm && j >= rt0 + kStrip : mirror_tile;
+                const bool mirror = ST ? herm && j >= rt0 + SH : mirror_tile;
                 if (i < ng && j < ng) {
-                    const double2 a = make_double2((double)accR[rb][cb][r], (double)accI[rb][cb][r]);
+                    const double2 a = make_double2((double)accR[c][cb][r], (double)accI[c][cb][r]);
                     const long idx = (long)i * ng + j;
                     C[idx] = accumulate ? cadd(C[idx], a) : a;
                     if (mirror) {
@@ -775,6 +793,7 @@ k_chi_rows(int npg, int NGP, long KP, int ng, const float2 *__restrict__ Ap, con
                     }
                 }
             }
+    }
 }
 
 __device__ __forceinline__ f16v mfma32_bf16(bf8 a, bf8 b, f16v c)
@@ -1108,11 +1127,19 @@ static bool use_strips(bool herm, int nw, int nfreq, int wide, long npair, int n
     return stail == 0;
 }
 
+// frequencies per workgroup of the strip tiling and its strip height: for a
+// Hermitian chi with frequencies in groups of eight, 8 on 32-row strips (whose
+// leading blocks waste a quarter of the 64-row strips' lower halves); else 4
+// on 64-row strips (for complex weights the 32-row strips measured no faster)
+static int strip_sm(int nfreq, bool herm) { return herm && nfreq % 8 == 0 ? 8 : 4; }
+static int strip_height(int nfreq, bool herm) { return strip_sm(nfreq, herm) == 8 ? 32 : 64; }
+
 // workgroups per frequency group and slice of the strip tiling
-static long strip_blocks(int ng, bool herm)
+static long strip_blocks(int ng, int nfreq, bool herm)
 {
+    const int h = strip_height(nfreq, herm);
     const long t = pad_ng(ng) / kTile;
-    return herm ? strip_tiles_total(ng) : 2 * t * t;
+    return herm ? strip_tiles_total(ng, h) : (long)(pad_ng(ng) / h) * t;
 }
 
 static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fill, int wide, int *nslice,
@@ -1122,8 +1149,8 @@ static void chi_slices(long npair, int ng, int nfreq, bool herm, int nw, int fil
     long tiles = herm ? (long)t * (t + 1) / 2 : (long)t * t;
     if (herm && strips_allowed(herm, nw, nfreq, wide)) {
         // (for complex weights the strips hold as many workgroups as the tiles)
-        tiles = strip_blocks(ng, herm);
-        nw = 4;
+        tiles = strip_blocks(ng, nfreq, herm);
+        nw = strip_sm(nfreq, herm);
     }
     int nstep = (int)(pad_pairs(npair) / kStep);
     if (wide) {
@@ -1287,18 +1314,29 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
         }
 #undef RP_CHIW
     } else if (use_strips(herm, nw, nfreq, wide, npair, ng, fill, S)) {
-        const dim3 grid((unsigned)strip_blocks(ng, herm), (unsigned)(nfreq / 4), (unsigned)S);
-#define RP_STRIPS(NT, RW)                                                                                     \
-    hipLaunchKernelGGL((k_chi_rows<NT, RW, true>), grid, dim3(256), 0, s, npg, NGP, KP, ng,                   \
+        const int sm = strip_sm(nfreq, herm);
+        const dim3 grid((unsigned)strip_blocks(ng, nfreq, herm), (unsigned)(nfreq / sm), (unsigned)S);
+#define RP_STRIPS(NT, RW, SM)                                                                                 \
+    hipLaunchKernelGGL((k_chi_rows<NT, RW, SM>), grid, dim3(256), 0, s, npg, NGP, KP, ng,                     \
                        (const float2 *)split_a, (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, \
                        chi, (int)herm, sps, P, 0, 0)
+#define RP_STRIPS_SM(NT, RW)     \
+    if (sm == 8) {               \
+        RP_STRIPS(NT, RW, 8);    \
+    } else {                     \
+        RP_STRIPS(NT, RW, 4);    \
+    }
         if (herm) {
-            if (nterm == 2) RP_STRIPS(2, true);
-            else RP_STRIPS(3, true);
+            if (nterm == 2) {
+                RP_STRIPS_SM(2, true)
+            } else {
+                RP_STRIPS_SM(3, true)
+            }
         } else {
-            if (nterm == 2) RP_STRIPS(2, false);
-            else RP_STRIPS(3, false);
+            if (nterm == 2) RP_STRIPS(2, false, 4);
+            else RP_STRIPS(3, false, 4);
         }
+#undef RP_STRIPS_SM
 #undef RP_STRIPS
     } else {
         const unsigned tiles = herm ? (unsigned)(t * (t + 1) / 2) : (unsigned)(t * t);
@@ -1315,7 +1353,7 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
                        (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P, \
                        nfull, stail)
 #define RP_ROWS(NT, RW)                                                                                       \
-    hipLaunchKernelGGL((k_chi_rows<NT, RW, false>), grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a,  \
+    hipLaunchKernelGGL((k_chi_rows<NT, RW, 0>), grid, dim3(256), 0, s, npg, NGP, KP, ng, (const float2 *)split_a,  \
                        (const bf8 *)split_b, nfreq, (const float2 *)split_w, accumulate, chi, (int)herm, sps, P, \
                        nfull, stail)
         if (nw == 1) {
@@ -1338,7 +1376,7 @@ void launch_chi_bf16(hipStream_t s, int nterm, long npair, int ng, int nfreq, in
     if (S > 1) {
         if (before_reduce) before_reduce();
         const int nc = NGP / 32;
-        const int hs = herm && strips_allowed(herm, nw, nfreq, wide) ? kStrip : kTile;
+        const int hs = herm && strips_allowed(herm, nw, nfreq, wide) ? strip_height(nfreq, herm) : kTile;
         hipLaunchKernelGGL(k_chi_reduce, dim3((unsigned)(nc * nc), 1, (unsigned)nfreq), dim3(256), 0, s, S, nfreq, ng,
                            NGP, (const float2 *)P, accumulate, (int)herm, hs, chi);
     }

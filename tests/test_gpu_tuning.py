@@ -188,10 +188,11 @@ def test_tail_split_matches(ctx, rp, herm):
 @pytest.mark.parametrize("ng", [89, 200, 300, 351])
 def test_strip_tiling(ctx, rp, ng, axis):
     """With a multiple of four frequencies the two-frequency row form runs as
-    64-row strips x 128 columns for four frequencies: over the upper triangle
-    with each strip's column tiles starting at its diagonal for a Hermitian
-    chi (imaginary frequencies, delta = 0), over the whole matrix for complex
-    weights (real frequencies, delta > 0).  On a 16^3 problem with 8
+    64-row strips x 128 columns for four frequencies over the whole matrix
+    for complex weights (real frequencies, delta > 0); a Hermitian chi
+    (imaginary frequencies, delta = 0) with a multiple of eight runs as 32-row
+    strips x 128 columns for eight frequencies over the upper triangle, each
+    strip's column tiles starting at its diagonal.  On a 16^3 problem with 8
     frequencies and N_G from under one tile (89) to ragged multiples (200,
     300, 351), unsliced and sliced, two- and three-term splits: the whole
     chi against the oracle element-wise (1e-5; the FP32 pair densities bound
