@@ -253,6 +253,22 @@ def _save_atomic(path: str, obj) -> None:
     os.replace(tmp, path)
 
 
+def _fingerprint(p) -> str:
+    """SHA-256 of a problem's small inputs (frequencies, broadening, G list
+    and tail, k mesh, band energies, cRPA T), so that a resume with other
+    inputs of the same sizes is refused; the plane-wave coefficients are not
+    included."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in (p.freq_eV, np.array([p.delta_eV], np.float64), p.gsph, getattr(p, "gtail", None), p.kmesh,
+              p.energy_eV, p.T):
+        if a is not None:
+            a = np.ascontiguousarray(np.asarray(a))
+            h.update(str(a.dtype).encode() + str(a.shape).encode())
+            h.update(a.tobytes())
+    return h.hexdigest()
+
+
 def run_q_checkpointed(ctx, d: DeviceInputs, out_dir: str, prec: int = _rp.RP_FP64, kbatch: int = 1,
                        every: int = 1, stop_after: Optional[int] = None):
     """run_q with its results kept in out_dir (the per-q result directories
@@ -264,7 +280,9 @@ def run_q_checkpointed(ctx, d: DeviceInputs, out_dir: str, prec: int = _rp.RP_FP
     with the same out_dir and the same parameters resumes after the last
     checkpoint (rp_chi0_run with accumulate = 1 on the restored chi, the
     same sums in the same order, so the results are those of an
-    uninterrupted run), and a finished q-point is read back, not recomputed.
+    uninterrupted run), and a finished q-point is read back, not recomputed;
+    other parameters or inputs (sizes, or the fingerprint of _fingerprint)
+    raise ValueError.
     stop_after (a count of k batches) returns None once that many batches
     have been checkpointed in this call, as an interrupted run would leave
     out_dir.  Returns a dict of host arrays and "source": "computed",
@@ -277,7 +295,7 @@ def run_q_checkpointed(ctx, d: DeviceInputs, out_dir: str, prec: int = _rp.RP_FP
     p = d.prob
     keys = ["chi", "eps_inv", "W"] + (["Wij"] if d.phi is not None else [])
     meta = dict(prec=int(prec), kbatch=int(kbatch), nk=d.nk, ng=d.ng, nfreq=d.nfreq,
-                iq=[int(x) for x in p.iq], nocc=int(p.nocc), nemp=int(p.nemp))
+                iq=[int(x) for x in p.iq], nocc=int(p.nocc), nemp=int(p.nemp), inputs=_fingerprint(p))
     done = os.path.join(out_dir, "done.json")
     if os.path.exists(done):
         with open(done) as f:
