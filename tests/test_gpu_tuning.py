@@ -184,7 +184,7 @@ def test_tail_split_matches(ctx, rp, herm):
     rp.rp_set_tuning(ctx, [])
 
 
-@pytest.mark.parametrize("axis", ["imaginary", "real"])
+@pytest.mark.parametrize("axis", ["imaginary", "imaginary4", "real"])
 @pytest.mark.parametrize("ng", [89, 200, 300, 351])
 def test_strip_tiling(ctx, rp, ng, axis):
     """With a multiple of four frequencies the two-frequency row form runs as
@@ -192,9 +192,10 @@ def test_strip_tiling(ctx, rp, ng, axis):
     for complex weights (real frequencies, delta > 0); a Hermitian chi
     (imaginary frequencies, delta = 0) with a multiple of eight runs as 32-row
     strips x 128 columns for eight frequencies over the upper triangle, each
-    strip's column tiles starting at its diagonal.  On a 16^3 problem with 8
-    frequencies and N_G from under one tile (89) to ragged multiples (200,
-    300, 351), unsliced and sliced, two- and three-term splits: the whole
+    strip's column tiles starting at its diagonal (with four frequencies, on
+    64-row strips for four).  On a 16^3 problem with 8 frequencies (4 for the
+    second imaginary case) and N_G from under one tile (89) to ragged
+    multiples (200, 300, 351), unsliced and sliced, two- and three-term splits: the whole
     chi against the oracle element-wise (1e-5; the FP32 pair densities bound
     both split forms at about 2e-6) and against the 128 x 128 one-frequency
     form (2e-6)."""
@@ -202,12 +203,14 @@ def test_strip_tiling(ctx, rp, ng, axis):
     from synth import make_problem
     if axis == "imaginary":
         freq, delta = 1j * np.array([0.0, 0.3, 1.0, 2.5, 6.0, 15.0, 40.0, 100.0]), 0.0
+    elif axis == "imaginary4":
+        freq, delta = 1j * np.array([0.0, 1.0, 6.0, 40.0]), 0.0
     else:
         freq, delta = np.array([0.0, 1.0, 2.5, 5.0, 8.0, 12.0, 16.0, 20.0]), 0.1
     p = make_problem(name="strips", a_bohr=7.26, fft=(16, 16, 16), kmesh=(2, 2, 2), iq=(1, 0, 0), nocc=8,
                      nemp=24, gpsi=2.4, ng=ng, freq_eV=freq, delta_eV=delta, seed=41)
     d = path.DeviceInputs(p)
-    assert d.ng == ng and d.nfreq == 8
+    assert d.ng == ng and d.nfreq == len(freq)
     M = oracle.pair_densities(p, 0, p.nocc, p.nocc, p.nband, 0, d.nk)
     w = oracle.prob_weights(p, 0, p.nocc, p.nocc, p.nband, 0, d.nk)
     want = oracle.chi0(M, w)
