@@ -213,16 +213,31 @@ k_gj_update(int ng, int c0, int nb, double2 *a, const double2 *rk)
             accR[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
             accI[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
         }
-    for (int kc = 0; kc < nb; kc += KC) {
-        for (int e = tid; e < 64 * KC; e += 256) {
+    // each thread moves 4 panel and 4 pivot-row elements of a chunk; the next
+    // chunk's are loaded into registers before the current chunk's matrix
+    // work, so their latency is covered by it
+    constexpr int PER = 64 * KC / 256;
+    double2 pp[PER], pr[PER];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int e = tid + q * 256;
             const int rr = e / KC, k = e - rr * KC, i = rt0 + rr;
-            sP[rr][k] = (i < ng && kc + k < nb) ? A[(long)i * ng + c0 + kc + k] : make_double2(0.0, 0.0);
+            pp[q] = (i < ng && kc + k < nb) ? A[(long)i * ng + c0 + kc + k] : make_double2(0.0, 0.0);
+            const int k2 = e >> 6, cc = e & 63, j = ct0 + cc;
+            pr[q] = (kc + k2 < nb && j < ng) ? R[(long)(kc + k2) * ng + j] : make_double2(0.0, 0.0);
         }
-        for (int e = tid; e < KC * 64; e += 256) {
-            const int k = e >> 6, cc = e & 63, j = ct0 + cc;
-            sR[k][cc] = (kc + k < nb && j < ng) ? R[(long)(kc + k) * ng + j] : make_double2(0.0, 0.0);
+    };
+    fetch(0);
+    for (int kc = 0; kc < nb; kc += KC) {
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int e = tid + q * 256;
+            sP[e / KC][e % KC] = pp[q];
+            sR[e >> 6][e & 63] = pr[q];
         }
         __syncthreads();
+        if (kc + KC < nb) fetch(kc + KC);
 #pragma unroll
         for (int k0 = 0; k0 < KC; k0 += 4) {
             double2 x[2], y[2];
