@@ -190,11 +190,13 @@ __device__ __forceinline__ d4 mfma64(double x, double y, d4 c)
 // i + 16k, B operand lane j + 16k, result register r of lane l at row
 // l / 16 + 4 r, column l % 16).  The panel columns of the tile's rows and the
 // pivot rows of its columns are staged in LDS.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 3)
 k_gj_update(int ng, int c0, int nb, double2 *a, const double2 *rk)
 {
     // the panel's 64 columns pass through LDS in chunks of 16, so that a CU
-    // holds several workgroups and one's loads overlap another's matrix work
+    // holds several workgroups and one's loads overlap another's matrix work;
+    // the registers are held to three waves per SIMD (three workgroups per
+    // CU; four would spill)
     constexpr int KC = 16;
     __shared__ double2 sP[64][KC + 1];
     __shared__ double2 sR[KC][64];
