@@ -245,8 +245,16 @@ template <typename C, int N, int NP> constexpr int lanes_l3max()
 // dynamic LDS of the call's window width: at least two workgroups share a CU
 // (three for the 15-wide window of a 32-point grid, where the registers then
 // limit it) and cover each other's load and barrier waits.
+// waves per SIMD the lane-group form asks of the compiler: four for FP32 lines
+// of up to 32 points on four lanes with at most 6 sphere points per thread
+// (which then fit 128 registers), else two
+template <typename C, int N, int MAXG> constexpr int pair_lanes_waves()
+{
+    return sizeof(C) == 8 && N % 4 == 0 && N <= 32 && MAXG <= 6 ? 4 : 2;
+}
+
 template <typename C, int N, int NA, int NB, int MAXG>
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(256, (pair_lanes_waves<C, N, MAXG>()))
 k_pair_lanes(const C *__restrict__ u_occ, const C *__restrict__ u_emp, int nO, int nE, int N1, int ng,
              const int *__restrict__ gsph, int g01, int g02, int g03, int lo3, int L3, double2 *__restrict__ M,
              SplitOps ops)
