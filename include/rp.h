@@ -575,7 +575,12 @@ rp_status rp_set_drude(rp_ctx *ctx, double wq_eV2, double delta_eV);
  * ng_max >= N_G and grid_max >= E; with no match, or no table, the defaults
  * apply.  The table is copied; n = 0 clears it.
  *   chi_nw     frequencies per workgroup of the split-BF16 contraction, 1 or
- *              2 (0: the default, 2)
+ *              2 (0: the default, 2); with 2 and a multiple of four
+ *              frequencies, form 0 runs as 64-row strips x 128 columns for
+ *              four frequencies (a Hermitian chi with a multiple of eight:
+ *              32-row strips for eight, each strip's tiles starting at its
+ *              diagonal), except unsliced complex-weight launches whose last
+ *              wave of 128 x 128 tiles is split over the chip
  *   chi_fill   workgroups the slicing of the pair steps aims for when the
  *              tiles alone give fewer than half of it (0: never slice, -1:
  *              the default, 1024)
