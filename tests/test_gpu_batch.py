@@ -9,6 +9,9 @@ Per system, on a band subset (8 occupied x 16 empty bands, k < 27):
 * chi Hermitian and negative semidefinite (real weights on the imaginary axis).
 Systems 7 and 8 have odd grid edges (25, 27): one lane per FFT line in FP32,
 the generic pair kernel in FP64; system 18 (30^3) has two lanes per line.
+The batch entry point is checked against per-problem calls on uneven batches,
+across its bounded graph pieces, and on a batch whose problems take four
+different contraction forms.
 """
 
 import numpy as np
@@ -224,3 +227,45 @@ def test_chi0_batch_across_graph_pieces(ctx, rp, prec):
     ew = max(np.abs(got[f] - want[f]).max() / np.abs(want[f]).max() for f in range(d.nfreq))
     print(f"[batch pieces] problem 0 vs oracle: {fro:.1e} (Frobenius), {ew:.1e} (element-wise)", flush=True)
     assert fro < tol and ew < tol
+
+
+def test_chi0_batch_mixed_contraction_forms(ctx, rp):
+    """One rp_chi0_batch call whose problems take different contraction forms:
+    16 imaginary frequencies (Hermitian, 32-row strips for eight), 12
+    (Hermitian, 64-row strips for four), 6 (Hermitian, 128 x 128 tiles of the
+    upper triangle) and 8 real frequencies with delta > 0 (complex weights,
+    64-row strips over the whole matrix), split-BF16: each problem equals its
+    per-problem calls, and two of them the oracle on sampled columns."""
+    import dataclasses
+
+    from paper_2001_02351_amd import path
+    from synth import make_problem
+    p16 = batch_system(21, 0)
+    p12 = dataclasses.replace(batch_system(7, 0), freq_eV=batch_system(7, 0).freq_eV[:12])
+    p6 = dataclasses.replace(batch_system(4, 0), freq_eV=batch_system(4, 0).freq_eV[:6])
+    preal = make_problem(name="mixed", a_bohr=7.26, fft=(16, 16, 16), kmesh=(2, 2, 2), iq=(1, 0, 0), nocc=8,
+                         nemp=24, gpsi=2.4, ng=200, freq_eV=np.linspace(0.0, 20.0, 8), delta_eV=0.1, seed=43)
+    ds = [path.DeviceInputs(p) for p in (p16, p12, p6, preal)]
+    assert [d.nfreq for d in ds] == [16, 12, 6, 8]
+    bands = [((0, 8), (d.prob.nocc, d.prob.nocc + 16)) for d in ds]
+    kbatch = 3
+    chis = [torch.full((d.nfreq, d.ng, d.ng, 2), float("nan"), dtype=torch.float64, device="cuda") for d in ds]
+    probs = [path.batch_problem(d, c, kbatch, o=o, e=e) for d, c, (o, e) in zip(ds, chis, bands)]
+    print(f"[batch mixed] {len(probs)} problems, N_G {[d.ng for d in ds]}", flush=True)
+    rp.rp_chi0_batch(ctx, probs, rp.RP_SPLIT_BF16)
+    rp.rp_synchronize(ctx)
+    for i, (d, (o, e), c) in enumerate(zip(ds, bands, chis)):
+        ref = _per_problem(ctx, rp, d, o, e, rp.RP_SPLIT_BF16, kbatch)
+        rp.rp_synchronize(ctx)
+        print(f"[batch mixed] problem {i}: exact {bool(torch.equal(c, ref))}", flush=True)
+        assert _rel(c.cpu().numpy(), ref.cpu().numpy()) <= 1e-14
+    for i in (1, 3):
+        d, (o, e) = ds[i], bands[i]
+        M = oracle.pair_densities(d.prob, *o, *e, 0, d.nk)
+        w = oracle.prob_weights(d.prob, *o, *e, 0, d.nk)
+        cols = np.unique(np.concatenate([np.random.default_rng(11).choice(d.ng, 24, replace=False), [d.ng - 1]]))
+        want = oracle.chi0(M[:, cols], w)
+        got = path.to_complex(chis[i])
+        err = max(_rel(got[f][cols][:, cols], want[f]) for f in range(d.nfreq))
+        print(f"[batch mixed] problem {i}: vs oracle {err:.1e}", flush=True)
+        assert err < 1e-5
