@@ -229,13 +229,15 @@ def test_chi0_batch_across_graph_pieces(ctx, rp, prec):
     assert fro < tol and ew < tol
 
 
-def test_chi0_batch_mixed_contraction_forms(ctx, rp):
+@pytest.mark.parametrize("prec", [1, 2])
+def test_chi0_batch_mixed_contraction_forms(ctx, rp, prec):
     """One rp_chi0_batch call whose problems take different contraction forms:
     16 imaginary frequencies (Hermitian, 32-row strips for eight), 12
     (Hermitian, 64-row strips for four), 6 (Hermitian, 128 x 128 tiles of the
     upper triangle) and 8 real frequencies with delta > 0 (complex weights,
-    64-row strips over the whole matrix), split-BF16: each problem equals its
-    per-problem calls, and two of them the oracle on sampled columns."""
+    64-row strips over the whole matrix), split-BF16 and x6: each problem
+    equals its per-problem calls, and two of them the oracle on sampled
+    columns."""
     import dataclasses
 
     from paper_2001_02351_amd import path
@@ -252,10 +254,10 @@ def test_chi0_batch_mixed_contraction_forms(ctx, rp):
     chis = [torch.full((d.nfreq, d.ng, d.ng, 2), float("nan"), dtype=torch.float64, device="cuda") for d in ds]
     probs = [path.batch_problem(d, c, kbatch, o=o, e=e) for d, c, (o, e) in zip(ds, chis, bands)]
     print(f"[batch mixed] {len(probs)} problems, N_G {[d.ng for d in ds]}", flush=True)
-    rp.rp_chi0_batch(ctx, probs, rp.RP_SPLIT_BF16)
+    rp.rp_chi0_batch(ctx, probs, prec)
     rp.rp_synchronize(ctx)
     for i, (d, (o, e), c) in enumerate(zip(ds, bands, chis)):
-        ref = _per_problem(ctx, rp, d, o, e, rp.RP_SPLIT_BF16, kbatch)
+        ref = _per_problem(ctx, rp, d, o, e, prec, kbatch)
         rp.rp_synchronize(ctx)
         print(f"[batch mixed] problem {i}: exact {bool(torch.equal(c, ref))}", flush=True)
         assert _rel(c.cpu().numpy(), ref.cpu().numpy()) <= 1e-14

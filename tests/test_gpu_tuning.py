@@ -185,7 +185,7 @@ def test_tail_split_matches(ctx, rp, herm):
 
 
 @pytest.mark.parametrize("axis", ["imaginary", "imaginary4", "real"])
-@pytest.mark.parametrize("ng", [89, 200, 300, 351])
+@pytest.mark.parametrize("ng", [1, 17, 89, 200, 300, 351])
 def test_strip_tiling(ctx, rp, ng, axis):
     """With a multiple of four frequencies the two-frequency row form runs as
     64-row strips x 128 columns for four frequencies over the whole matrix
